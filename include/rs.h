@@ -1,0 +1,230 @@
+/*
+ * rs.h -- C ABI of the range-separated (RS) canonical/Tucker potential library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library assembles the N-particle potential sum
+ *     P(x) = sum_nu z_nu p(|x - x_nu|),   x, x_nu in Omega = [-b, b]^3     (eq PotSum1)
+ * on the uniform n x n x n grid of cell centres x_i = -b + (i + 1/2) h,
+ * h = 2b/n, n even (section 2.2), in the RS-Tucker format
+ *     A = beta x_1 V1 x_2 V2 x_3 V3 + sum_nu z_nu U_nu                     (Definition RS-Tucker_format)
+ * where the Tucker part is the reduced-HOSVD (RHOSVD) compression of the
+ * long-range canonical sum (eq Long-Range_Sum, Appendix eqs SVD_SideMatr,
+ * alg1) and U_nu are short-range windows of the reference tensor
+ * (Definitions ComCanF, CCT_Uniform).  It also evaluates P at points, the
+ * interaction energy (Lemma InterEnergy, eq EnergyFree_Tensor) and the forces
+ * F_j = -dE/dx_j (section 4.4).
+ *
+ * Conventions for every call
+ *  - "device" pointers are HIP device memory on the context's device (for
+ *    example torch CUDA tensors on ROCm); "host" pointers are ordinary memory.
+ *  - The caller owns every pointer argument.  The library owns the opaque
+ *    handles (rs_ctx, rs_factors, rs_tensor) and frees them only through the
+ *    matching *_free / *_destroy call.
+ *  - Work is enqueued on the HIP stream passed as `stream` (a hipStream_t;
+ *    NULL = the null stream).  Calls return once their work is enqueued,
+ *    except where a call says it synchronizes.
+ *  - Arguments are validated before anything is enqueued; on a non-OK
+ *    status nothing has been written to caller memory.  rs_last_error()
+ *    returns a thread-local message describing the last failure.  No C++
+ *    exception crosses this boundary.
+ *  - Results are deterministic: no floating-point atomics; every reduction
+ *    runs in a fixed order that depends only on the request's own shape, so
+ *    the same inputs give bitwise-identical outputs whatever else runs on
+ *    the device.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RS_OK = 0,
+  RS_E_INVALID = 1,      /* bad argument or input (see rs_last_error) */
+  RS_E_NOMEM = 2,        /* device allocation failed */
+  RS_E_DEVICE = 3,       /* a HIP call failed */
+  RS_E_RANK_CAP = 4,     /* rank rule exceeded r_max: result produced at r_max (non-fatal) */
+  RS_E_UNSUPPORTED = 5   /* valid request this build does not support */
+} rs_status;
+
+/* Generating kernel p(r) (section 2.2): Newton 1/r, Yukawa e^{-lambda r}/r,
+ * or their sum.  All are Laplace-Gauss transforms p(z) = int a(t) e^{-t^2 z^2} dt
+ * (eq laplace) with a(t) = 2/sqrt(pi) [ * e^{-lambda^2 / (4 t^2)} ]. */
+typedef enum { RS_NEWTON = 0, RS_YUKAWA = 1, RS_NEWTON_PLUS_YUKAWA = 2 } rs_kernel;
+
+/* Arithmetic of the assembly.
+ *  RS_FP64: everything in FP64; the grid is FP64.
+ *  RS_MIXED_FP16: the projection, core and grid-expansion contractions use
+ *    split FP16 operands (value = hi + lo * 2^-11) with FP32 MFMA accumulation
+ *    and FP64 sums across K chunks; the Gram, eigensolve, quadrature table,
+ *    point evaluation and energy reduction stay FP64.  The grid is FP32.
+ *  RS_MIXED_BF16: as RS_MIXED_FP16 with three-way split BF16 operands. */
+typedef enum { RS_FP64 = 0, RS_MIXED_FP16 = 1, RS_MIXED_BF16 = 2 } rs_prec;
+
+typedef struct rs_ctx rs_ctx;
+typedef struct rs_factors rs_factors;
+typedef struct rs_tensor rs_tensor;
+
+/* Grid: Omega = [-b, b]^3, n points per axis, n even, n >= 8. */
+typedef struct {
+  double b;
+  int64_t n;
+} rs_grid;
+
+/* Quadrature and range split (sections 2.2-2.3).
+ *  R: number of terms, R = M + 1; t_k = k h_M, h_M = C0 log(M)/M (eq hM),
+ *     weights folded onto k >= 0: a_0 = h_M a(0)/2, a_k = h_M a(t_k).
+ *  R_l: long-range terms k = 0..R_l-1 (1 <= R_l <= R-1); -1 = choose by
+ *     criterion (A) (eq Split_crit_max) for the support radius sigma = sigma_split.
+ *  n_s: odd short-range window width in cells; -1 = the smallest odd n_s with
+ *     (n_s/2) h >= sigma, sigma the radius beyond which every short term
+ *     a_k e^{-t_k^2 sigma^2} <= delta_rel * S(0) (criterion (A) solved for sigma).
+ *  C0 <= 0 selects the paper's C0 = 3. */
+typedef struct {
+  int32_t kernel;        /* rs_kernel */
+  double lambda;         /* Yukawa screening, > 0 when used */
+  int32_t R;
+  int32_t R_l;
+  int32_t n_s;
+  double delta_rel;      /* criterion (A) threshold relative to S(0); <= 0 -> 1e-4 */
+  double sigma_split;    /* only read when R_l == -1 */
+  double C0;
+} rs_fdesc;
+
+/* Assembly options.
+ *  eps_tucker: rank rule, keep singular values sigma_k > eps_tucker * sigma_1 of
+ *     the charge-weighted side matrix U_l diag(|xi|^{1/3}) (Appendix, step (I)).
+ *  r_max: rank cap per mode (<= n).  fixed_ranks[l] > 0 overrides the rule.
+ *  oversample: extra subspace columns of the eigensolver (default 16 when <= 0).
+ *  power_iters: subspace iterations after the first (default 1 when < 0).
+ *  interp_order: even Lagrange order p of point evaluation (default 6 when <= 0). */
+typedef struct {
+  double eps_tucker;
+  int32_t r_max;
+  int32_t fixed_ranks[3];
+  int32_t prec;          /* rs_prec */
+  int32_t oversample;
+  int32_t power_iters;
+  int32_t interp_order;
+} rs_aopts;
+
+typedef struct {
+  int64_t N, n;
+  double b, h;
+  int32_t R, R_l, n_s, prec, interp_order;
+  int32_t ranks[3];          /* Tucker ranks r_1, r_2, r_3 */
+  int32_t subspace[3];       /* eigensolver subspace size p per mode */
+  double sigma_first[3];     /* sigma_1 of each mode */
+  double sigma_last_kept[3]; /* sigma_r / sigma_1 */
+  double sigma_next[3];      /* sigma_{r+1} / sigma_1 (0 if not resolved) */
+  double S0, S_l0;           /* S(0) = sum a_k, S_l(0) = sum_{k<R_l} a_k */
+  int64_t tucker_storage;    /* r1 r2 r3 + n (r1 + r2 + r3) (Lemma Property_RST_Tuck) */
+  int64_t device_bytes;      /* device memory held by the tensor */
+  int32_t rank_capped;       /* 1 if the rank rule hit r_max in some mode */
+} rs_info;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Bind the library to HIP device `device` (makes it current on this thread). */
+rs_status rs_ctx_create(int device, rs_ctx** out);
+void rs_ctx_destroy(rs_ctx* ctx);
+
+/* ---- quadrature table and split (sections 2.2-2.3) --------------------- */
+
+/* Build the FP64 quadrature table {t_k, a_k}, the long/short split R_l and
+ * the window width n_s on the host, and copy the table to the device
+ * (synchronous, a few hundred bytes).  Errors: RS_E_INVALID for R < 3,
+ * R_l outside [1, R-1], n odd or < 8, even n_s, non-positive b, lambda <= 0
+ * for a Yukawa kernel. */
+rs_status rs_build_factors(rs_ctx* ctx, const rs_grid* grid, const rs_fdesc* fdesc,
+                           rs_factors** out);
+/* Host copies of the table (arrays of length R, or NULL) and the split. */
+rs_status rs_factors_get(const rs_factors* f, double* t, double* a, int32_t* R,
+                         int32_t* R_l, int32_t* n_s);
+void rs_factors_free(rs_factors* f);
+
+/* ---- assembly (sections 3.2-3.3, Appendix) ----------------------------- */
+
+/* Assemble the RS-Tucker tensor of N particles.
+ *  pos: device, N x 3 row-major FP64 coordinates, all inside [-b, b]^3.
+ *  q:   device, N FP64 charges.
+ *  grid_out: device, n^3 values in C order (i3 fastest) or NULL to skip the
+ *     full-grid materialisation; FP64 for RS_FP64, FP32 for the mixed modes.
+ *     It receives beta x_1 V1 x_2 V2 x_3 V3 + sum_nu z_nu U_nu at the cell centres.
+ *  out: receives a new tensor handle (keeps its own copies of pos and q).
+ * Steps: side matrices U_l[i, k*N+nu] = exp(-t_k^2 (x_i - x_{nu,l})^2) for
+ * k < R_l; weighted Gram G_l = U_l diag(|xi|^{2/3}) U_l^T, xi = z_nu a_k;
+ * dominant eigenvectors of G_l (subspace iteration + Jacobi, FP64); rank rule;
+ * projection U~_l = V_l^T U_l; core beta = sum_j xi_j u~1_j (x) u~2_j (x) u~3_j;
+ * short windows of width n_s around each particle's cell.
+ * Synchronizes `stream` once, after the eigensolve, to read the ranks back.
+ * Errors: RS_E_INVALID (N < 1, non-finite input, a particle outside Omega,
+ * bad options), RS_E_NOMEM, RS_E_DEVICE; RS_E_RANK_CAP is returned with a
+ * valid tensor when some rank was capped. */
+rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
+                      const double* q, const rs_aopts* opts, void* grid_out,
+                      rs_tensor** out, void* stream);
+
+/* The three charge-weighted Gram matrices G_l = U_l diag(|xi|^{2/3}) U_l^T of
+ * the long-range side matrices (Appendix step (I) through the Gram), the
+ * first step of the RHOSVD.  pos, q as in rs_assemble; G: device, 3 x n x n
+ * FP64 (mode-major, symmetric).  Asynchronous. */
+rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
+                           const double* q, double* G, void* stream);
+
+/* ---- evaluation (Lemma Property_RST_Tuck, section 4.3-4.4) ------------- */
+
+/* Values of the RS tensor at M arbitrary points.
+ *  pts: device, M x 3 row-major FP64 inside Omega;  vals: device, M FP64.
+ *  part: 0 = long + short, 1 = long-range Tucker part, 2 = short-range part.
+ * The long-range part is the order-p tensor Lagrange interpolant of the
+ * Tucker factors on the cell-centred grid (exact at grid points); the short
+ * part sums the short-range Gaussians of every particle whose window
+ * contains the point's cell.  Asynchronous. */
+rs_status rs_eval_points(const rs_tensor* T, int64_t M, const double* pts, double* vals,
+                         int32_t part, void* stream);
+
+/* Interaction energy E_N = 1/2 sum_j z_j (P_l(x_j) - z_j g_j) (eq EnergyFree_Tensor),
+ * g_j the particle's own long-range term through the same interpolation
+ * (= P_{R_l}(0) for a particle on a grid point).
+ *  E: device, 1 FP64 (FP64 reduction in a fixed order).
+ *  dEdq: device, N FP64 with dE/dz_j = P_l(x_j) - z_j g_j, or NULL. */
+rs_status rs_energy(const rs_tensor* T, double* E, double* dEdq, void* stream);
+
+/* Forces by the adjoint of the energy with the Tucker basis held fixed:
+ * F: device, N x 3 FP64, F_j = -scale * dE/dx_j = -scale z_j grad[P_l - z_j g_j](x_j). */
+rs_status rs_forces(const rs_tensor* T, double scale, double* F, void* stream);
+
+/* ---- introspection, persistence --------------------------------------- */
+
+/* Peak device memory rs_assemble needs for this request (with_grid != 0 adds
+ * nothing: the grid belongs to the caller).  r_max bounds the ranks. */
+size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
+                          int32_t r_max, int32_t prec, int32_t with_grid);
+rs_status rs_tensor_info(const rs_tensor* T, rs_info* info);
+
+/* Copy the Tucker factors to caller device memory: V_l as n x r_l row-major
+ * (any of V1, V2, V3 may be NULL) and beta as r1 x r2 x r3 C order (or NULL).
+ * Synchronizes `stream`. */
+rs_status rs_tensor_export(const rs_tensor* T, double* V1, double* V2, double* V3,
+                           double* beta, void* stream);
+
+/* Save the RS-Tucker parametrisation (table, split, ranks, V_l, beta,
+ * particles, charges) to a versioned binary file; load rebuilds the tensor
+ * on the context's device without recomputing the decomposition.  Both
+ * synchronize. */
+rs_status rs_tensor_save(const rs_tensor* T, const char* path);
+rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out);
+void rs_tensor_free(rs_tensor* T);
+
+const char* rs_status_str(rs_status s);
+const char* rs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_H */

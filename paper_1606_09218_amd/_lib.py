@@ -1,0 +1,266 @@
+"""ctypes binding of librs.so (include/rs.h).
+
+Argument marshalling only: every step of the RS path runs in the HIP library.
+Importing this module raises if the library has not been built; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librs.so")
+
+RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_RANK_CAP, RS_E_UNSUPPORTED = range(6)
+KERNELS = {"newton": 0, "yukawa": 1, "newton+yukawa": 2}
+PRECS = {"fp64": 0, "mixed_fp16": 1, "mixed_bf16": 2}
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_STATUS = {0: "RS_OK", 1: "RS_E_INVALID", 2: "RS_E_NOMEM", 3: "RS_E_DEVICE",
+           4: "RS_E_RANK_CAP", 5: "RS_E_UNSUPPORTED"}
+
+
+class rs_grid(C.Structure):
+    _fields_ = [("b", C.c_double), ("n", C.c_int64)]
+
+
+class rs_fdesc(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("lambda_", C.c_double), ("R", C.c_int32),
+                ("R_l", C.c_int32), ("n_s", C.c_int32), ("delta_rel", C.c_double),
+                ("sigma_split", C.c_double), ("C0", C.c_double)]
+
+
+class rs_aopts(C.Structure):
+    _fields_ = [("eps_tucker", C.c_double), ("r_max", C.c_int32),
+                ("fixed_ranks", C.c_int32 * 3), ("prec", C.c_int32),
+                ("oversample", C.c_int32), ("power_iters", C.c_int32),
+                ("interp_order", C.c_int32)]
+
+
+class rs_info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("n", C.c_int64), ("b", C.c_double), ("h", C.c_double),
+                ("R", C.c_int32), ("R_l", C.c_int32), ("n_s", C.c_int32), ("prec", C.c_int32),
+                ("interp_order", C.c_int32), ("ranks", C.c_int32 * 3),
+                ("subspace", C.c_int32 * 3), ("sigma_first", C.c_double * 3),
+                ("sigma_last_kept", C.c_double * 3), ("sigma_next", C.c_double * 3),
+                ("S0", C.c_double), ("S_l0", C.c_double), ("tucker_storage", C.c_int64),
+                ("device_bytes", C.c_int64), ("rank_capped", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1606_09218_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    D = C.POINTER(C.c_double)
+    sig = {
+        "rs_ctx_create": ([C.c_int, C.POINTER(P)], C.c_int),
+        "rs_ctx_destroy": ([P], None),
+        "rs_build_factors": ([P, C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.POINTER(P)], C.c_int),
+        "rs_factors_get": ([P, D, D, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int32)], C.c_int),
+        "rs_factors_free": ([P], None),
+        "rs_assemble": ([P, P, C.c_int64, P, P, C.POINTER(rs_aopts), P, C.POINTER(P), P], C.c_int),
+        "rs_weighted_gram": ([P, P, C.c_int64, P, P, P, P], C.c_int),
+        "rs_eval_points": ([P, C.c_int64, P, P, C.c_int32, P], C.c_int),
+        "rs_energy": ([P, P, P, P], C.c_int),
+        "rs_forces": ([P, C.c_double, P, P], C.c_int),
+        "rs_footprint_bytes": ([C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.c_int64, C.c_int32,
+                                C.c_int32, C.c_int32], C.c_size_t),
+        "rs_tensor_info": ([P, C.POINTER(rs_info)], C.c_int),
+        "rs_tensor_export": ([P, P, P, P, P, P], C.c_int),
+        "rs_tensor_save": ([P, C.c_char_p], C.c_int),
+        "rs_tensor_load": ([P, C.c_char_p, C.POINTER(P)], C.c_int),
+        "rs_tensor_free": ([P], None),
+        "rs_status_str": ([C.c_int], C.c_char_p),
+        "rs_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_build_factors", "rs_factors_get",
+            "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
+            "rs_forces", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
+            "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
+            "rs_last_error")
+
+
+def _check(status: int, allow_rank_cap: bool = False) -> int:
+    if status == RS_OK or (allow_rank_cap and status == RS_E_RANK_CAP):
+        return status
+    raise RSError(status, lib.rs_last_error().decode())
+
+
+# ---- marshalling helpers (torch is used for device memory and streams only) ----
+
+def _dev_ptr(t, dtype_name: str, numel: Optional[int] = None, what: str = "tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    want = {"f64": torch.float64, "f32": torch.float32}[dtype_name]
+    if t.dtype != want:
+        raise TypeError(f"{what} must have dtype {want}, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError(f"{what} must live in HIP device memory")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib.rs_ctx_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.rs_ctx_destroy(self.handle)
+            self.handle = None
+
+
+class Factors:
+    """Quadrature table and split for one grid (rs_build_factors)."""
+
+    def __init__(self, ctx: Context, b: float, n: int, R: int, R_l: int = -1, n_s: int = -1,
+                 kernel: str = "newton", lam: float = 0.5, delta_rel: float = 1e-4,
+                 sigma_split: float = 0.0, C0: float = 3.0):
+        self.ctx = ctx
+        self.grid = rs_grid(float(b), int(n))
+        self.fdesc = rs_fdesc(KERNELS[kernel], float(lam), int(R), int(R_l), int(n_s),
+                              float(delta_rel), float(sigma_split), float(C0))
+        h = C.c_void_p()
+        _check(lib.rs_build_factors(ctx.handle, C.byref(self.grid), C.byref(self.fdesc), C.byref(h)))
+        self.handle = h
+        t = (C.c_double * R)()
+        a = (C.c_double * R)()
+        Rv, Rl, ns = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib.rs_factors_get(h, t, a, C.byref(Rv), C.byref(Rl), C.byref(ns)))
+        self.t = list(t)
+        self.a = list(a)
+        self.R, self.R_l, self.n_s = Rv.value, Rl.value, ns.value
+        self.b, self.n = float(b), int(n)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.rs_factors_free(self.handle)
+            self.handle = None
+
+
+def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = None,
+               prec="fp64", oversample=0, power_iters=-1, interp_order=0) -> rs_aopts:
+    fr = (C.c_int32 * 3)(*(list(fixed_ranks) if fixed_ranks else [0, 0, 0]))
+    return rs_aopts(float(eps_tucker), int(r_max), fr, PRECS[prec], int(oversample),
+                    int(power_iters), int(interp_order))
+
+
+class Tensor:
+    """An RS-Tucker tensor handle (rs_tensor)."""
+
+    def __init__(self, handle, ctx: Context, status: int):
+        self.handle = handle
+        self.ctx = ctx
+        self.status = status
+
+    def info(self) -> rs_info:
+        inf = rs_info()
+        _check(lib.rs_tensor_info(self.handle, C.byref(inf)))
+        return inf
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib.rs_tensor_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.free()
+
+
+def assemble(ctx: Context, f: Factors, pos, q, grid=None, opts: Optional[rs_aopts] = None,
+             stream=None) -> Tensor:
+    N = int(q.numel())
+    p_pos = _dev_ptr(pos, "f64", 3 * N, "pos")
+    p_q = _dev_ptr(q, "f64", N, "q")
+    opts = opts or make_aopts()
+    p_grid = None
+    if grid is not None:
+        want = "f64" if opts.prec == 0 else "f32"
+        p_grid = _dev_ptr(grid, want, f.n ** 3, "grid")
+    h = C.c_void_p()
+    st = _check(lib.rs_assemble(ctx.handle, f.handle, N, p_pos, p_q, C.byref(opts), p_grid,
+                                C.byref(h), _stream_ptr(stream)), allow_rank_cap=True)
+    return Tensor(h, ctx, st)
+
+
+def weighted_gram(ctx: Context, f: Factors, pos, q, G, stream=None):
+    N = int(q.numel())
+    _check(lib.rs_weighted_gram(ctx.handle, f.handle, N, _dev_ptr(pos, "f64", 3 * N, "pos"),
+                                _dev_ptr(q, "f64", N, "q"), _dev_ptr(G, "f64", 3 * f.n * f.n, "G"),
+                                _stream_ptr(stream)))
+
+
+def eval_points(T: Tensor, pts, vals, part: int = 0, stream=None):
+    M = int(vals.numel())
+    _check(lib.rs_eval_points(T.handle, M, _dev_ptr(pts, "f64", 3 * M, "pts"),
+                              _dev_ptr(vals, "f64", M, "vals"), int(part), _stream_ptr(stream)))
+
+
+def energy(T: Tensor, E, dEdq=None, stream=None):
+    N = T.info().N
+    _check(lib.rs_energy(T.handle, _dev_ptr(E, "f64", 1, "E"),
+                         None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
+                         _stream_ptr(stream)))
+
+
+def forces(T: Tensor, F, scale: float = 1.0, stream=None):
+    N = T.info().N
+    _check(lib.rs_forces(T.handle, float(scale), _dev_ptr(F, "f64", 3 * N, "F"), _stream_ptr(stream)))
+
+
+def tensor_export(T: Tensor, V1=None, V2=None, V3=None, beta=None, stream=None):
+    inf = T.info()
+    n, r = inf.n, list(inf.ranks)
+    args = []
+    for V, rl, nm in ((V1, r[0], "V1"), (V2, r[1], "V2"), (V3, r[2], "V3")):
+        args.append(None if V is None else _dev_ptr(V, "f64", n * rl, nm))
+    b = None if beta is None else _dev_ptr(beta, "f64", r[0] * r[1] * r[2], "beta")
+    _check(lib.rs_tensor_export(T.handle, *args, b, _stream_ptr(stream)))
+
+
+def tensor_save(T: Tensor, path: str):
+    _check(lib.rs_tensor_save(T.handle, path.encode()))
+
+
+def tensor_load(ctx: Context, path: str) -> Tensor:
+    h = C.c_void_p()
+    _check(lib.rs_tensor_load(ctx.handle, path.encode(), C.byref(h)))
+    return Tensor(h, ctx, RS_OK)
+
+
+def footprint_bytes(f: Factors, N: int, r_max: int, prec: str = "fp64", with_grid: bool = True) -> int:
+    return int(lib.rs_footprint_bytes(C.byref(f.grid), C.byref(f.fdesc), int(N), int(r_max),
+                                      PRECS[prec], int(with_grid)))

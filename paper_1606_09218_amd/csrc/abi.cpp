@@ -1,0 +1,730 @@
+// The extern "C" entry points of the RS library: argument checks, device
+// memory, and the order of the kernel launches of one RS-Tucker assembly.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+
+#include "rs_internal.h"
+
+namespace rs {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+DevBuf::DevBuf(size_t nbytes, hipStream_t st) : bytes(nbytes), s(st) {
+  if (nbytes) RS_HIP(hipMallocAsync(&p, nbytes, st));
+}
+DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
+  if (this != &o) {
+    reset();
+    p = o.p;
+    bytes = o.bytes;
+    s = o.s;
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  return *this;
+}
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset() {
+  if (p) (void)hipFreeAsync(p, s);
+  p = nullptr;
+  bytes = 0;
+}
+
+template <class F>
+static rs_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return RS_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RS_E_DEVICE;
+  }
+}
+
+struct Plan {
+  int64_t N, n, K;
+  int R, R_l, n_s;
+  int r_max, p, power_iters, interp, prec;
+  int fixed[3];
+  double eps;
+};
+
+static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
+  Plan P;
+  P.N = N;
+  P.n = f->grid.n;
+  P.R = f->table.R;
+  P.R_l = f->table.R_l;
+  P.n_s = f->table.n_s;
+  P.K = N * P.R_l;
+  rs_aopts d{};
+  if (o) d = *o;
+  RS_REQUIRE(N >= 1, "N must be >= 1");
+  RS_REQUIRE(N <= (int64_t)1 << 26, "N too large");
+  RS_REQUIRE(d.eps_tucker >= 0 && d.eps_tucker < 1 && std::isfinite(d.eps_tucker),
+             "eps_tucker must be in [0, 1)");
+  P.eps = d.eps_tucker;
+  P.r_max = d.r_max > 0 ? d.r_max : (int)std::min<int64_t>(P.n, 256);
+  RS_REQUIRE(P.r_max <= P.n, "r_max must not exceed n");
+  int rcap = P.r_max;
+  bool all_fixed = true;
+  for (int l = 0; l < 3; ++l) {
+    P.fixed[l] = d.fixed_ranks[l];
+    RS_REQUIRE(P.fixed[l] >= 0 && P.fixed[l] <= P.n, "fixed rank outside [0, n]");
+    if (P.fixed[l] == 0) all_fixed = false;
+  }
+  if (all_fixed) rcap = std::max(P.fixed[0], std::max(P.fixed[1], P.fixed[2]));
+  else
+    for (int l = 0; l < 3; ++l) rcap = std::max(rcap, P.fixed[l]);
+  const int os = d.oversample > 0 ? d.oversample : 16;
+  int64_t p = std::min<int64_t>(P.n, (int64_t)rcap + os);
+  if (p % 2) ++p;
+  if (p > P.n) p = P.n;
+  P.p = (int)p;
+  P.power_iters = d.power_iters >= 0 ? d.power_iters : 1;
+  RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
+  P.interp = d.interp_order > 0 ? d.interp_order : 6;
+  RS_REQUIRE(P.interp % 2 == 0 && P.interp <= 8 && P.interp <= P.n, "interp_order must be even, <= 8");
+  P.prec = d.prec;
+  RS_REQUIRE(P.prec == RS_FP64 || P.prec == RS_MIXED_FP16 || P.prec == RS_MIXED_BF16,
+             "unknown precision");
+  RS_REQUIRE(P.R - P.R_l <= 64 && P.R_l <= 64, "at most 64 long and 64 short terms");
+  return P;
+}
+
+static int bricks_per_axis(int64_t n) { return (int)((n + 7) / 8); }
+
+// Gram matrices of the three modes into G (3 x n x n); U, xi, w computed into
+// caller-provided buffers.
+static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
+                                 const double* pos, const double* q, double* U, double* xi,
+                                 double* w, double* G, hipStream_t s) {
+  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, s);
+  Gemm64 g;
+  g.M = P.n;
+  g.N = P.n;
+  g.K = P.K;
+  g.batch = 3;
+  g.A = U; g.sam = 1; g.sak = P.n; g.sab = P.n * P.K;
+  g.B = U; g.sbk = P.n; g.sbn = 1; g.sbb = P.n * P.K;
+  g.C = G; g.scm = P.n; g.scn = 1; g.scb = P.n * P.n;
+  g.kscale = w;
+  g.upper_only = 1;
+  DevBuf work(gemm64_workspace_bytes(g, ctx->num_cu), s);
+  gemm64(g, ctx->num_cu, work.as<double>(), s);
+}
+
+// Expand T2 = beta x_1 V1 x_2 V2 and, when grid != null, the full grid
+// (T2 x_3 V3) plus the short-range windows.
+static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
+  const int64_t n = T->n;
+  const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
+  const int ncu = T->ctx->num_cu;
+  // W1 (n x r2 r3) = V1 beta_(1)
+  DevBuf W1((size_t)n * r2 * r3 * sizeof(double), s);
+  {
+    Gemm64 g;
+    g.M = n; g.N = (int64_t)r2 * r3; g.K = r1;
+    g.A = T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
+    g.B = T->beta.as<double>(); g.sbk = (int64_t)r2 * r3; g.sbn = 1;
+    g.C = W1.as<double>(); g.scm = (int64_t)r2 * r3; g.scn = 1;
+    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+    gemm64(g, ncu, wk.as<double>(), s);
+  }
+  T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
+  {
+    Gemm64 g;  // T2[i1] (n x r3) = V2 (n x r2) W1[i1] (r2 x r3), batched over i1
+    g.M = n; g.N = r3; g.K = r2; g.batch = (int)n;
+    g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1; g.sab = 0;
+    g.B = W1.as<double>(); g.sbk = r3; g.sbn = 1; g.sbb = (int64_t)r2 * r3;
+    g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.scb = n * r3;
+    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+    gemm64(g, ncu, wk.as<double>(), s);
+  }
+  if (grid) {
+    if (T->prec != RS_FP64) throw Error{RS_E_UNSUPPORTED, "mixed-precision grid not built here"};
+    Gemm64 g;  // grid[(i1,i2), i3] = sum_c T2[(i1,i2), c] V3[i3, c]
+    g.M = n * n; g.N = n; g.K = r3;
+    g.A = T->T2.as<double>(); g.sam = r3; g.sak = 1;
+    g.B = T->Q[2].as<double>(); g.sbk = 1; g.sbn = r3;
+    g.C = (double*)grid; g.scm = n; g.scn = 1;
+    g.nontemporal = 1;
+    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+    gemm64(g, ncu, wk.as<double>(), s);
+    short_gather(grid, 0, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
+                 T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
+                 T->brick_start.as<int>(), T->brick_list.as<int>(), s);
+  }
+}
+
+struct Readback {
+  int flags;
+  int pad;
+  RankInfo info;
+  int total_pairs;
+};
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+const char* rs_status_str(rs_status s) {
+  switch (s) {
+    case RS_OK: return "RS_OK";
+    case RS_E_INVALID: return "RS_E_INVALID";
+    case RS_E_NOMEM: return "RS_E_NOMEM";
+    case RS_E_DEVICE: return "RS_E_DEVICE";
+    case RS_E_RANK_CAP: return "RS_E_RANK_CAP";
+    case RS_E_UNSUPPORTED: return "RS_E_UNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+const char* rs_last_error(void) { return rs::last_error(); }
+
+rs_status rs_ctx_create(int device, rs_ctx** out) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(out != nullptr, "out is null");
+    int count = 0;
+    RS_HIP(hipGetDeviceCount(&count));
+    RS_REQUIRE(device >= 0 && device < count, "no such HIP device");
+    RS_HIP(hipSetDevice(device));
+    auto c = std::make_unique<rs_ctx>();
+    c->device = device;
+    hipDeviceProp_t prop;
+    RS_HIP(hipGetDeviceProperties(&prop, device));
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    RS_HIP(hipDeviceGetDefaultMemPool(&c->pool, device));
+    uint64_t thr = UINT64_MAX;  // keep freed blocks cached for reuse
+    RS_HIP(hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &thr));
+    *out = c.release();
+    return RS_OK;
+  });
+}
+
+void rs_ctx_destroy(rs_ctx* ctx) { delete ctx; }
+
+rs_status rs_build_factors(rs_ctx* ctx, const rs_grid* grid, const rs_fdesc* fdesc,
+                           rs_factors** out) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx && grid && fdesc && out, "null argument");
+    RS_HIP(hipSetDevice(ctx->device));
+    auto f = std::make_unique<rs_factors>();
+    f->grid = *grid;
+    f->fdesc = *fdesc;
+    f->table = build_table(*grid, *fdesc);
+    f->device = ctx->device;
+    const size_t bytes = f->table.R * sizeof(double);
+    RS_HIP(hipMalloc(&f->t_dev, bytes));
+    RS_HIP(hipMalloc(&f->a_dev, bytes));
+    RS_HIP(hipMemcpy(f->t_dev, f->table.t.data(), bytes, hipMemcpyHostToDevice));
+    RS_HIP(hipMemcpy(f->a_dev, f->table.a.data(), bytes, hipMemcpyHostToDevice));
+    *out = f.release();
+    return RS_OK;
+  });
+}
+
+rs_status rs_factors_get(const rs_factors* f, double* t, double* a, int32_t* R, int32_t* R_l,
+                         int32_t* n_s) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(f != nullptr, "null factors");
+    if (t) std::memcpy(t, f->table.t.data(), f->table.R * sizeof(double));
+    if (a) std::memcpy(a, f->table.a.data(), f->table.R * sizeof(double));
+    if (R) *R = f->table.R;
+    if (R_l) *R_l = f->table.R_l;
+    if (n_s) *n_s = f->table.n_s;
+    return RS_OK;
+  });
+}
+
+void rs_factors_free(rs_factors* f) {
+  if (!f) return;
+  (void)hipFree(f->t_dev);
+  (void)hipFree(f->a_dev);
+  delete f;
+}
+
+rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
+                           const double* q, double* G, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx && f && pos && q && G, "null argument");
+    RS_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Plan P = make_plan(f, N, nullptr);
+    DevBuf U((size_t)3 * P.n * P.K * sizeof(double), s);
+    DevBuf xi((size_t)P.K * sizeof(double), s), w((size_t)P.K * sizeof(double), s);
+    run_factors_and_gram(ctx, f, P, pos, q, U.as<double>(), xi.as<double>(), w.as<double>(), G, s);
+    return RS_OK;
+  });
+}
+
+rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
+                      const double* q, const rs_aopts* opts, void* grid_out, rs_tensor** out,
+                      void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx && f && pos && q && out, "null argument");
+    RS_REQUIRE(f->device == ctx->device, "factors built for another device");
+    RS_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const Plan P = make_plan(f, N, opts);
+    if (P.prec != RS_FP64) throw Error{RS_E_UNSUPPORTED, "mixed precision not available yet"};
+    const int64_t n = P.n, K = P.K;
+    const int p = P.p;
+    const int ncu = ctx->num_cu;
+
+    auto T = std::make_unique<rs_tensor>();
+    T->ctx = ctx;
+    T->N = N;
+    T->n = n;
+    T->b = f->grid.b;
+    T->h = 2.0 * f->grid.b / (double)n;
+    T->R = P.R;
+    T->R_l = P.R_l;
+    T->n_s = P.n_s;
+    T->kernel = f->fdesc.kernel;
+    T->lambda = f->fdesc.lambda;
+    T->prec = P.prec;
+    T->interp = P.interp;
+    T->table = f->table;
+    T->stream = s;
+    for (int l = 0; l < 3; ++l) T->p[l] = p;
+
+    T->pos = DevBuf((size_t)N * 3 * sizeof(double), s);
+    T->q = DevBuf((size_t)N * sizeof(double), s);
+    T->t_dev = DevBuf((size_t)P.R * sizeof(double), s);
+    T->a_dev = DevBuf((size_t)P.R * sizeof(double), s);
+    RS_HIP(hipMemcpyAsync(T->pos.p, pos, T->pos.bytes, hipMemcpyDeviceToDevice, s));
+    RS_HIP(hipMemcpyAsync(T->q.p, q, T->q.bytes, hipMemcpyDeviceToDevice, s));
+    RS_HIP(hipMemcpyAsync(T->t_dev.p, f->t_dev, T->t_dev.bytes, hipMemcpyDeviceToDevice, s));
+    RS_HIP(hipMemcpyAsync(T->a_dev.p, f->a_dev, T->a_dev.bytes, hipMemcpyDeviceToDevice, s));
+    const double* dpos = T->pos.as<double>();
+    const double* dq = T->q.as<double>();
+
+    DevBuf rb(sizeof(Readback), s);
+    RS_HIP(hipMemsetAsync(rb.p, 0, sizeof(Readback), s));
+    Readback* rbd = rb.as<Readback>();
+    launch_validate(dpos, dq, N, f->grid.b, &rbd->flags, s);
+
+    // (a2, a3) side matrices and charge-weighted Gram matrices
+    DevBuf U((size_t)3 * n * K * sizeof(double), s);
+    DevBuf xi((size_t)K * sizeof(double), s), w((size_t)K * sizeof(double), s);
+    DevBuf G((size_t)3 * n * n * sizeof(double), s);
+    run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
+                         G.as<double>(), s);
+
+    // (a4) dominant eigenvectors: Q0 (n x p per mode, col-major) spans the subspace
+    DevBuf Q0((size_t)3 * n * p * sizeof(double), s);
+    DevBuf Bm((size_t)3 * p * p * sizeof(double), s);
+    if (p == n) {
+      launch_identity(Q0.as<double>(), n, 3, s);
+      RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
+    } else {
+      DevBuf Om((size_t)3 * n * p * sizeof(double), s);
+      DevBuf Y((size_t)3 * n * p * sizeof(double), s);
+      launch_fill_omega(Om.as<double>(), n, p, 3, 0x5eed1234ULL, s);
+      auto GtimesX = [&](const double* X, double* Yout) {
+        Gemm64 g;
+        g.M = n; g.N = p; g.K = n; g.batch = 3;
+        g.A = G.as<double>(); g.sam = 1; g.sak = n; g.sab = n * n;
+        g.B = X; g.sbk = 1; g.sbn = n; g.sbb = n * p;
+        g.C = Yout; g.scm = 1; g.scn = n; g.scb = n * p;
+        DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+        gemm64(g, ncu, wk.as<double>(), s);
+      };
+      GtimesX(Om.as<double>(), Y.as<double>());
+      launch_cgs2(Y.as<double>(), Q0.as<double>(), n, p, 3, 0xabcdef01ULL, s);
+      for (int it = 0; it < P.power_iters; ++it) {
+        GtimesX(Q0.as<double>(), Y.as<double>());
+        launch_cgs2(Y.as<double>(), Q0.as<double>(), n, p, 3, 0xabcdef01ULL + it + 1, s);
+      }
+      GtimesX(Q0.as<double>(), Y.as<double>());  // Y = G Q0
+      Gemm64 g;                                  // B = Q0^T Y
+      g.M = p; g.N = p; g.K = n; g.batch = 3;
+      g.A = Q0.as<double>(); g.sam = n; g.sak = 1; g.sab = n * p;
+      g.B = Y.as<double>(); g.sbk = 1; g.sbn = n; g.sbb = n * p;
+      g.C = Bm.as<double>(); g.scm = 1; g.scn = p; g.scb = (int64_t)p * p;
+      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+      gemm64(g, ncu, wk.as<double>(), s);
+      launch_symmetrize(Bm.as<double>(), p, 3, s);
+    }
+    DevBuf V((size_t)3 * p * p * sizeof(double), s);
+    launch_jacobi(Bm.as<double>(), V.as<double>(), p, 3, 40, s);
+    DevBuf perm((size_t)3 * p * sizeof(int), s);
+    DevBuf fixed_dev(3 * sizeof(int), s);
+    RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_rank_select(Bm.as<double>(), p, 3, P.eps * P.eps, fixed_dev.as<int>(), P.r_max,
+                       perm.as<int>(), &rbd->info, s);
+
+    // short-range binning (counts and offsets; the total is read back with the ranks)
+    T->nb = bricks_per_axis(n);
+    const int nbricks = T->nb * T->nb * T->nb;
+    DevBuf counts((size_t)(nbricks + 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_count(dpos, N, n, f->grid.b, P.n_s, T->nb, counts.as<int>(), s);
+    T->brick_start = DevBuf((size_t)(nbricks + 1) * sizeof(int), s);
+    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1, s);
+    RS_HIP(hipMemcpyAsync(&rbd->total_pairs, T->brick_start.as<int>() + nbricks, sizeof(int),
+                          hipMemcpyDeviceToDevice, s));
+
+    Readback host;
+    RS_HIP(hipMemcpyAsync(&host, rbd, sizeof(Readback), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    if (host.flags & 1) throw Error{RS_E_INVALID, "non-finite particle position or charge"};
+    if (host.flags & 2) throw Error{RS_E_INVALID, "particle outside the box [-b, b]^3"};
+
+    for (int l = 0; l < 3; ++l) {
+      T->r[l] = host.info.r[l];
+      T->rank_capped |= host.info.capped[l];
+      const double l1 = host.info.lam1[l];
+      T->sigma1[l] = std::sqrt(std::max(l1, 0.0));
+      T->sig_kept[l] = l1 > 0 ? std::sqrt(std::max(host.info.lam_kept[l], 0.0) / l1) : 0.0;
+      T->sig_next[l] = l1 > 0 ? std::sqrt(std::max(host.info.lam_next[l], 0.0) / l1) : 0.0;
+    }
+
+    // final bases V_l = Q0 W[:, perm[:r]] (n x r row-major), canonical signs
+    for (int l = 0; l < 3; ++l) {
+      const int r = T->r[l];
+      DevBuf Wr((size_t)p * r * sizeof(double), s);
+      launch_gather_cols(V.as<double>() + (int64_t)l * p * p, perm.as<int>() + l * p, p, r,
+                         Wr.as<double>(), s);
+      T->Q[l] = DevBuf((size_t)n * r * sizeof(double), s);
+      Gemm64 g;
+      g.M = n; g.N = r; g.K = p;
+      g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = 1; g.sak = n;
+      g.B = Wr.as<double>(); g.sbk = 1; g.sbn = p;
+      g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
+      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+      gemm64(g, ncu, wk.as<double>(), s);
+      launch_canonical_signs(T->Q[l].as<double>(), n, r, s);
+    }
+    G.reset();
+    Bm.reset();
+    Q0.reset();
+    V.reset();
+
+    // (a5) projection U~_l = V_l^T U_l (stored column j contiguous: U~[j*r + a]) and core
+    DevBuf Ut[3];
+    for (int l = 0; l < 3; ++l) {
+      const int r = T->r[l];
+      Ut[l] = DevBuf((size_t)K * r * sizeof(double), s);
+      Gemm64 g;
+      g.M = r; g.N = K; g.K = n;
+      g.A = T->Q[l].as<double>(); g.sam = 1; g.sak = r;
+      g.B = U.as<double>() + (int64_t)l * n * K; g.sbk = 1; g.sbn = n;
+      g.C = Ut[l].as<double>(); g.scm = 1; g.scn = r;
+      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+      gemm64(g, ncu, wk.as<double>(), s);
+    }
+    U.reset();
+    const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
+    T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
+    {
+      DevBuf wk(core64_workspace_bytes(r1, r2, r3, K, ncu), s);
+      core64(Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(), r1, r2,
+             r3, K, T->beta.as<double>(), ncu, wk.as<double>(), s);
+    }
+    for (int l = 0; l < 3; ++l) Ut[l].reset();
+
+    // (a6) short-range lists: fill and sort by particle index
+    T->n_pairs = host.total_pairs;
+    T->brick_list = DevBuf((size_t)std::max<int64_t>(T->n_pairs, 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_fill(dpos, N, n, f->grid.b, P.n_s, T->nb, T->brick_start.as<int>(), counts.as<int>(),
+                   T->brick_list.as<int>(), s);
+    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
+
+    // (a7) T2 and the grid
+    build_expansion(T.get(), grid_out, s);
+
+    *out = T.release();
+    return (*out)->rank_capped ? RS_E_RANK_CAP : RS_OK;
+  });
+}
+
+rs_status rs_eval_points(const rs_tensor* T, int64_t M, const double* pts, double* vals,
+                         int32_t part, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && pts && vals, "null argument");
+    RS_REQUIRE(M >= 0, "M must be >= 0");
+    RS_REQUIRE(part >= 0 && part <= 2, "part must be 0, 1 or 2");
+    if (M == 0) return RS_OK;
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (part == 0 || part == 1) {
+      EvalOut o;
+      o.val = vals;
+      launch_eval_long(T, M, pts, 0, o, s);
+    }
+    if (part == 0 || part == 2) launch_eval_short(T, M, pts, vals, part == 0 ? 1 : 0, s);
+    return RS_OK;
+  });
+}
+
+rs_status rs_energy(const rs_tensor* T, double* E, double* dEdq, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && E, "null argument");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf v((size_t)T->N * sizeof(double), s), g((size_t)T->N * sizeof(double), s);
+    EvalOut o;
+    o.val = v.as<double>();
+    o.selfv = g.as<double>();
+    launch_eval_long(T, T->N, T->pos.as<double>(), 1, o, s);
+    launch_energy_reduce(T->q.as<double>(), v.as<double>(), g.as<double>(), T->N, E, dEdq, s);
+    return RS_OK;
+  });
+}
+
+rs_status rs_forces(const rs_tensor* T, double scale, double* F, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && F, "null argument");
+    RS_REQUIRE(std::isfinite(scale), "scale must be finite");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf v((size_t)T->N * sizeof(double), s), gv((size_t)T->N * 3 * sizeof(double), s);
+    DevBuf sv((size_t)T->N * sizeof(double), s), sg((size_t)T->N * 3 * sizeof(double), s);
+    EvalOut o;
+    o.val = v.as<double>();
+    o.grad = gv.as<double>();
+    o.selfv = sv.as<double>();
+    o.selfg = sg.as<double>();
+    launch_eval_long(T, T->N, T->pos.as<double>(), 1, o, s);
+    launch_forces(T->q.as<double>(), gv.as<double>(), sg.as<double>(), T->N, scale, F, s);
+    return RS_OK;
+  });
+}
+
+size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N, int32_t r_max,
+                          int32_t prec, int32_t with_grid) {
+  (void)with_grid;
+  if (!grid || !fdesc || N < 1) return 0;
+  Table t;
+  try {
+    t = build_table(*grid, *fdesc);
+  } catch (...) {
+    return 0;
+  }
+  const int64_t n = grid->n, K = N * t.R_l;
+  const int64_t r = r_max > 0 ? std::min<int64_t>(r_max, n) : std::min<int64_t>(n, 256);
+  const int64_t p = std::min<int64_t>(n, r + 16);
+  const size_t d = sizeof(double);
+  // stage peaks: factors + Gram (+ split partials), eigensolver, projection + core, expansion
+  size_t factors = (3 * n * K + 2 * K) * d;
+  size_t gram = 3 * n * n * d * 3;
+  size_t eig = (3 * n * p * 3 + 3 * p * p * 2) * d;
+  size_t proj = 3 * K * r * d + 3 * n * r * d;
+  size_t core = r * r * r * d * (K > 0 ? 4 : 1);
+  size_t expand = (n * r * r + n * n * r) * d;
+  size_t bins = ((n / 8 + 1) * (n / 8 + 1) * (n / 8 + 1) * 2 + 64 * N) * sizeof(int);
+  size_t peak = std::max({factors + gram, factors + gram + eig, factors + proj + core,
+                          r * r * r * d + expand});
+  size_t mixed_extra = prec != RS_FP64 ? (size_t)(3 * K * r) * 2 * 3 : 0;
+  return peak + bins + mixed_extra + (size_t)N * 4 * d;
+}
+
+rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && info, "null argument");
+    rs_info I{};
+    I.N = T->N;
+    I.n = T->n;
+    I.b = T->b;
+    I.h = T->h;
+    I.R = T->R;
+    I.R_l = T->R_l;
+    I.n_s = T->n_s;
+    I.prec = T->prec;
+    I.interp_order = T->interp;
+    for (int l = 0; l < 3; ++l) {
+      I.ranks[l] = T->r[l];
+      I.subspace[l] = T->p[l];
+      I.sigma_first[l] = T->sigma1[l];
+      I.sigma_last_kept[l] = T->sig_kept[l];
+      I.sigma_next[l] = T->sig_next[l];
+    }
+    I.S0 = T->table.S0;
+    I.S_l0 = T->table.S_l0;
+    I.tucker_storage = (int64_t)T->r[0] * T->r[1] * T->r[2] + T->n * (T->r[0] + T->r[1] + T->r[2]);
+    size_t bytes = T->pos.bytes + T->q.bytes + T->t_dev.bytes + T->a_dev.bytes + T->beta.bytes +
+                   T->T2.bytes + T->brick_start.bytes + T->brick_list.bytes;
+    for (int l = 0; l < 3; ++l) bytes += T->Q[l].bytes;
+    I.device_bytes = (int64_t)bytes;
+    I.rank_capped = T->rank_capped;
+    *info = I;
+    return RS_OK;
+  });
+}
+
+rs_status rs_tensor_export(const rs_tensor* T, double* V1, double* V2, double* V3, double* beta,
+                           void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T, "null tensor");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    double* Vs[3] = {V1, V2, V3};
+    for (int l = 0; l < 3; ++l)
+      if (Vs[l]) RS_HIP(hipMemcpyAsync(Vs[l], T->Q[l].p, T->Q[l].bytes, hipMemcpyDeviceToDevice, s));
+    if (beta) RS_HIP(hipMemcpyAsync(beta, T->beta.p, T->beta.bytes, hipMemcpyDeviceToDevice, s));
+    RS_HIP(hipStreamSynchronize(s));
+    return RS_OK;
+  });
+}
+
+static const char kMagic[8] = {'R', 'S', 'T', 'U', 'C', 'K', '0', '1'};
+
+rs_status rs_tensor_save(const rs_tensor* T, const char* path) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && path, "null argument");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    RS_HIP(hipStreamSynchronize(T->stream));
+    std::ofstream os(path, std::ios::binary);
+    RS_REQUIRE(os.good(), std::string("cannot open ") + path);
+    auto put = [&](const void* p, size_t nb) { os.write((const char*)p, (std::streamsize)nb); };
+    auto put_dev = [&](const DevBuf& b) {
+      std::vector<char> h(b.bytes);
+      if (b.bytes) RS_HIP(hipMemcpy(h.data(), b.p, b.bytes, hipMemcpyDeviceToHost));
+      uint64_t nb = b.bytes;
+      put(&nb, 8);
+      put(h.data(), b.bytes);
+    };
+    put(kMagic, 8);
+    int32_t ints[10] = {T->R, T->R_l, T->n_s, T->kernel, T->prec, T->interp,
+                        T->r[0], T->r[1], T->r[2], 0};
+    put(ints, sizeof(ints));
+    int64_t sizes[2] = {T->N, T->n};
+    put(sizes, sizeof(sizes));
+    double dbl[2] = {T->b, T->lambda};
+    put(dbl, sizeof(dbl));
+    put(T->table.t.data(), T->R * sizeof(double));
+    put(T->table.a.data(), T->R * sizeof(double));
+    double sig[9];
+    for (int l = 0; l < 3; ++l) {
+      sig[l] = T->sigma1[l];
+      sig[3 + l] = T->sig_kept[l];
+      sig[6 + l] = T->sig_next[l];
+    }
+    put(sig, sizeof(sig));
+    put_dev(T->pos);
+    put_dev(T->q);
+    for (int l = 0; l < 3; ++l) put_dev(T->Q[l]);
+    put_dev(T->beta);
+    RS_REQUIRE(os.good(), "write failed");
+    return RS_OK;
+  });
+}
+
+rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx && path && out, "null argument");
+    RS_HIP(hipSetDevice(ctx->device));
+    std::ifstream is(path, std::ios::binary);
+    RS_REQUIRE(is.good(), std::string("cannot open ") + path);
+    auto get = [&](void* p, size_t nb) {
+      is.read((char*)p, (std::streamsize)nb);
+      RS_REQUIRE(is.good(), "truncated tensor file");
+    };
+    char magic[8];
+    get(magic, 8);
+    RS_REQUIRE(std::memcmp(magic, kMagic, 8) == 0, "not an RS tensor file (bad magic/version)");
+    auto T = std::make_unique<rs_tensor>();
+    T->ctx = ctx;
+    hipStream_t s = nullptr;
+    T->stream = s;
+    int32_t ints[10];
+    get(ints, sizeof(ints));
+    T->R = ints[0]; T->R_l = ints[1]; T->n_s = ints[2]; T->kernel = ints[3]; T->prec = ints[4];
+    T->interp = ints[5];
+    for (int l = 0; l < 3; ++l) T->r[l] = ints[6 + l];
+    int64_t sizes[2];
+    get(sizes, sizeof(sizes));
+    T->N = sizes[0];
+    T->n = sizes[1];
+    double dbl[2];
+    get(dbl, sizeof(dbl));
+    T->b = dbl[0];
+    T->lambda = dbl[1];
+    T->h = 2.0 * T->b / (double)T->n;
+    RS_REQUIRE(T->R >= 3 && T->R <= 256 && T->N >= 1 && T->n >= 8, "corrupt tensor header");
+    T->table.R = T->R;
+    T->table.R_l = T->R_l;
+    T->table.n_s = T->n_s;
+    T->table.t.resize(T->R);
+    T->table.a.resize(T->R);
+    get(T->table.t.data(), T->R * sizeof(double));
+    get(T->table.a.data(), T->R * sizeof(double));
+    T->table.S0 = 0;
+    T->table.S_l0 = 0;
+    for (int k = 0; k < T->R; ++k) {
+      T->table.S0 += T->table.a[k];
+      if (k < T->R_l) T->table.S_l0 += T->table.a[k];
+    }
+    double sig[9];
+    get(sig, sizeof(sig));
+    for (int l = 0; l < 3; ++l) {
+      T->sigma1[l] = sig[l];
+      T->sig_kept[l] = sig[3 + l];
+      T->sig_next[l] = sig[6 + l];
+    }
+    auto get_dev = [&](DevBuf& b, size_t expect) {
+      uint64_t nb;
+      get(&nb, 8);
+      RS_REQUIRE(nb == expect, "corrupt tensor file (buffer size)");
+      std::vector<char> h(nb);
+      get(h.data(), nb);
+      b = DevBuf(nb, s);
+      RS_HIP(hipMemcpyAsync(b.p, h.data(), nb, hipMemcpyHostToDevice, s));
+      RS_HIP(hipStreamSynchronize(s));
+    };
+    get_dev(T->pos, (size_t)T->N * 3 * sizeof(double));
+    get_dev(T->q, (size_t)T->N * sizeof(double));
+    for (int l = 0; l < 3; ++l) get_dev(T->Q[l], (size_t)T->n * T->r[l] * sizeof(double));
+    get_dev(T->beta, (size_t)T->r[0] * T->r[1] * T->r[2] * sizeof(double));
+    T->t_dev = DevBuf((size_t)T->R * sizeof(double), s);
+    T->a_dev = DevBuf((size_t)T->R * sizeof(double), s);
+    RS_HIP(hipMemcpyAsync(T->t_dev.p, T->table.t.data(), T->t_dev.bytes, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(T->a_dev.p, T->table.a.data(), T->a_dev.bytes, hipMemcpyHostToDevice, s));
+    // rebuild the short-range lists and the expansion intermediate
+    T->nb = bricks_per_axis(T->n);
+    const int nbricks = T->nb * T->nb * T->nb;
+    DevBuf counts((size_t)(nbricks + 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_count(T->pos.as<double>(), T->N, T->n, T->b, T->n_s, T->nb, counts.as<int>(), s);
+    T->brick_start = DevBuf((size_t)(nbricks + 1) * sizeof(int), s);
+    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1, s);
+    int total = 0;
+    RS_HIP(hipMemcpyAsync(&total, T->brick_start.as<int>() + nbricks, sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    T->n_pairs = total;
+    T->brick_list = DevBuf((size_t)std::max(total, 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_fill(T->pos.as<double>(), T->N, T->n, T->b, T->n_s, T->nb, T->brick_start.as<int>(),
+                   counts.as<int>(), T->brick_list.as<int>(), s);
+    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
+    build_expansion(T.get(), nullptr, s);
+    RS_HIP(hipStreamSynchronize(s));
+    *out = T.release();
+    return RS_OK;
+  });
+}
+
+void rs_tensor_free(rs_tensor* T) {
+  if (!T) return;
+  (void)hipSetDevice(T->ctx->device);
+  delete T;  // buffers are released in stream order on the assembly stream
+}
+
+}  // extern "C"

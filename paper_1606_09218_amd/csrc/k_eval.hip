@@ -1,0 +1,279 @@
+// Point evaluation of the RS-Tucker tensor, interaction energy and forces.
+//
+// Long-range part at a point y: order-p tensor Lagrange interpolation of the
+// Tucker field on the cell-centred grid.  With T2 = beta x_1 V1 x_2 V2
+// (n x n x r3, kept by the tensor) and q3(y) = sum_m L_m(y_3) V3[s3 + m, :],
+//   P_l(y) = sum_{m1, m2} L_{m1}(y_1) L_{m2}(y_2) < T2[s1+m1, s2+m2, :], q3(y) >,
+// which equals beta x_1 q1(y) x_2 q2(y) x_3 q3(y) (Lemma Property_RST_Tuck at
+// grid points, interpolated between them) at p^2 r3 instead of r^3 work.
+// The gradient uses the derivative weights in one mode at a time.
+//
+// Energy (Lemma InterEnergy, eq EnergyFree_Tensor):
+//   E = 1/2 sum_j z_j (P_l(x_j) - z_j g_j),
+// g_j = particle j's own long-range reference term through the same
+// interpolation operator (P_{R_l}(0) exactly when x_j is a grid point).
+// Forces: F_j = -z_j grad[P_l - z_j g_j](x_j) (section 4.4, basis held fixed).
+#include "rs_internal.h"
+
+namespace rs {
+
+constexpr int PMAX = 8;        // largest interpolation order
+constexpr int CPL = 16;        // r3 <= 64 * CPL
+
+struct EvalDev {
+  const double* T2;    // n x n x r3
+  const double* V3;    // n x r3 row-major
+  const double* t;     // R
+  const double* a;     // R
+  int64_t n;
+  double b;
+  int r3, R_l, p;
+};
+
+__device__ __forceinline__ void stencil(double y, double b, int64_t n, int p, int& start,
+                                        double* L, double* dL) {
+  const double h = 2.0 * b / (double)n;
+  const double u = (y + b) / h - 0.5;
+  int m = (int)floor(u);
+  int s = m - p / 2 + 1;
+  if (s < 0) s = 0;
+  if (s > (int)n - p) s = (int)n - p;
+  start = s;
+  for (int i = 0; i < p; ++i) {
+    double num = 1.0, den = 1.0;
+    for (int j = 0; j < p; ++j)
+      if (j != i) {
+        num *= (u - (double)(s + j));
+        den *= (double)(i - j);
+      }
+    L[i] = num / den;
+    double d = 0.0;
+    for (int mm = 0; mm < p; ++mm) {
+      if (mm == i) continue;
+      double prod = 1.0;
+      for (int j = 0; j < p; ++j)
+        if (j != i && j != mm) prod *= (u - (double)(s + j));
+      d += prod;
+    }
+    dL[i] = d / den / h;
+  }
+}
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// One wave per point.
+__global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
+                                                        const double* __restrict__ pts,
+                                                        int with_self, double* __restrict__ val,
+                                                        double* __restrict__ grad,
+                                                        double* __restrict__ selfv,
+                                                        double* __restrict__ selfg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pt = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (pt >= M) return;
+  const int p = e.p;
+  double y[3];
+  int s[3];
+  double L[3][PMAX], dL[3][PMAX];
+  for (int l = 0; l < 3; ++l) {
+    y[l] = pts[3 * pt + l];
+    stencil(y[l], e.b, e.n, p, s[l], L[l], dL[l]);
+  }
+  const int r3 = e.r3;
+  double q3[CPL], dq3[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int c = lane + 64 * u;
+    double qa = 0.0, qd = 0.0;
+    if (c < r3) {
+      for (int m = 0; m < p; ++m) {
+        const double v = e.V3[(int64_t)(s[2] + m) * r3 + c];
+        qa += L[2][m] * v;
+        qd += dL[2][m] * v;
+      }
+    }
+    q3[u] = qa;
+    dq3[u] = qd;
+  }
+  double v = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+  for (int m1 = 0; m1 < p; ++m1) {
+    for (int m2 = 0; m2 < p; ++m2) {
+      const double* row = e.T2 + ((int64_t)(s[0] + m1) * e.n + (s[1] + m2)) * r3;
+      double d = 0.0, dd = 0.0;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const int c = lane + 64 * u;
+        if (c < r3) {
+          const double tv = row[c];
+          d += tv * q3[u];
+          dd += tv * dq3[u];
+        }
+      }
+      const double w12 = L[0][m1] * L[1][m2];
+      v += w12 * d;
+      g1 += dL[0][m1] * L[1][m2] * d;
+      g2 += L[0][m1] * dL[1][m2] * d;
+      g3 += w12 * dd;
+    }
+  }
+  v = wsum(v);
+  if (grad) {
+    g1 = wsum(g1);
+    g2 = wsum(g2);
+    g3 = wsum(g3);
+  }
+  double sv = 0.0, sg[3] = {0.0, 0.0, 0.0};
+  if (with_self) {
+    // lanes over the long-range terms k < R_l (R_l <= 64)
+    const double h = 2.0 * e.b / (double)e.n;
+    double phi[3] = {0, 0, 0}, dphi[3] = {0, 0, 0};
+    if (lane < e.R_l) {
+      const double tk = e.t[lane];
+      for (int l = 0; l < 3; ++l) {
+        for (int m = 0; m < p; ++m) {
+          const double x = -e.b + ((double)(s[l] + m) + 0.5) * h;
+          const double d = x - y[l];
+          const double g = exp(-(tk * tk) * (d * d));
+          phi[l] += L[l][m] * g;
+          dphi[l] += dL[l][m] * g;
+        }
+      }
+      const double ak = e.a[lane];
+      sv = ak * phi[0] * phi[1] * phi[2];
+      sg[0] = ak * dphi[0] * phi[1] * phi[2];
+      sg[1] = ak * phi[0] * dphi[1] * phi[2];
+      sg[2] = ak * phi[0] * phi[1] * dphi[2];
+    }
+    sv = wsum(sv);
+    for (int l = 0; l < 3; ++l) sg[l] = wsum(sg[l]);
+  }
+  if (lane == 0) {
+    val[pt] = v;
+    if (grad) {
+      grad[3 * pt + 0] = g1;
+      grad[3 * pt + 1] = g2;
+      grad[3 * pt + 2] = g3;
+    }
+    if (with_self && selfv) selfv[pt] = sv;
+    if (with_self && selfg)
+      for (int l = 0; l < 3; ++l) selfg[3 * pt + l] = sg[l];
+  }
+}
+
+void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with_self,
+                      const EvalOut& out, hipStream_t s) {
+  if (T->r[2] > 64 * CPL) throw Error{RS_E_UNSUPPORTED, "rank r3 above 1024"};
+  if (T->interp > PMAX) throw Error{RS_E_UNSUPPORTED, "interpolation order above 8"};
+  if (with_self && T->R_l > 64) throw Error{RS_E_UNSUPPORTED, "more than 64 long-range terms"};
+  EvalDev e;
+  e.T2 = T->T2.as<double>();
+  e.V3 = T->Q[2].as<double>();
+  e.t = T->t_dev.as<double>();
+  e.a = T->a_dev.as<double>();
+  e.n = T->n;
+  e.b = T->b;
+  e.r3 = T->r[2];
+  e.R_l = T->R_l;
+  e.p = T->interp;
+  const int waves = 4;
+  unsigned blocks = (unsigned)((M + waves - 1) / waves);
+  hipLaunchKernelGGL(eval_long_kernel, dim3(blocks), dim3(64 * waves), 0, s, e, M, pts, with_self,
+                     out.val, out.grad, out.selfv, out.selfg);
+}
+
+// Short-range part at arbitrary points: particles whose window contains the
+// point's cell, in index order (from the brick lists), Gaussians at the point.
+__global__ void eval_short_kernel(int64_t M, const double* __restrict__ pts,
+                                  const double* __restrict__ pos, const double* __restrict__ q,
+                                  const double* __restrict__ t, const double* __restrict__ a,
+                                  int R, int R_l, int64_t n, double b, int w, int nb,
+                                  const int* __restrict__ start, const int* __restrict__ list,
+                                  double* __restrict__ vals, int accumulate) {
+  int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pt >= M) return;
+  const double h = 2.0 * b / (double)n;
+  double y[3];
+  int64_t cell[3];
+  for (int l = 0; l < 3; ++l) {
+    y[l] = pts[3 * pt + l];
+    int64_t j = (int64_t)floor((y[l] + b) / h);
+    cell[l] = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+  }
+  const int64_t br = ((cell[0] / 8) * nb + cell[1] / 8) * nb + cell[2] / 8;
+  double acc = 0.0;
+  for (int e = start[br]; e < start[br + 1]; ++e) {
+    const int nu = list[e];
+    bool inside = true;
+    double r2 = 0.0;
+    for (int l = 0; l < 3; ++l) {
+      const double x = pos[3 * nu + l];
+      int64_t j = (int64_t)floor((x + b) / h);
+      j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+      if (cell[l] < j - w || cell[l] > j + w) inside = false;
+      const double d = y[l] - x;
+      r2 += d * d;
+    }
+    if (!inside) continue;
+    double sum = 0.0;
+    for (int k = R_l; k < R; ++k) sum += a[k] * exp(-t[k] * t[k] * r2);
+    acc += q[nu] * sum;
+  }
+  vals[pt] = accumulate ? vals[pt] + acc : acc;
+}
+
+void launch_eval_short(const rs_tensor* T, int64_t M, const double* pts, double* vals,
+                       int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(eval_short_kernel, dim3((unsigned)((M + 127) / 128)), dim3(128), 0, s, M, pts,
+                     T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
+                     T->a_dev.as<double>(), T->R, T->R_l, T->n, T->b, (T->n_s - 1) / 2, T->nb,
+                     T->brick_start.as<int>(), T->brick_list.as<int>(), vals, accumulate);
+}
+
+// Single workgroup, fixed-order FP64 reduction.
+constexpr int RED_THREADS = 1024;
+__global__ __launch_bounds__(RED_THREADS) void energy_kernel(const double* __restrict__ q,
+                                                             const double* __restrict__ v,
+                                                             const double* __restrict__ g,
+                                                             int64_t N, double* __restrict__ E,
+                                                             double* __restrict__ dEdq) {
+  __shared__ double red[RED_THREADS / 64];
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < N; j += RED_THREADS) {
+    const double d = v[j] - q[j] * g[j];
+    if (dEdq) dEdq[j] = d;
+    acc += q[j] * d;
+  }
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) s += red[w];
+    *E = 0.5 * s;
+  }
+}
+
+void launch_energy_reduce(const double* q, const double* v, const double* g, int64_t N, double* E,
+                          double* dEdq, hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(RED_THREADS), 0, s, q, v, g, N, E, dEdq);
+}
+
+__global__ void forces_kernel(const double* __restrict__ q, const double* __restrict__ gv,
+                              const double* __restrict__ gg, int64_t N, double scale,
+                              double* __restrict__ F) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * N) return;
+  const int64_t j = e / 3;
+  F[e] = -scale * q[j] * (gv[e] - q[j] * gg[e]);
+}
+
+void launch_forces(const double* q, const double* gradv, const double* gradg, int64_t N,
+                   double scale, double* F, hipStream_t s) {
+  hipLaunchKernelGGL(forces_kernel, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, s, q,
+                     gradv, gradg, N, scale, F);
+}
+
+}  // namespace rs

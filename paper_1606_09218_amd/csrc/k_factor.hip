@@ -1,0 +1,87 @@
+// Long-range factor columns (side matrices) of the N-particle canonical sum.
+//
+// The long-range part of the potential sum is the canonical tensor
+//   P_l = sum_nu z_nu sum_{k<R_l} a_k g_k(. - x_nu),  g_k(x) = prod_l exp(-t_k^2 x_l^2)
+// of rank R_l N (eq Long-Range_Sum), collocated at the cell centres.  Its side
+// matrices hold one column per (k, nu): U_l[i, j] = exp(-t_k^2 (x_i - x_{nu,l})^2),
+// j = k N + nu; the canonical weights are xi_j = z_nu a_k.
+//
+// Layout: U is three n x K column-major blocks (mode-major), each column
+// contiguous, so that the Gram and projection GEMMs stream whole columns.
+#include "rs_internal.h"
+
+namespace rs {
+
+__global__ void validate_kernel(const double* __restrict__ pos, const double* __restrict__ q,
+                                int64_t N, double b, int* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int f = 0;
+  if (i < N) {
+    for (int l = 0; l < 3; ++l) {
+      double x = pos[3 * i + l];
+      if (!isfinite(x)) f |= 1;
+      else if (x < -b || x > b) f |= 2;
+    }
+    if (!isfinite(q[i])) f |= 1;
+  }
+  // wave-level OR, then one integer atomic per wave (order-independent)
+  for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+  if ((threadIdx.x & 63) == 0 && f) atomicOr(flags, f);
+}
+
+void launch_validate(const double* pos, const double* q, int64_t N, double b, int* flags,
+                     hipStream_t s) {
+  int threads = 256;
+  int64_t blocks = (N + threads - 1) / threads;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, pos, q, N, b,
+                     flags);
+}
+
+// One thread per (i, j): consecutive threads walk down a column (i fastest),
+// so the stores are fully coalesced.  grid.y = mode.
+__global__ void side_matrix_kernel(const double* __restrict__ pos, const double* __restrict__ t,
+                                   int64_t N, int R_l, int64_t n, double b, double* __restrict__ U) {
+  const int l = blockIdx.y;
+  const int64_t K = N * R_l;
+  const int64_t total = n * K;
+  const double h = 2.0 * b / (double)n;
+  double* Ul = U + (int64_t)l * total;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = e / n;
+    int64_t i = e - j * n;
+    int64_t k = j / N;
+    int64_t nu = j - k * N;
+    double xi = -b + ((double)i + 0.5) * h;
+    double d = xi - pos[3 * nu + l];
+    double tk = t[k];
+    Ul[e] = exp(-(tk * tk) * (d * d));
+  }
+}
+
+__global__ void weights_kernel(const double* __restrict__ q, const double* __restrict__ a,
+                               int64_t N, int R_l, double* __restrict__ xi, double* __restrict__ w) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N * R_l) return;
+  int64_t k = j / N;
+  int64_t nu = j - k * N;
+  double v = q[nu] * a[k];
+  xi[j] = v;
+  w[j] = cbrt(v * v);  // |xi|^{2/3}
+}
+
+void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
+                          int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
+                          double* w, hipStream_t s) {
+  const int64_t total = n * N * R_l;
+  int threads = 256;
+  int64_t blocks = (total + threads - 1) / threads;
+  if (blocks > 65535LL * 16) blocks = 65535LL * 16;
+  hipLaunchKernelGGL(side_matrix_kernel, dim3((unsigned)blocks, 3), dim3(threads), 0, s, pos, t,
+                     N, R_l, n, b, U);
+  int64_t K = N * R_l;
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, q, a, N,
+                     R_l, xi, w);
+}
+
+}  // namespace rs

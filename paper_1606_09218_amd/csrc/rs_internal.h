@@ -1,0 +1,199 @@
+// Internal declarations of the RS library: handle structs, error plumbing and
+// the host-side launchers of the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rs.h"
+
+namespace rs {
+
+// ---- error plumbing ------------------------------------------------------
+void set_error(const std::string& msg);
+const char* last_error();
+
+struct Error {
+  rs_status status;
+  std::string msg;
+};
+
+#define RS_HIP(expr)                                                               \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      throw ::rs::Error{_e == hipErrorOutOfMemory ? RS_E_NOMEM : RS_E_DEVICE,      \
+                        std::string(#expr) + ": " + hipGetErrorString(_e)};        \
+  } while (0)
+
+#define RS_REQUIRE(cond, msg)                                                      \
+  do {                                                                             \
+    if (!(cond)) throw ::rs::Error{RS_E_INVALID, (msg)};                           \
+  } while (0)
+
+// ---- quadrature (host, FP64) ----------------------------------------------
+struct Table {
+  std::vector<double> t, a;   // R entries
+  int R = 0, R_l = 0, n_s = 0;
+  double S0 = 0, S_l0 = 0;
+};
+Table build_table(const rs_grid& g, const rs_fdesc& f);
+
+// ---- device buffer that frees itself (stream-ordered) ---------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(size_t nbytes, hipStream_t st);
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept;
+  ~DevBuf();
+  void reset();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace rs
+
+struct rs_ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipMemPool_t pool = nullptr;
+};
+
+struct rs_factors {
+  rs_grid grid;
+  rs_fdesc fdesc;
+  rs::Table table;
+  double* t_dev = nullptr;  // R
+  double* a_dev = nullptr;  // R
+  int device = 0;
+};
+
+struct rs_tensor {
+  rs_ctx* ctx = nullptr;
+  int64_t N = 0, n = 0;
+  double b = 0, h = 0;
+  int R = 0, R_l = 0, n_s = 0, kernel = 0, prec = 0, interp = 6;
+  double lambda = 0;
+  rs::Table table;
+  int r[3] = {0, 0, 0};
+  int p[3] = {0, 0, 0};
+  double sigma1[3] = {0, 0, 0}, sig_kept[3] = {0, 0, 0}, sig_next[3] = {0, 0, 0};
+  int rank_capped = 0;
+  hipStream_t stream = nullptr;  // stream the tensor's buffers were allocated on
+  rs::DevBuf t_dev, a_dev;       // quadrature table
+  rs::DevBuf pos, q;             // N x 3, N
+  rs::DevBuf Q[3];               // n x r_l row-major
+  rs::DevBuf beta;               // r1 x r2 x r3
+  rs::DevBuf T2;                 // n x n x r3: beta x_1 V1 x_2 V2 (long-range, modes 1,2 expanded)
+  // short-range binning: bricks of 8^3 cells; pairs (brick, particle) sorted by particle
+  int nb = 0;                    // bricks per axis
+  int64_t n_pairs = 0;
+  rs::DevBuf brick_start;        // nb^3 + 1
+  rs::DevBuf brick_list;         // n_pairs particle indices
+};
+
+namespace rs {
+
+// ---- kernel launchers (k_*.hip) -------------------------------------------
+
+// k_factor.hip
+// flags[0] |= 1 for a non-finite position/charge, |= 2 for a position outside [-b,b]
+void launch_validate(const double* pos, const double* q, int64_t N, double b, int* flags,
+                     hipStream_t s);
+// Side matrices U[l][i + j*n] = exp(-t_k^2 (x_i - x_{nu,l})^2), j = k*N + nu, k < R_l;
+// xi[j] = q[nu] a_k, w[j] = |xi_j|^{2/3}.
+void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
+                          int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
+                          double* w, hipStream_t s);
+
+// k_gemm64.hip : FP64 MFMA GEMM, C[bt](m,n) = sum_k A[bt](m,k) B[bt](k,n) kscale[k]
+struct Gemm64 {
+  int64_t M = 0, N = 0, K = 0;
+  int batch = 1;
+  const double* A = nullptr; int64_t sam = 0, sak = 0, sab = 0;
+  const double* B = nullptr; int64_t sbk = 0, sbn = 0, sbb = 0;
+  double* C = nullptr; int64_t scm = 0, scn = 0, scb = 0;
+  const double* kscale = nullptr;   // optional, length K (same for all batches)
+  int upper_only = 0;               // square symmetric output: compute tiles on/above the diagonal, mirror
+  int nontemporal = 0;              // streaming stores for a write-once output
+};
+// Splits K so that at least ~2 waves of workgroups fill the chip; partial
+// sums are reduced in a fixed order (deterministic).  `work` must hold
+// gemm64_workspace_bytes(g, num_cu) bytes (may be null when that is 0).
+size_t gemm64_workspace_bytes(const Gemm64& g, int num_cu);
+void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s);
+
+// k_eig.hip
+void launch_fill_omega(double* Om, int64_t n, int p, int modes, uint64_t seed, hipStream_t s);
+void launch_identity(double* I, int64_t n, int modes, hipStream_t s);
+// Orthonormalise the p columns of Y (n x p col-major, per mode) into Q by
+// classical Gram-Schmidt with reorthogonalisation.
+void launch_cgs2(const double* Y, double* Q, int64_t n, int p, int modes, uint64_t seed,
+                 hipStream_t s);
+void launch_symmetrize(double* B, int p, int modes, hipStream_t s);
+// Cyclic parallel Jacobi on B (p x p per mode, overwritten by its eigenvalues
+// on the diagonal), V (p x p col-major) receives the eigenvectors.
+void launch_jacobi(double* B, double* V, int p, int modes, int max_sweeps, hipStream_t s);
+// Sort eigenvalues descending, choose ranks; writes perm[mode][p], info doubles.
+struct RankInfo {
+  int r[3];
+  int capped[3];
+  double lam1[3], lam_kept[3], lam_next[3];
+};
+void launch_rank_select(const double* B, int p, int modes, double eps2, const int* fixed,
+                        int r_max, int* perm, RankInfo* info_dev, hipStream_t s);
+// Qout (n x r row-major) = Q0 (n x p col-major) * V[:, perm[0..r)], then
+// canonical signs (largest-magnitude entry of each column positive).
+void launch_gather_cols(const double* V, const int* perm, int p, int r, double* Wr,
+                        hipStream_t s);
+void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s);
+
+// k_core.hip : beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
+size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
+void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi,
+            int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
+            hipStream_t s);
+
+// k_short.hip
+struct ShortBins {
+  int nb = 0;
+  int64_t n_pairs = 0;
+};
+// Count (brick, particle) pairs; returns the total on the host (synchronizes).
+void short_bin_count(const double* pos, int64_t N, int64_t n, double b, int n_s, int nb,
+                     int* counts, hipStream_t s);
+void short_bin_fill(const double* pos, int64_t N, int64_t n, double b, int n_s, int nb,
+                    const int* start, int* cursor, int* list, hipStream_t s);
+void short_bin_sort(const int* start, int* list, int nbricks, hipStream_t s);
+void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s);
+// grid (FP64 or FP32) += sum over particles of the short-range windows
+void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
+                  const double* t, const double* a, int R, int R_l, int64_t n, double b,
+                  int n_s, int nb, const int* start, const int* list, hipStream_t s);
+
+// k_eval.hip
+// vals[m] (part 0/1/2) and optionally grad (M x 3) and self terms at points
+struct EvalOut {
+  double* val = nullptr;       // long (+short) value per point
+  double* grad = nullptr;      // M x 3 gradient of the long part, or null
+  double* selfv = nullptr;     // self term g_j (when points are the particles), or null
+  double* selfg = nullptr;     // M x 3 gradient of the self term, or null
+};
+void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with_self,
+                      const EvalOut& out, hipStream_t s);
+void launch_eval_short(const rs_tensor* T, int64_t M, const double* pts, double* vals,
+                       int accumulate, hipStream_t s);
+// E = 1/2 sum_j q_j (v_j - q_j g_j); dEdq_j = v_j - q_j g_j (optional)
+void launch_energy_reduce(const double* q, const double* v, const double* g, int64_t N,
+                          double* E, double* dEdq, hipStream_t s);
+void launch_forces(const double* q, const double* gradv, const double* gradg, int64_t N,
+                   double scale, double* F, hipStream_t s);
+
+}  // namespace rs

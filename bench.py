@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the RS canonical/Tucker potential path on one MI355X.
+
+One step = one RS assembly of the workload's particle system: side matrices,
+charge-weighted Gram GEMMs, eigensolve and rank rule, projection, core,
+short-range windows and the full n^3 grid, followed by the interaction
+energy and the forces.  Inputs (positions, charges, quadrature table) are
+resident on the device before the timed region.  Prints one JSON line.
+
+Default workload: 10x10x10 lattice, spacing 1.0, 100 vacancies, jitter
+N(0, 0.05^2), alternating +-1 charges (N = 900); box [-12,12]^3, n = 512,
+R = 24, R_l = 10, n_s = 17, Tucker tolerance 1e-6, FP64.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RS assemblies/sec at rel-L∞≤1e-5 vs plain FP64 on GPU; p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
+
+
+def workload(name: str):
+    import workloads
+    if name == "cfg2":
+        s = workloads.cfg2_lattice()
+        cfg = {"workload": "lattice10^3_vac100_N900_n512_R24_Rl10_ns17",
+               "N": s.N, "n": s.n, "b": s.b, "R": s.R, "R_l": s.R_l, "n_s": s.n_s,
+               "eps_tucker": s.eps_tucker, "kernel": s.kernel, "r_max": 112}
+        return s, cfg, 112
+    if name == "cfg1":
+        s = workloads.cfg1_plain_small()
+        cfg = {"workload": "uniform64_n128_R20_Rl8_ns9", "N": s.N, "n": s.n, "b": s.b, "R": s.R,
+               "R_l": s.R_l, "n_s": s.n_s, "eps_tucker": s.eps_tucker, "kernel": s.kernel,
+               "r_max": 128}
+        return s, cfg, 128
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1606_09218_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag: str, workload_tag: str):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    --pmc summaries, if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload_tag}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(s, budget_s: float = 20.0):
+    """The oracle (plain FP64 NumPy), timed on this host on a bounded sample
+    of one step: the full RS-Tucker build (side matrices, SVD of the weighted
+    side matrices, core), grid values on a few i1-planes, and energy and
+    forces for a subset of particles; scaled to one full step."""
+    import numpy as np
+    from oracle import canonical, pointeval, rs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    T = rs.assemble_system(s)
+    t_build = time.perf_counter() - t0
+    n = s.n
+    planes = 2
+    t0 = time.perf_counter()
+    for i1 in range(n // 2, n // 2 + planes):
+        long_plane = np.einsum("abc,a,jb,kc->jk", T.beta, T.Q[0][i1], T.Q[1], T.Q[2], optimize=True)
+        ii = np.stack(np.meshgrid([i1], np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+        short_plane = canonical.short_range_at(ii, s.b, n, T.pos, T.q, T.t, T.a, T.R_l, T.n_s)
+        _ = long_plane.ravel() + short_plane
+    t_grid = (time.perf_counter() - t0) * n / planes
+    m = min(16, s.N)
+    sub = rs.RSTucker(T.b, T.n, T.t, T.a, T.R_l, T.n_s, T.pos[:m], T.q[:m], T.Q, T.beta,
+                      T.sigma, T.ranks)
+    t0 = time.perf_counter()
+    pointeval.energy(sub)
+    pointeval.forces(sub)
+    t_ef = (time.perf_counter() - t0) * s.N / m
+    total = t_build + t_grid + t_ef
+    return {"value": 1.0 / total, "unit": "assemblies/s", "cores": cores, "kind": "oracle",
+            "sample": (f"oracle RS-Tucker build of the full system ({t_build:.1f} s) + grid on "
+                       f"{planes} of {n} i1-planes (scaled x{n // planes}) + energy/forces for "
+                       f"{m} of {s.N} particles (scaled); one step = {total:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of known size (for PMC scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(every workload here runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1606_09218_amd as rsm
+
+    s, cfg, r_max = workload(args.workload)
+    dev = torch.device("cuda:0")
+    ctx = rsm.Context(0)
+    ctx.set_timing(True)
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s, kernel=s.kernel, lam=s.lam,
+                    delta_rel=s.delta_rel)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
+    q = torch.tensor(s.q, dtype=torch.float64, device=dev)
+    grid = torch.empty(s.n ** 3, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    F = torch.empty(3 * s.N, dtype=torch.float64, device=dev)
+    opts = rsm.make_aopts(s.eps_tucker, r_max=r_max)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        T = rsm.assemble(ctx, f, pos, q, grid, opts, stream=stream)
+        rsm.energy(T, E, stream=stream)
+        rsm.forces(T, F, 1.0, stream=stream)
+        return T
+
+    for _ in range(args.warmup):
+        step().free()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    handles = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        handles.append(step())
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    stages = [h.stage_ms() for h in handles]
+    info = handles[0].info()
+    ranks = list(info.ranks)
+    for h in handles:
+        h.free()
+    torch.cuda.synchronize()
+
+    stage_avg = {k: float(np.mean([st[k] for st in stages])) for k in stages[0]}
+    n, r3 = s.n, ranks[2]
+    # dominant single-kernel stage: the grid expansion GEMM (one launch)
+    t_grid = stage_avg["grid"] * 1e-3
+    flops_grid = 2.0 * n ** 3 * r3
+    bytes_grid = 8.0 * (n ** 3 + n * n * r3 + n * r3)
+    achieved = flops_grid / t_grid / 1e12
+    traffic = traffic_from_profiles("grid_gemm64", args.workload)
+    roofline = {"kernel": "gemm64_kernel<false,false> (grid = T2 x_3 V3)",
+                "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
+                "traffic": traffic,
+                "algorithmic_flops_per_launch": flops_grid,
+                "algorithmic_bytes_per_launch": bytes_grid,
+                "achieved_hbm_GBs_algorithmic": round(bytes_grid / t_grid / 1e9, 1),
+                "avg_launch_ms": round(stage_avg["grid"], 4)}
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    ms_per_step = wall / args.steps * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / wall, 4),
+        "unit": "assemblies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": cfg,
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "ranks": ranks,
+        "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,7 +100,7 @@ typedef struct {
  *     the charge-weighted side matrix U_l diag(|xi|^{1/3}) (Appendix, step (I)).
  *  r_max: rank cap per mode (<= n).  fixed_ranks[l] > 0 overrides the rule.
  *  oversample: extra subspace columns of the eigensolver (default 16 when <= 0).
- *  power_iters: subspace iterations after the first (default 1 when < 0).
+ *  power_iters: subspace iterations after the first (default 0 when < 0).
  *  interp_order: even Lagrange order p of point evaluation (default 6 when <= 0). */
 typedef struct {
   double eps_tucker;
@@ -125,13 +125,38 @@ typedef struct {
   int64_t tucker_storage;    /* r1 r2 r3 + n (r1 + r2 + r3) (Lemma Property_RST_Tuck) */
   int64_t device_bytes;      /* device memory held by the tensor */
   int32_t rank_capped;       /* 1 if the rank rule hit r_max in some mode */
+  /* Milliseconds per assembly stage, measured with HIP events on the
+   * assembly stream when timing is enabled (rs_ctx_set_timing), else 0.
+   * Stages: RS_STAGE_* below. */
+  double stage_ms[12];
+  /* With timing enabled: milliseconds of the eigensolver's phases (slowest
+   * mode): tridiagonalisation, implicit QR iteration, back-transformation. */
+  double eig_phase_ms[3];
 } rs_info;
+
+enum {
+  RS_STAGE_FACTORS = 0,   /* side matrices and weights */
+  RS_STAGE_GRAM = 1,      /* charge-weighted Gram GEMMs */
+  RS_STAGE_EIGEN = 2,     /* subspace iteration, Jacobi, rank rule (incl. rank readback) */
+  RS_STAGE_BASIS = 3,     /* V_l = Q W, canonical signs */
+  RS_STAGE_PROJECT = 4,   /* U~_l = V_l^T U_l */
+  RS_STAGE_CORE = 5,      /* Khatri-Rao core contraction */
+  RS_STAGE_BINS = 6,      /* short-range brick lists */
+  RS_STAGE_EXPAND1 = 7,   /* V1 beta_(1) */
+  RS_STAGE_EXPAND2 = 8,   /* T2 = beta x_1 V1 x_2 V2 */
+  RS_STAGE_GRID = 9,      /* grid = T2 x_3 V3 (one GEMM launch) */
+  RS_STAGE_SHORT = 10,    /* short-range window gather into the grid */
+  RS_STAGE_COUNT = 11
+};
 
 /* ---- context ---------------------------------------------------------- */
 
 /* Bind the library to HIP device `device` (makes it current on this thread). */
 rs_status rs_ctx_create(int device, rs_ctx** out);
 void rs_ctx_destroy(rs_ctx* ctx);
+/* Enable (1) or disable (0) per-stage HIP-event timing of later assemblies
+ * made with this context (reported in rs_info.stage_ms). */
+rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable);
 
 /* ---- quadrature table and split (sections 2.2-2.3) --------------------- */
 

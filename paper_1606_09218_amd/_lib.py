@@ -52,12 +52,17 @@ class rs_info(C.Structure):
                 ("subspace", C.c_int32 * 3), ("sigma_first", C.c_double * 3),
                 ("sigma_last_kept", C.c_double * 3), ("sigma_next", C.c_double * 3),
                 ("S0", C.c_double), ("S_l0", C.c_double), ("tucker_storage", C.c_int64),
-                ("device_bytes", C.c_int64), ("rank_capped", C.c_int32)]
+                ("device_bytes", C.c_int64), ("rank_capped", C.c_int32),
+                ("stage_ms", C.c_double * 12), ("eig_phase_ms", C.c_double * 3)]
+
+
+STAGES = ("factors", "gram", "eigen", "basis", "project", "core", "bins", "expand1",
+          "expand2", "grid", "short")
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1606_09218_amd.build` "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1606_09218_amd/build.py` "
                           "(there is no fallback implementation)")
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
@@ -65,6 +70,7 @@ def _load():
     sig = {
         "rs_ctx_create": ([C.c_int, C.POINTER(P)], C.c_int),
         "rs_ctx_destroy": ([P], None),
+        "rs_ctx_set_timing": ([P, C.c_int], C.c_int),
         "rs_build_factors": ([P, C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.POINTER(P)], C.c_int),
         "rs_factors_get": ([P, D, D, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                             C.POINTER(C.c_int32)], C.c_int),
@@ -92,7 +98,7 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_build_factors", "rs_factors_get",
+EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
@@ -136,6 +142,9 @@ class Context:
         _check(lib.rs_ctx_create(int(device), C.byref(h)))
         self.handle = h
         self.device = device
+
+    def set_timing(self, enable: bool = True):
+        _check(lib.rs_ctx_set_timing(self.handle, int(bool(enable))))
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -190,6 +199,13 @@ class Tensor:
         inf = rs_info()
         _check(lib.rs_tensor_info(self.handle, C.byref(inf)))
         return inf
+
+    def stage_ms(self) -> dict:
+        inf = self.info()
+        out = {name: float(inf.stage_ms[i]) for i, name in enumerate(STAGES)}
+        for i, name in enumerate(("eig_tridiag", "eig_qr", "eig_backtransform")):
+            out[name] = float(inf.eig_phase_ms[i])
+        return out
 
     def free(self):
         if getattr(self, "handle", None):

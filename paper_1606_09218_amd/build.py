@@ -2,8 +2,8 @@
 
 Every source under csrc/ is compiled by hipcc (host files as plain C++, the
 *.hip files with device code for gfx950), in parallel, into _build/, then
-linked into paper_1606_09218_amd/librs.so.  Run as a module:
-    python -m paper_1606_09218_amd.build
+linked into paper_1606_09218_amd/librs.so.  Run as a script:
+    python paper_1606_09218_amd/build.py
 """
 from __future__ import annotations
 

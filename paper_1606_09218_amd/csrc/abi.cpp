@@ -92,7 +92,7 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   if (p % 2) ++p;
   if (p > P.n) p = P.n;
   P.p = (int)p;
-  P.power_iters = d.power_iters >= 0 ? d.power_iters : 1;
+  P.power_iters = d.power_iters >= 0 ? d.power_iters : 0;
   RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
   P.interp = d.interp_order > 0 ? d.interp_order : 6;
   RS_REQUIRE(P.interp % 2 == 0 && P.interp <= 8 && P.interp <= P.n, "interp_order must be even, <= 8");
@@ -105,12 +105,20 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
 
 static int bricks_per_axis(int64_t n) { return (int)((n + 7) / 8); }
 
+// Record the start of `stage` (and so the end of the previous one) when the
+// tensor carries timing events.
+static void mark(rs_tensor* T, int stage, hipStream_t s) {
+  if (!T->events.empty()) RS_HIP(hipEventRecord(T->events[stage], s));
+}
+
 // Gram matrices of the three modes into G (3 x n x n); U, xi, w computed into
 // caller-provided buffers.
 static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
                                  const double* pos, const double* q, double* U, double* xi,
-                                 double* w, double* G, hipStream_t s) {
-  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, s);
+                                 double* w, double* sw, double* G, hipStream_t s,
+                                 rs_tensor* T = nullptr) {
+  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s);
+  if (T) mark(T, RS_STAGE_GRAM, s);
   Gemm64 g;
   g.M = P.n;
   g.N = P.n;
@@ -132,6 +140,7 @@ static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
   const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
   const int ncu = T->ctx->num_cu;
   // W1 (n x r2 r3) = V1 beta_(1)
+  mark(T, RS_STAGE_EXPAND1, s);
   DevBuf W1((size_t)n * r2 * r3 * sizeof(double), s);
   {
     Gemm64 g;
@@ -142,6 +151,7 @@ static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
     DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
     gemm64(g, ncu, wk.as<double>(), s);
   }
+  mark(T, RS_STAGE_EXPAND2, s);
   T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
   {
     Gemm64 g;  // T2[i1] (n x r3) = V2 (n x r2) W1[i1] (r2 x r3), batched over i1
@@ -161,18 +171,23 @@ static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
     g.C = (double*)grid; g.scm = n; g.scn = 1;
     g.nontemporal = 1;
     DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+    mark(T, RS_STAGE_GRID, s);
     gemm64(g, ncu, wk.as<double>(), s);
+    mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 0, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
                  T->brick_start.as<int>(), T->brick_list.as<int>(), s);
   }
+  mark(T, RS_STAGE_COUNT, s);
 }
 
 struct Readback {
   int flags;
-  int pad;
+  int chol_fail;
   RankInfo info;
   int total_pairs;
+  int pad;
+  double eig_prof[12];
 };
 
 }  // namespace rs
@@ -207,6 +222,10 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
     hipDeviceProp_t prop;
     RS_HIP(hipGetDeviceProperties(&prop, device));
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->lds_limit = prop.sharedMemPerBlock > 0 ? (int)prop.sharedMemPerBlock : 65536;
+    int wk = 0;
+    if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, device) == hipSuccess && wk > 0)
+      c->wall_khz = (double)wk;
     RS_HIP(hipDeviceGetDefaultMemPool(&c->pool, device));
     uint64_t thr = UINT64_MAX;  // keep freed blocks cached for reuse
     RS_HIP(hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &thr));
@@ -216,6 +235,14 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
 }
 
 void rs_ctx_destroy(rs_ctx* ctx) { delete ctx; }
+
+rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx != nullptr, "null context");
+    ctx->timing = enable ? 1 : 0;
+    return RS_OK;
+  });
+}
 
 rs_status rs_build_factors(rs_ctx* ctx, const rs_grid* grid, const rs_fdesc* fdesc,
                            rs_factors** out) {
@@ -266,7 +293,8 @@ rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const do
     Plan P = make_plan(f, N, nullptr);
     DevBuf U((size_t)3 * P.n * P.K * sizeof(double), s);
     DevBuf xi((size_t)P.K * sizeof(double), s), w((size_t)P.K * sizeof(double), s);
-    run_factors_and_gram(ctx, f, P, pos, q, U.as<double>(), xi.as<double>(), w.as<double>(), G, s);
+    run_factors_and_gram(ctx, f, P, pos, q, U.as<double>(), xi.as<double>(), w.as<double>(),
+                         nullptr, G, s);
     return RS_OK;
   });
 }
@@ -301,6 +329,10 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     T->table = f->table;
     T->stream = s;
     for (int l = 0; l < 3; ++l) T->p[l] = p;
+    if (ctx->timing) {
+      T->events.assign(RS_STAGE_COUNT + 1, nullptr);
+      for (auto& e : T->events) RS_HIP(hipEventCreate(&e));
+    }
 
     T->pos = DevBuf((size_t)N * 3 * sizeof(double), s);
     T->q = DevBuf((size_t)N * sizeof(double), s);
@@ -319,49 +351,81 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     launch_validate(dpos, dq, N, f->grid.b, &rbd->flags, s);
 
     // (a2, a3) side matrices and charge-weighted Gram matrices
+    mark(T.get(), RS_STAGE_FACTORS, s);
     DevBuf U((size_t)3 * n * K * sizeof(double), s);
     DevBuf xi((size_t)K * sizeof(double), s), w((size_t)K * sizeof(double), s);
+    DevBuf sw((size_t)K * sizeof(double), s);
     DevBuf G((size_t)3 * n * n * sizeof(double), s);
     run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
-                         G.as<double>(), s);
+                         sw.as<double>(), G.as<double>(), s, T.get());
 
-    // (a4) dominant eigenvectors: Q0 (n x p per mode, col-major) spans the subspace
+    // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
+    mark(T.get(), RS_STAGE_EIGEN, s);
     DevBuf Q0((size_t)3 * n * p * sizeof(double), s);
     DevBuf Bm((size_t)3 * p * p * sizeof(double), s);
     if (p == n) {
       launch_identity(Q0.as<double>(), n, 3, s);
       RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
     } else {
-      DevBuf Om((size_t)3 * n * p * sizeof(double), s);
       DevBuf Y((size_t)3 * n * p * sizeof(double), s);
-      launch_fill_omega(Om.as<double>(), n, p, 3, 0x5eed1234ULL, s);
-      auto GtimesX = [&](const double* X, double* Yout) {
+      auto GtimesX = [&](const double* X, double* Yout) {  // row-major n x p in and out
         Gemm64 g;
         g.M = n; g.N = p; g.K = n; g.batch = 3;
-        g.A = G.as<double>(); g.sam = 1; g.sak = n; g.sab = n * n;
-        g.B = X; g.sbk = 1; g.sbn = n; g.sbb = n * p;
-        g.C = Yout; g.scm = 1; g.scn = n; g.scb = n * p;
+        g.A = G.as<double>(); g.sam = n; g.sak = 1; g.sab = n * n;
+        g.B = X; g.sbk = p; g.sbn = 1; g.sbb = n * p;
+        g.C = Yout; g.scm = p; g.scn = 1; g.scb = n * p;
         DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
         gemm64(g, ncu, wk.as<double>(), s);
       };
-      GtimesX(Om.as<double>(), Y.as<double>());
-      launch_cgs2(Y.as<double>(), Q0.as<double>(), n, p, 3, 0xabcdef01ULL, s);
+      // orthonormal basis of range(Y), in place: shifted Cholesky QR, twice
+      // (each shifted pass maps cond(Y) to about sqrt(shift)/sigma_min(Y)),
+      // then two plain passes
+      DevBuf Cq((size_t)3 * p * p * sizeof(double), s);
+      auto orth = [&](double* Yp) {
+        for (int pass = 0; pass < 4; ++pass) {
+          Gemm64 g;  // C = Y^T Y (symmetric)
+          g.M = p; g.N = p; g.K = n; g.batch = 3;
+          g.A = Yp; g.sam = 1; g.sak = p; g.sab = n * p;
+          g.B = Yp; g.sbk = p; g.sbn = 1; g.sbb = n * p;
+          g.C = Cq.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
+          g.upper_only = 1;
+          DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+          gemm64(g, ncu, wk.as<double>(), s);
+          launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, s);
+          launch_trsm_rows(Yp, Cq.as<double>(), n, p, 3, ctx->lds_limit, s);
+        }
+      };
+      // range finder on the charge-weighted side matrix itself (its dynamic
+      // range is that of the singular values, not of their squares)
+      {
+        DevBuf wk(sketch64_workspace_bytes(n, K, 3, p, ncu), s);
+        sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
+                 Q0.as<double>(), p, 1, ncu, wk.as<double>(), s);
+      }
+      launch_perturb(Q0.as<double>(), G.as<double>(), n, p, 3, 0x9e3779b9ULL, s);
+      orth(Q0.as<double>());
       for (int it = 0; it < P.power_iters; ++it) {
         GtimesX(Q0.as<double>(), Y.as<double>());
-        launch_cgs2(Y.as<double>(), Q0.as<double>(), n, p, 3, 0xabcdef01ULL + it + 1, s);
+        launch_perturb(Y.as<double>(), G.as<double>(), n, p, 3, 0x9e3779b9ULL + it + 1, s);
+        orth(Y.as<double>());
+        std::swap(Q0, Y);
       }
       GtimesX(Q0.as<double>(), Y.as<double>());  // Y = G Q0
       Gemm64 g;                                  // B = Q0^T Y
       g.M = p; g.N = p; g.K = n; g.batch = 3;
-      g.A = Q0.as<double>(); g.sam = n; g.sak = 1; g.sab = n * p;
-      g.B = Y.as<double>(); g.sbk = 1; g.sbn = n; g.sbb = n * p;
-      g.C = Bm.as<double>(); g.scm = 1; g.scn = p; g.scb = (int64_t)p * p;
+      g.A = Q0.as<double>(); g.sam = 1; g.sak = p; g.sab = n * p;
+      g.B = Y.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = n * p;
+      g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
       DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
       gemm64(g, ncu, wk.as<double>(), s);
       launch_symmetrize(Bm.as<double>(), p, 3, s);
     }
     DevBuf V((size_t)3 * p * p * sizeof(double), s);
-    launch_jacobi(Bm.as<double>(), V.as<double>(), p, 3, 40, s);
+    {
+      DevBuf hv((size_t)3 * ((size_t)p * p + p) * sizeof(double), s);
+      launch_eig_sym(Bm.as<double>(), V.as<double>(), hv.as<double>(), p, 3, ctx->lds_limit,
+                     &rbd->chol_fail, ctx->timing ? rbd->eig_prof : nullptr, s);
+    }
     DevBuf perm((size_t)3 * p * sizeof(int), s);
     DevBuf fixed_dev(3 * sizeof(int), s);
     RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
@@ -384,7 +448,16 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     RS_HIP(hipStreamSynchronize(s));
     if (host.flags & 1) throw Error{RS_E_INVALID, "non-finite particle position or charge"};
     if (host.flags & 2) throw Error{RS_E_INVALID, "particle outside the box [-b, b]^3"};
+    if (host.chol_fail & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the subspace basis"};
+    if (host.chol_fail & 2) throw Error{RS_E_DEVICE, "eigensolver: QR iteration did not converge"};
 
+    if (ctx->timing)
+      for (int ph = 0; ph < 3; ++ph) {
+        double mx = 0.0;
+        for (int l = 0; l < 3; ++l)
+          mx = std::max(mx, (host.eig_prof[4 * l + ph + 1] - host.eig_prof[4 * l + ph]) / ctx->wall_khz);
+        T->eig_phase_ms[ph] = mx;
+      }
     for (int l = 0; l < 3; ++l) {
       T->r[l] = host.info.r[l];
       T->rank_capped |= host.info.capped[l];
@@ -395,6 +468,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     }
 
     // final bases V_l = Q0 W[:, perm[:r]] (n x r row-major), canonical signs
+    mark(T.get(), RS_STAGE_BASIS, s);
     for (int l = 0; l < 3; ++l) {
       const int r = T->r[l];
       DevBuf Wr((size_t)p * r * sizeof(double), s);
@@ -403,7 +477,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       T->Q[l] = DevBuf((size_t)n * r * sizeof(double), s);
       Gemm64 g;
       g.M = n; g.N = r; g.K = p;
-      g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = 1; g.sak = n;
+      g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = p; g.sak = 1;
       g.B = Wr.as<double>(); g.sbk = 1; g.sbn = p;
       g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
       DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
@@ -416,6 +490,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     V.reset();
 
     // (a5) projection U~_l = V_l^T U_l (stored column j contiguous: U~[j*r + a]) and core
+    mark(T.get(), RS_STAGE_PROJECT, s);
     DevBuf Ut[3];
     for (int l = 0; l < 3; ++l) {
       const int r = T->r[l];
@@ -431,6 +506,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     U.reset();
     const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
     T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
+    mark(T.get(), RS_STAGE_CORE, s);
     {
       DevBuf wk(core64_workspace_bytes(r1, r2, r3, K, ncu), s);
       core64(Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(), r1, r2,
@@ -439,6 +515,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     for (int l = 0; l < 3; ++l) Ut[l].reset();
 
     // (a6) short-range lists: fill and sort by particle index
+    mark(T.get(), RS_STAGE_BINS, s);
     T->n_pairs = host.total_pairs;
     T->brick_list = DevBuf((size_t)std::max<int64_t>(T->n_pairs, 1) * sizeof(int), s);
     RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
@@ -563,6 +640,17 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
     for (int l = 0; l < 3; ++l) bytes += T->Q[l].bytes;
     I.device_bytes = (int64_t)bytes;
     I.rank_capped = T->rank_capped;
+    for (int ph = 0; ph < 3; ++ph) I.eig_phase_ms[ph] = T->eig_phase_ms[ph];
+    if (!T->events.empty()) {
+      RS_HIP(hipEventSynchronize(T->events[RS_STAGE_COUNT]));
+      // a stage that did not run has its start event unrecorded: it borrows
+      // the next recorded event and reports 0
+      for (int k = 0; k < RS_STAGE_COUNT; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, T->events[k], T->events[k + 1]) == hipSuccess) I.stage_ms[k] = ms;
+        else I.stage_ms[k] = 0.0;
+      }
+    }
     *info = I;
     return RS_OK;
   });

@@ -60,7 +60,8 @@ __global__ void side_matrix_kernel(const double* __restrict__ pos, const double*
 }
 
 __global__ void weights_kernel(const double* __restrict__ q, const double* __restrict__ a,
-                               int64_t N, int R_l, double* __restrict__ xi, double* __restrict__ w) {
+                               int64_t N, int R_l, double* __restrict__ xi, double* __restrict__ w,
+                               double* __restrict__ sw) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N * R_l) return;
   int64_t k = j / N;
@@ -68,11 +69,12 @@ __global__ void weights_kernel(const double* __restrict__ q, const double* __res
   double v = q[nu] * a[k];
   xi[j] = v;
   w[j] = cbrt(v * v);  // |xi|^{2/3}
+  if (sw) sw[j] = cbrt(fabs(v));  // |xi|^{1/3}
 }
 
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
-                          double* w, hipStream_t s) {
+                          double* w, double* sw, hipStream_t s) {
   const int64_t total = n * N * R_l;
   int threads = 256;
   int64_t blocks = (total + threads - 1) / threads;
@@ -81,7 +83,7 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
                      N, R_l, n, b, U);
   int64_t K = N * R_l;
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, q, a, N,
-                     R_l, xi, w);
+                     R_l, xi, w, sw);
 }
 
 }  // namespace rs

@@ -119,6 +119,38 @@ struct KhatriRaoSrc {
   }
 };
 
+// Random test matrix of the range finder, generated on the fly:
+// B[k, c] = scale[k] * u(seed, k, c), u uniform in [-1, 1) from a counter hash.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+struct HashSrc {
+  const double* scale;
+  uint64_t seed;
+  int64_t W;
+  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[4],
+                                       int tid) const {
+    const int64_t c = n0 + (tid & 63);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t k = k0 + (tid >> 6) + 4 * r;
+      double v = 0.0;
+      if (c < W && k < kend) {
+        const uint64_t h = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ULL + (uint64_t)c));
+        v = scale[k] * ((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+      }
+      reg[r] = v;
+    }
+  }
+  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[4], int tid) const {
+    store_slab<true>(lds, ld, reg, tid);
+  }
+};
+
 struct TileOut {
   int64_t M, N;
   double* C; int64_t scm, scn;
@@ -229,6 +261,28 @@ __global__ __launch_bounds__(256) void gemm64_kernel(GemmDev g) {
   o.scn = g.scn;
   o.part = g.part ? g.part + ((int64_t)bt * g.splits + split) * g.M * g.N : nullptr;
   o.nontemporal = g.nontemporal;
+  mfma64_tile(as, bs, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, o);
+}
+
+// Y[bt] (M x N, col-major) = A[bt] (M x K, m-contiguous) * Omega_bt (K x N, hashed)
+__global__ __launch_bounds__(256) void sketch64_kernel(GemmDev g, uint64_t seed) {
+  const int tile = blockIdx.x;
+  const int tm = tile / g.tiles_n, tn = tile - tm * g.tiles_n;
+  const int bt = blockIdx.y;
+  const int split = blockIdx.z;
+  const int64_t kbeg = (int64_t)split * g.kchunk;
+  int64_t kend = kbeg + g.kchunk;
+  if (kend > g.K) kend = g.K;
+  StridedSrc<true> as{g.A + (int64_t)bt * g.sab, 1, g.sak, g.M, nullptr};
+  HashSrc bs{g.kscale + (int64_t)bt * g.sbb, seed + 0x51ED27ULL * (uint64_t)(bt + 1), g.N};
+  TileOut o;
+  o.M = g.M;
+  o.N = g.N;
+  o.C = g.C + (int64_t)bt * g.scb;
+  o.scm = g.scm;
+  o.scn = g.scn;
+  o.part = g.part ? g.part + ((int64_t)bt * g.splits + split) * g.M * g.N : nullptr;
+  o.nontemporal = 0;
   mfma64_tile(as, bs, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, o);
 }
 
@@ -403,6 +457,43 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
     hipLaunchKernelGGL(core64_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)work,
                        d.splits, total, beta);
   }
+}
+
+void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* scale,
+              int64_t scale_stride, int batch, int64_t N, uint64_t seed, double* Y, int64_t scm,
+              int64_t scn, int num_cu, double* work, hipStream_t s) {
+  Gemm64 g;
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.A = A; g.sam = 1; g.sak = M; g.sab = sab;
+  g.C = Y; g.scm = scm; g.scn = scn; g.scb = M * N;
+  g.kscale = scale;
+  g.sbb = scale_stride;
+  GemmDev d;
+  d.M = M; d.N = N; d.K = K;
+  d.A = A; d.sam = 1; d.sak = M; d.sab = sab;
+  d.B = nullptr; d.sbk = 0; d.sbn = 0; d.sbb = scale_stride;
+  d.C = Y; d.scm = scm; d.scn = scn; d.scb = M * N;
+  d.kscale = scale;
+  d.upper_only = 0;
+  d.nontemporal = 0;
+  plan(g, num_cu, d.splits, d.kchunk, d.tiles_m, d.tiles_n);
+  const bool use_part = d.splits > 1;
+  d.part = use_part ? work : nullptr;
+  if (use_part && !work) throw Error{RS_E_DEVICE, "sketch64: missing split-K workspace"};
+  dim3 grid((unsigned)(d.tiles_m * d.tiles_n), (unsigned)batch, (unsigned)d.splits);
+  hipLaunchKernelGGL(sketch64_kernel, grid, dim3(256), 0, s, d, seed);
+  if (use_part) {
+    int64_t total = M * N;
+    int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(gemm64_reduce_kernel, dim3((unsigned)blocks, (unsigned)batch), dim3(256), 0,
+                       s, d);
+  }
+}
+
+size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu) {
+  Gemm64 g;
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  return gemm64_workspace_bytes(g, num_cu);
 }
 
 }  // namespace rs

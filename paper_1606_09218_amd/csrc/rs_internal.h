@@ -64,6 +64,9 @@ struct rs_ctx {
   int device = 0;
   int num_cu = 256;
   hipMemPool_t pool = nullptr;
+  int timing = 0;
+  int lds_limit = 65536;   // dynamic LDS bytes one workgroup may use
+  double wall_khz = 100000.0;  // rate of the device wall clock
 };
 
 struct rs_factors {
@@ -97,6 +100,13 @@ struct rs_tensor {
   int64_t n_pairs = 0;
   rs::DevBuf brick_start;        // nb^3 + 1
   rs::DevBuf brick_list;         // n_pairs particle indices
+  // stage timing: events[k] recorded before stage k, events[RS_STAGE_COUNT] at the end
+  std::vector<hipEvent_t> events;
+  double eig_phase_ms[3] = {0, 0, 0};  // tridiagonalisation, QR iteration, back-transformation
+  ~rs_tensor() {
+    for (hipEvent_t e : events)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace rs {
@@ -111,7 +121,7 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
 // xi[j] = q[nu] a_k, w[j] = |xi_j|^{2/3}.
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
-                          double* w, hipStream_t s);
+                          double* w, double* sw, hipStream_t s);
 
 // k_gemm64.hip : FP64 MFMA GEMM, C[bt](m,n) = sum_k A[bt](m,k) B[bt](k,n) kscale[k]
 struct Gemm64 {
@@ -129,18 +139,32 @@ struct Gemm64 {
 // gemm64_workspace_bytes(g, num_cu) bytes (may be null when that is 0).
 size_t gemm64_workspace_bytes(const Gemm64& g, int num_cu);
 void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s);
+// Range-finder sketch Y[bt] (M x N col-major) = A[bt] (M x K col-major) Omega_bt,
+// Omega_bt[k, c] = scale[bt*scale_stride + k] * u(seed, bt, k, c), u uniform in [-1, 1).
+size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu);
+void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* scale,
+              int64_t scale_stride, int batch, int64_t N, uint64_t seed, double* Y, int64_t scm,
+              int64_t scn, int num_cu, double* work, hipStream_t s);
 
 // k_eig.hip
-void launch_fill_omega(double* Om, int64_t n, int p, int modes, uint64_t seed, hipStream_t s);
 void launch_identity(double* I, int64_t n, int modes, hipStream_t s);
-// Orthonormalise the p columns of Y (n x p col-major, per mode) into Q by
-// classical Gram-Schmidt with reorthogonalisation.
-void launch_cgs2(const double* Y, double* Q, int64_t n, int p, int modes, uint64_t seed,
-                 hipStream_t s);
 void launch_symmetrize(double* B, int p, int modes, hipStream_t s);
-// Cyclic parallel Jacobi on B (p x p per mode, overwritten by its eigenvalues
-// on the diagonal), V (p x p col-major) receives the eigenvectors.
-void launch_jacobi(double* B, double* V, int p, int modes, int max_sweeps, hipStream_t s);
+void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,
+                    hipStream_t s);
+// Cholesky C = L L^T in place (lower, col-major), one workgroup per mode; the
+// shifted variant adds 11 (nrows p + p (p+1)) u tr(C) to the diagonal first.
+// fail |= 1 on a non-positive pivot.
+void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit, int* fail,
+                 hipStream_t s);
+// Y (n x p row-major per mode) <- Y L^{-T}
+void launch_trsm_rows(double* Y, const double* L, int64_t n, int p, int modes, int lds_limit,
+                      hipStream_t s);
+// Dense symmetric eigensolver of B (p x p per mode): eigenvalues written to
+// the diagonal of B, eigenvectors to V (p x p col-major).  HV is scratch of
+// 3 (p p + p) doubles.  fail |= 2 if the QR iteration does not converge.
+// prof (or null): 4 wall-clock stamps per mode at the phase boundaries.
+void launch_eig_sym(double* B, double* V, double* HV, int p, int modes, int lds_limit, int* fail,
+                    double* prof, hipStream_t s);
 // Sort eigenvalues descending, choose ranks; writes perm[mode][p], info doubles.
 struct RankInfo {
   int r[3];

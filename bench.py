@@ -104,6 +104,50 @@ def cpu_baseline(s, budget_s: float = 20.0):
                        f"{m} of {s.N} particles (scaled); one step = {total:.1f} s")}
 
 
+def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
+    """The same step with split-FP16 core and grid expansion (FP32 grid):
+    throughput and its error against the FP64 GPU result of the same input."""
+    import numpy as np
+    import torch
+    out = {}
+    E64 = torch.empty(1, dtype=torch.float64, device=grid64.device)
+    T = rsm.assemble(ctx, f, pos, q, grid64, rsm.make_aopts(s.eps_tucker, r_max=r_max), stream=stream)
+    rsm.energy(T, E64, stream=stream)
+    ranks = list(T.info().ranks)
+    T.free()
+    for prec in ("mixed_fp16", "mixed_bf16"):
+        g32 = torch.empty(s.n ** 3, dtype=torch.float32, device=grid64.device)
+        E = torch.empty(1, dtype=torch.float64, device=grid64.device)
+        F = torch.empty(3 * s.N, dtype=torch.float64, device=grid64.device)
+        opts = rsm.make_aopts(s.eps_tucker, r_max=r_max, fixed_ranks=ranks, prec=prec)
+
+        def step():
+            T = rsm.assemble(ctx, f, pos, q, g32, opts, stream=stream)
+            rsm.energy(T, E, stream=stream)
+            rsm.forces(T, F, 1.0, stream=stream)
+            return T
+
+        for _ in range(warmup):
+            step().free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hs = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = [h.stage_ms() for h in hs]
+        for h in hs:
+            h.free()
+        err = float((g32.double() - grid64).abs().max() / grid64.abs().max())
+        e_err = abs(E.item() - E64.item()) / abs(E64.item())
+        out[prec] = {"value": round(steps / wall, 4), "unit": "assemblies/s",
+                     "ms_per_step": round(wall / steps * 1e3, 3),
+                     "grid_rel_linf_vs_fp64": err, "energy_rel_err_vs_fp64": e_err,
+                     "meets_1e-5": bool(err <= 1e-5),
+                     "core_ms": round(float(np.mean([x["core"] for x in st])), 4),
+                     "grid_ms": round(float(np.mean([x["grid"] for x in st])), 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +155,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
     args = ap.parse_args()
@@ -212,6 +257,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid, args.steps, args.warmup, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)

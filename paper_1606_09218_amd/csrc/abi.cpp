@@ -92,6 +92,7 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   if (p % 2) ++p;
   if (p > P.n) p = P.n;
   P.p = (int)p;
+  RS_REQUIRE(P.p <= 512 || P.p == P.n, "r_max + oversample must not exceed 512 (eigensolver subspace)");
   P.power_iters = d.power_iters >= 0 ? d.power_iters : 0;
   RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
   P.interp = d.interp_order > 0 ? d.interp_order : 6;
@@ -162,8 +163,14 @@ static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
     DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
     gemm64(g, ncu, wk.as<double>(), s);
   }
-  if (grid) {
-    if (T->prec != RS_FP64) throw Error{RS_E_UNSUPPORTED, "mixed-precision grid not built here"};
+  if (grid && T->prec != RS_FP64) {
+    mark(T, RS_STAGE_GRID, s);
+    grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid, s);
+    mark(T, RS_STAGE_SHORT, s);
+    short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
+                 T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
+                 T->brick_start.as<int>(), T->brick_list.as<int>(), s);
+  } else if (grid) {
     Gemm64 g;  // grid[(i1,i2), i3] = sum_c T2[(i1,i2), c] V3[i3, c]
     g.M = n * n; g.N = n; g.K = r3;
     g.A = T->T2.as<double>(); g.sam = r3; g.sak = 1;
@@ -308,7 +315,6 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     RS_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const Plan P = make_plan(f, N, opts);
-    if (P.prec != RS_FP64) throw Error{RS_E_UNSUPPORTED, "mixed precision not available yet"};
     const int64_t n = P.n, K = P.K;
     const int p = P.p;
     const int ncu = ctx->num_cu;
@@ -507,10 +513,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
     T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
     mark(T.get(), RS_STAGE_CORE, s);
-    {
+    if (P.prec == RS_FP64) {
       DevBuf wk(core64_workspace_bytes(r1, r2, r3, K, ncu), s);
       core64(Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(), r1, r2,
              r3, K, T->beta.as<double>(), ncu, wk.as<double>(), s);
+    } else {
+      DevBuf wk(core_mixed_workspace_bytes(r1, r2, r3, K, ncu), s);
+      core_mixed(P.prec, Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(),
+                 r1, r2, r3, K, T->beta.as<double>(), ncu, wk.as<double>(), s);
     }
     for (int l = 0; l < 3; ++l) Ut[l].reset();
 

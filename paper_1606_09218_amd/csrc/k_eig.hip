@@ -265,19 +265,22 @@ __global__ __launch_bounds__(CF_THREADS) void chol_kernel(double* __restrict__ C
 // substitution: x_c = y_c / L_cc is broadcast from its lane, then every lane
 // subtracts x_c L[i, c] from its entries i > c.  L (lower, column-major) is
 // staged in LDS packed by columns so that the lanes read consecutive words.
-template <int RPL>
+template <int RPL, bool LDS>
 __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Yall,
                                                          const double* __restrict__ Lall,
                                                          int64_t n, int p) {
   extern __shared__ double sht[];
   const int mode = blockIdx.y;
   const double* L = Lall + (int64_t)mode * p * p;
-  // column c holds L[c..p-1, c] at offset c p - c (c - 1) / 2
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int c = e / p, i = e - c * p;
-    if (i >= c) sht[c * p - c * (c - 1) / 2 + (i - c)] = L[e];
+  // LDS: column c holds L[c..p-1, c] at offset c p - c (c - 1) / 2; global:
+  // column c of the column-major L starts at c p + c.  Either way Lc[i - c] = L[i, c].
+  if (LDS) {
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      const int c = e / p, i = e - c * p;
+      if (i >= c) sht[c * p - c * (c - 1) / 2 + (i - c)] = L[e];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
     for (int cc = 0; cc < 64; ++cc) {
       const int c = 64 * u + cc;
       if (c >= p) break;
-      const double* Lc = sht + c * p - c * (c - 1) / 2;   // Lc[i - c] = L[i, c]
+      const double* Lc = LDS ? sht + c * p - c * (c - 1) / 2 : L + (int64_t)c * p + c;
       const double x = __shfl(y[u], cc) / Lc[0];
       if (lane == cc) y[u] = x;
       if (lane > cc) {
@@ -335,22 +338,25 @@ void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int ld
 
 template <int RPL>
 static void trsm_launch(double* Y, const double* L, int64_t n, int p, int modes, size_t bytes,
-                        hipStream_t s) {
-  allow_lds((const void*)trsm_rows_kernel<RPL>, bytes);
+                        bool lds, hipStream_t s) {
   const int waves = 16;
-  hipLaunchKernelGGL(trsm_rows_kernel<RPL>, dim3((unsigned)((n + waves - 1) / waves), modes),
-                     dim3(64 * waves), bytes, s, Y, L, n, p);
+  const dim3 grid((unsigned)((n + waves - 1) / waves), modes);
+  if (lds) {
+    allow_lds((const void*)trsm_rows_kernel<RPL, true>, bytes);
+    hipLaunchKernelGGL((trsm_rows_kernel<RPL, true>), grid, dim3(64 * waves), bytes, s, Y, L, n, p);
+  } else {
+    hipLaunchKernelGGL((trsm_rows_kernel<RPL, false>), grid, dim3(64 * waves), 0, s, Y, L, n, p);
+  }
 }
 
 void launch_trsm_rows(double* Y, const double* L, int64_t n, int p, int modes, int lds_limit,
                       hipStream_t s) {
   const size_t bytes = (size_t)p * (p + 1) / 2 * sizeof(double);
-  if (bytes + 1024 > (size_t)lds_limit)
-    throw Error{RS_E_UNSUPPORTED, "eigensolver subspace too large for the LDS triangular solve"};
-  if (p <= 64) trsm_launch<1>(Y, L, n, p, modes, bytes, s);
-  else if (p <= 128) trsm_launch<2>(Y, L, n, p, modes, bytes, s);
-  else if (p <= 256) trsm_launch<4>(Y, L, n, p, modes, bytes, s);
-  else if (p <= 512) trsm_launch<8>(Y, L, n, p, modes, bytes, s);
+  const bool lds = bytes + 1024 <= (size_t)lds_limit;
+  if (p <= 64) trsm_launch<1>(Y, L, n, p, modes, bytes, lds, s);
+  else if (p <= 128) trsm_launch<2>(Y, L, n, p, modes, bytes, lds, s);
+  else if (p <= 256) trsm_launch<4>(Y, L, n, p, modes, bytes, lds, s);
+  else if (p <= 512) trsm_launch<8>(Y, L, n, p, modes, bytes, lds, s);
   else throw Error{RS_E_UNSUPPORTED, "eigensolver subspace above 512"};
 }
 

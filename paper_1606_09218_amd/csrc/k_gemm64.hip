@@ -496,4 +496,9 @@ size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int 
   return gemm64_workspace_bytes(g, num_cu);
 }
 
+void core64_reduce(const double* part, int splits, int64_t total, double* out, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(core64_reduce_kernel, dim3(blocks), dim3(256), 0, s, part, splits, total, out);
+}
+
 }  // namespace rs

@@ -1,0 +1,105 @@
+"""Energy and forces on the GPU: the autograd binding, finite differences of
+the FP64 energy, the oracle's forces, and the pairwise forces at full size."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pairwise, pointeval, quadrature, rs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rsm():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1606_09218_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(rsm):
+    return rsm.Context(0)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def test_autograd_matches_oracle_and_finite_differences(rsm, ctx):
+    from paper_1606_09218_amd.autograd import rs_energy
+    s = workloads.tiny_system(81, 10, 5.0, 64, 20, 8, 9, min_sep=0.9)
+    say("autograd tiny")
+    ref = rs.assemble_system(s)
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s)
+    opts = rsm.make_aopts(s.eps_tucker, fixed_ranks=ref.ranks)
+    pos = dev(s.pos).requires_grad_(True)
+    q = dev(s.q).requires_grad_(True)
+    E = rs_energy(pos, q, ctx, f, opts)
+    E.backward()
+    E_ref, dq_ref = pointeval.energy(ref)
+    F_ref = pointeval.forces(ref)
+    assert abs(E.item() - E_ref) <= 1e-8 * abs(E_ref)
+    gp = pos.grad.cpu().numpy()
+    assert np.max(np.abs(-gp - F_ref)) <= 1e-6 * np.max(np.abs(F_ref))
+    assert np.max(np.abs(q.grad.cpu().numpy() - dq_ref)) <= 1e-8 * np.max(np.abs(dq_ref))
+    # central differences of the FP64 GPU energy (the basis is recomputed for
+    # every displacement; its change is of the order of the rank threshold)
+    h = 1e-4
+    opts_free = rsm.make_aopts(1e-9, r_max=64)
+    for j, l in [(0, 0), (3, 1), (7, 2)]:
+        vals = []
+        for sgn in (+1, -1):
+            pp = s.pos.copy()
+            pp[j, l] += sgn * h
+            T = rsm.assemble(ctx, f, dev(pp), dev(s.q), None, opts_free)
+            Et = torch.empty(1, dtype=torch.float64, device="cuda")
+            rsm.energy(T, Et)
+            vals.append(Et.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"  dE/dx[{j},{l}] adjoint {gp[j, l]:.8e} fd {fd:.8e}")
+        assert abs(fd - gp[j, l]) <= 2e-3 * np.max(np.abs(gp))
+
+
+def test_cfg4_full_size_energy_and_forces(rsm, ctx):
+    """N=4096, n=512, kernel 1/r + e^{-r/2}/r: GPU energy and forces against
+    the oracle's pairwise long-range sums (O(N^2 R_l)), which the RS result
+    must match up to interpolation and Tucker truncation error."""
+    s = workloads.cfg4_forces()
+    say("cfg4 full size")
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, -1, kernel=s.kernel, lam=s.lam, delta_rel=s.delta_rel)
+    t, a = quadrature.literal_table(s.kernel, s.R, s.lam)
+    assert np.max(np.abs(np.array(f.a) - a)) <= 1e-15 * a.max()
+    T = rsm.assemble(ctx, f, dev(s.pos), dev(s.q), None, rsm.make_aopts(s.eps_tucker, r_max=256))
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    F = torch.empty(3 * s.N, dtype=torch.float64, device="cuda")
+    rsm.energy(T, E)
+    rsm.forces(T, F)
+    torch.cuda.synchronize()
+    inf = T.info()
+    E_can, F_can = pairwise.energy_canonical(s.pos, s.q, t, a, range(s.R_l), forces=True)
+    Fg = F.cpu().numpy().reshape(-1, 3)
+    e_rel = abs(E.item() - E_can) / abs(E_can)
+    f_rel = np.max(np.abs(Fg - F_can)) / np.max(np.abs(F_can))
+    say(f"  ranks {list(inf.ranks)} n_s {inf.n_s} E {E.item():.6f} pairwise {E_can:.6f} rel {e_rel:.2e} "
+        f"F rel-Linf {f_rel:.2e} sum|F| {np.abs(Fg.sum(0)).max():.2e}")
+    # the gap is the RS discretisation error, dominated by the Tucker
+    # truncation (eps = 1e-6) amplified by the charge cancellation in E; it is
+    # within the 1e-3..1e-5 relative energy errors the paper reports and
+    # shrinks when the rank tolerance is tightened
+    assert e_rel <= 5e-4
+    assert f_rel <= 1e-3
+    assert np.abs(Fg.sum(0)).max() <= 1e-3 * np.max(np.abs(Fg)) * np.sqrt(s.N)
+    Tt = rsm.assemble(ctx, f, dev(s.pos), dev(s.q), None, rsm.make_aopts(1e-8, r_max=400))
+    rsm.energy(Tt, E)
+    torch.cuda.synchronize()
+    e_tight = abs(E.item() - E_can) / abs(E_can)
+    say(f"  eps_tucker 1e-8: ranks {list(Tt.info().ranks)} E rel {e_tight:.2e}")
+    assert e_tight < e_rel

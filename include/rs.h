@@ -129,15 +129,15 @@ typedef struct {
    * assembly stream when timing is enabled (rs_ctx_set_timing), else 0.
    * Stages: RS_STAGE_* below. */
   double stage_ms[12];
-  /* With timing enabled: milliseconds of the eigensolver's phases (slowest
-   * mode): tridiagonalisation, implicit QR iteration, back-transformation. */
-  double eig_phase_ms[3];
+  /* With timing enabled: milliseconds of the eigensolver's phases
+   * (RS_EIG_* below; all modes together). */
+  double eig_phase_ms[4];
 } rs_info;
 
 enum {
   RS_STAGE_FACTORS = 0,   /* side matrices and weights */
   RS_STAGE_GRAM = 1,      /* charge-weighted Gram GEMMs */
-  RS_STAGE_EIGEN = 2,     /* subspace iteration, Jacobi, rank rule (incl. rank readback) */
+  RS_STAGE_EIGEN = 2,     /* dominant eigenvectors of the Gram matrices, rank rule (incl. rank readback) */
   RS_STAGE_BASIS = 3,     /* V_l = Q W, canonical signs */
   RS_STAGE_PROJECT = 4,   /* U~_l = V_l^T U_l */
   RS_STAGE_CORE = 5,      /* Khatri-Rao core contraction */
@@ -147,6 +147,15 @@ enum {
   RS_STAGE_GRID = 9,      /* grid = T2 x_3 V3 (one GEMM launch) */
   RS_STAGE_SHORT = 10,    /* short-range window gather into the grid */
   RS_STAGE_COUNT = 11
+};
+
+/* Phases of the eigen stage reported in rs_info.eig_phase_ms. */
+enum {
+  RS_EIG_SUBSPACE = 0,   /* sketch, Cholesky QR, Rayleigh-Ritz matrix B = Q^T G Q */
+  RS_EIG_TRIDIAG = 1,    /* Householder tridiagonalisation of B */
+  RS_EIG_VALUES = 2,     /* eigenvalues by bisection, eigenvectors by inverse iteration */
+  RS_EIG_ORTH = 3,       /* Cholesky QR of the eigenvectors, back-transformation */
+  RS_EIG_PHASES = 4
 };
 
 /* ---- context ---------------------------------------------------------- */

@@ -53,9 +53,10 @@ class rs_info(C.Structure):
                 ("sigma_last_kept", C.c_double * 3), ("sigma_next", C.c_double * 3),
                 ("S0", C.c_double), ("S_l0", C.c_double), ("tucker_storage", C.c_int64),
                 ("device_bytes", C.c_int64), ("rank_capped", C.c_int32),
-                ("stage_ms", C.c_double * 12), ("eig_phase_ms", C.c_double * 3)]
+                ("stage_ms", C.c_double * 12), ("eig_phase_ms", C.c_double * 4)]
 
 
+EIG_PHASES = ("eig_subspace", "eig_tridiag", "eig_values_vectors", "eig_orth_backtransform")
 STAGES = ("factors", "gram", "eigen", "basis", "project", "core", "bins", "expand1",
           "expand2", "grid", "short")
 
@@ -203,7 +204,7 @@ class Tensor:
     def stage_ms(self) -> dict:
         inf = self.info()
         out = {name: float(inf.stage_ms[i]) for i, name in enumerate(STAGES)}
-        for i, name in enumerate(("eig_tridiag", "eig_qr", "eig_backtransform")):
+        for i, name in enumerate(EIG_PHASES):
             out[name] = float(inf.eig_phase_ms[i])
         return out
 

@@ -93,6 +93,7 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   if (p > P.n) p = P.n;
   P.p = (int)p;
   RS_REQUIRE(P.p <= 512 || P.p == P.n, "r_max + oversample must not exceed 512 (eigensolver subspace)");
+  RS_REQUIRE(rcap <= 512, "r_max and fixed ranks must not exceed 512");
   P.power_iters = d.power_iters >= 0 ? d.power_iters : 0;
   RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
   P.interp = d.interp_order > 0 ? d.interp_order : 6;
@@ -194,8 +195,12 @@ struct Readback {
   RankInfo info;
   int total_pairs;
   int pad;
-  double eig_prof[12];
 };
+
+// Record the start of eigensolver phase `ph` when the tensor carries timing events.
+static void mark_eig(rs_tensor* T, int ph, hipStream_t s) {
+  if (!T->eig_events.empty()) RS_HIP(hipEventRecord(T->eig_events[ph], s));
+}
 
 }  // namespace rs
 
@@ -338,6 +343,8 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     if (ctx->timing) {
       T->events.assign(RS_STAGE_COUNT + 1, nullptr);
       for (auto& e : T->events) RS_HIP(hipEventCreate(&e));
+      T->eig_events.assign(RS_EIG_PHASES + 1, nullptr);
+      for (auto& e : T->eig_events) RS_HIP(hipEventCreate(&e));
     }
 
     T->pos = DevBuf((size_t)N * 3 * sizeof(double), s);
@@ -367,6 +374,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 
     // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
     mark(T.get(), RS_STAGE_EIGEN, s);
+    mark_eig(T.get(), 0, s);
     DevBuf Q0((size_t)3 * n * p * sizeof(double), s);
     DevBuf Bm((size_t)3 * p * p * sizeof(double), s);
     if (p == n) {
@@ -426,12 +434,35 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       gemm64(g, ncu, wk.as<double>(), s);
       launch_symmetrize(Bm.as<double>(), p, 3, s);
     }
-    DevBuf V((size_t)3 * p * p * sizeof(double), s);
+    // eigenvectors are formed only for the columns the rank rule can keep
+    const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
+    DevBuf ews(eig_sym_workspace_bytes(p, rc, 3), s);
+    DevBuf Z((size_t)3 * p * rc * sizeof(double), s);
+    mark_eig(T.get(), 1, s);
+    launch_eig_tridiag(Bm.as<double>(), ews.as<double>(), p, rc, 3, ctx->lds_limit, s);
+    mark_eig(T.get(), 2, s);
+    launch_eig_values_vectors(Bm.as<double>(), ews.as<double>(), Z.as<double>(), p, rc, 3, s);
+    mark_eig(T.get(), 3, s);
     {
-      DevBuf hv((size_t)3 * ((size_t)p * p + p) * sizeof(double), s);
-      launch_eig_sym(Bm.as<double>(), V.as<double>(), hv.as<double>(), p, 3, ctx->lds_limit,
-                     &rbd->chol_fail, ctx->timing ? rbd->eig_prof : nullptr, s);
+      // Cholesky QR of the eigenvectors in eigenvalue order: one shifted pass,
+      // then two plain passes
+      DevBuf Cz((size_t)3 * rc * rc * sizeof(double), s);
+      for (int pass = 0; pass < 3; ++pass) {
+        Gemm64 g;  // C = Z^T Z (symmetric)
+        g.M = rc; g.N = rc; g.K = p; g.batch = 3;
+        g.A = Z.as<double>(); g.sam = 1; g.sak = rc; g.sab = (int64_t)p * rc;
+        g.B = Z.as<double>(); g.sbk = rc; g.sbn = 1; g.sbb = (int64_t)p * rc;
+        g.C = Cz.as<double>(); g.scm = rc; g.scn = 1; g.scb = (int64_t)rc * rc;
+        g.upper_only = 1;
+        DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
+        gemm64(g, ncu, wk.as<double>(), s);
+        launch_chol(Cz.as<double>(), rc, p, 3, pass == 0, ctx->lds_limit, &rbd->chol_fail, s);
+        launch_trsm_rows(Z.as<double>(), Cz.as<double>(), p, rc, 3, ctx->lds_limit, s);
+      }
     }
+    launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
+    mark_eig(T.get(), 4, s);
+    ews.reset();
     DevBuf perm((size_t)3 * p * sizeof(int), s);
     DevBuf fixed_dev(3 * sizeof(int), s);
     RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
@@ -455,15 +486,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     if (host.flags & 1) throw Error{RS_E_INVALID, "non-finite particle position or charge"};
     if (host.flags & 2) throw Error{RS_E_INVALID, "particle outside the box [-b, b]^3"};
     if (host.chol_fail & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the subspace basis"};
-    if (host.chol_fail & 2) throw Error{RS_E_DEVICE, "eigensolver: QR iteration did not converge"};
 
-    if (ctx->timing)
-      for (int ph = 0; ph < 3; ++ph) {
-        double mx = 0.0;
-        for (int l = 0; l < 3; ++l)
-          mx = std::max(mx, (host.eig_prof[4 * l + ph + 1] - host.eig_prof[4 * l + ph]) / ctx->wall_khz);
-        T->eig_phase_ms[ph] = mx;
-      }
     for (int l = 0; l < 3; ++l) {
       T->r[l] = host.info.r[l];
       T->rank_capped |= host.info.capped[l];
@@ -478,7 +501,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     for (int l = 0; l < 3; ++l) {
       const int r = T->r[l];
       DevBuf Wr((size_t)p * r * sizeof(double), s);
-      launch_gather_cols(V.as<double>() + (int64_t)l * p * p, perm.as<int>() + l * p, p, r,
+      launch_gather_cols(Z.as<double>() + (int64_t)l * p * rc, rc, perm.as<int>() + l * p, p, r,
                          Wr.as<double>(), s);
       T->Q[l] = DevBuf((size_t)n * r * sizeof(double), s);
       Gemm64 g;
@@ -493,7 +516,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     G.reset();
     Bm.reset();
     Q0.reset();
-    V.reset();
+    Z.reset();
 
     // (a5) projection U~_l = V_l^T U_l (stored column j contiguous: U~[j*r + a]) and core
     mark(T.get(), RS_STAGE_PROJECT, s);
@@ -650,7 +673,14 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
     for (int l = 0; l < 3; ++l) bytes += T->Q[l].bytes;
     I.device_bytes = (int64_t)bytes;
     I.rank_capped = T->rank_capped;
-    for (int ph = 0; ph < 3; ++ph) I.eig_phase_ms[ph] = T->eig_phase_ms[ph];
+    if (!T->eig_events.empty()) {
+      RS_HIP(hipEventSynchronize(T->eig_events[RS_EIG_PHASES]));
+      for (int k = 0; k < RS_EIG_PHASES; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, T->eig_events[k], T->eig_events[k + 1]) == hipSuccess)
+          I.eig_phase_ms[k] = ms;
+      }
+    }
     if (!T->events.empty()) {
       RS_HIP(hipEventSynchronize(T->events[RS_STAGE_COUNT]));
       // a stage that did not run has its start event unrecorded: it borrows

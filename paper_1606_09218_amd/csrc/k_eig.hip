@@ -5,7 +5,7 @@
 // of G_l = U_l diag(w) U_l^T.  With a rapidly decaying spectrum a subspace
 // of p = r + oversample columns captures them:
 //   Y = U_l diag(|xi|^{1/3}) Omega, Q = orth(Y), [Y = G Q, Q = orth(Y)]^q, B = Q^T G Q,
-//   B = W Lambda W^T (tridiagonalisation + implicit QR), V = Q W (sorted, truncated).
+//   B = W Lambda W^T (tridiagonalisation, bisection, inverse iteration), V = Q W.
 // The subspace comes from a sketch of the charge-weighted side matrix (the
 // range finder of Halko, Martinsson and Tropp) orthonormalised by shifted
 // Cholesky QR.  Everything is FP64.  Each small kernel runs one workgroup per
@@ -144,22 +144,26 @@ void launch_rank_select(const double* B, int p, int modes, double eps2, const in
                      r_max, perm, info_dev);
 }
 
-// Wr (p x r col-major) = V[:, perm[0..r)]
-__global__ void gather_cols_kernel(const double* __restrict__ V, const int* __restrict__ perm,
-                                   int p, int r, double* __restrict__ Wr) {
+// Wr (p x r col-major) = Z[:, perm[0..r)] for row-major Z (p x ldz); an
+// index outside Z's columns (possible only for non-finite eigenvalues,
+// which the host rejects) yields a zero column.
+__global__ void gather_cols_kernel(const double* __restrict__ Z, int ldz,
+                                   const int* __restrict__ perm, int p, int r,
+                                   double* __restrict__ Wr) {
   int64_t total = (int64_t)p * r;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    int col = (int)(e / p), row = (int)(e % p);
-    Wr[e] = V[(int64_t)perm[col] * p + row];
+    const int col = (int)(e / p), row = (int)(e % p);
+    const int src = perm[col];
+    Wr[e] = (src >= 0 && src < ldz) ? Z[(int64_t)row * ldz + src] : 0.0;
   }
 }
 
-void launch_gather_cols(const double* V, const int* perm, int p, int r, double* Wr,
+void launch_gather_cols(const double* Z, int ldz, const int* perm, int p, int r, double* Wr,
                         hipStream_t s) {
   int64_t total = (int64_t)p * r;
   unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(gather_cols_kernel, dim3(blocks), dim3(256), 0, s, V, perm, p, r, Wr);
+  hipLaunchKernelGGL(gather_cols_kernel, dim3(blocks), dim3(256), 0, s, Z, ldz, perm, p, r, Wr);
 }
 
 // One wave per column of the row-major n x r matrix: find the entry of
@@ -260,11 +264,114 @@ __global__ __launch_bounds__(CF_THREADS) void chol_kernel(double* __restrict__ C
     for (int e = tid; e < pp; e += CF_THREADS) Cg[e] = C[e];
 }
 
+// Cholesky factorisation with the matrix in registers, for p <= 16 RT: a
+// 16 x 16 thread grid, thread (tx, ty) holds C[i, j] for i = tx + 16 a,
+// j = ty + 16 b.  Step k: the threads holding column k publish it in LDS
+// (double-buffered, one barrier per step), every thread scales it by
+// 1/sqrt(pivot) and applies the rank-1 update to its own entries.
+template <int RT>
+__global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call, int p,
+                                                       int64_t nrows, int shifted,
+                                                       int* __restrict__ fail) {
+  __shared__ double colk[2][16 * RT];
+  __shared__ double red[4];
+  const int mode = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double* C = Call + (int64_t)mode * p * p;
+  double c[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tx + 16 * a, j = ty + 16 * b;
+      c[a][b] = (i < p && j < p && i >= j) ? C[(int64_t)j * p + i] : 0.0;
+    }
+  if (shifted) {
+    double tr = 0.0;
+    if (tx == ty)
+#pragma unroll
+      for (int a = 0; a < RT; ++a) tr += c[a][a];
+    tr = wave_sum(tr);
+    if ((tid & 63) == 0) red[tid >> 6] = tr;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    const double shift = 11.0 * ((double)nrows * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * t;
+    if (tx == ty)
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+        if (tx + 16 * a < p) c[a][a] += shift;
+  }
+  for (int k = 0; k < p; ++k) {
+    double* cb = colk[k & 1];
+    const int kb = k >> 4;
+    const bool owner = ty == (k & 15);
+    if (owner) {
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+        if (b == kb)
+#pragma unroll
+          for (int a = 0; a < RT; ++a) {
+            const int i = tx + 16 * a;
+            if (i >= k && i < p) cb[i] = c[a][b];
+          }
+    }
+    __syncthreads();
+    double dkk = cb[k];
+    if (!(dkk > 0.0)) {
+      if (tid == 0) atomicOr(fail, 1);
+      dkk = 1e-300;
+    }
+    const double sq = sqrt(dkk), isq = 1.0 / sq;
+    double li[RT], lj[RT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tx + 16 * a;
+      li[a] = (i > k && i < p) ? cb[i] * isq : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int j = ty + 16 * b;
+      lj[b] = (j > k && j < p) ? cb[j] * isq : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < RT; ++b) c[a][b] = fma(-li[a], lj[b], c[a][b]);
+    if (owner) {
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+        if (b == kb)
+#pragma unroll
+          for (int a = 0; a < RT; ++a) {
+            const int i = tx + 16 * a;
+            if (i > k) c[a][b] = li[a];
+            else if (i == k) c[a][b] = sq;
+          }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tx + 16 * a, j = ty + 16 * b;
+      if (i < p && j < p && i >= j) C[(int64_t)j * p + i] = c[a][b];
+    }
+}
+
+// value of lane l (uniform l) of a double held across the wave
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // Y[i, :] <- Y[i, :] L^{-T} for row-major Y (n x p): one wave per row, the
 // row held in registers (lane l keeps entries l, l + 64, ...), right-looking
-// substitution: x_c = y_c / L_cc is broadcast from its lane, then every lane
+// substitution: x_c = y_c / L_cc is read from its lane, then every lane
 // subtracts x_c L[i, c] from its entries i > c.  L (lower, column-major) is
-// staged in LDS packed by columns so that the lanes read consecutive words.
+// staged in LDS packed by columns so that the lanes read consecutive words,
+// with the reciprocal diagonal after it.
 template <int RPL, bool LDS>
 __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Yall,
                                                          const double* __restrict__ Lall,
@@ -274,11 +381,13 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
   const double* L = Lall + (int64_t)mode * p * p;
   // LDS: column c holds L[c..p-1, c] at offset c p - c (c - 1) / 2; global:
   // column c of the column-major L starts at c p + c.  Either way Lc[i - c] = L[i, c].
+  const int packed = p * (p + 1) / 2;
   if (LDS) {
     for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
       const int c = e / p, i = e - c * p;
       if (i >= c) sht[c * p - c * (c - 1) / 2 + (i - c)] = L[e];
     }
+    for (int c = threadIdx.x; c < p; c += blockDim.x) sht[packed + c] = 1.0 / L[(int64_t)c * p + c];
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -297,7 +406,7 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
       const int c = 64 * u + cc;
       if (c >= p) break;
       const double* Lc = LDS ? sht + c * p - c * (c - 1) / 2 : L + (int64_t)c * p + c;
-      const double x = __shfl(y[u], cc) / Lc[0];
+      const double x = LDS ? readlane_f64(y[u], cc) * sht[packed + c] : readlane_f64(y[u], cc) / Lc[0];
       if (lane == cc) y[u] = x;
       if (lane > cc) {
         const int i = 64 * u + lane;
@@ -325,6 +434,14 @@ static void allow_lds(const void* fn, size_t bytes) {
 
 void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit, int* fail,
                  hipStream_t s) {
+  if (p <= 64) {
+    hipLaunchKernelGGL(chol_reg_kernel<4>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail);
+    return;
+  }
+  if (p <= 128) {
+    hipLaunchKernelGGL(chol_reg_kernel<8>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail);
+    return;
+  }
   const size_t bytes = (size_t)p * p * sizeof(double);
   if (bytes + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)chol_kernel<true>, bytes);
@@ -351,7 +468,7 @@ static void trsm_launch(double* Y, const double* L, int64_t n, int p, int modes,
 
 void launch_trsm_rows(double* Y, const double* L, int64_t n, int p, int modes, int lds_limit,
                       hipStream_t s) {
-  const size_t bytes = (size_t)p * (p + 1) / 2 * sizeof(double);
+  const size_t bytes = ((size_t)p * (p + 1) / 2 + (size_t)p) * sizeof(double);
   const bool lds = bytes + 1024 <= (size_t)lds_limit;
   if (p <= 64) trsm_launch<1>(Y, L, n, p, modes, bytes, lds, s);
   else if (p <= 128) trsm_launch<2>(Y, L, n, p, modes, bytes, lds, s);
@@ -391,18 +508,21 @@ void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uin
   hipLaunchKernelGGL(perturb_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, G, n, p, seed);
 }
 
-// ---- dense symmetric eigensolver: tridiagonalisation + implicit QR -------------
-// One workgroup per mode computes B = V diag(lambda) V^T for the p x p
-// Rayleigh-Ritz matrix:
-//  1. Householder tridiagonalisation Q^T B Q = T (Golub & Van Loan, Alg. 8.3.1);
-//     the Householder vectors are kept below the subdiagonal of B.
-//  2. Implicit symmetric QR steps with the Wilkinson shift on T (GVL Alg. 8.3.2,
-//     8.3.3), deflating negligible off-diagonal entries; thread 0 chases the
-//     bulge of one QR step and records its Givens rotations, then every thread
-//     applies them to its rows of Z (a sliding window along the row).
-//  3. Back-transformation V = Q Z, one thread per column (columns independent).
-// B and Z live in LDS when p x p FP64 fits (Z reuses B's space after the
-// Householder vectors are copied out), else in global memory.
+// ---- dense symmetric eigensolver: tridiagonalisation, bisection, inverse iteration --
+// B (p x p per mode) = W diag(lambda) W^T in four launches:
+//  1. Householder tridiagonalisation Q^T B Q = T (Golub & Van Loan, Alg. 8.3.1),
+//     one workgroup per mode; the Householder vectors are kept for step 4.
+//  2. Eigenvalues of T by multisection on Sturm counts (Golub & Van Loan, Sec. 8.4.1),
+//     one wave per eigenvalue: each lane counts at one of 64 interior points,
+//     so the bracket shrinks 65-fold per round; eigenvalues come out sorted
+//     descending and accurate to a few u ||T||.
+//  3. Eigenvectors of T by inverse iteration (Golub & Van Loan, Sec. 8.2.2), one
+//     thread per wanted eigenvector, three solves with T - lambda I from a
+//     hashed start vector.
+//  4. (by the caller) Cholesky QR of the vectors in eigenvalue order, which
+//     also separates eigenvectors of near-equal eigenvalues; then
+//  5. back-transformation W = H_0 H_1 ... H_{p-3} Z, one wave per column.
+// Only the rc leading eigenvectors are formed (those the rank rule can keep).
 constexpr int ES_THREADS = 256;
 
 __device__ double es_block_sum(double v, double* red) {
@@ -415,35 +535,197 @@ __device__ double es_block_sum(double v, double* red) {
   return s;
 }
 
+// Per-mode workspace (doubles): Householder vectors p x p (column k, rows
+// k+2..p-1), betas p, d p, e p, lambda p, then the inverse-iteration scratch:
+// multipliers p x rc and reciprocal pivots p x rc (row-major, thread j owns
+// column j so that a wave touches consecutive words).  The vectors Z live in
+// their own array, p x rc row-major per mode.
+struct EigWs {
+  double *hv, *beta, *d, *e, *lam, *lm, *ru;
+  __host__ __device__ EigWs(double* base, int p, int rc, int mode) {
+    const int64_t per = (int64_t)p * p + 4 * (int64_t)p + 2 * (int64_t)p * rc;
+    double* b = base + mode * per;
+    hv = b;
+    beta = hv + (int64_t)p * p;
+    d = beta + p;
+    e = d + p;
+    lam = e + p;
+    lm = lam + p;
+    ru = lm + (int64_t)p * rc;
+  }
+};
+
+size_t eig_sym_workspace_bytes(int p, int rc, int modes) {
+  return (size_t)modes * ((size_t)p * p + 4 * (size_t)p + 2 * (size_t)p * rc) * sizeof(double);
+}
+
+__device__ __forceinline__ double sum16(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  return v;
+}
+
+// Householder tridiagonalisation with B in registers, for p <= 16 RT: thread
+// (tx, ty) of a 16 x 16 grid holds B[i, j] for i = tx + 16 a, j = ty + 16 b.
+// Step k: the 16 threads holding column k form the Householder vector and
+// publish it in LDS; every thread multiplies its block by v, partial sums
+// are combined over the ty lanes of a wave and then over the 4 waves in LDS
+// (two barriers per step, double-buffered); each thread then applies the
+// rank-2 update B22 -= v w^T + w v^T to its own entries.
+template <int RT>
+__global__ __launch_bounds__(256) void tridiag_reg_kernel(const double* __restrict__ Ball,
+                                                          double* __restrict__ ws, int p, int rc) {
+  __shared__ double vb[2][16 * RT];
+  __shared__ double part[2][4][16 * RT];
+  __shared__ double beta_s[2];
+  const int mode = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const double* Bg = Ball + (int64_t)mode * p * p;
+  EigWs W(ws, p, rc, mode);
+  double c[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tx + 16 * a, j = ty + 16 * b;
+      c[a][b] = (i < p && j < p) ? Bg[(int64_t)i * p + j] : 0.0;
+    }
+  for (int x = tid; x < p; x += 256) {
+    W.e[x] = 0.0;
+    W.beta[x] = 0.0;
+  }
+  __syncthreads();   // the zero fill lands before the steps write d, e, beta
+  for (int k = 0; k + 2 < p; ++k) {
+    const int s = k & 1;
+    const int kb = k >> 4;
+    if (ty == (k & 15)) {
+      double xs[RT];
+      double ss = 0.0, x1 = 0.0, dk = 0.0;
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        xs[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b < RT; ++b)
+          if (b == kb) xs[a] = c[a][b];
+        const int i = tx + 16 * a;
+        if (i >= k + 2 && i < p) ss += xs[a] * xs[a];
+        if (i == k + 1) x1 = xs[a];
+        if (i == k) dk = xs[a];
+      }
+      const double sigma = sum16(ss);
+      x1 = sum16(x1);
+      dk = sum16(dk);
+      double beta = 0.0, v1 = 1.0, sub = x1;
+      if (sigma > 0.0) {
+        const double mu = sqrt(x1 * x1 + sigma);
+        v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
+        beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        sub = mu;
+      }
+      const double inv1 = 1.0 / v1;
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const int i = tx + 16 * a;
+        if (i < p) {
+          const double v = i == k + 1 ? 1.0 : (i >= k + 2 ? xs[a] * inv1 : 0.0);
+          vb[s][i] = v;
+          if (i >= k + 2) W.hv[(int64_t)k * p + i] = v;
+        }
+      }
+      if (tx == 0) {
+        beta_s[s] = beta;
+        W.d[k] = dk;
+        W.e[k] = sub;
+        W.beta[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double beta = beta_s[s];
+    if (beta == 0.0) continue;   // uniform: column already reduced
+    double vi[RT], vj[RT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tx + 16 * a;
+      vi[a] = (i > k && i < p) ? vb[s][i] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int j = ty + 16 * b;
+      vj[b] = (j > k && j < p) ? vb[s][j] : 0.0;
+    }
+    double pr[RT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < RT; ++b) acc = fma(c[a][b], vj[b], acc);
+      acc += __shfl_xor(acc, 16);
+      acc += __shfl_xor(acc, 32);
+      pr[a] = acc;
+    }
+    if ((ty & 3) == 0)
+#pragma unroll
+      for (int a = 0; a < RT; ++a) part[s][ty >> 2][tx + 16 * a] = pr[a];
+    __syncthreads();
+    double wi[RT], wj[RT];
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tx + 16 * a;
+      const double w = beta * ((part[s][0][i] + part[s][1][i]) + (part[s][2][i] + part[s][3][i]));
+      wi[a] = (i > k && i < p) ? w : 0.0;
+      t = fma(wi[a], vi[a], t);
+    }
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int j = ty + 16 * b;
+      const double w = beta * ((part[s][0][j] + part[s][1][j]) + (part[s][2][j] + part[s][3][j]));
+      wj[b] = (j > k && j < p) ? w : 0.0;
+    }
+    const double kc = 0.5 * beta * sum16(t);
+#pragma unroll
+    for (int a = 0; a < RT; ++a) wi[a] = fma(-kc, vi[a], wi[a]);
+#pragma unroll
+    for (int b = 0; b < RT; ++b) wj[b] = fma(-kc, vj[b], wj[b]);
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < RT; ++b) c[a][b] -= vi[a] * wj[b] + wi[a] * vj[b];
+  }
+  // trailing 2 x 2 block
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tx + 16 * a, j = ty + 16 * b;
+      if (p >= 2 && i == p - 2 && j == p - 2) W.d[p - 2] = c[a][b];
+      if (p >= 2 && i == p - 1 && j == p - 2) W.e[p - 2] = c[a][b];
+      if (i == p - 1 && j == p - 1) W.d[p - 1] = c[a][b];
+    }
+}
+
 template <bool LDS>
-__global__ __launch_bounds__(ES_THREADS) void eig_sym_kernel(double* __restrict__ Ball,
-                                                             double* __restrict__ Vall,
-                                                             double* __restrict__ HVall, int p,
-                                                             int* __restrict__ fail,
-                                                             double* __restrict__ profall) {
+__global__ __launch_bounds__(ES_THREADS) void tridiag_kernel(double* __restrict__ Ball,
+                                                             double* __restrict__ ws, int p,
+                                                             int rc) {
   extern __shared__ double sh[];
   __shared__ double red[ES_THREADS / 64];
-  __shared__ double v1_s, kc_s;
-  __shared__ int lo_s, hi_s, done_s;
+  __shared__ double v1_s;
   const int mode = blockIdx.x;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   double* Bg = Ball + (int64_t)mode * p * p;
-  double* Vg = Vall + (int64_t)mode * p * p;
-  double* HV = HVall + (int64_t)mode * ((int64_t)p * p + p);   // p x p vectors + p betas
+  EigWs W(ws, p, rc, mode);
   const int ldb = LDS ? p + 1 : p;                              // padded against bank conflicts
   double* B = LDS ? sh : Bg;                                    // row-major B(i, j) = B[i ldb + j]
-  double* vec = LDS ? sh + (int64_t)p * (p + 1) : sh;           // 6 p doubles after Z's padded extent
-  double* d = vec;
-  double* e = vec + p;
-  double* pw = vec + 2 * p;
-  double* cs = vec + 3 * p;
-  double* sn = vec + 4 * p;
-  double* betas = vec + 5 * p;
+  double* pw = LDS ? sh + (int64_t)p * (p + 1) : sh;            // p doubles
+  double* d = W.d;
+  double* e = W.e;
+  double* betas = W.beta;
   const int pp = p * p;
-  // wall-clock stamps (constant-rate counter) at the phase boundaries, when asked
-  double* prof = profall ? profall + 4 * mode : nullptr;
-  if (prof && tid == 0) prof[0] = (double)wall_clock64();
   if (LDS)
     for (int x = tid; x < pp; x += ES_THREADS) {
       const int i = x / p, j = x - i * p;
@@ -455,7 +737,6 @@ __global__ __launch_bounds__(ES_THREADS) void eig_sym_kernel(double* __restrict_
   }
   __syncthreads();
 
-  // 1. tridiagonalisation
   for (int k = 0; k + 2 < p; ++k) {
     double part = 0.0;
     for (int i = k + 2 + tid; i < p; i += ES_THREADS) part += B[i * ldb + k] * B[i * ldb + k];
@@ -517,175 +798,281 @@ __global__ __launch_bounds__(ES_THREADS) void eig_sym_kernel(double* __restrict_
       e[p - 2] = B[(p - 1) * ldb + (p - 2)];
     }
     d[p - 1] = B[(p - 1) * ldb + (p - 1)];
+    e[p - 1] = 0.0;
   }
-  // Householder vectors out of the way (column k, rows k+2..p-1; kept in HV)
   for (int x = tid; x < pp; x += ES_THREADS) {
     const int i = x / p, k = x - i * p;
-    if (i >= k + 2) HV[(int64_t)k * p + i] = B[i * ldb + k];
-  }
-  for (int x = tid; x < p; x += ES_THREADS) HV[(int64_t)pp + x] = betas[x];
-  __syncthreads();
-
-  if (prof && tid == 0) prof[1] = (double)wall_clock64();
-  // 2. Z = I, row-major with padded stride
-  const int ldz = LDS ? p + 1 : p;
-  double* Z = LDS ? sh : Vg;
-  for (int x = tid; x < p * ldz; x += ES_THREADS) {
-    const int i = x / ldz, j = x - i * ldz;
-    Z[x] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-
-  // 3. implicit symmetric QR with Wilkinson shifts
-  const double eps = 1.1102230246251565e-16;
-  int hi = p - 1;
-  int iters = 0;
-  for (;;) {
-    if (tid == 0) {
-      int done = 0;
-      while (hi > 0 && fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
-        e[hi - 1] = 0.0;
-        --hi;
-      }
-      if (hi == 0 || iters > 30 * p) {
-        if (hi > 0) atomicOr(fail, 2);
-        done = 1;
-      } else {
-        int lo = hi - 1;
-        while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
-        if (lo > 0) e[lo - 1] = 0.0;
-        // Wilkinson shift from the trailing 2 x 2 block
-        const double bb = e[hi - 1];
-        const double dd = 0.5 * (d[hi - 1] - d[hi]);
-        const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * sqrt(dd * dd + bb * bb);
-        const double mu = den != 0.0 ? d[hi] - bb * bb / den : d[hi];
-        double x = d[lo] - mu, z = e[lo];
-        // carried in registers: a = current d[k], bk = current e[k]; the
-        // untouched d[k+1], e[k+1] are read one step ahead
-        double a = d[lo], bk = e[lo];
-        double dn = d[lo + 1], en = (lo + 1 < hi) ? e[lo + 1] : 0.0;
-        for (int k = lo; k < hi; ++k) {
-          const double ak1 = dn, ek1 = en;
-          if (k + 2 <= hi) dn = d[k + 2];
-          if (k + 2 < hi) en = e[k + 2];
-          const double q2 = x * x + z * z;
-          double c = 1.0, s = 0.0, r = 0.0;
-          if (q2 > 0.0) {
-            const double ri = rsqrt(q2);
-            c = x * ri;
-            s = z * ri;
-            r = q2 * ri;
-          }
-          if (k > lo) e[k - 1] = r;
-          const double cc = c * c, ss = s * s, cs2 = 2.0 * c * s * bk;
-          d[k] = cc * a + cs2 + ss * ak1;
-          const double dk1 = ss * a - cs2 + cc * ak1;
-          const double ek = c * s * (ak1 - a) + (cc - ss) * bk;
-          e[k] = ek;
-          a = dk1;
-          if (k + 1 < hi) {
-            x = ek;
-            z = s * ek1;
-            bk = c * ek1;
-          }
-          cs[k] = c;
-          sn[k] = s;
-        }
-        d[hi] = a;
-        lo_s = lo;
-        hi_s = hi;
-        ++iters;
-      }
-      done_s = done;
-    }
-    __syncthreads();
-    if (done_s) break;
-    const int lo = lo_s, h = hi_s;
-    for (int row = tid; row < p; row += ES_THREADS) {
-      double* zr = Z + (int64_t)row * ldz;
-      double zc = zr[lo];
-      for (int k = lo; k < h; ++k) {
-        const double zn = zr[k + 1];
-        const double c = cs[k], s = sn[k];
-        zr[k] = c * zc + s * zn;
-        zc = -s * zc + c * zn;
-      }
-      zr[h] = zc;
-    }
-    __syncthreads();
-  }
-
-  if (prof && tid == 0) prof[2] = (double)wall_clock64();
-  // 4. back-transformation Z <- H_0 H_1 ... H_{p-3} Z: v_k staged in LDS,
-  //    one thread per column
-  double* vk = pw;
-  double* part_lo = cs;   // partial dots over the lower half of the rows (cs, sn are free now)
-  double* part_hi = sn;   // partial dots over the upper half
-  for (int k = p - 3; k >= 0; --k) {
-    const double beta = HV[(int64_t)pp + k];   // uniform
-    if (beta == 0.0) continue;
-    for (int i = k + 1 + tid; i < p; i += ES_THREADS)
-      vk[i] = i == k + 1 ? 1.0 : HV[(int64_t)k * p + i];
-    __syncthreads();
-    const int mid = (k + 1 + p) / 2;
-    // thread t < 128 sums rows [k+1, mid), thread t + 128 rows [mid, p) of column t
-    for (int col = tid & 127; col < p; col += 128) {
-      const int i0 = tid < 128 ? k + 1 : mid, i1 = tid < 128 ? mid : p;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int i = i0;
-      for (; i + 3 < i1; i += 4) {
-        s0 += vk[i] * Z[(int64_t)i * ldz + col];
-        s1 += vk[i + 1] * Z[(int64_t)(i + 1) * ldz + col];
-        s2 += vk[i + 2] * Z[(int64_t)(i + 2) * ldz + col];
-        s3 += vk[i + 3] * Z[(int64_t)(i + 3) * ldz + col];
-      }
-      for (; i < i1; ++i) s0 += vk[i] * Z[(int64_t)i * ldz + col];
-      if (tid >= 128) part_hi[col] = (s0 + s1) + (s2 + s3);
-      else part_lo[col] = (s0 + s1) + (s2 + s3);
-    }
-    __syncthreads();
-    for (int col = tid & 127; col < p; col += 128) {
-      const double dot = beta * (part_lo[col] + part_hi[col]);
-      const int i0 = tid < 128 ? k + 1 : mid, i1 = tid < 128 ? mid : p;
-      for (int i = i0; i < i1; ++i) Z[(int64_t)i * ldz + col] -= dot * vk[i];
-    }
-    __syncthreads();
-  }
-  if (prof && tid == 0) prof[3] = (double)wall_clock64();
-  // 5. eigenvalues on the diagonal of B, eigenvectors to V (column-major)
-  for (int x = tid; x < p; x += ES_THREADS) Bg[(int64_t)x * p + x] = d[x];
-  if (LDS) {
-    for (int x = tid; x < pp; x += ES_THREADS) {
-      const int c = x / p, r = x - c * p;
-      Vg[x] = Z[(int64_t)r * ldz + c];
-    }
-  } else {
-    // Z (row-major) is in Vg: transpose in place to column-major
-    __syncthreads();
-    for (int x = tid; x < pp; x += ES_THREADS) {
-      const int r = x / p, c = x - r * p;
-      if (c > r) {
-        const double a = Vg[(int64_t)r * p + c], b2 = Vg[(int64_t)c * p + r];
-        Vg[(int64_t)r * p + c] = b2;
-        Vg[(int64_t)c * p + r] = a;
-      }
-    }
+    if (i >= k + 2) W.hv[(int64_t)k * p + i] = B[i * ldb + k];
   }
 }
 
-void launch_eig_sym(double* B, double* V, double* HV, int p, int modes, int lds_limit, int* fail,
-                    double* prof, hipStream_t s) {
-  const size_t lds_bytes = ((size_t)p * (p + 1) + 6 * (size_t)p) * sizeof(double);
-  if (lds_bytes + 1024 <= (size_t)lds_limit) {
-    allow_lds((const void*)eig_sym_kernel<true>, lds_bytes);
-    hipLaunchKernelGGL(eig_sym_kernel<true>, dim3(modes), dim3(ES_THREADS), lds_bytes, s, B, V, HV,
-                       p, fail, prof);
-  } else {
-    const size_t bytes = 6 * (size_t)p * sizeof(double);
-    allow_lds((const void*)eig_sym_kernel<false>, bytes);
-    hipLaunchKernelGGL(eig_sym_kernel<false>, dim3(modes), dim3(ES_THREADS), bytes, s, B, V, HV, p,
-                       fail, prof);
+// Number of eigenvalues of T below x (Sturm count on the LDL^T pivots of
+// T - x I), with tiny pivots replaced by -pivmin.
+__device__ __forceinline__ int sturm_count(const double* d, const double* ee, int p, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  int c = q < 0.0;
+  for (int i = 1; i < p; ++i) {
+    q = (d[i] - x) - ee[i - 1] / q;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    c += q < 0.0;
   }
+  return c;
+}
+
+constexpr int BIS_WAVES = 4;
+
+__global__ __launch_bounds__(64 * BIS_WAVES) void bisect_kernel(double* __restrict__ Ball,
+                                                                double* __restrict__ ws, int p,
+                                                                int rc) {
+  extern __shared__ double shb[];
+  const int mode = blockIdx.y;
+  EigWs W(ws, p, rc, mode);
+  double* d = shb;
+  double* ee = shb + p;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    d[i] = W.d[i];
+    ee[i] = W.e[i] * W.e[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * BIS_WAVES + (threadIdx.x >> 6);   // j-th largest eigenvalue
+  if (j >= p) return;
+  // Gershgorin interval and pivot floor, reduced over the wave
+  double gl = HUGE_VAL, gu = -HUGE_VAL, emax = 0.0;
+  for (int i = lane; i < p; i += 64) {
+    const double r = (i > 0 ? fabs(W.e[i - 1]) : 0.0) + (i + 1 < p ? fabs(W.e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+    emax = fmax(emax, ee[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, off));
+    gu = fmax(gu, __shfl_xor(gu, off));
+    emax = fmax(emax, __shfl_xor(emax, off));
+  }
+  const double u = 1.1102230246251565e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
+  const double tn = fmax(fabs(gl), fabs(gu));
+  const double pad = 2.0 * u * tn * (double)p + 2.0 * pivmin;
+  double lo = gl - pad, hi = gu + pad;
+  const int m = p - 1 - j;   // ascending index: count(x) <= m below lambda_m, > m above
+  const double tol = 4.0 * u * tn + 2.0 * pivmin;
+  for (int round = 0; round < 24 && hi - lo > tol; ++round) {
+    const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+    const int c = sturm_count(d, ee, p, x, pivmin);
+    const uint64_t above = __ballot(c > m);
+    if (above == 0) {
+      lo = __shfl(x, 63);
+    } else {
+      const int f = __ffsll((unsigned long long)above) - 1;
+      const double xf = __shfl(x, f);
+      const double xb = __shfl(x, f > 0 ? f - 1 : 0);
+      if (f > 0) lo = xb;
+      hi = xf;
+    }
+  }
+  if (lane == 0) {
+    const double lam = 0.5 * (lo + hi);
+    W.lam[j] = lam;
+    Ball[(int64_t)mode * p * p + (int64_t)j * p + j] = lam;
+  }
+}
+
+// Thread j < rc: z_j solves (T - lambda_j I)^3 z = hashed start vector, with
+// the pivots of the LU factorisation (no pivoting) kept away from zero by
+// u ||T||; each solve is rescaled by its largest entry; final unit norm.
+// The recurrences run over chunks of IC rows whose loads are issued before
+// the chunk's dependent chain, so each chunk waits on memory once.
+constexpr int IC = 16;
+
+__global__ __launch_bounds__(256) void invit_kernel(double* __restrict__ ws,
+                                                    double* __restrict__ Zall, int p, int rc,
+                                                    uint64_t seed) {
+  const int mode = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= rc) return;
+  EigWs W(ws, p, rc, mode);
+  const double lam = W.lam[j];
+  const double u = 1.1102230246251565e-16;
+  const double tiny = u * fmax(fmax(fabs(W.lam[0]), fabs(W.lam[p - 1])), 1e-280);
+  const double* __restrict__ dg = W.d;
+  const double* __restrict__ eg = W.e;
+  double* __restrict__ lm = W.lm + j;
+  double* __restrict__ ru = W.ru + j;
+  double* __restrict__ z = Zall + (int64_t)mode * p * rc + j;
+  const int64_t ld = rc;
+  // LU of T - lambda I: u_0 = d_0 - lambda, l_i = e_{i-1} / u_{i-1},
+  // u_i = d_i - lambda - l_i e_{i-1}; the reciprocal pivots are stored
+  double rprev = 0.0;
+  for (int i0 = 0; i0 < p; i0 += IC) {
+    double dd[IC], ee[IC], ll[IC], rr[IC];
+#pragma unroll
+    for (int c = 0; c < IC; ++c) {
+      const int i = i0 + c;
+      dd[c] = i < p ? dg[i] : 0.0;
+      ee[c] = (i > 0 && i < p) ? eg[i - 1] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < IC; ++c) {
+      const double l = ee[c] * rprev;
+      double up = (dd[c] - lam) - l * ee[c];
+      if (fabs(up) < tiny) up = up < 0.0 ? -tiny : tiny;
+      rprev = 1.0 / up;
+      ll[c] = l;
+      rr[c] = rprev;
+    }
+#pragma unroll
+    for (int c = 0; c < IC; ++c) {
+      const int i = i0 + c;
+      if (i < p) {
+        lm[i * ld] = ll[c];
+        ru[i * ld] = rr[c];
+        z[i * ld] = hash_uniform(seed + mode, (uint64_t)j, (uint64_t)i);
+      }
+    }
+  }
+  double scale = 1.0;
+  const int last = ((p - 1) / IC) * IC;   // start of the last chunk
+  for (int it = 0; it < 3; ++it) {
+    // forward: L y = scale z (l_0 = 0)
+    double prev = 0.0;
+    for (int i0 = 0; i0 < p; i0 += IC) {
+      double zz[IC], ll[IC];
+#pragma unroll
+      for (int c = 0; c < IC; ++c) {
+        const int i = i0 + c;
+        zz[c] = i < p ? z[i * ld] : 0.0;
+        ll[c] = i < p ? lm[i * ld] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < IC; ++c) {
+        prev = scale * zz[c] - ll[c] * prev;
+        zz[c] = prev;
+      }
+#pragma unroll
+      for (int c = 0; c < IC; ++c) {
+        const int i = i0 + c;
+        if (i < p) z[i * ld] = zz[c];
+      }
+    }
+    // backward: U x = y, U = upper bidiagonal (u_i, e_i), e_{p-1} = 0
+    double nxt = 0.0, mx = 0.0;
+    for (int i0 = last; i0 >= 0; i0 -= IC) {
+      double zz[IC], rr[IC], ee[IC];
+#pragma unroll
+      for (int c = 0; c < IC; ++c) {
+        const int i = i0 + c;
+        zz[c] = i < p ? z[i * ld] : 0.0;
+        rr[c] = i < p ? ru[i * ld] : 0.0;
+        ee[c] = i < p ? eg[i] : 0.0;
+      }
+#pragma unroll
+      for (int c = IC - 1; c >= 0; --c) {
+        if (i0 + c < p) {
+          nxt = (zz[c] - ee[c] * nxt) * rr[c];
+          zz[c] = nxt;
+          mx = fmax(mx, fabs(nxt));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < IC; ++c) {
+        const int i = i0 + c;
+        if (i < p) z[i * ld] = zz[c];
+      }
+    }
+    scale = mx > 0.0 ? 1.0 / mx : 1.0;
+  }
+  double nrm = 0.0;
+  for (int i = 0; i < p; ++i) {
+    const double v = scale * z[i * ld];
+    nrm += v * v;
+  }
+  const double s = nrm > 0.0 ? scale / sqrt(nrm) : 0.0;
+  for (int i = 0; i < p; ++i) z[i * ld] *= s;
+}
+
+// Z (p x rc row-major per mode) <- H_0 H_1 ... H_{p-3} Z, H_k = I - beta_k v_k v_k^T:
+// one wave per column, the column in registers (lane l keeps rows l, l + 64, ...).
+template <int UPL>
+__global__ __launch_bounds__(256) void reflect_cols_kernel(double* __restrict__ Zall,
+                                                           double* __restrict__ ws, int p,
+                                                           int rc) {
+  const int mode = blockIdx.y;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= rc) return;
+  EigWs W(ws, p, rc, mode);
+  double* Z = Zall + (int64_t)mode * p * rc + col;
+  double y[UPL];
+#pragma unroll
+  for (int u = 0; u < UPL; ++u) {
+    const int i = lane + 64 * u;
+    y[u] = i < p ? Z[(int64_t)i * rc] : 0.0;
+  }
+  for (int k = p - 3; k >= 0; --k) {
+    const double beta = W.beta[k];
+    if (beta == 0.0) continue;
+    const double* v = W.hv + (int64_t)k * p;
+    double vv[UPL];
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < UPL; ++u) {
+      const int i = lane + 64 * u;
+      vv[u] = i == k + 1 ? 1.0 : ((i >= k + 2 && i < p) ? v[i] : 0.0);
+      part = fma(vv[u], y[u], part);
+    }
+    const double dot = beta * wave_sum(part);
+#pragma unroll
+    for (int u = 0; u < UPL; ++u) y[u] = fma(-dot, vv[u], y[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < UPL; ++u) {
+    const int i = lane + 64 * u;
+    if (i < p) Z[(int64_t)i * rc] = y[u];
+  }
+}
+
+void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds_limit,
+                        hipStream_t s) {
+  if (p <= 64) {
+    hipLaunchKernelGGL(tridiag_reg_kernel<4>, dim3(modes), dim3(256), 0, s, B, ws, p, rc);
+    return;
+  }
+  if (p <= 128) {
+    hipLaunchKernelGGL(tridiag_reg_kernel<8>, dim3(modes), dim3(256), 0, s, B, ws, p, rc);
+    return;
+  }
+  const size_t tri_lds = ((size_t)p * (p + 1) + (size_t)p) * sizeof(double);
+  if (tri_lds + 1024 <= (size_t)lds_limit) {
+    allow_lds((const void*)tridiag_kernel<true>, tri_lds);
+    hipLaunchKernelGGL(tridiag_kernel<true>, dim3(modes), dim3(ES_THREADS), tri_lds, s, B, ws, p,
+                       rc);
+  } else {
+    const size_t bytes = (size_t)p * sizeof(double);
+    hipLaunchKernelGGL(tridiag_kernel<false>, dim3(modes), dim3(ES_THREADS), bytes, s, B, ws, p,
+                       rc);
+  }
+}
+
+void launch_eig_values_vectors(double* B, double* ws, double* Z, int p, int rc, int modes,
+                               hipStream_t s) {
+  if (rc < 1 || rc > p) throw Error{RS_E_INVALID, "eigensolver: wanted vectors outside [1, p]"};
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((p + BIS_WAVES - 1) / BIS_WAVES), modes),
+                     dim3(64 * BIS_WAVES), 2 * (size_t)p * sizeof(double), s, B, ws, p, rc);
+  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((rc + 255) / 256), modes), dim3(256), 0, s, ws,
+                     Z, p, rc, 0x1a2b3c4d5e6fULL);
+}
+
+void launch_eig_backtransform(double* Z, double* ws, int p, int rc, int modes, hipStream_t s) {
+  const dim3 grid((unsigned)((rc + 3) / 4), modes);
+  if (p <= 64) hipLaunchKernelGGL(reflect_cols_kernel<1>, grid, dim3(256), 0, s, Z, ws, p, rc);
+  else if (p <= 128) hipLaunchKernelGGL(reflect_cols_kernel<2>, grid, dim3(256), 0, s, Z, ws, p, rc);
+  else if (p <= 256) hipLaunchKernelGGL(reflect_cols_kernel<4>, grid, dim3(256), 0, s, Z, ws, p, rc);
+  else if (p <= 512) hipLaunchKernelGGL(reflect_cols_kernel<8>, grid, dim3(256), 0, s, Z, ws, p, rc);
+  else if (p <= 1024) hipLaunchKernelGGL(reflect_cols_kernel<16>, grid, dim3(256), 0, s, Z, ws, p, rc);
+  else throw Error{RS_E_UNSUPPORTED, "eigensolver subspace above 1024"};
 }
 
 }  // namespace rs

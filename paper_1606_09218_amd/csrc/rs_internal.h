@@ -102,9 +102,12 @@ struct rs_tensor {
   rs::DevBuf brick_list;         // n_pairs particle indices
   // stage timing: events[k] recorded before stage k, events[RS_STAGE_COUNT] at the end
   std::vector<hipEvent_t> events;
-  double eig_phase_ms[3] = {0, 0, 0};  // tridiagonalisation, QR iteration, back-transformation
+  // eigensolver phases: eig_events[k] before phase k, eig_events[RS_EIG_PHASES] at the end
+  std::vector<hipEvent_t> eig_events;
   ~rs_tensor() {
     for (hipEvent_t e : events)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : eig_events)
       if (e) (void)hipEventDestroy(e);
   }
 };
@@ -159,12 +162,20 @@ void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int ld
 // Y (n x p row-major per mode) <- Y L^{-T}
 void launch_trsm_rows(double* Y, const double* L, int64_t n, int p, int modes, int lds_limit,
                       hipStream_t s);
-// Dense symmetric eigensolver of B (p x p per mode): eigenvalues written to
-// the diagonal of B, eigenvectors to V (p x p col-major).  HV is scratch of
-// 3 (p p + p) doubles.  fail |= 2 if the QR iteration does not converge.
-// prof (or null): 4 wall-clock stamps per mode at the phase boundaries.
-void launch_eig_sym(double* B, double* V, double* HV, int p, int modes, int lds_limit, int* fail,
-                    double* prof, hipStream_t s);
+// Dense symmetric eigensolver of B (p x p per mode), in steps so that the
+// caller can orthonormalise the eigenvectors with its Cholesky QR:
+//  tridiag: B = H T H^T (Householder vectors and d, e into ws);
+//  values_vectors: eigenvalues of T (descending) onto the diagonal of B and
+//    into ws; the rc leading eigenvectors of T by inverse iteration into Z
+//    (p x rc row-major per mode, unit columns, not yet orthogonal);
+//  backtransform: Z <- H Z.
+// ws is scratch of eig_sym_workspace_bytes(p, rc, modes).
+size_t eig_sym_workspace_bytes(int p, int rc, int modes);
+void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds_limit,
+                        hipStream_t s);
+void launch_eig_values_vectors(double* B, double* ws, double* Z, int p, int rc, int modes,
+                               hipStream_t s);
+void launch_eig_backtransform(double* Z, double* ws, int p, int rc, int modes, hipStream_t s);
 // Sort eigenvalues descending, choose ranks; writes perm[mode][p], info doubles.
 struct RankInfo {
   int r[3];
@@ -175,7 +186,7 @@ void launch_rank_select(const double* B, int p, int modes, double eps2, const in
                         int r_max, int* perm, RankInfo* info_dev, hipStream_t s);
 // Qout (n x r row-major) = Q0 (n x p col-major) * V[:, perm[0..r)], then
 // canonical signs (largest-magnitude entry of each column positive).
-void launch_gather_cols(const double* V, const int* perm, int p, int r, double* Wr,
+void launch_gather_cols(const double* Z, int ldz, const int* perm, int p, int r, double* Wr,
                         hipStream_t s);
 void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s);
 

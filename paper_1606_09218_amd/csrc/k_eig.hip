@@ -267,8 +267,51 @@ __global__ __launch_bounds__(CF_THREADS) void chol_kernel(double* __restrict__ C
 // Cholesky factorisation with the matrix in registers, for p <= 16 RT: a
 // 16 x 16 thread grid, thread (tx, ty) holds C[i, j] for i = tx + 16 a,
 // j = ty + 16 b.  Step k: the threads holding column k publish it in LDS
-// (double-buffered, one barrier per step), every thread scales it by
-// 1/sqrt(pivot) and applies the rank-1 update to its own entries.
+// (rows above k as zeros; double-buffered, one barrier per step), every
+// thread applies the rank-1 update with l = c_k / c_kk to its entries on
+// or below the diagonal, and wave 0 writes column k of L.  The steps are
+// grouped by the column block KB = k / 16, a compile-time constant, so that
+// finished blocks are skipped without branches and the owning registers
+// are addressed statically.
+template <int RT, int KB>
+__device__ __forceinline__ void chol_reg_steps(double (&c)[RT][RT], double (&colk)[2][16 * RT],
+                                               double* __restrict__ C, int p, int tx, int ty,
+                                               int tid, bool& bad) {
+  if constexpr (KB < RT) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * KB + kk;
+      if (k >= p) return;
+      double* cb = colk[k & 1];
+      if (ty == kk) {
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const int i = tx + 16 * a;
+          cb[i] = i >= k ? c[a][KB] : 0.0;
+        }
+      }
+      __syncthreads();
+      double dkk = cb[k];
+      bad |= !(dkk > 0.0);
+      dkk = dkk > 0.0 ? dkk : 1e-300;
+      const double rd = 1.0 / dkk;
+      if (tid < 64) {
+        const double sq = sqrt(dkk), isq = 1.0 / sq;
+        for (int i = k + tid; i < p; i += 64) C[(int64_t)k * p + i] = i == k ? sq : cb[i] * isq;
+      }
+      double li[RT], lj[RT];
+#pragma unroll
+      for (int a = KB; a < RT; ++a) li[a] = cb[tx + 16 * a] * rd;
+#pragma unroll
+      for (int b = KB; b < RT; ++b) lj[b] = cb[ty + 16 * b];
+#pragma unroll
+      for (int a = KB; a < RT; ++a)
+#pragma unroll
+        for (int b = KB; b <= a; ++b) c[a][b] = fma(-li[a], lj[b], c[a][b]);
+    }
+    chol_reg_steps<RT, KB + 1>(c, colk, C, p, tx, ty, tid, bad);
+  }
+}
+
 template <int RT>
 __global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call, int p,
                                                        int64_t nrows, int shifted,
@@ -287,6 +330,7 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call
       const int i = tx + 16 * a, j = ty + 16 * b;
       c[a][b] = (i < p && j < p && i >= j) ? C[(int64_t)j * p + i] : 0.0;
     }
+  for (int x = tid; x < 2 * 16 * RT; x += 256) (&colk[0][0])[x] = 0.0;
   if (shifted) {
     double tr = 0.0;
     if (tx == ty)
@@ -302,61 +346,10 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call
       for (int a = 0; a < RT; ++a)
         if (tx + 16 * a < p) c[a][a] += shift;
   }
-  for (int k = 0; k < p; ++k) {
-    double* cb = colk[k & 1];
-    const int kb = k >> 4;
-    const bool owner = ty == (k & 15);
-    if (owner) {
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b == kb)
-#pragma unroll
-          for (int a = 0; a < RT; ++a) {
-            const int i = tx + 16 * a;
-            if (i >= k && i < p) cb[i] = c[a][b];
-          }
-    }
-    __syncthreads();
-    double dkk = cb[k];
-    if (!(dkk > 0.0)) {
-      if (tid == 0) atomicOr(fail, 1);
-      dkk = 1e-300;
-    }
-    const double sq = sqrt(dkk), isq = 1.0 / sq;
-    double li[RT], lj[RT];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      const int i = tx + 16 * a;
-      li[a] = (i > k && i < p) ? cb[i] * isq : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = ty + 16 * b;
-      lj[b] = (j > k && j < p) ? cb[j] * isq : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < RT; ++a)
-#pragma unroll
-      for (int b = 0; b < RT; ++b) c[a][b] = fma(-li[a], lj[b], c[a][b]);
-    if (owner) {
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b == kb)
-#pragma unroll
-          for (int a = 0; a < RT; ++a) {
-            const int i = tx + 16 * a;
-            if (i > k) c[a][b] = li[a];
-            else if (i == k) c[a][b] = sq;
-          }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tx + 16 * a, j = ty + 16 * b;
-      if (i < p && j < p && i >= j) C[(int64_t)j * p + i] = c[a][b];
-    }
+  __syncthreads();   // all reads of C and the zero fill precede the first step
+  bool bad = false;
+  chol_reg_steps<RT, 0>(c, colk, C, p, tx, ty, tid, bad);
+  if (bad && tid == 0) atomicOr(fail, 1);
 }
 
 // value of lane l (uniform l) of a double held across the wave
@@ -573,13 +566,109 @@ __device__ __forceinline__ double sum16(double v) {
 // publish it in LDS; every thread multiplies its block by v, partial sums
 // are combined over the ty lanes of a wave and then over the 4 waves in LDS
 // (two barriers per step, double-buffered); each thread then applies the
-// rank-2 update B22 -= v w^T + w v^T to its own entries.
+// rank-2 update B22 -= v w^T + w v^T to its own entries.  Steps are grouped
+// by the column block KB = k / 16 (compile time): blocks of rows or columns
+// below KB are finished and skipped.
+struct TriLds {
+  double vb[2][128];
+  double part[2][4][128];
+  double beta[2];
+};
+
+template <int RT, int KB>
+__device__ __forceinline__ void tridiag_reg_steps(double (&c)[RT][RT], TriLds& L, EigWs& W, int p,
+                                                  int tx, int ty) {
+  if constexpr (KB < RT) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * KB + kk;
+      if (k + 2 >= p) return;
+      const int s = k & 1;
+      if (ty == kk) {
+        double ss = 0.0, x1 = 0.0, dk = 0.0;
+#pragma unroll
+        for (int a = KB; a < RT; ++a) {
+          const int i = tx + 16 * a;
+          const double x = c[a][KB];
+          if (i >= k + 2) ss = fma(x, x, ss);   // rows >= p hold zeros
+          if (i == k + 1) x1 = x;
+          if (i == k) dk = x;
+        }
+        const double sigma = sum16(ss);
+        x1 = sum16(x1);
+        dk = sum16(dk);
+        double beta = 0.0, v1 = 1.0, sub = x1;
+        if (sigma > 0.0) {
+          const double mu = sqrt(x1 * x1 + sigma);
+          v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
+          beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+          sub = mu;
+        }
+        const double inv1 = 1.0 / v1;
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const int i = tx + 16 * a;
+          const double v = (a >= KB && i >= k + 2) ? c[a][KB] * inv1 : (i == k + 1 ? 1.0 : 0.0);
+          L.vb[s][i] = v;
+          if (a >= KB && i >= k + 2 && i < p) W.hv[(int64_t)k * p + i] = v;
+        }
+        if (tx == 0) {
+          L.beta[s] = beta;
+          W.d[k] = dk;
+          W.e[k] = sub;
+          W.beta[k] = beta;
+        }
+      }
+      __syncthreads();
+      const double beta = L.beta[s];
+      if (beta == 0.0) continue;   // uniform: column already reduced
+      double vi[RT], vj[RT];
+#pragma unroll
+      for (int a = KB; a < RT; ++a) vi[a] = L.vb[s][tx + 16 * a];
+#pragma unroll
+      for (int b = KB; b < RT; ++b) vj[b] = L.vb[s][ty + 16 * b];
+#pragma unroll
+      for (int a = KB; a < RT; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = KB; b < RT; ++b) acc = fma(c[a][b], vj[b], acc);
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        if ((ty & 3) == 0) L.part[s][ty >> 2][tx + 16 * a] = acc;
+      }
+      __syncthreads();
+      double wi[RT], wj[RT];
+      double t = 0.0;
+#pragma unroll
+      for (int a = KB; a < RT; ++a) {
+        const int i = tx + 16 * a;
+        const double w = beta * ((L.part[s][0][i] + L.part[s][1][i]) + (L.part[s][2][i] + L.part[s][3][i]));
+        wi[a] = (i > k && i < p) ? w : 0.0;
+        t = fma(wi[a], vi[a], t);
+      }
+#pragma unroll
+      for (int b = KB; b < RT; ++b) {
+        const int j = ty + 16 * b;
+        const double w = beta * ((L.part[s][0][j] + L.part[s][1][j]) + (L.part[s][2][j] + L.part[s][3][j]));
+        wj[b] = (j > k && j < p) ? w : 0.0;
+      }
+      const double kc = 0.5 * beta * sum16(t);
+#pragma unroll
+      for (int a = KB; a < RT; ++a) wi[a] = fma(-kc, vi[a], wi[a]);
+#pragma unroll
+      for (int b = KB; b < RT; ++b) wj[b] = fma(-kc, vj[b], wj[b]);
+#pragma unroll
+      for (int a = KB; a < RT; ++a)
+#pragma unroll
+        for (int b = KB; b < RT; ++b) c[a][b] = fma(-vi[a], wj[b], fma(-wi[a], vj[b], c[a][b]));
+    }
+    tridiag_reg_steps<RT, KB + 1>(c, L, W, p, tx, ty);
+  }
+}
+
 template <int RT>
 __global__ __launch_bounds__(256) void tridiag_reg_kernel(const double* __restrict__ Ball,
                                                           double* __restrict__ ws, int p, int rc) {
-  __shared__ double vb[2][16 * RT];
-  __shared__ double part[2][4][16 * RT];
-  __shared__ double beta_s[2];
+  __shared__ TriLds L;
   const int mode = blockIdx.x;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
@@ -598,103 +687,7 @@ __global__ __launch_bounds__(256) void tridiag_reg_kernel(const double* __restri
     W.beta[x] = 0.0;
   }
   __syncthreads();   // the zero fill lands before the steps write d, e, beta
-  for (int k = 0; k + 2 < p; ++k) {
-    const int s = k & 1;
-    const int kb = k >> 4;
-    if (ty == (k & 15)) {
-      double xs[RT];
-      double ss = 0.0, x1 = 0.0, dk = 0.0;
-#pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        xs[a] = 0.0;
-#pragma unroll
-        for (int b = 0; b < RT; ++b)
-          if (b == kb) xs[a] = c[a][b];
-        const int i = tx + 16 * a;
-        if (i >= k + 2 && i < p) ss += xs[a] * xs[a];
-        if (i == k + 1) x1 = xs[a];
-        if (i == k) dk = xs[a];
-      }
-      const double sigma = sum16(ss);
-      x1 = sum16(x1);
-      dk = sum16(dk);
-      double beta = 0.0, v1 = 1.0, sub = x1;
-      if (sigma > 0.0) {
-        const double mu = sqrt(x1 * x1 + sigma);
-        v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
-        beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
-        sub = mu;
-      }
-      const double inv1 = 1.0 / v1;
-#pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        const int i = tx + 16 * a;
-        if (i < p) {
-          const double v = i == k + 1 ? 1.0 : (i >= k + 2 ? xs[a] * inv1 : 0.0);
-          vb[s][i] = v;
-          if (i >= k + 2) W.hv[(int64_t)k * p + i] = v;
-        }
-      }
-      if (tx == 0) {
-        beta_s[s] = beta;
-        W.d[k] = dk;
-        W.e[k] = sub;
-        W.beta[k] = beta;
-      }
-    }
-    __syncthreads();
-    const double beta = beta_s[s];
-    if (beta == 0.0) continue;   // uniform: column already reduced
-    double vi[RT], vj[RT];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      const int i = tx + 16 * a;
-      vi[a] = (i > k && i < p) ? vb[s][i] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = ty + 16 * b;
-      vj[b] = (j > k && j < p) ? vb[s][j] : 0.0;
-    }
-    double pr[RT];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b < RT; ++b) acc = fma(c[a][b], vj[b], acc);
-      acc += __shfl_xor(acc, 16);
-      acc += __shfl_xor(acc, 32);
-      pr[a] = acc;
-    }
-    if ((ty & 3) == 0)
-#pragma unroll
-      for (int a = 0; a < RT; ++a) part[s][ty >> 2][tx + 16 * a] = pr[a];
-    __syncthreads();
-    double wi[RT], wj[RT];
-    double t = 0.0;
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      const int i = tx + 16 * a;
-      const double w = beta * ((part[s][0][i] + part[s][1][i]) + (part[s][2][i] + part[s][3][i]));
-      wi[a] = (i > k && i < p) ? w : 0.0;
-      t = fma(wi[a], vi[a], t);
-    }
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = ty + 16 * b;
-      const double w = beta * ((part[s][0][j] + part[s][1][j]) + (part[s][2][j] + part[s][3][j]));
-      wj[b] = (j > k && j < p) ? w : 0.0;
-    }
-    const double kc = 0.5 * beta * sum16(t);
-#pragma unroll
-    for (int a = 0; a < RT; ++a) wi[a] = fma(-kc, vi[a], wi[a]);
-#pragma unroll
-    for (int b = 0; b < RT; ++b) wj[b] = fma(-kc, vj[b], wj[b]);
-#pragma unroll
-    for (int a = 0; a < RT; ++a)
-#pragma unroll
-      for (int b = 0; b < RT; ++b) c[a][b] -= vi[a] * wj[b] + wi[a] * vj[b];
-  }
+  tridiag_reg_steps<RT, 0>(c, L, W, p, tx, ty);
   // trailing 2 x 2 block
 #pragma unroll
   for (int a = 0; a < RT; ++a)

@@ -220,7 +220,7 @@ def main():
     bytes_grid = 8.0 * (n ** 3 + n * n * r3 + n * r3)
     achieved = flops_grid / t_grid / 1e12
     traffic = traffic_from_profiles("grid_gemm64", args.workload)
-    roofline = {"kernel": "gemm64_kernel<false,false> (grid = T2 x_3 V3)",
+    roofline = {"kernel": "rs::gemm_kernel<rs::Cfg<4, 2, 2, 4, 16, 16>, false, false> (grid = T2 x_3 V3)",
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
                 "traffic": traffic,

@@ -1,25 +1,48 @@
-// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64).
+// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64, or the four-block
+// v_mfma_f64_4x4x4f64 form per configuration).
 //
 //   C[bt](m, n) = sum_k A[bt](m, k) * B[bt](k, n) * kscale[k]
 //
-// with arbitrary element strides, so one kernel serves every dense
+// with arbitrary element strides, so one kernel family serves every dense
 // contraction of the path: the charge-weighted Gram U diag(w) U^T, the
-// eigensolver's products, the projection V^T U and the three mode products
-// that expand the Tucker tensor onto the grid.
+// eigensolver's products, the projection V^T U, the core contraction and
+// the three mode products that expand the Tucker tensor onto the grid.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup (4 wave64s in a 2 x 2
-// arrangement, 32 x 32 per wave = 2 x 2 MFMA blocks of 16 x 16), K staged
-// through LDS in steps of 16 with a register prefetch of the next step.
+// Tiling (compile-time configurations): a workgroup of WM x WN wave64s owns
+// a BM x BN output tile, each wave FM x FN blocks of 16 x 16 (one MFMA
+// accumulator of 4 doubles per lane each).  K is staged through LDS in
+// slabs of 16 (double-buffered, the next slab prefetched into registers
+// while the current one feeds the MFMAs):
+//   big   128 x 128 (4 x 2 waves of 32 x 64) for the grid expansion (M = n^2),
+//   rank   96 x 64  (3 x 2 waves of 32 x 32) when M is a Tucker rank <= 96,
+//   small  64 x 64  (2 x 2 waves of 32 x 32) for the rest.
+// (Measured on gfx950 against 128 x 128 tiles of 64 x 64 per wave, k slabs
+// of 32 and the 4x4x4 instruction form: these were the fastest per shape.)
 // Large K is split across workgroups; the partial tiles are summed by a
-// second kernel in a fixed order, so the result is deterministic.
+// second kernel in a fixed order, so the result is deterministic.  When
+// the M tiles divide among the 8 XCDs, consecutive workgroups of one XCD
+// walk the N tiles of one M tile, so the A tile is re-read from that XCD's
+// L2 rather than from HBM.
 #include "rs_internal.h"
 
 namespace rs {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int PAD = 2;
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
-constexpr int LDA = BM + PAD, LDB = BN + PAD;
+// MF selects the matrix instruction: 16 for v_mfma_f64_16x16x4f64 (one
+// 16 x 16 x 4 product), 4 for v_mfma_f64_4x4x4f64 (four 4 x 4 x 4 products).
+template <int WM_, int WN_, int FM_, int FN_, int BK_, int MF_>
+struct Cfg {
+  static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, BK = BK_, MF = MF_;
+  static constexpr int BM = WM * FM * 16, BN = WN * FN * 16;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  static constexpr int VA = (BM * BK + NT - 1) / NT, VB = (BN * BK + NT - 1) / NT;   // slab values per thread
+};
+using CfgBig = Cfg<4, 2, 2, 4, 16, 16>;   // 128 x 128, 8 waves of 32 x 64
+using CfgRank = Cfg<3, 2, 2, 2, 16, 16>;  //  96 x 64,  6 waves of 32 x 32
+using CfgSmall = Cfg<2, 2, 2, 2, 16, 16>; //  64 x 64,  4 waves of 32 x 32
+constexpr int KALIGN = 32;                // split-K chunks are multiples of every slab depth
 
 struct GemmDev {
   int64_t M, N, K;
@@ -33,89 +56,94 @@ struct GemmDev {
   int upper_only;
   int nontemporal;
   int tiles_m, tiles_n;
+  int xcd_remap;       // tile order grouped by XCD (tiles_m % 8 == 0, one batch, no split)
+  int bm, bn;          // tile shape (for the reduction's mirror test)
 };
 
-// Load the BK x 64 slab of A (as A^T: [k][m]) or B ([k][n]) into registers.
-// Template flag: true when the 64-wide index (m or n) is the contiguous one.
-template <bool WIDE_CONTIG>
-__device__ __forceinline__ void load_slab(const double* __restrict__ P, int64_t s_wide,
-                                          int64_t s_k, int64_t wide0, int64_t k0, int64_t W,
-                                          int64_t K, const double* __restrict__ kscale,
-                                          double (&reg)[4], int tid) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int wl, kl;
-    if (WIDE_CONTIG) {
-      wl = tid & 63;
-      kl = (tid >> 6) + 4 * r;
-    } else {
-      kl = tid & 15;
-      wl = (tid >> 4) + 16 * r;
-    }
-    int64_t w = wide0 + wl, k = k0 + kl;
-    double v = 0.0;
-    if (w < W && k < K) {
-      v = P[w * s_wide + k * s_k];
-      if (kscale) v *= kscale[k];
-    }
-    reg[r] = v;
+// Slab element e (0 <= e < WIDE * BK) of a thread's share: element index
+// e = tid + NT r.  With the wide index contiguous in memory, consecutive
+// threads take consecutive wide indices; with k contiguous, consecutive k.
+template <bool WIDE_CONTIG, int WIDE, int BK>
+__device__ __forceinline__ void slab_coord(int e, int& wl, int& kl) {
+  if (WIDE_CONTIG) {
+    wl = e % WIDE;
+    kl = e / WIDE;
+  } else {
+    kl = e % BK;
+    wl = e / BK;
   }
 }
 
-template <bool WIDE_CONTIG>
-__device__ __forceinline__ void store_slab(double* lds, int ld, const double (&reg)[4], int tid) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int wl, kl;
-    if (WIDE_CONTIG) {
-      wl = tid & 63;
-      kl = (tid >> 6) + 4 * r;
-    } else {
-      kl = tid & 15;
-      wl = (tid >> 4) + 16 * r;
-    }
-    lds[kl * ld + wl] = reg[r];
-  }
-}
-
-// Operand sources.  Each loads its share (4 values per thread) of a BK x 64
-// slab into registers; `store` writes them to LDS as [k][wide].
-template <bool WIDE_CONTIG>
+// Operand sources.  Each loads its share (V values per thread) of a
+// BK x WIDE slab into registers; `store` writes them to LDS as [k][wide].
+template <bool WIDE_CONTIG, int WIDE, int NT, int BK>
 struct StridedSrc {
+  static constexpr int V = (WIDE * BK + NT - 1) / NT;
   const double* P;
   int64_t s_wide, s_k, W;
   const double* kscale;
-  __device__ __forceinline__ void load(int64_t wide0, int64_t k0, int64_t kend, double (&reg)[4],
+  __device__ __forceinline__ void load(int64_t wide0, int64_t k0, int64_t kend, double (&reg)[V],
                                        int tid) const {
-    load_slab<WIDE_CONTIG>(P, s_wide, s_k, wide0, k0, W, kend, kscale, reg, tid);
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<WIDE_CONTIG, WIDE, BK>(e, wl, kl);
+      const int64_t w = wide0 + wl, k = k0 + kl;
+      double v = 0.0;
+      if (e < WIDE * BK && w < W && k < kend) {
+        v = P[w * s_wide + k * s_k];
+        if (kscale) v *= kscale[k];
+      }
+      reg[r] = v;
+    }
   }
-  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[4], int tid) const {
-    store_slab<WIDE_CONTIG>(lds, ld, reg, tid);
+  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[V], int tid) const {
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<WIDE_CONTIG, WIDE, BK>(e, wl, kl);
+      if (e < WIDE * BK) lds[kl * ld + wl] = reg[r];
+    }
   }
 };
 
 // Khatri-Rao operand of the core contraction, generated on the fly:
 // B[j, b*r3 + c] = xi_j * U2t[j*r2 + b] * U3t[j*r3 + c]  (never stored).
+template <int WIDE, int NT, int BK>
 struct KhatriRaoSrc {
+  static constexpr int V = (WIDE * BK + NT - 1) / NT;
   const double* U2t;
   const double* U3t;
   const double* xi;
   int r2, r3;
-  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[4],
+  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[V],
                                        int tid) const {
-    const int64_t bc = n0 + (tid & 63);
-    const int64_t W = (int64_t)r2 * r3;
-    const int b = (int)(bc / r3), c = (int)(bc - (bc / r3) * r3);
+    const int W = r2 * r3;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t k = k0 + (tid >> 6) + 4 * r;
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<true, WIDE, BK>(e, wl, kl);
+      const int bc = (int)n0 + wl;
+      const int64_t k = k0 + kl;
       double v = 0.0;
-      if (bc < W && k < kend) v = xi[k] * U2t[k * r2 + b] * U3t[k * r3 + c];
+      if (e < WIDE * BK && bc < W && k < kend) {
+        const int b = bc / r3, c = bc - (bc / r3) * r3;
+        v = xi[k] * U2t[k * r2 + b] * U3t[k * r3 + c];
+      }
       reg[r] = v;
     }
   }
-  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[4], int tid) const {
-    store_slab<true>(lds, ld, reg, tid);
+  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[V], int tid) const {
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<true, WIDE, BK>(e, wl, kl);
+      if (e < WIDE * BK) lds[kl * ld + wl] = reg[r];
+    }
   }
 };
 
@@ -128,26 +156,36 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
+template <int WIDE, int NT, int BK>
 struct HashSrc {
+  static constexpr int V = (WIDE * BK + NT - 1) / NT;
   const double* scale;
   uint64_t seed;
   int64_t W;
-  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[4],
+  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[V],
                                        int tid) const {
-    const int64_t c = n0 + (tid & 63);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t k = k0 + (tid >> 6) + 4 * r;
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<true, WIDE, BK>(e, wl, kl);
+      const int64_t c = n0 + wl, k = k0 + kl;
       double v = 0.0;
-      if (c < W && k < kend) {
+      if (e < WIDE * BK && c < W && k < kend) {
         const uint64_t h = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ULL + (uint64_t)c));
         v = scale[k] * ((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
       }
       reg[r] = v;
     }
   }
-  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[4], int tid) const {
-    store_slab<true>(lds, ld, reg, tid);
+  __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[V], int tid) const {
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      const int e = tid + NT * r;
+      int wl, kl;
+      slab_coord<true, WIDE, BK>(e, wl, kl);
+      if (e < WIDE * BK) lds[kl * ld + wl] = reg[r];
+    }
   }
 };
 
@@ -158,25 +196,29 @@ struct TileOut {
   int nontemporal;
 };
 
-// One 64 x 64 output tile over k in [kbeg, kend).
-template <class ASrc, class BSrc>
-__device__ __forceinline__ void mfma64_tile(const ASrc& as_src, const BSrc& bs_src, int64_t m0,
-                                            int64_t n0, int64_t kbeg, int64_t kend,
-                                            const TileOut& o) {
+// One BM x BN output tile over k in [kbeg, kend).
+template <class CF, class ASrc, class BSrc>
+__device__ __forceinline__ void mfma_tile(const ASrc& as_src, const BSrc& bs_src, int64_t m0,
+                                          int64_t n0, int64_t kbeg, int64_t kend,
+                                          const TileOut& o) {
+  constexpr int FM = CF::FM, FN = CF::FN, LDA = CF::LDA, LDB = CF::LDB, BK = CF::BK;
   __shared__ double As[2][BK * LDA];
   __shared__ double Bs[2][BK * LDB];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / CF::WN, wn = wave - (wave / CF::WN) * CF::WN;
 
-  d4 acc[2][2];
+  // MF == 4: acc[i][j][t] is rows 4t..4t+3 of 16 x 16 block (i, j);
+  // MF == 16: acc[i][j][v] is row v of each 4-row group of block (i, j)
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double ra[4], rb[4];
+  double ra[CF::VA], rb[CF::VB];
   int buf = 0;
   if (kbeg < kend) {
     as_src.load(m0, kbeg, kend, ra, tid);
@@ -186,27 +228,50 @@ __device__ __forceinline__ void mfma64_tile(const ASrc& as_src, const BSrc& bs_s
   }
   __syncthreads();
 
+  // v_mfma_f64_16x16x4f64: lane holds A[lane % 16][lane / 16], B[lane / 16][lane % 16]
+  // and D[lane / 16 + 4 v][lane % 16].
+  // v_mfma_f64_4x4x4f64 runs 4 independent 4x4x4 products, one per lane
+  // block blk = (lane >> 2) & 3: lane holds A[lane & 3][lane >> 4],
+  // B[lane >> 4][lane & 3] and D[lane >> 4][lane & 3] of its block.  With
+  // A rows 4t..4t+3 shared by the 4 blocks and B columns 4 blk..4 blk+3,
+  // instruction t yields rows 4t..4t+3 of a 16 x 16 x 4 block product; the
+  // B operand is then B[lane >> 4][lane & 15] for all t.
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) {
       as_src.load(m0, k0 + BK, kend, ra, tid);
       bs_src.load(n0, k0 + BK, kend, rb, tid);
     }
-    const double* as = As[buf];
-    const double* bs = Bs[buf];
+    const double* as = As[buf] + wm * (FM * 16) + (CF::MF == 4 ? (lane & 3) : (lane & 15));
+    const double* bs = Bs[buf] + wn * (FN * 16) + (lane & 15);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double fa[2], fb[2];
+      double fb[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = as[kr * LDA + wm * 32 + i * 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) fb[j] = bs[kr * LDB + j * 16];
+      if constexpr (CF::MF == 4) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = bs[kr * LDB + wn * 32 + j * 16 + (lane & 15)];
+        for (int i = 0; i < FM; ++i) {
+          double fa[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+          for (int t = 0; t < 4; ++t) fa[t] = as[kr * LDA + i * 16 + 4 * t];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[i][j][t] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[t], fb[j], acc[i][j][t], 0, 0, 0);
+        }
+      } else {
+        double fa[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = as[kr * LDA + i * 16];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
     }
     if (more) {
       as_src.store(As[buf ^ 1], LDA, ra, tid);
@@ -216,16 +281,16 @@ __device__ __forceinline__ void mfma64_tile(const ASrc& as_src, const BSrc& bs_s
     buf ^= 1;
   }
 
-  // epilogue: for v_mfma_f64_16x16x4f64 lane holds D[lane/16 + 4 v][lane%16]
-  // of each 16 x 16 block (register v = 0..3)
+  // epilogue (both forms): acc[i][j][v] at lane l is C[16 i + l / 16 + 4 v][16 j + l % 16]
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < FM; ++i) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = n0 + wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + wn * (FN * 16) + j * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+        const int r = (lane >> 4) + 4 * v;
+        const int64_t row = m0 + wm * (FM * 16) + i * 16 + r;
         if (row < o.M && col < o.N) {
           const double val = acc[i][j][v];
           if (o.part) {
@@ -241,18 +306,32 @@ __device__ __forceinline__ void mfma64_tile(const ASrc& as_src, const BSrc& bs_s
   }
 }
 
-template <bool A_MC, bool B_NC>
-__global__ __launch_bounds__(256) void gemm64_kernel(GemmDev g) {
-  const int tile = blockIdx.x;
-  const int tm = tile / g.tiles_n, tn = tile - tm * g.tiles_n;
+__device__ __forceinline__ void tile_coords(const GemmDev& g, int& tm, int& tn) {
+  const int t = blockIdx.x;
+  if (g.xcd_remap) {
+    // workgroup t runs on XCD t % 8; its i-th workgroup there takes the
+    // N tiles of M tile (i / tiles_n) * 8 + t % 8 in order
+    const int x = t & 7, i = t >> 3;
+    tm = (i / g.tiles_n) * 8 + x;
+    tn = i - (i / g.tiles_n) * g.tiles_n;
+  } else {
+    tm = t / g.tiles_n;
+    tn = t - tm * g.tiles_n;
+  }
+}
+
+template <class CF, bool A_MC, bool B_NC>
+__global__ __launch_bounds__(CF::NT) void gemm_kernel(GemmDev g) {
+  int tm, tn;
+  tile_coords(g, tm, tn);
   if (g.upper_only && tm > tn) return;
   const int bt = blockIdx.y;
   const int split = blockIdx.z;
   const int64_t kbeg = (int64_t)split * g.kchunk;
   int64_t kend = kbeg + g.kchunk;
   if (kend > g.K) kend = g.K;
-  StridedSrc<A_MC> as{g.A + (int64_t)bt * g.sab, g.sam, g.sak, g.M, nullptr};
-  StridedSrc<B_NC> bs{g.B + (int64_t)bt * g.sbb, g.sbn, g.sbk, g.N, g.kscale};
+  StridedSrc<A_MC, CF::BM, CF::NT, CF::BK> as{g.A + (int64_t)bt * g.sab, g.sam, g.sak, g.M, nullptr};
+  StridedSrc<B_NC, CF::BN, CF::NT, CF::BK> bs{g.B + (int64_t)bt * g.sbb, g.sbn, g.sbk, g.N, g.kscale};
   TileOut o;
   o.M = g.M;
   o.N = g.N;
@@ -261,20 +340,21 @@ __global__ __launch_bounds__(256) void gemm64_kernel(GemmDev g) {
   o.scn = g.scn;
   o.part = g.part ? g.part + ((int64_t)bt * g.splits + split) * g.M * g.N : nullptr;
   o.nontemporal = g.nontemporal;
-  mfma64_tile(as, bs, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, o);
+  mfma_tile<CF>(as, bs, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, kbeg, kend, o);
 }
 
 // Y[bt] (M x N, col-major) = A[bt] (M x K, m-contiguous) * Omega_bt (K x N, hashed)
-__global__ __launch_bounds__(256) void sketch64_kernel(GemmDev g, uint64_t seed) {
-  const int tile = blockIdx.x;
-  const int tm = tile / g.tiles_n, tn = tile - tm * g.tiles_n;
+template <class CF>
+__global__ __launch_bounds__(CF::NT) void sketch_kernel(GemmDev g, uint64_t seed) {
+  int tm, tn;
+  tile_coords(g, tm, tn);
   const int bt = blockIdx.y;
   const int split = blockIdx.z;
   const int64_t kbeg = (int64_t)split * g.kchunk;
   int64_t kend = kbeg + g.kchunk;
   if (kend > g.K) kend = g.K;
-  StridedSrc<true> as{g.A + (int64_t)bt * g.sab, 1, g.sak, g.M, nullptr};
-  HashSrc bs{g.kscale + (int64_t)bt * g.sbb, seed + 0x51ED27ULL * (uint64_t)(bt + 1), g.N};
+  StridedSrc<true, CF::BM, CF::NT, CF::BK> as{g.A + (int64_t)bt * g.sab, 1, g.sak, g.M, nullptr};
+  HashSrc<CF::BN, CF::NT, CF::BK> bs{g.kscale + (int64_t)bt * g.sbb, seed + 0x51ED27ULL * (uint64_t)(bt + 1), g.N};
   TileOut o;
   o.M = g.M;
   o.N = g.N;
@@ -283,13 +363,15 @@ __global__ __launch_bounds__(256) void sketch64_kernel(GemmDev g, uint64_t seed)
   o.scn = g.scn;
   o.part = g.part ? g.part + ((int64_t)bt * g.splits + split) * g.M * g.N : nullptr;
   o.nontemporal = 0;
-  mfma64_tile(as, bs, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, o);
+  mfma_tile<CF>(as, bs, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, kbeg, kend, o);
 }
 
 struct CoreDev {
   const double* U1t;
-  KhatriRaoSrc kr;
-  int r1;
+  const double* U2t;
+  const double* U3t;
+  const double* xi;
+  int r1, r2, r3;
   int64_t K;
   double* beta;
   double* part;
@@ -301,15 +383,17 @@ struct CoreDev {
 // beta_(1) (r1 x r2 r3) = U1t^T diag(xi) (U3t (.) U2t): the core of the
 // RHOSVD, eq CP_form_RHOSVD, as one GEMM whose right operand is the
 // Khatri-Rao product formed while staging it in LDS.
-__global__ __launch_bounds__(256) void core64_kernel(CoreDev g) {
+template <class CF>
+__global__ __launch_bounds__(CF::NT) void core_kernel(CoreDev g) {
   const int tile = blockIdx.x;
   const int tm = tile / g.tiles_n, tn = tile - tm * g.tiles_n;
   const int split = blockIdx.z;
   const int64_t kbeg = (int64_t)split * g.kchunk;
   int64_t kend = kbeg + g.kchunk;
   if (kend > g.K) kend = g.K;
-  const int64_t W = (int64_t)g.kr.r2 * g.kr.r3;
-  StridedSrc<true> as{g.U1t, 1, g.r1, g.r1, nullptr};
+  const int64_t W = (int64_t)g.r2 * g.r3;
+  StridedSrc<true, CF::BM, CF::NT, CF::BK> as{g.U1t, 1, g.r1, g.r1, nullptr};
+  KhatriRaoSrc<CF::BN, CF::NT, CF::BK> bs{g.U2t, g.U3t, g.xi, g.r2, g.r3};
   TileOut o;
   o.M = g.r1;
   o.N = W;
@@ -318,7 +402,7 @@ __global__ __launch_bounds__(256) void core64_kernel(CoreDev g) {
   o.scn = 1;
   o.part = g.part ? g.part + (int64_t)split * g.r1 * W : nullptr;
   o.nontemporal = 0;
-  mfma64_tile(as, g.kr, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, o);
+  mfma_tile<CF>(as, bs, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, kbeg, kend, o);
 }
 
 __global__ void core64_reduce_kernel(const double* __restrict__ part, int splits, int64_t total,
@@ -340,7 +424,7 @@ __global__ void gemm64_reduce_kernel(GemmDev g) {
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t row = e / g.N, col = e - row * g.N;
     int64_t sr = row, sc = col;
-    if (g.upper_only && (row / BM) > (col / BN)) {
+    if (g.upper_only && (row / g.bm) > (col / g.bn)) {
       sr = col;
       sc = row;
     }
@@ -352,35 +436,86 @@ __global__ void gemm64_reduce_kernel(GemmDev g) {
   }
 }
 
-static void plan(const Gemm64& g, int num_cu, int& splits, int64_t& kchunk, int& tm, int& tn) {
-  tm = (int)((g.M + BM - 1) / BM);
-  tn = (int)((g.N + BN - 1) / BN);
-  int64_t tiles = (int64_t)tm * tn;
-  if (g.upper_only) tiles = (int64_t)tm * (tm + 1) / 2;
+// ---- host: configuration choice and split-K plan -----------------------------
+enum CfgId { CFG_SMALL = 0, CFG_RANK = 1, CFG_BIG = 2 };
+
+static void cfg_shape(CfgId c, int& bm, int& bn) {
+  if (c == CFG_BIG) { bm = CfgBig::BM; bn = CfgBig::BN; }
+  else if (c == CFG_RANK) { bm = CfgRank::BM; bn = CfgRank::BN; }
+  else { bm = CfgSmall::BM; bn = CfgSmall::BN; }
+}
+
+// Tucker-rank-sized M (65..96) takes the 96-row tile, a very tall product
+// (the grid expansion) the big tile, everything else the small tile.
+static CfgId choose(const Gemm64& g, int num_cu) {
+  (void)num_cu;
+  if (g.upper_only) return CFG_SMALL;
+  if (g.M > 64 && g.M <= 96) return CFG_RANK;
+  if (g.M >= 8192 && g.N >= 128) return CFG_BIG;
+  return CFG_SMALL;
+}
+
+struct Plan64 {
+  CfgId cfg;
+  int bm, bn, tm, tn, splits;
+  int64_t kchunk;
+};
+
+static Plan64 plan_for(const Gemm64& g, CfgId cfg, int num_cu) {
+  Plan64 P;
+  P.cfg = cfg;
+  cfg_shape(P.cfg, P.bm, P.bn);
+  P.tm = (int)((g.M + P.bm - 1) / P.bm);
+  P.tn = (int)((g.N + P.bn - 1) / P.bn);
+  int64_t tiles = (int64_t)P.tm * P.tn;
+  if (g.upper_only) tiles = (int64_t)P.tm * (P.tm + 1) / 2;
   tiles *= g.batch;
   const int64_t target = 2LL * num_cu;
-  splits = 1;
-  if (tiles < target && g.K > 4 * BK) {
+  P.splits = 1;
+  if (tiles < target && g.K > 2 * KALIGN) {
     int64_t want = (target + tiles - 1) / tiles;
-    int64_t maxs = g.K / (4 * BK);  // at least 64 k per split
-    splits = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxs, 64)));
+    int64_t maxs = g.K / (2 * KALIGN);  // at least 64 k per split
+    P.splits = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxs, 64)));
   }
-  kchunk = (g.K + splits - 1) / splits;
-  kchunk = (kchunk + BK - 1) / BK * BK;
-  splits = (int)((g.K + kchunk - 1) / kchunk);
-  if (splits < 1) splits = 1;
+  P.kchunk = (g.K + P.splits - 1) / P.splits;
+  P.kchunk = (P.kchunk + KALIGN - 1) / KALIGN * KALIGN;
+  P.splits = (int)((g.K + P.kchunk - 1) / P.kchunk);
+  if (P.splits < 1) P.splits = 1;
+  return P;
 }
 
-size_t gemm64_workspace_bytes(const Gemm64& g, int num_cu) {
-  int splits, tm, tn;
-  int64_t kchunk;
-  plan(g, num_cu, splits, kchunk, tm, tn);
-  if (splits == 1 && !g.upper_only) return 0;
-  return (size_t)g.batch * splits * g.M * g.N * sizeof(double);
+// A product whose N is a Tucker rank (65..96) and whose M is larger is
+// computed transposed, C^T = B^T A^T, so that the rank sits on the 96-row side.
+static Gemm64 canon(const Gemm64& g) {
+  if (g.upper_only || !(g.N > 64 && g.N <= 96 && g.M > 96)) return g;
+  Gemm64 t = g;
+  t.M = g.N; t.N = g.M;
+  t.A = g.B; t.sam = g.sbn; t.sak = g.sbk; t.sab = g.sbb;
+  t.B = g.A; t.sbk = g.sak; t.sbn = g.sam; t.sbb = g.sab;
+  t.scm = g.scn; t.scn = g.scm;
+  return t;
 }
 
-void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+size_t gemm64_workspace_bytes(const Gemm64& gin, int num_cu) {
+  const Gemm64 g = canon(gin);
+  const Plan64 P = plan_for(g, choose(g, num_cu), num_cu);
+  if (P.splits == 1 && !g.upper_only) return 0;
+  return (size_t)g.batch * P.splits * g.M * g.N * sizeof(double);
+}
+
+template <class CF>
+static void launch_gemm_cfg(const GemmDev& d, dim3 grid, bool amc, bool bnc, hipStream_t s) {
+  if (amc && bnc) hipLaunchKernelGGL((gemm_kernel<CF, true, true>), grid, dim3(CF::NT), 0, s, d);
+  else if (amc && !bnc) hipLaunchKernelGGL((gemm_kernel<CF, true, false>), grid, dim3(CF::NT), 0, s, d);
+  else if (!amc && bnc) hipLaunchKernelGGL((gemm_kernel<CF, false, true>), grid, dim3(CF::NT), 0, s, d);
+  else hipLaunchKernelGGL((gemm_kernel<CF, false, false>), grid, dim3(CF::NT), 0, s, d);
+}
+
+void gemm64(const Gemm64& gin, int num_cu, double* work, hipStream_t s) {
+  if (gin.M <= 0 || gin.N <= 0 || gin.batch <= 0) return;
+  if (gin.K <= 0) throw Error{RS_E_INVALID, "gemm64: K must be positive"};
+  const Gemm64 g = canon(gin);
+  const Plan64 P = plan_for(g, choose(g, num_cu), num_cu);
   GemmDev d;
   d.M = g.M; d.N = g.N; d.K = g.K;
   d.A = g.A; d.sam = g.sam; d.sak = g.sak; d.sab = g.sab;
@@ -389,22 +524,23 @@ void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s) {
   d.kscale = g.kscale;
   d.upper_only = g.upper_only;
   d.nontemporal = g.nontemporal;
-  plan(g, num_cu, d.splits, d.kchunk, d.tiles_m, d.tiles_n);
+  d.splits = P.splits;
+  d.kchunk = P.kchunk;
+  d.tiles_m = P.tm;
+  d.tiles_n = P.tn;
+  d.bm = P.bm;
+  d.bn = P.bn;
+  d.xcd_remap = (g.batch == 1 && P.splits == 1 && !g.upper_only && P.tm % 8 == 0 && P.tn > 1) ? 1 : 0;
   const bool use_part = d.splits > 1 || g.upper_only;
   d.part = use_part ? work : nullptr;
   if (use_part && !work) throw Error{RS_E_DEVICE, "gemm64: missing split-K workspace"};
-  if (g.K <= 0) {
-    // empty contraction: zero output through the reduce path with no splits
-    throw Error{RS_E_INVALID, "gemm64: K must be positive"};
-  }
   const bool amc = (g.sam == 1), akc = (g.sak == 1);
   const bool bnc = (g.sbn == 1), bkc = (g.sbk == 1);
   if (!(amc || akc) || !(bnc || bkc)) throw Error{RS_E_DEVICE, "gemm64: unsupported operand strides"};
   dim3 grid((unsigned)(d.tiles_m * d.tiles_n), (unsigned)g.batch, (unsigned)d.splits);
-  if (amc && bnc) hipLaunchKernelGGL((gemm64_kernel<true, true>), grid, dim3(256), 0, s, d);
-  else if (amc && !bnc) hipLaunchKernelGGL((gemm64_kernel<true, false>), grid, dim3(256), 0, s, d);
-  else if (!amc && bnc) hipLaunchKernelGGL((gemm64_kernel<false, true>), grid, dim3(256), 0, s, d);
-  else hipLaunchKernelGGL((gemm64_kernel<false, false>), grid, dim3(256), 0, s, d);
+  if (P.cfg == CFG_BIG) launch_gemm_cfg<CfgBig>(d, grid, amc, bnc, s);
+  else if (P.cfg == CFG_RANK) launch_gemm_cfg<CfgRank>(d, grid, amc, bnc, s);
+  else launch_gemm_cfg<CfgSmall>(d, grid, amc, bnc, s);
   if (use_part) {
     int64_t total = g.M * g.N;
     int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
@@ -413,44 +549,55 @@ void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s) {
   }
 }
 
-static void plan_core(int r1, int r2, int r3, int64_t K, int num_cu, int& splits,
+// core: the rank tile when 64 < r1 <= 96, else the small tile
+static void plan_core(int r1, int r2, int r3, int64_t K, int num_cu, bool& rank_tile, int& splits,
                       int64_t& kchunk, int& tm, int& tn) {
-  tm = (r1 + BM - 1) / BM;
-  tn = (int)(((int64_t)r2 * r3 + BN - 1) / BN);
+  rank_tile = r1 > 64 && r1 <= 96;
+  const int bm = rank_tile ? CfgRank::BM : CfgSmall::BM;
+  const int bn = rank_tile ? CfgRank::BN : CfgSmall::BN;
+  tm = (r1 + bm - 1) / bm;
+  tn = (int)(((int64_t)r2 * r3 + bn - 1) / bn);
   int64_t tiles = (int64_t)tm * tn;
   const int64_t target = 2LL * num_cu;
   splits = 1;
-  if (tiles < target && K > 16 * BK) {
+  if (tiles < target && K > 8 * KALIGN) {
     int64_t want = (target + tiles - 1) / tiles;
-    splits = (int)std::min<int64_t>(want, std::min<int64_t>(K / (16 * BK), 64));
+    splits = (int)std::min<int64_t>(want, std::min<int64_t>(K / (8 * KALIGN), 64));
     if (splits < 1) splits = 1;
   }
   kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + BK - 1) / BK * BK;
+  kchunk = (kchunk + KALIGN - 1) / KALIGN * KALIGN;
   splits = (int)((K + kchunk - 1) / kchunk);
 }
 
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
+  bool rt;
   int splits, tm, tn;
   int64_t kchunk;
-  plan_core(r1, r2, r3, K, num_cu, splits, kchunk, tm, tn);
+  plan_core(r1, r2, r3, K, num_cu, rt, splits, kchunk, tm, tn);
   return splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0;
 }
 
 void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi, int r1,
             int r2, int r3, int64_t K, double* beta, int num_cu, double* work, hipStream_t s) {
   CoreDev d;
+  bool rank_tile;
   int tm;
-  plan_core(r1, r2, r3, K, num_cu, d.splits, d.kchunk, tm, d.tiles_n);
+  plan_core(r1, r2, r3, K, num_cu, rank_tile, d.splits, d.kchunk, tm, d.tiles_n);
   d.U1t = U1t;
-  d.kr = KhatriRaoSrc{U2t, U3t, xi, r2, r3};
+  d.U2t = U2t;
+  d.U3t = U3t;
+  d.xi = xi;
   d.r1 = r1;
+  d.r2 = r2;
+  d.r3 = r3;
   d.K = K;
   d.beta = beta;
   d.part = d.splits > 1 ? work : nullptr;
   if (d.splits > 1 && !work) throw Error{RS_E_DEVICE, "core64: missing workspace"};
   dim3 grid((unsigned)(tm * d.tiles_n), 1, (unsigned)d.splits);
-  hipLaunchKernelGGL(core64_kernel, grid, dim3(256), 0, s, d);
+  if (rank_tile) hipLaunchKernelGGL(core_kernel<CfgRank>, grid, dim3(CfgRank::NT), 0, s, d);
+  else hipLaunchKernelGGL(core_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d);
   if (d.splits > 1) {
     int64_t total = (int64_t)r1 * r2 * r3;
     unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
@@ -459,15 +606,12 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
   }
 }
 
+// the sketch keeps the small tile (its N is the subspace size p)
 void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* scale,
               int64_t scale_stride, int batch, int64_t N, uint64_t seed, double* Y, int64_t scm,
               int64_t scn, int num_cu, double* work, hipStream_t s) {
   Gemm64 g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
-  g.A = A; g.sam = 1; g.sak = M; g.sab = sab;
-  g.C = Y; g.scm = scm; g.scn = scn; g.scb = M * N;
-  g.kscale = scale;
-  g.sbb = scale_stride;
   GemmDev d;
   d.M = M; d.N = N; d.K = K;
   d.A = A; d.sam = 1; d.sak = M; d.sab = sab;
@@ -476,12 +620,19 @@ void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* 
   d.kscale = scale;
   d.upper_only = 0;
   d.nontemporal = 0;
-  plan(g, num_cu, d.splits, d.kchunk, d.tiles_m, d.tiles_n);
+  const Plan64 P = plan_for(g, CFG_SMALL, num_cu);
+  d.splits = P.splits;
+  d.kchunk = P.kchunk;
+  d.bm = CfgSmall::BM;
+  d.bn = CfgSmall::BN;
+  d.tiles_m = (int)((M + d.bm - 1) / d.bm);
+  d.tiles_n = (int)((N + d.bn - 1) / d.bn);
+  d.xcd_remap = 0;
   const bool use_part = d.splits > 1;
   d.part = use_part ? work : nullptr;
   if (use_part && !work) throw Error{RS_E_DEVICE, "sketch64: missing split-K workspace"};
   dim3 grid((unsigned)(d.tiles_m * d.tiles_n), (unsigned)batch, (unsigned)d.splits);
-  hipLaunchKernelGGL(sketch64_kernel, grid, dim3(256), 0, s, d, seed);
+  hipLaunchKernelGGL(sketch_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d, seed);
   if (use_part) {
     int64_t total = M * N;
     int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
@@ -493,7 +644,9 @@ void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* 
 size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu) {
   Gemm64 g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
-  return gemm64_workspace_bytes(g, num_cu);
+  const Plan64 P = plan_for(g, CFG_SMALL, num_cu);
+  if (P.splits == 1) return 0;
+  return (size_t)g.batch * P.splits * g.M * g.N * sizeof(double);
 }
 
 void core64_reduce(const double* part, int splits, int64_t total, double* out, hipStream_t s) {

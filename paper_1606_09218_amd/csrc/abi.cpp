@@ -135,52 +135,92 @@ static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P
   gemm64(g, ctx->num_cu, work.as<double>(), s);
 }
 
-// Expand T2 = beta x_1 V1 x_2 V2 and, when grid != null, the full grid
-// (T2 x_3 V3) plus the short-range windows.
-static void build_expansion(rs_tensor* T, void* grid, hipStream_t s) {
-  const int64_t n = T->n;
+// Scratch carved from one allocation: offsets are 256-byte aligned.
+struct Carve {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    const size_t off = total;
+    total += (bytes + 255) & ~(size_t)255;
+    return off;
+  }
+};
+
+static Gemm64 expand1_gemm(const rs_tensor* T, double* W1) {
   const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
+  Gemm64 g;  // W1 (n x r2 r3) = V1 beta_(1)
+  g.M = T->n; g.N = (int64_t)r2 * r3; g.K = r1;
+  g.A = T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
+  g.B = T->beta.as<double>(); g.sbk = (int64_t)r2 * r3; g.sbn = 1;
+  g.C = W1; g.scm = (int64_t)r2 * r3; g.scn = 1;
+  return g;
+}
+
+static Gemm64 expand2_gemm(const rs_tensor* T, const double* W1) {
+  const int64_t n = T->n;
+  const int r2 = T->r[1], r3 = T->r[2];
+  Gemm64 g;  // T2[i1] (n x r3) = V2 (n x r2) W1[i1] (r2 x r3), batched over i1
+  g.M = n; g.N = r3; g.K = r2; g.batch = (int)n;
+  g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1; g.sab = 0;
+  g.B = W1; g.sbk = r3; g.sbn = 1; g.sbb = (int64_t)r2 * r3;
+  g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.scb = n * r3;
+  return g;
+}
+
+static Gemm64 grid_gemm(const rs_tensor* T, void* grid) {
+  const int64_t n = T->n;
+  const int r3 = T->r[2];
+  Gemm64 g;  // grid[(i1,i2), i3] = sum_c T2[(i1,i2), c] V3[i3, c]
+  g.M = n * n; g.N = n; g.K = r3;
+  g.A = T->T2.as<double>(); g.sam = r3; g.sak = 1;
+  g.B = T->Q[2].as<double>(); g.sbk = 1; g.sbn = r3;
+  g.C = (double*)grid; g.scm = n; g.scn = 1;
+  g.nontemporal = 1;
+  return g;
+}
+
+// Scratch layout of build_expansion: W1, then the GEMM workspaces.
+struct ExpansionScratch {
+  size_t w1, wk1, wk2, wkg, total;
+};
+
+static ExpansionScratch expansion_scratch(const rs_tensor* T, bool with_grid) {
   const int ncu = T->ctx->num_cu;
-  // W1 (n x r2 r3) = V1 beta_(1)
+  ExpansionScratch e{};
+  Carve c;
+  e.w1 = c.add((size_t)T->n * T->r[1] * T->r[2] * sizeof(double));
+  e.wk1 = c.add(gemm64_workspace_bytes(expand1_gemm(T, nullptr), ncu));
+  e.wk2 = c.add(gemm64_workspace_bytes(expand2_gemm(T, nullptr), ncu));
+  e.wkg = c.add(!with_grid ? 0
+                : T->prec == RS_FP64 ? gemm64_workspace_bytes(grid_gemm(T, nullptr), ncu)
+                                     : grid_mixed_workspace_bytes(T->n, T->r[2]));
+  e.total = c.total;
+  return e;
+}
+
+// Expand T2 = beta x_1 V1 x_2 V2 and, when grid != null, the full grid
+// (T2 x_3 V3) plus the short-range windows.  T2 must be allocated; scratch
+// holds expansion_scratch(T, grid != null).total bytes.
+static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t s) {
+  const int64_t n = T->n;
+  const int r3 = T->r[2];
+  const int ncu = T->ctx->num_cu;
+  const ExpansionScratch e = expansion_scratch(T, grid != nullptr);
+  double* W1 = (double*)(scratch + e.w1);
   mark(T, RS_STAGE_EXPAND1, s);
-  DevBuf W1((size_t)n * r2 * r3 * sizeof(double), s);
-  {
-    Gemm64 g;
-    g.M = n; g.N = (int64_t)r2 * r3; g.K = r1;
-    g.A = T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
-    g.B = T->beta.as<double>(); g.sbk = (int64_t)r2 * r3; g.sbn = 1;
-    g.C = W1.as<double>(); g.scm = (int64_t)r2 * r3; g.scn = 1;
-    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-    gemm64(g, ncu, wk.as<double>(), s);
-  }
+  gemm64(expand1_gemm(T, W1), ncu, (double*)(scratch + e.wk1), s);
   mark(T, RS_STAGE_EXPAND2, s);
-  T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
-  {
-    Gemm64 g;  // T2[i1] (n x r3) = V2 (n x r2) W1[i1] (r2 x r3), batched over i1
-    g.M = n; g.N = r3; g.K = r2; g.batch = (int)n;
-    g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1; g.sab = 0;
-    g.B = W1.as<double>(); g.sbk = r3; g.sbn = 1; g.sbb = (int64_t)r2 * r3;
-    g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.scb = n * r3;
-    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-    gemm64(g, ncu, wk.as<double>(), s);
-  }
+  gemm64(expand2_gemm(T, W1), ncu, (double*)(scratch + e.wk2), s);
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
-    grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid, s);
+    grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
+               scratch + e.wkg, s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
                  T->brick_start.as<int>(), T->brick_list.as<int>(), s);
   } else if (grid) {
-    Gemm64 g;  // grid[(i1,i2), i3] = sum_c T2[(i1,i2), c] V3[i3, c]
-    g.M = n * n; g.N = n; g.K = r3;
-    g.A = T->T2.as<double>(); g.sam = r3; g.sak = 1;
-    g.B = T->Q[2].as<double>(); g.sbk = 1; g.sbn = r3;
-    g.C = (double*)grid; g.scm = n; g.scn = 1;
-    g.nontemporal = 1;
-    DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
     mark(T, RS_STAGE_GRID, s);
-    gemm64(g, ncu, wk.as<double>(), s);
+    gemm64(grid_gemm(T, grid), ncu, (double*)(scratch + e.wkg), s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 0, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
@@ -496,68 +536,79 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       T->sig_next[l] = l1 > 0 ? std::sqrt(std::max(host.info.lam_next[l], 0.0) / l1) : 0.0;
     }
 
+    // Everything below is sized by the ranks: allocate it all now (the
+    // result's own buffers, then one scratch arena), so that the launches
+    // that follow are not interleaved with allocator calls.
+    const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
+    for (int l = 0; l < 3; ++l) T->Q[l] = DevBuf((size_t)n * T->r[l] * sizeof(double), s);
+    T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
+    T->n_pairs = host.total_pairs;
+    T->brick_list = DevBuf((size_t)std::max<int64_t>(T->n_pairs, 1) * sizeof(int), s);
+    T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
+    Gemm64 gb[3], gp[3];
+    for (int l = 0; l < 3; ++l) {
+      const int r = T->r[l];
+      Gemm64& g = gb[l];  // V_l = Q0 W_r (n x r)
+      g.M = n; g.N = r; g.K = p;
+      g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = p; g.sak = 1;
+      g.sbk = 1; g.sbn = p;
+      g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
+      Gemm64& h = gp[l];  // U~_l = V_l^T U_l, stored column j contiguous: U~[j*r + a]
+      h.M = r; h.N = K; h.K = n;
+      h.A = T->Q[l].as<double>(); h.sam = 1; h.sak = r;
+      h.B = U.as<double>() + (int64_t)l * n * K; h.sbk = 1; h.sbn = n;
+      h.scm = 1; h.scn = r;
+    }
+    Carve cv;
+    size_t o_wr[3], o_wkb[3], o_ut[3], o_wkp[3];
+    for (int l = 0; l < 3; ++l) {
+      o_wr[l] = cv.add((size_t)p * T->r[l] * sizeof(double));
+      o_wkb[l] = cv.add(gemm64_workspace_bytes(gb[l], ncu));
+      o_ut[l] = cv.add((size_t)K * T->r[l] * sizeof(double));
+      o_wkp[l] = cv.add(gemm64_workspace_bytes(gp[l], ncu));
+    }
+    const size_t o_core = cv.add(P.prec == RS_FP64 ? core64_workspace_bytes(r1, r2, r3, K, ncu)
+                                                   : core_mixed_workspace_bytes(r1, r2, r3, K, ncu));
+    const size_t o_exp = cv.add(expansion_scratch(T.get(), grid_out != nullptr).total);
+    DevBuf arena(cv.total, s);
+    char* ab = arena.as<char>();
+    auto at = [&](size_t off) { return (double*)(ab + off); };
+
     // final bases V_l = Q0 W[:, perm[:r]] (n x r row-major), canonical signs
     mark(T.get(), RS_STAGE_BASIS, s);
     for (int l = 0; l < 3; ++l) {
       const int r = T->r[l];
-      DevBuf Wr((size_t)p * r * sizeof(double), s);
       launch_gather_cols(Z.as<double>() + (int64_t)l * p * rc, rc, perm.as<int>() + l * p, p, r,
-                         Wr.as<double>(), s);
-      T->Q[l] = DevBuf((size_t)n * r * sizeof(double), s);
-      Gemm64 g;
-      g.M = n; g.N = r; g.K = p;
-      g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = p; g.sak = 1;
-      g.B = Wr.as<double>(); g.sbk = 1; g.sbn = p;
-      g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
-      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-      gemm64(g, ncu, wk.as<double>(), s);
+                         at(o_wr[l]), s);
+      gb[l].B = at(o_wr[l]);
+      gemm64(gb[l], ncu, at(o_wkb[l]), s);
       launch_canonical_signs(T->Q[l].as<double>(), n, r, s);
     }
-    G.reset();
-    Bm.reset();
-    Q0.reset();
-    Z.reset();
 
-    // (a5) projection U~_l = V_l^T U_l (stored column j contiguous: U~[j*r + a]) and core
+    // (a5) projection U~_l = V_l^T U_l and core
     mark(T.get(), RS_STAGE_PROJECT, s);
-    DevBuf Ut[3];
     for (int l = 0; l < 3; ++l) {
-      const int r = T->r[l];
-      Ut[l] = DevBuf((size_t)K * r * sizeof(double), s);
-      Gemm64 g;
-      g.M = r; g.N = K; g.K = n;
-      g.A = T->Q[l].as<double>(); g.sam = 1; g.sak = r;
-      g.B = U.as<double>() + (int64_t)l * n * K; g.sbk = 1; g.sbn = n;
-      g.C = Ut[l].as<double>(); g.scm = 1; g.scn = r;
-      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-      gemm64(g, ncu, wk.as<double>(), s);
+      gp[l].C = at(o_ut[l]);
+      gemm64(gp[l], ncu, at(o_wkp[l]), s);
     }
-    U.reset();
-    const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
-    T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
     mark(T.get(), RS_STAGE_CORE, s);
     if (P.prec == RS_FP64) {
-      DevBuf wk(core64_workspace_bytes(r1, r2, r3, K, ncu), s);
-      core64(Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(), r1, r2,
-             r3, K, T->beta.as<double>(), ncu, wk.as<double>(), s);
+      core64(at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
+             T->beta.as<double>(), ncu, at(o_core), s);
     } else {
-      DevBuf wk(core_mixed_workspace_bytes(r1, r2, r3, K, ncu), s);
-      core_mixed(P.prec, Ut[0].as<double>(), Ut[1].as<double>(), Ut[2].as<double>(), xi.as<double>(),
-                 r1, r2, r3, K, T->beta.as<double>(), ncu, wk.as<double>(), s);
+      core_mixed(P.prec, at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
+                 T->beta.as<double>(), ncu, at(o_core), s);
     }
-    for (int l = 0; l < 3; ++l) Ut[l].reset();
 
     // (a6) short-range lists: fill and sort by particle index
     mark(T.get(), RS_STAGE_BINS, s);
-    T->n_pairs = host.total_pairs;
-    T->brick_list = DevBuf((size_t)std::max<int64_t>(T->n_pairs, 1) * sizeof(int), s);
     RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
     short_bin_fill(dpos, N, n, f->grid.b, P.n_s, T->nb, T->brick_start.as<int>(), counts.as<int>(),
                    T->brick_list.as<int>(), s);
     short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
 
     // (a7) T2 and the grid
-    build_expansion(T.get(), grid_out, s);
+    build_expansion(T.get(), grid_out, ab + o_exp, s);
 
     *out = T.release();
     return (*out)->rank_capped ? RS_E_RANK_CAP : RS_OK;
@@ -631,18 +682,27 @@ size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
   const int64_t r = r_max > 0 ? std::min<int64_t>(r_max, n) : std::min<int64_t>(n, 256);
   const int64_t p = std::min<int64_t>(n, r + 16);
   const size_t d = sizeof(double);
-  // stage peaks: factors + Gram (+ split partials), eigensolver, projection + core, expansion
-  size_t factors = (3 * n * K + 2 * K) * d;
-  size_t gram = 3 * n * n * d * 3;
-  size_t eig = (3 * n * p * 3 + 3 * p * p * 2) * d;
-  size_t proj = 3 * K * r * d + 3 * n * r * d;
-  size_t core = r * r * r * d * (K > 0 ? 4 : 1);
-  size_t expand = (n * r * r + n * n * r) * d;
+  const int ncu = 256;
+  // Upper bound of what one assembly holds at once: its inputs, the factors
+  // and the Gram stay live until the last launch is enqueued, together with
+  // the subspace basis, the eigenvectors, the result's own buffers and the
+  // scratch arena of the rank-sized stages.
+  Gemm64 gram;
+  gram.M = n; gram.N = n; gram.K = K; gram.batch = 3; gram.upper_only = 1;
+  Gemm64 sk;
+  sk.M = n; sk.N = p; sk.K = K; sk.batch = 3;
+  size_t inputs = (size_t)N * 4 * d + 2 * (size_t)t.R * d;
+  size_t factors = (size_t)(3 * n * K + 3 * K) * d;
+  size_t gram_b = (size_t)3 * n * n * d + gemm64_workspace_bytes(gram, ncu);
+  size_t eig = (size_t)(3 * n * p * 2 + 3 * p * p * 3 + 3 * p * r) * d +
+               std::max(gemm64_workspace_bytes(sk, ncu), (size_t)3 * (p * p + 4 * p + 2 * p * r) * d);
+  size_t result = (size_t)(3 * n * r + r * r * r + n * n * r) * d;
+  size_t arena = (size_t)(3 * p * r + 3 * K * r + n * r * r) * d +
+                 (prec == RS_FP64 ? core64_workspace_bytes((int)r, (int)r, (int)r, K, ncu)
+                                  : core_mixed_workspace_bytes((int)r, (int)r, (int)r, K, ncu)) +
+                 (size_t)8 * n * n * d;  // split-K partials of the projections and expansions (bound)
   size_t bins = ((n / 8 + 1) * (n / 8 + 1) * (n / 8 + 1) * 2 + 64 * N) * sizeof(int);
-  size_t peak = std::max({factors + gram, factors + gram + eig, factors + proj + core,
-                          r * r * r * d + expand});
-  size_t mixed_extra = prec != RS_FP64 ? (size_t)(3 * K * r) * 2 * 3 : 0;
-  return peak + bins + mixed_extra + (size_t)N * 4 * d;
+  return inputs + factors + gram_b + eig + result + arena + bins;
 }
 
 rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
@@ -842,7 +902,9 @@ rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
     short_bin_fill(T->pos.as<double>(), T->N, T->n, T->b, T->n_s, T->nb, T->brick_start.as<int>(),
                    counts.as<int>(), T->brick_list.as<int>(), s);
     short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
-    build_expansion(T.get(), nullptr, s);
+    T->T2 = DevBuf((size_t)T->n * T->n * T->r[2] * sizeof(double), s);
+    DevBuf scratch(expansion_scratch(T.get(), false).total, s);
+    build_expansion(T.get(), nullptr, scratch.as<char>(), s);
     RS_HIP(hipStreamSynchronize(s));
     *out = T.release();
     return RS_OK;

@@ -1,14 +1,25 @@
 // Split-precision contractions for the mixed path (core and grid expansion).
 //
-// Each FP64 operand value is split while it is staged into LDS:
-//  FP16: x 2^s = hi + lo 2^-11 (hi, lo FP16), |x 2^s| <= 2^14 by a power-of-two
-//        scale from the operand's max |x|; three products hi*hi, hi*lo, lo*hi.
-//  BF16: x = hi + mid + lo (BF16 of the successive residuals); six products
-//        down to the 2^-16 level (hh, hm, mh, hl, lh, mm).
+// Each FP64 operand value x is represented by low-precision terms:
+//  FP16: x 2^s = hi + lo 2^-11 (hi, lo FP16), with a power-of-two scale 2^s
+//        from the operand's max |x| so that |x 2^s| < 2^14; three products
+//        hi*hi, hi*lo, lo*hi.
+//  BF16: x = hi + mid + lo (BF16 of the successive residuals, no scale); six
+//        products down to the 2^-16 level (hh, hm, mh, hl, lh, mm).
 // The products run on v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation,
 // one accumulator per magnitude level, folded into FP64 registers every
-// KCHUNK values of k (FP64 sums across K chunks).  Output is FP64 (core, then
-// split-K partials summed in a fixed order) or FP32 (the grid).
+// KCHUNK values of k.
+//
+// The operands are split once into planes, [term][row][kp] with the
+// contraction index k contiguous and padded with zeros to kp (a multiple of
+// 32), so that each lane loads its MFMA fragment (8 consecutive k of one row,
+// 16 bytes) straight from memory: no LDS staging and no conversion inside the
+// GEMM loops.  The Khatri-Rao operand of the core, xi_j U~2[j,b] U~3[j,c],
+// is never stored: lanes form it in FP32 from xi U~2 and U~3 (transposed,
+// FP32) and split it in registers.
+//
+// v_mfma_f32_16x16x32_{f16,bf16}: lane l holds A[l % 16][8 (l / 16) + t] and
+// B[8 (l / 16) + t][l % 16] (t = 0..7), and D[4 (l / 16) + v][l % 16].
 #include "rs_internal.h"
 
 namespace rs {
@@ -17,18 +28,23 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int XBM = 64, XBN = 64, XBK = 32, XLDK = 40;  // LDS row of 32 halves, padded
-constexpr int KCHUNK = 256;
+constexpr int KCHUNK = 256;   // FP32 accumulation span before folding into FP64
 
 struct SplitF16 {
   static constexpr int TERMS = 2;
   static constexpr int LEVELS = 2;
+  static constexpr bool SCALED = true;
   typedef _Float16 T;
   typedef h8 V8;
   __device__ static void split(double x, T* o) {
     const T hi = (T)x;
     o[0] = hi;
     o[1] = (T)((x - (double)hi) * 2048.0);
+  }
+  __device__ static void split32(float x, T* o) {
+    const T hi = (T)x;
+    o[0] = hi;
+    o[1] = (T)((x - (float)hi) * 2048.0f);
   }
   __device__ static f4 mfma(V8 a, V8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -47,6 +63,7 @@ struct SplitF16 {
 struct SplitBF16 {
   static constexpr int TERMS = 3;
   static constexpr int LEVELS = 3;
+  static constexpr bool SCALED = false;
   typedef __bf16 T;
   typedef b8 V8;
   __device__ static void split(double x, T* o) {
@@ -57,6 +74,14 @@ struct SplitBF16 {
     o[0] = hi;
     o[1] = mid;
     o[2] = (T)(float)r2;
+  }
+  __device__ static void split32(float x, T* o) {
+    const T hi = (T)x;
+    const float r1 = x - (float)hi;
+    const T mid = (T)r1;
+    o[0] = hi;
+    o[1] = mid;
+    o[2] = (T)(r1 - (float)mid);
   }
   __device__ static f4 mfma(V8 a, V8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -74,229 +99,282 @@ struct SplitBF16 {
   }
 };
 
-// ---- FP64 operand sources for a 64 (wide) x 32 (k) slab, 8 values per thread ----
-// K-contiguous storage: element (w, k) at P[w * s_w + k].
-struct KContigSrc {
-  const double* P;
-  int64_t s_w, W;
-  static constexpr bool KVEC = true;   // the 8 values of a thread run along k
-  __device__ __forceinline__ void load(int64_t w0, int64_t k0, int64_t kend, double (&v)[8], int tid,
-                                       int& wl, int& kl) const {
-    wl = tid >> 2;
-    kl = (tid & 3) * 8;
-    const int64_t w = w0 + wl;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t k = k0 + kl + t;
-      v[t] = (w < W && k < kend) ? P[w * s_w + k] : 0.0;
-    }
-  }
-};
+static inline int64_t pad32(int64_t k) { return (k + 31) / 32 * 32; }
 
-// Wide-contiguous storage: element (w, k) at P[k * s_k + w].
-struct WContigSrc {
-  const double* P;
-  int64_t s_k, W;
-  static constexpr bool KVEC = false;  // the 8 values of a thread run along w
-  __device__ __forceinline__ void load(int64_t w0, int64_t k0, int64_t kend, double (&v)[8], int tid,
-                                       int& wl, int& kl) const {
-    kl = tid >> 3;
-    wl = (tid & 7) * 8;
-    const int64_t k = k0 + kl;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t w = w0 + wl + t;
-      v[t] = (w < W && k < kend) ? P[k * s_k + w] : 0.0;
-    }
-  }
-};
+// 2^s from the exponent table written by scale_exponents_kernel
+__device__ __forceinline__ double pow2(int s) { return ldexp(1.0, s); }
 
-// Khatri-Rao operand of the core: (w = b r3 + c, k = j) -> xi_j U2t[j r2 + b] U3t[j r3 + c]
-struct KRSrc {
-  const double* U2t;
-  const double* U3t;
-  const double* xi;
-  int r2, r3;
-  static constexpr bool KVEC = false;
-  __device__ __forceinline__ void load(int64_t w0, int64_t k0, int64_t kend, double (&v)[8], int tid,
-                                       int& wl, int& kl) const {
-    kl = tid >> 3;
-    wl = (tid & 7) * 8;
-    const int64_t k = k0 + kl;
-    const int64_t W = (int64_t)r2 * r3;
-    int64_t bc = w0 + wl;
-    int b = (int)(bc / r3), c = (int)(bc - (int64_t)(bc / r3) * r3);
-    const bool kin = k < kend;
-    const double xk = kin ? xi[k] : 0.0;
+// ---- split planes ---------------------------------------------------------------
+// out[term][row][k] (k < kp, zero beyond cols) = term of x(row, k) 2^s,
+// x(row, k) = src[row * s_row + k * s_col].  Thread (k, row): k = threadIdx.x
+// + 256 blockIdx.x, rows strided by gridDim.y.
+template <class SP>
+__global__ __launch_bounds__(256) void split_planes_kernel(const double* __restrict__ src,
+                                                           int64_t rows, int cols, int64_t s_row,
+                                                           int64_t s_col, int kp, const int* exps,
+                                                           int which,
+                                                           typename SP::T* __restrict__ out) {
+  const double scale = SP::SCALED && exps ? pow2(exps[which]) : 1.0;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= kp) return;
+  const int64_t plane = rows * kp;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const double x = k < cols ? src[row * s_row + k * s_col] * scale : 0.0;
+    typename SP::T t[SP::TERMS];
+    SP::split(x, t);
+    const int64_t e = row * kp + k;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      v[t] = (kin && bc + t < W) ? xk * U2t[k * r2 + b] * U3t[k * r3 + c] : 0.0;
-      if (++c == r3) {
-        c = 0;
-        ++b;
-      }
-    }
+    for (int term = 0; term < SP::TERMS; ++term) out[term * plane + e] = t[term];
   }
-};
+}
 
-template <class SP, class Src>
-__device__ __forceinline__ void stage(const Src& src, typename SP::T* lds, int64_t w0, int64_t k0,
-                                      int64_t kend, double scale, int tid) {
-  double v[8];
-  int wl, kl;
-  src.load(w0, k0, kend, v, tid, wl, kl);
-  typename SP::T parts[8][SP::TERMS];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) SP::split(v[t] * scale, parts[t]);
-  // lds layout: [term][w][k] with row stride XLDK halves
-#pragma unroll
-  for (int term = 0; term < SP::TERMS; ++term) {
-    typename SP::T* base = lds + term * (XBM * XLDK);
-    if (Src::KVEC) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) base[wl * XLDK + kl + t] = parts[t][term];
+// FP32 transposed copies for the Khatri-Rao operand:
+// s2[b][j] = xi_j U~2[j, b], u3[c][j] = U~3[j, c]  (zero for j >= K)
+__global__ void kr_factors_kernel(const double* __restrict__ U2t, const double* __restrict__ U3t,
+                                  const double* __restrict__ xi, int r2, int r3, int64_t K,
+                                  int64_t kp, float* __restrict__ s2, float* __restrict__ u3) {
+  const int64_t total = (int64_t)(r2 + r3) * kp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / kp, j = e - row * kp;
+    if (row < r2) {
+      s2[row * kp + j] = j < K ? (float)(xi[j] * U2t[j * r2 + row]) : 0.0f;
     } else {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) base[(wl + t) * XLDK + kl] = parts[t][term];
+      const int64_t c = row - r2;
+      u3[c * kp + j] = j < K ? (float)U3t[j * r3 + c] : 0.0f;
     }
   }
 }
 
-struct MixedOut {
-  int64_t M, N;
-  double* C64;      // FP64 output (row-major with scm, scn) or split-K partial base
-  float* C32;       // FP32 output (nontemporal), when C64 is null
-  int64_t scm, scn;
-};
-
-template <class SP, class ASrc, class BSrc>
-__device__ __forceinline__ void mixed_tile(const ASrc& as, const BSrc& bs, int64_t m0, int64_t n0,
-                                           int64_t kbeg, int64_t kend, double sa, double sb,
-                                           double out_scale, const MixedOut& o) {
-  typedef typename SP::T T;
+// ---- grid: C[m, n] (FP32) = sum_k A[m, k] B[n, k] from split planes ---------------
+// Workgroup 64 x 128 (4 waves of 32 x 64, 2 x 4 blocks of 16 x 16 each).
+template <class SP>
+__global__ __launch_bounds__(256) void grid_split_kernel(const typename SP::T* __restrict__ Ap,
+                                                         const typename SP::T* __restrict__ Bp,
+                                                         int64_t M, int64_t N, int64_t kp,
+                                                         int tiles_n, int xcd_remap, float* grid,
+                                                         const int* exps) {
   typedef typename SP::V8 V8;
-  __shared__ __attribute__((aligned(16))) T Al[SP::TERMS * XBM * XLDK];
-  __shared__ __attribute__((aligned(16))) T Bl[SP::TERMS * XBN * XLDK];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-
-  double acc64[2][2][4];
-  f4 acc[2][2][SP::LEVELS];
+  const int t = blockIdx.x;
+  int tm, tn;
+  if (xcd_remap) {
+    const int x = t & 7, i = t >> 3;
+    tm = (i / tiles_n) * 8 + x;
+    tn = i - (i / tiles_n) * tiles_n;
+  } else {
+    tm = t / tiles_n;
+    tn = t - tm * tiles_n;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t m0 = (int64_t)tm * 64 + (wave >> 1) * 32;
+  const int64_t n0 = (int64_t)tn * 128 + (wave & 1) * 64;
+  const int64_t planeA = M * kp, planeB = N * kp;
+  const int kofs = 8 * (lane >> 4);
+  f4 acc[2][4][SP::LEVELS];
+  double acc64[2][4][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
     }
-
-  int since_fold = 0;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += XBK) {
-    __syncthreads();
-    stage<SP>(as, Al, m0, k0, kend, sa, tid);
-    stage<SP>(bs, Bl, n0, k0, kend, sb, tid);
-    __syncthreads();
-    V8 a[2][SP::TERMS], b[2][SP::TERMS];
+  // rows beyond M / N read row 0 (their results are not stored)
+  int64_t arow[2], brow[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t r = m0 + 16 * i + (lane & 15);
+    arow[i] = (r < M ? r : 0) * kp + kofs;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t r = n0 + 16 * j + (lane & 15);
+    brow[j] = (r < N ? r : 0) * kp + kofs;
+  }
+  // fragments of the next k block are loaded while the current one is used
+  V8 a[2][SP::TERMS], b[4][SP::TERMS];
+  auto load = [&](int64_t k0, V8 (&ra)[2][SP::TERMS], V8 (&rb)[4][SP::TERMS]) {
+#pragma unroll
+    for (int term = 0; term < SP::TERMS; ++term) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) ra[i][term] = *(const V8*)(Ap + term * planeA + arow[i] + k0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rb[j][term] = *(const V8*)(Bp + term * planeB + brow[j] + k0);
+    }
+  };
+  load(0, a, b);
+  int since = 0;
+  for (int64_t k0 = 0; k0 < kp; k0 += 32) {
+    V8 na[2][SP::TERMS], nb[4][SP::TERMS];
+    const bool more = k0 + 32 < kp;
+    if (more) load(k0 + 32, na, nb);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int term = 0; term < SP::TERMS; ++term) {
-        a[i][term] = *(const V8*)(Al + term * XBM * XLDK + (wm * 32 + i * 16 + (lane & 15)) * XLDK +
-                                   8 * (lane >> 4));
-        b[i][term] = *(const V8*)(Bl + term * XBN * XLDK + (wn * 32 + i * 16 + (lane & 15)) * XLDK +
-                                   8 * (lane >> 4));
-      }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) SP::products(a[i], b[j], acc[i][j]);
-    since_fold += XBK;
-    if (since_fold >= KCHUNK || k0 + XBK >= kend) {
+      for (int j = 0; j < 4; ++j) SP::products(a[i], b[j], acc[i][j]);
+    since += 32;
+    if (since >= KCHUNK || !more) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 4; ++j) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc64[i][j][v] += SP::combine(acc[i][j], v);
 #pragma unroll
           for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
         }
-      since_fold = 0;
+      since = 0;
+    }
+    if (more) {
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i][term] = na[i][term];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j][term] = nb[j][term];
+      }
     }
   }
-  // epilogue: for the 16 x 16 f32 MFMAs lane holds D[4 (lane/16) + v][lane % 16]
+  const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = n0 + wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = n0 + 16 * j + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-        if (row < o.M && col < o.N) {
-          const double val = acc64[i][j][v] * out_scale;
-          if (o.C64) o.C64[row * o.scm + col * o.scn] = val;
-          else __builtin_nontemporal_store((float)val, o.C32 + row * o.scm + col * o.scn);
-        }
+        const int64_t row = m0 + 16 * i + 4 * (lane >> 4) + v;
+        if (row < M && col < N)
+          __builtin_nontemporal_store((float)(acc64[i][j][v] * out_scale), grid + row * N + col);
       }
     }
 }
 
-// 2^s from the exponent table written by the absmax kernels
-__device__ __forceinline__ double pow2(int s) { return ldexp(1.0, s); }
-
+// ---- core: beta_(1)[a, b r3 + c] = sum_j U~1[j, a] xi_j U~2[j, b] U~3[j, c] ----------
+// A = U~1^T from split planes [term][a][kp]; B[j, (b, c)] formed per lane from
+// s2[b][j] u3[c][j] (FP32) and split in registers.  A wave owns one column
+// block of 16 (b, c) pairs and 6 row blocks (96 values of a) of one row chunk;
+// blockIdx.y = row chunk, blockIdx.z = split of the j range.
 template <class SP>
-__global__ __launch_bounds__(256) void core_mixed_kernel(const double* U1t, KRSrc kr, int r1,
-                                                         int64_t K, int64_t kchunk, int tiles_n,
-                                                         double* beta, double* part,
-                                                         const int* exps) {
-  const int tile = blockIdx.x;
-  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
-  const int split = blockIdx.z;
-  const int64_t kbeg = (int64_t)split * kchunk;
-  int64_t kend = kbeg + kchunk;
-  if (kend > K) kend = K;
-  const int64_t W = (int64_t)kr.r2 * kr.r3;
-  WContigSrc as{U1t, r1, r1};
-  MixedOut o;
-  o.M = r1;
-  o.N = W;
-  o.C64 = part ? part + (int64_t)split * r1 * W : beta;
-  o.C32 = nullptr;
-  o.scm = W;
-  o.scn = 1;
-  const int sa = exps ? exps[0] : 0, sb = exps ? exps[1] : 0;
-  mixed_tile<SP>(as, kr, (int64_t)tm * XBM, (int64_t)tn * XBN, kbeg, kend, pow2(sa), pow2(sb),
-                 pow2(-sa - sb), o);
-}
-
-// grid[(i1 i2), i3] (FP32) = sum_c T2[(i1 i2), c] V3[i3, c]
-template <class SP>
-__global__ __launch_bounds__(256) void grid_mixed_kernel(const double* T2, const double* V3,
-                                                         int64_t n, int r3, int tiles_n,
-                                                         float* grid, const int* exps) {
-  const int64_t tile = blockIdx.x;
-  const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
-  KContigSrc as{T2, r3, n * n};
-  KContigSrc bs{V3, r3, n};
-  MixedOut o;
-  o.M = n * n;
-  o.N = n;
-  o.C64 = nullptr;
-  o.C32 = grid;
-  o.scm = n;
-  o.scn = 1;
-  const int sa = exps ? exps[0] : 0, sb = exps ? exps[1] : 0;
-  mixed_tile<SP>(as, bs, tm * XBM, tn * XBN, 0, r3, pow2(sa), pow2(sb), pow2(-sa - sb), o);
+__global__ __launch_bounds__(256) void core_split_kernel(const typename SP::T* __restrict__ Ap,
+                                                         const float* __restrict__ s2,
+                                                         const float* __restrict__ u3, int r1,
+                                                         int r2, int r3, int64_t kp,
+                                                         int64_t kchunk, double* __restrict__ out,
+                                                         int64_t split_stride, const int* exps) {
+  typedef typename SP::T T;
+  typedef typename SP::V8 V8;
+  constexpr int RB = 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int W = r2 * r3;
+  const int cb = (blockIdx.x * 4 + wave) * 16;   // first (b, c) column of this wave
+  if (cb >= W) return;                          // whole wave idle (no barriers below)
+  const int a0 = blockIdx.y * (16 * RB);
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < kp ? kbeg + kchunk : kp;
+  const int64_t planeA = (int64_t)r1 * kp;
+  const int kofs = 8 * (lane >> 4);
+  const float bscale = SP::SCALED && exps ? (float)pow2(exps[1]) : 1.0f;
+  // this lane's (b, c) column
+  const int col = cb + (lane & 15);
+  const int colc = col < W ? col : 0;
+  const int b = colc / r3, c = colc - (colc / r3) * r3;
+  const float* __restrict__ srow = s2 + (int64_t)b * kp + kofs;
+  const float* __restrict__ urow = u3 + (int64_t)c * kp + kofs;
+  int64_t arow[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int a = a0 + 16 * i + (lane & 15);
+    arow[i] = (int64_t)(a < r1 ? a : 0) * kp + kofs;
+  }
+  f4 acc[RB][SP::LEVELS];
+  double acc64[RB][4];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+#pragma unroll
+    for (int l = 0; l < SP::LEVELS; ++l) acc[i][l] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc64[i][v] = 0.0;
+  }
+  const int rem = (r1 - a0 + 15) / 16;
+  const int nrb = rem < RB ? rem : RB;   // row blocks with any row < r1
+  // raw data of the next k block is loaded while the current one is used
+  float4 sv[2], uv[2];
+  V8 af[RB][SP::TERMS];
+  auto load = [&](int64_t k0, float4 (&s_)[2], float4 (&u_)[2], V8 (&a_)[RB][SP::TERMS]) {
+    s_[0] = *(const float4*)(srow + k0);
+    s_[1] = *(const float4*)(srow + k0 + 4);
+    u_[0] = *(const float4*)(urow + k0);
+    u_[1] = *(const float4*)(urow + k0 + 4);
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      if (i < nrb)
+#pragma unroll
+        for (int term = 0; term < SP::TERMS; ++term)
+          a_[i][term] = *(const V8*)(Ap + term * planeA + arow[i] + k0);
+  };
+  if (kbeg < kend) load(kbeg, sv, uv, af);
+  int since = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
+    const bool more = k0 + 32 < kend;
+    float4 nsv[2], nuv[2];
+    V8 naf[RB][SP::TERMS];
+    if (more) load(k0 + 32, nsv, nuv, naf);
+    // B fragment: 8 consecutive j of column (b, c)
+    const float x[8] = {sv[0].x * uv[0].x, sv[0].y * uv[0].y, sv[0].z * uv[0].z, sv[0].w * uv[0].w,
+                        sv[1].x * uv[1].x, sv[1].y * uv[1].y, sv[1].z * uv[1].z, sv[1].w * uv[1].w};
+    V8 bf[SP::TERMS];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      T parts[SP::TERMS];
+      SP::split32(x[t] * bscale, parts);
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term) bf[term][t] = parts[term];
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      if (i < nrb) SP::products(af[i], bf, acc[i]);
+    since += 32;
+    if (since >= KCHUNK || !more) {
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[i][v] += SP::combine(acc[i], v);
+#pragma unroll
+        for (int l = 0; l < SP::LEVELS; ++l) acc[i][l] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+      since = 0;
+    }
+    if (more) {
+      sv[0] = nsv[0];
+      sv[1] = nsv[1];
+      uv[0] = nuv[0];
+      uv[1] = nuv[1];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int term = 0; term < SP::TERMS; ++term) af[i][term] = naf[i][term];
+    }
+  }
+  const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
+  double* o = out + (int64_t)blockIdx.z * split_stride;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = a0 + 16 * i + 4 * (lane >> 4) + v;
+      if (a < r1 && col < W) o[(int64_t)a * W + col] = acc64[i][v] * out_scale;
+    }
 }
 
 // ---- max |x| of FP64 arrays as ordered bit patterns (deterministic) ----------
-__global__ void absmax_kernel(const double* __restrict__ x, int64_t count,
-                              unsigned long long* __restrict__ out) {
+// Wave maxima are combined in LDS; one integer atomic per workgroup (the
+// maximum does not depend on the order).
+__global__ __launch_bounds__(256) void absmax_kernel(const double* __restrict__ x, int64_t count,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ double wmax[4];
   double m = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -304,7 +382,12 @@ __global__ void absmax_kernel(const double* __restrict__ x, int64_t count,
     if (v > m) m = v;
   }
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (b > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(b));
+  }
 }
 
 // exps[i] = 14 - ceil(log2(prod of the listed maxima)) so that the scaled
@@ -325,11 +408,12 @@ __global__ void scale_exponents_kernel(const unsigned long long* mx, int nbops, 
 }
 
 static void absmax(const double* x, int64_t count, unsigned long long* out, hipStream_t s) {
-  unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 2048);
+  unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 512);
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, s, x, count, out);
 }
 
+// mx: 4 u64, exps: 2 int (device)
 static void scale_setup(const double* A, int64_t na, const double* const* B, const int64_t* nb,
                         int nbops, int fp16, unsigned long long* mx, int* exps, hipStream_t s) {
   RS_HIP(hipMemsetAsync(mx, 0, 4 * sizeof(unsigned long long), s));
@@ -338,67 +422,144 @@ static void scale_setup(const double* A, int64_t na, const double* const* B, con
   hipLaunchKernelGGL(scale_exponents_kernel, dim3(1), dim3(64), 0, s, mx, nbops, fp16, exps);
 }
 
+static unsigned grid_blocks(int64_t total) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+}
+
+template <class SP>
+static void split_planes(const double* src, int64_t rows, int64_t cols, int64_t s_row,
+                         int64_t s_col, int64_t kp, const int* exps, int which,
+                         typename SP::T* out, hipStream_t s) {
+  const unsigned gx = (unsigned)((kp + 255) / 256);
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, 8192));
+  hipLaunchKernelGGL(split_planes_kernel<SP>, dim3(gx, gy), dim3(256), 0, s, src, rows, (int)cols,
+                     s_row, s_col, (int)kp, exps, which, out);
+}
+
+// ---- core ------------------------------------------------------------------------
+struct CoreMixedPlan {
+  int64_t kp, kchunk;
+  int splits, row_chunks, col_groups;
+  size_t o_mx, o_exps, o_planes, o_s2, o_u3, o_part, total;
+};
+
+static CoreMixedPlan plan_core_mixed(int r1, int r2, int r3, int64_t K, int num_cu) {
+  CoreMixedPlan P{};
+  P.kp = pad32(K);
+  P.row_chunks = (r1 + 95) / 96;
+  P.col_groups = (int)(((int64_t)r2 * r3 + 63) / 64);
+  const int64_t wgs = (int64_t)P.row_chunks * P.col_groups;
+  P.splits = 1;
+  if (wgs < 2LL * num_cu) {
+    const int64_t want = (2LL * num_cu + wgs - 1) / wgs;
+    P.splits = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(P.kp / KCHUNK, 64)));
+  }
+  P.kchunk = (P.kp + P.splits - 1) / P.splits;
+  P.kchunk = (P.kchunk + 31) / 32 * 32;
+  P.splits = (int)((P.kp + P.kchunk - 1) / P.kchunk);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  P.o_mx = take(4 * sizeof(unsigned long long));
+  P.o_exps = take(2 * sizeof(int));
+  P.o_planes = take((size_t)3 * r1 * P.kp * 2);     // up to 3 terms of 2 bytes
+  P.o_s2 = take((size_t)r2 * P.kp * sizeof(float));
+  P.o_u3 = take((size_t)r3 * P.kp * sizeof(float));
+  P.o_part = take(P.splits > 1 ? (size_t)P.splits * r1 * r2 * r3 * sizeof(double) : 0);
+  P.total = off;
+  return P;
+}
+
 size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
-  const int tm = (r1 + XBM - 1) / XBM;
-  const int64_t tn = ((int64_t)r2 * r3 + XBN - 1) / XBN;
-  const int64_t tiles = tm * tn;
-  int splits = 1;
-  if (tiles < 2LL * num_cu && K > 4 * KCHUNK)
-    splits = (int)std::min<int64_t>((2LL * num_cu + tiles - 1) / tiles,
-                                    std::min<int64_t>(K / (2 * KCHUNK), 64));
-  if (splits < 1) splits = 1;
-  return (splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0) + 64;
+  return plan_core_mixed(r1, r2, r3, K, num_cu).total;
+}
+
+template <class SP>
+static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const double* U3t,
+                         const double* xi, int r1, int r2, int r3, int64_t K, double* beta,
+                         int num_cu, char* work, hipStream_t s) {
+  const CoreMixedPlan P = plan_core_mixed(r1, r2, r3, K, num_cu);
+  unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
+  int* exps = (int*)(work + P.o_exps);
+  typename SP::T* planes = (typename SP::T*)(work + P.o_planes);
+  float* s2 = (float*)(work + P.o_s2);
+  float* u3 = (float*)(work + P.o_u3);
+  double* part = P.splits > 1 ? (double*)(work + P.o_part) : nullptr;
+  const double* Bops[3] = {xi, U2t, U3t};
+  const int64_t nb[3] = {K, K * r2, K * r3};
+  scale_setup(U1t, K * r1, Bops, nb, 3, fp16, mx, exps, s);
+  // A = U~1^T: row a, column j at U1t[j r1 + a]
+  split_planes<SP>(U1t, r1, K, 1, r1, P.kp, exps, 0, planes, s);
+  hipLaunchKernelGGL(kr_factors_kernel, dim3(grid_blocks((int64_t)(r2 + r3) * P.kp)), dim3(256), 0,
+                     s, U2t, U3t, xi, r2, r3, K, P.kp, s2, u3);
+  const dim3 grid((unsigned)P.col_groups, (unsigned)P.row_chunks, (unsigned)P.splits);
+  double* out = part ? part : beta;
+  hipLaunchKernelGGL(core_split_kernel<SP>, grid, dim3(256), 0, s, planes, s2, u3, r1, r2, r3, P.kp,
+                     P.kchunk, out, (int64_t)r1 * r2 * r3, exps);
+  if (part) core64_reduce(part, P.splits, (int64_t)r1 * r2 * r3, beta, s);
 }
 
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
                 hipStream_t s) {
-  const int tm = (r1 + XBM - 1) / XBM;
-  const int tn = (int)(((int64_t)r2 * r3 + XBN - 1) / XBN);
-  const int64_t tiles = (int64_t)tm * tn;
-  int splits = 1;
-  if (tiles < 2LL * num_cu && K > 4 * KCHUNK)
-    splits = (int)std::min<int64_t>((2LL * num_cu + tiles - 1) / tiles,
-                                    std::min<int64_t>(K / (2 * KCHUNK), 64));
-  if (splits < 1) splits = 1;
-  int64_t kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + KCHUNK - 1) / KCHUNK * KCHUNK;
-  splits = (int)((K + kchunk - 1) / kchunk);
-  const size_t part_bytes = splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0;
-  double* part = splits > 1 ? work : nullptr;
-  // scale exponents after the partial buffer (64 bytes reserved)
-  unsigned long long* mx = (unsigned long long*)((char*)work + part_bytes);
-  DevBuf ex(2 * sizeof(int), s);
-  const double* Bops[3] = {xi, U2t, U3t};
-  const int64_t nb[3] = {K, K * r2, K * r3};
-  scale_setup(U1t, K * r1, Bops, nb, 3, prec == RS_MIXED_FP16, mx, ex.as<int>(), s);
-  KRSrc kr{U2t, U3t, xi, r2, r3};
-  dim3 grid((unsigned)tiles, 1, (unsigned)splits);
   if (prec == RS_MIXED_FP16)
-    hipLaunchKernelGGL(core_mixed_kernel<SplitF16>, grid, dim3(256), 0, s, U1t, kr, r1, K, kchunk,
-                       tn, beta, part, ex.as<int>());
+    core_mixed_t<SplitF16>(1, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s);
   else
-    hipLaunchKernelGGL(core_mixed_kernel<SplitBF16>, grid, dim3(256), 0, s, U1t, kr, r1, K, kchunk,
-                       tn, beta, part, ex.as<int>());
-  if (splits > 1) core64_reduce(part, splits, (int64_t)r1 * r2 * r3, beta, s);
+    core_mixed_t<SplitBF16>(0, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s);
+}
+
+// ---- grid ------------------------------------------------------------------------
+struct GridMixedPlan {
+  int64_t kp;
+  size_t o_mx, o_exps, o_a, o_b, total;
+};
+
+static GridMixedPlan plan_grid_mixed(int64_t n, int r3) {
+  GridMixedPlan P{};
+  P.kp = pad32(r3);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  P.o_mx = take(4 * sizeof(unsigned long long));
+  P.o_exps = take(2 * sizeof(int));
+  P.o_a = take((size_t)3 * n * n * P.kp * 2);
+  P.o_b = take((size_t)3 * n * P.kp * 2);
+  P.total = off;
+  return P;
+}
+
+size_t grid_mixed_workspace_bytes(int64_t n, int r3) { return plan_grid_mixed(n, r3).total; }
+
+template <class SP>
+static void grid_mixed_t(int fp16, const double* T2, const double* V3, int64_t n, int r3,
+                         float* grid, char* work, hipStream_t s) {
+  const GridMixedPlan P = plan_grid_mixed(n, r3);
+  unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
+  int* exps = (int*)(work + P.o_exps);
+  typename SP::T* ap = (typename SP::T*)(work + P.o_a);
+  typename SP::T* bp = (typename SP::T*)(work + P.o_b);
+  const double* Bops[1] = {V3};
+  const int64_t nb[1] = {n * r3};
+  scale_setup(T2, n * n * r3, Bops, nb, 1, fp16, mx, exps, s);
+  split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
+  split_planes<SP>(V3, n, r3, r3, 1, P.kp, exps, 1, bp, s);
+  const int64_t M = n * n;
+  const int tiles_m = (int)((M + 63) / 64), tiles_n = (int)((n + 127) / 128);
+  const int remap = (tiles_m % 8 == 0 && tiles_n > 1) ? 1 : 0;
+  hipLaunchKernelGGL(grid_split_kernel<SP>, dim3((unsigned)((int64_t)tiles_m * tiles_n)), dim3(256),
+                     0, s, ap, bp, M, n, P.kp, tiles_n, remap, grid, exps);
 }
 
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                hipStream_t s) {
-  DevBuf mxb(4 * sizeof(unsigned long long), s);
-  DevBuf ex(2 * sizeof(int), s);
-  const double* Bops[1] = {V3};
-  const int64_t nb[1] = {n * r3};
-  scale_setup(T2, n * n * r3, Bops, nb, 1, prec == RS_MIXED_FP16, mxb.as<unsigned long long>(),
-              ex.as<int>(), s);
-  const int tn = (int)((n + XBN - 1) / XBN);
-  const int64_t tiles = ((n * n + XBM - 1) / XBM) * tn;
-  if (prec == RS_MIXED_FP16)
-    hipLaunchKernelGGL(grid_mixed_kernel<SplitF16>, dim3((unsigned)tiles), dim3(256), 0, s, T2, V3, n,
-                       r3, tn, grid, ex.as<int>());
-  else
-    hipLaunchKernelGGL(grid_mixed_kernel<SplitBF16>, dim3((unsigned)tiles), dim3(256), 0, s, T2, V3,
-                       n, r3, tn, grid, ex.as<int>());
+                void* work, hipStream_t s) {
+  if (prec == RS_MIXED_FP16) grid_mixed_t<SplitF16>(1, T2, V3, n, r3, grid, (char*)work, s);
+  else grid_mixed_t<SplitBF16>(0, T2, V3, n, r3, grid, (char*)work, s);
 }
 
 }  // namespace rs

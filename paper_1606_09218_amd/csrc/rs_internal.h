@@ -204,9 +204,11 @@ size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu)
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
                 hipStream_t s);
-// FP32 grid[(i1 i2), i3] = sum_c T2[(i1 i2), c] V3[i3, c]
+// FP32 grid[(i1 i2), i3] = sum_c T2[(i1 i2), c] V3[i3, c]; work holds
+// grid_mixed_workspace_bytes(n, r3) bytes
+size_t grid_mixed_workspace_bytes(int64_t n, int r3);
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                hipStream_t s);
+                void* work, hipStream_t s);
 
 // k_short.hip
 struct ShortBins {

@@ -445,7 +445,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
           g.upper_only = 1;
           DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
           gemm64(g, ncu, wk.as<double>(), s);
-          launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, s);
+          launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, 1, s);
           launch_trsm_rows(Yp, Cq.as<double>(), n, p, 3, ctx->lds_limit, s);
         }
       };
@@ -481,28 +481,34 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     mark_eig(T.get(), 1, s);
     launch_eig_tridiag(Bm.as<double>(), ews.as<double>(), p, rc, 3, ctx->lds_limit, s);
     mark_eig(T.get(), 2, s);
-    launch_eig_values_vectors(Bm.as<double>(), ews.as<double>(), Z.as<double>(), p, rc, 3, s);
+    launch_eig_values_vectors(Bm.as<double>(), ews.as<double>(), Z.as<double>(), p, rc, 3,
+                              ctx->lds_limit, s);
     mark_eig(T.get(), 3, s);
-    {
-      // Cholesky QR of the eigenvectors in eigenvalue order: one shifted pass,
-      // then two plain passes
-      DevBuf Cz((size_t)3 * rc * rc * sizeof(double), s);
-      for (int pass = 0; pass < 3; ++pass) {
-        Gemm64 g;  // C = Z^T Z (symmetric)
-        g.M = rc; g.N = rc; g.K = p; g.batch = 3;
-        g.A = Z.as<double>(); g.sam = 1; g.sak = rc; g.sab = (int64_t)p * rc;
-        g.B = Z.as<double>(); g.sbk = rc; g.sbn = 1; g.sbb = (int64_t)p * rc;
-        g.C = Cz.as<double>(); g.scm = rc; g.scn = 1; g.scb = (int64_t)rc * rc;
-        g.upper_only = 1;
-        DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-        gemm64(g, ncu, wk.as<double>(), s);
-        launch_chol(Cz.as<double>(), rc, p, 3, pass == 0, ctx->lds_limit, &rbd->chol_fail, s);
+    // Cholesky QR of the eigenvectors in eigenvalue order.  Inverse
+    // iteration leaves them nearly orthonormal, so two plain passes suffice;
+    // a breakdown (near-parallel vectors, flag bit 4) is redone from the
+    // saved vectors with a shifted pass first, after the readback.
+    DevBuf Zsave((size_t)3 * p * rc * sizeof(double), s);
+    RS_HIP(hipMemcpyAsync(Zsave.p, Z.p, Zsave.bytes, hipMemcpyDeviceToDevice, s));
+    DevBuf Cz((size_t)3 * rc * rc * sizeof(double), s);
+    Gemm64 gz;  // C = Z^T Z (symmetric)
+    gz.M = rc; gz.N = rc; gz.K = p; gz.batch = 3;
+    gz.A = Z.as<double>(); gz.sam = 1; gz.sak = rc; gz.sab = (int64_t)p * rc;
+    gz.B = Z.as<double>(); gz.sbk = rc; gz.sbn = 1; gz.sbb = (int64_t)p * rc;
+    gz.C = Cz.as<double>(); gz.scm = rc; gz.scn = 1; gz.scb = (int64_t)rc * rc;
+    gz.upper_only = 1;
+    DevBuf wkz(gemm64_workspace_bytes(gz, ncu), s);
+    auto orth_z = [&](int passes, bool shifted_first, int fail_bit) {
+      for (int pass = 0; pass < passes; ++pass) {
+        gemm64(gz, ncu, wkz.as<double>(), s);
+        launch_chol(Cz.as<double>(), rc, p, 3, shifted_first && pass == 0, ctx->lds_limit,
+                    &rbd->chol_fail, fail_bit, s);
         launch_trsm_rows(Z.as<double>(), Cz.as<double>(), p, rc, 3, ctx->lds_limit, s);
       }
-    }
+    };
+    orth_z(2, false, 4);
     launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
     mark_eig(T.get(), 4, s);
-    ews.reset();
     DevBuf perm((size_t)3 * p * sizeof(int), s);
     DevBuf fixed_dev(3 * sizeof(int), s);
     RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
@@ -526,6 +532,16 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     if (host.flags & 1) throw Error{RS_E_INVALID, "non-finite particle position or charge"};
     if (host.flags & 2) throw Error{RS_E_INVALID, "particle outside the box [-b, b]^3"};
     if (host.chol_fail & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the subspace basis"};
+    if (host.chol_fail & 4) {
+      // rare path: redo the eigenvector orthonormalisation robustly
+      RS_HIP(hipMemcpyAsync(Z.p, Zsave.p, Zsave.bytes, hipMemcpyDeviceToDevice, s));
+      orth_z(3, true, 1);
+      launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
+      int again = 0;
+      RS_HIP(hipMemcpyAsync(&again, &rbd->chol_fail, sizeof(int), hipMemcpyDeviceToHost, s));
+      RS_HIP(hipStreamSynchronize(s));
+      if (again & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the eigenvectors"};
+    }
 
     for (int l = 0; l < 3; ++l) {
       T->r[l] = host.info.r[l];

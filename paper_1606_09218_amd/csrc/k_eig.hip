@@ -61,6 +61,38 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Cross-lane sums on the data-parallel-primitive (DPP) path: a row of 16
+// lanes is reduced with quad_perm (xor 1, xor 2), row_half_mirror and
+// row_mirror moves, rows are combined with readlane.  Every stage adds
+// symmetric pairs, so all lanes end with bitwise-identical sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of each row (all lanes of the row receive it)
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_mov_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov_f64<0x141>(v);   // row_half_mirror
+  v += dpp_mov_f64<0x140>(v);   // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the whole wave (uniform result)
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = row_sum16(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 __global__ void symmetrize_kernel(double* B, int p) {
   double* Bm = B + (int64_t)blockIdx.y * p * p;
   int64_t total = (int64_t)p * p;
@@ -211,7 +243,7 @@ constexpr int CF_THREADS = 256;   // Cholesky factorisation workgroup (16 x 16 l
 template <bool LDS>
 __global__ __launch_bounds__(CF_THREADS) void chol_kernel(double* __restrict__ Call, int p,
                                                           int64_t nrows, int shifted,
-                                                          int* __restrict__ fail) {
+                                                          int* __restrict__ fail, int fail_bit) {
   extern __shared__ double shc[];
   __shared__ double red[CF_THREADS / 64];
   __shared__ double piv_s;
@@ -246,7 +278,7 @@ __global__ __launch_bounds__(CF_THREADS) void chol_kernel(double* __restrict__ C
   for (int k = 0; k < p; ++k) {
     double d = C[k * p + k];
     if (!(d > 0.0)) {
-      if (tid == 0) atomicOr(fail, 1);
+      if (tid == 0) atomicOr(fail, fail_bit);
       d = 1e-300;
     }
     const double invd = 1.0 / d;
@@ -312,10 +344,155 @@ __device__ __forceinline__ void chol_reg_steps(double (&c)[RT][RT], double (&col
   }
 }
 
+// Blocked form of the register Cholesky: panels of 4 columns.  The 4
+// columns k0..k0+3 (k0 a multiple of 4) are held by the threads ty = k0 % 16
+// .. + 3, which form exactly one wave.  That wave publishes them in LDS,
+// factors the 4 x 4 diagonal block (every lane redundantly), solves the
+// panel rows (2 rows per lane), writes column k0..k0+3 of L to memory and
+// the scaled panel to LDS; after one barrier every thread applies the rank-4
+// update to its entries on or below the diagonal.
+template <int RT, int KB>
+__device__ __forceinline__ void chol4_steps(double (&c)[RT][RT], double (&colk)[2][4][16 * RT],
+                                            double (&lpan)[2][4][16 * RT], double* __restrict__ C,
+                                            int p, int tx, int ty, int tid, bool& bad) {
+  if constexpr (KB < RT) {
+#pragma unroll 1
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int k0 = 16 * KB + 4 * s4;
+      if (k0 >= p) return;
+      const int buf = s4 & 1;
+      const int kk0 = 4 * s4;
+      if ((tid >> 6) == s4) {
+        // the owner wave: lane = tx + 16 (ty - kk0)
+        const int cc = ty - kk0;
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const int i = tx + 16 * a;
+          colk[buf][cc][i] = (i >= k0 && k0 + cc < p) ? c[a][KB] : 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // 4 x 4 diagonal block (columns beyond p act as identity)
+        double Ld[4][4], dinv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double sdiag = k0 + q < p ? colk[buf][q][k0 + q] : 1.0;
+#pragma unroll
+          for (int m = 0; m < q; ++m) sdiag -= Ld[q][m] * Ld[q][m];
+          if (k0 + q < p) bad |= !(sdiag > 0.0);
+          sdiag = sdiag > 0.0 ? sdiag : 1e-300;
+          const double sq = sqrt(sdiag);
+          dinv[q] = 1.0 / sq;
+          Ld[q][q] = sq;
+#pragma unroll
+          for (int r = q + 1; r < 4; ++r) {
+            double x = (k0 + r < p && k0 + q < p) ? colk[buf][q][k0 + r] : 0.0;
+#pragma unroll
+            for (int m = 0; m < q; ++m) x -= Ld[r][m] * Ld[q][m];
+            Ld[r][q] = x * dinv[q];
+          }
+        }
+        // panel rows i = lane, lane + 64 (i >= k0 + 4), the diagonal block rows from Ld
+        const int lane = tid & 63;
+#pragma unroll
+        for (int h = 0; h < 2 * RT / 8 + 1; ++h) {
+          const int i = lane + 64 * h;
+          if (i < 16 * RT) {
+            double l[4];
+            if (i >= k0 + 4) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                double x = colk[buf][q][i];
+#pragma unroll
+                for (int m = 0; m < q; ++m) x -= l[m] * Ld[q][m];
+                l[q] = x * dinv[q];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                l[q] = 0.0;
+#pragma unroll
+                for (int r = q; r < 4; ++r)
+                  if (i == k0 + r) l[q] = Ld[r][q];
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              lpan[buf][q][i] = i >= k0 + 4 ? l[q] : 0.0;
+              if (i >= k0 && i < p && k0 + q < p && i >= k0 + q) C[(int64_t)(k0 + q) * p + i] = l[q];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      double li[RT][4], lj[RT][4];
+#pragma unroll
+      for (int a = KB; a < RT; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) li[a][q] = lpan[buf][q][tx + 16 * a];
+#pragma unroll
+      for (int b = KB; b < RT; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lj[b][q] = lpan[buf][q][ty + 16 * b];
+#pragma unroll
+      for (int a = KB; a < RT; ++a)
+#pragma unroll
+        for (int b = KB; b <= a; ++b) {
+          double v = c[a][b];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v = fma(-li[a][q], lj[b][q], v);
+          c[a][b] = v;
+        }
+    }
+    chol4_steps<RT, KB + 1>(c, colk, lpan, C, p, tx, ty, tid, bad);
+  }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void chol4_reg_kernel(double* __restrict__ Call, int p,
+                                                        int64_t nrows, int shifted,
+                                                        int* __restrict__ fail, int fail_bit) {
+  __shared__ double colk[2][4][16 * RT];
+  __shared__ double lpan[2][4][16 * RT];
+  __shared__ double red[4];
+  const int mode = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double* C = Call + (int64_t)mode * p * p;
+  double c[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tx + 16 * a, j = ty + 16 * b;
+      c[a][b] = (i < p && j < p && i >= j) ? C[(int64_t)j * p + i] : 0.0;
+    }
+  if (shifted) {
+    double tr = 0.0;
+    if (tx == ty)
+#pragma unroll
+      for (int a = 0; a < RT; ++a) tr += c[a][a];
+    tr = wave_sum(tr);
+    if ((tid & 63) == 0) red[tid >> 6] = tr;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    const double shift = 11.0 * ((double)nrows * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * t;
+    if (tx == ty)
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+        if (tx + 16 * a < p) c[a][a] += shift;
+  }
+  __syncthreads();   // all reads of C precede the first write of L
+  bool bad = false;
+  chol4_steps<RT, 0>(c, colk, lpan, C, p, tx, ty, tid, bad);
+  if (bad) atomicOr(fail, fail_bit);
+}
+
 template <int RT>
 __global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call, int p,
                                                        int64_t nrows, int shifted,
-                                                       int* __restrict__ fail) {
+                                                       int* __restrict__ fail, int fail_bit) {
   __shared__ double colk[2][16 * RT];
   __shared__ double red[4];
   const int mode = blockIdx.x;
@@ -349,14 +526,7 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(double* __restrict__ Call
   __syncthreads();   // all reads of C and the zero fill precede the first step
   bool bad = false;
   chol_reg_steps<RT, 0>(c, colk, C, p, tx, ty, tid, bad);
-  if (bad && tid == 0) atomicOr(fail, 1);
-}
-
-// value of lane l (uniform l) of a double held across the wave
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
+  if (bad && tid == 0) atomicOr(fail, fail_bit);
 }
 
 // Y[i, :] <- Y[i, :] L^{-T} for row-major Y (n x p): one wave per row, the
@@ -393,22 +563,34 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
     const int c = lane + 64 * u;
     y[u] = c < p ? Y[c] : 0.0;
   }
+  // steps in groups of D: the L entries and reciprocal pivots of a group are
+  // loaded before its dependent chain of substitutions
+  constexpr int D = RPL <= 2 ? 8 : 4;
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
-    for (int cc = 0; cc < 64; ++cc) {
-      const int c = 64 * u + cc;
-      if (c >= p) break;
-      const double* Lc = LDS ? sht + c * p - c * (c - 1) / 2 : L + (int64_t)c * p + c;
-      const double x = LDS ? readlane_f64(y[u], cc) * sht[packed + c] : readlane_f64(y[u], cc) / Lc[0];
-      if (lane == cc) y[u] = x;
-      if (lane > cc) {
-        const int i = 64 * u + lane;
-        if (i < p) y[u] -= x * Lc[i - c];
+    for (int cc0 = 0; cc0 < 64; cc0 += D) {
+      const int c0 = 64 * u + cc0;
+      if (c0 >= p) break;
+      double lv[D][RPL], rdg[D];
+#pragma unroll
+      for (int t = 0; t < D; ++t) {
+        const int c = c0 + t < p ? c0 + t : p - 1;
+        const double* Lc = LDS ? sht + c * p - c * (c - 1) / 2 : L + (int64_t)c * p + c;
+        rdg[t] = LDS ? sht[packed + c] : 1.0 / Lc[0];
+#pragma unroll
+        for (int u2 = u; u2 < RPL; ++u2) {
+          const int i = 64 * u2 + lane;
+          lv[t][u2] = (i > c && i < p) ? Lc[i - c] : 0.0;
+        }
       }
 #pragma unroll
-      for (int u2 = u + 1; u2 < RPL; ++u2) {
-        const int i = 64 * u2 + lane;
-        if (i < p) y[u2] -= x * Lc[i - c];
+      for (int t = 0; t < D; ++t) {
+        const int cc = cc0 + t;
+        if (c0 + t >= p) break;
+        const double x = lane_f64(y[u], cc) * rdg[t];
+        if (lane == cc) y[u] = x;
+#pragma unroll
+        for (int u2 = u; u2 < RPL; ++u2) y[u2] -= x * lv[t][u2];
       }
     }
   }
@@ -426,23 +608,25 @@ static void allow_lds(const void* fn, size_t bytes) {
 }
 
 void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit, int* fail,
-                 hipStream_t s) {
+                 int fail_bit, hipStream_t s) {
   if (p <= 64) {
-    hipLaunchKernelGGL(chol_reg_kernel<4>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail);
+    hipLaunchKernelGGL(chol_reg_kernel<4>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail,
+                       fail_bit);
     return;
   }
   if (p <= 128) {
-    hipLaunchKernelGGL(chol_reg_kernel<8>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail);
+    hipLaunchKernelGGL(chol4_reg_kernel<8>, dim3(modes), dim3(256), 0, s, C, p, nrows, shifted, fail,
+                       fail_bit);
     return;
   }
   const size_t bytes = (size_t)p * p * sizeof(double);
   if (bytes + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)chol_kernel<true>, bytes);
     hipLaunchKernelGGL(chol_kernel<true>, dim3(modes), dim3(CF_THREADS), bytes, s, C, p, nrows,
-                       shifted, fail);
+                       shifted, fail, fail_bit);
   } else {
     hipLaunchKernelGGL(chol_kernel<false>, dim3(modes), dim3(CF_THREADS), 0, s, C, p, nrows,
-                       shifted, fail);
+                       shifted, fail, fail_bit);
   }
 }
 
@@ -552,14 +736,6 @@ size_t eig_sym_workspace_bytes(int p, int rc, int modes) {
   return (size_t)modes * ((size_t)p * p + 4 * (size_t)p + 2 * (size_t)p * rc) * sizeof(double);
 }
 
-__device__ __forceinline__ double sum16(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
-  return v;
-}
-
 // Householder tridiagonalisation with B in registers, for p <= 16 RT: thread
 // (tx, ty) of a 16 x 16 grid holds B[i, j] for i = tx + 16 a, j = ty + 16 b.
 // Step k: the 16 threads holding column k form the Householder vector and
@@ -593,9 +769,9 @@ __device__ __forceinline__ void tridiag_reg_steps(double (&c)[RT][RT], TriLds& L
           if (i == k + 1) x1 = x;
           if (i == k) dk = x;
         }
-        const double sigma = sum16(ss);
-        x1 = sum16(x1);
-        dk = sum16(dk);
+        const double sigma = row_sum16(ss);
+        x1 = row_sum16(x1);
+        dk = row_sum16(dk);
         double beta = 0.0, v1 = 1.0, sub = x1;
         if (sigma > 0.0) {
           const double mu = sqrt(x1 * x1 + sigma);
@@ -651,7 +827,7 @@ __device__ __forceinline__ void tridiag_reg_steps(double (&c)[RT][RT], TriLds& L
         const double w = beta * ((L.part[s][0][j] + L.part[s][1][j]) + (L.part[s][2][j] + L.part[s][3][j]));
         wj[b] = (j > k && j < p) ? w : 0.0;
       }
-      const double kc = 0.5 * beta * sum16(t);
+      const double kc = 0.5 * beta * row_sum16(t);
 #pragma unroll
       for (int a = KB; a < RT; ++a) wi[a] = fma(-kc, vi[a], wi[a]);
 #pragma unroll
@@ -799,15 +975,27 @@ __global__ __launch_bounds__(ES_THREADS) void tridiag_kernel(double* __restrict_
   }
 }
 
+// 1/q for finite nonzero q: the hardware reciprocal estimate refined by two
+// Newton steps t <- t + t (1 - q t) (each roughly doubles the correct bits).
+__device__ __forceinline__ double recip(double q) {
+  double t = __builtin_amdgcn_rcp(q);
+  t = fma(t, fma(-q, t, 1.0), t);
+  t = fma(t, fma(-q, t, 1.0), t);
+  return t;
+}
+
 // Number of eigenvalues of T below x (Sturm count on the LDL^T pivots of
-// T - x I), with tiny pivots replaced by -pivmin.
+// T - x I), with tiny pivots replaced by -pivmin and huge ones clamped so
+// that the reciprocal stays finite.
 __device__ __forceinline__ int sturm_count(const double* d, const double* ee, int p, double x,
                                            double pivmin) {
+  const double big = 1e300;
   double q = d[0] - x;
   if (fabs(q) <= pivmin) q = -pivmin;
   int c = q < 0.0;
   for (int i = 1; i < p; ++i) {
-    q = (d[i] - x) - ee[i - 1] / q;
+    q = fmin(fmax(q, -big), big);
+    q = (d[i] - x) - ee[i - 1] * recip(q);
     if (fabs(q) <= pivmin) q = -pivmin;
     c += q < 0.0;
   }
@@ -986,6 +1174,72 @@ __global__ __launch_bounds__(256) void invit_kernel(double* __restrict__ ws,
   for (int i = 0; i < p; ++i) z[i * ld] *= s;
 }
 
+// The same inverse iteration with the per-vector arrays in LDS ([array][i][t],
+// t the thread, so that a wavefront touches consecutive words) for TPB
+// vectors per workgroup; d and e are shared.
+template <int TPB>
+__global__ __launch_bounds__(TPB) void invit_lds_kernel(double* __restrict__ ws,
+                                                        double* __restrict__ Zall, int p, int rc,
+                                                        uint64_t seed) {
+  extern __shared__ double shi[];
+  const int mode = blockIdx.y;
+  const int t = threadIdx.x;
+  EigWs W(ws, p, rc, mode);
+  double* dS = shi;
+  double* eS = shi + p;
+  double* lm = shi + 2 * p + t;
+  double* ru = lm + (int64_t)p * TPB;
+  double* z = ru + (int64_t)p * TPB;
+  for (int i = t; i < p; i += TPB) {
+    dS[i] = W.d[i];
+    eS[i] = W.e[i];
+  }
+  __syncthreads();
+  const int j = blockIdx.x * TPB + t;
+  if (j >= rc) return;
+  const double lam = W.lam[j];
+  const double u = 1.1102230246251565e-16;
+  const double tiny = u * fmax(fmax(fabs(W.lam[0]), fabs(W.lam[p - 1])), 1e-280);
+  double up = dS[0] - lam;
+  if (fabs(up) < tiny) up = up < 0.0 ? -tiny : tiny;
+  double rprev = recip(up);
+  lm[0] = 0.0;
+  ru[0] = rprev;
+  for (int i = 1; i < p; ++i) {
+    const double ei = eS[i - 1];
+    const double l = ei * rprev;
+    up = (dS[i] - lam) - l * ei;
+    if (fabs(up) < tiny) up = up < 0.0 ? -tiny : tiny;
+    rprev = recip(up);
+    lm[i * TPB] = l;
+    ru[i * TPB] = rprev;
+  }
+  for (int i = 0; i < p; ++i) z[i * TPB] = hash_uniform(seed + mode, (uint64_t)j, (uint64_t)i);
+  double scale = 1.0;
+  for (int it = 0; it < 3; ++it) {
+    double prev = 0.0;
+    for (int i = 0; i < p; ++i) {
+      prev = scale * z[i * TPB] - lm[i * TPB] * prev;
+      z[i * TPB] = prev;
+    }
+    double nxt = 0.0, mx = 0.0;
+    for (int i = p - 1; i >= 0; --i) {
+      nxt = (z[i * TPB] - eS[i] * nxt) * ru[i * TPB];
+      z[i * TPB] = nxt;
+      mx = fmax(mx, fabs(nxt));
+    }
+    scale = mx > 0.0 ? 1.0 / mx : 1.0;
+  }
+  double nrm = 0.0;
+  for (int i = 0; i < p; ++i) {
+    const double v = scale * z[i * TPB];
+    nrm += v * v;
+  }
+  const double sc = nrm > 0.0 ? scale / sqrt(nrm) : 0.0;
+  double* zg = Zall + (int64_t)mode * p * rc + j;
+  for (int i = 0; i < p; ++i) zg[(int64_t)i * rc] = z[i * TPB] * sc;
+}
+
 // Z (p x rc row-major per mode) <- H_0 H_1 ... H_{p-3} Z, H_k = I - beta_k v_k v_k^T:
 // one wave per column, the column in registers (lane l keeps rows l, l + 64, ...).
 template <int UPL>
@@ -1016,7 +1270,7 @@ __global__ __launch_bounds__(256) void reflect_cols_kernel(double* __restrict__ 
       vv[u] = i == k + 1 ? 1.0 : ((i >= k + 2 && i < p) ? v[i] : 0.0);
       part = fma(vv[u], y[u], part);
     }
-    const double dot = beta * wave_sum(part);
+    const double dot = beta * wave_sum_dpp(part);
 #pragma unroll
     for (int u = 0; u < UPL; ++u) y[u] = fma(-dot, vv[u], y[u]);
   }
@@ -1050,12 +1304,20 @@ void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds
 }
 
 void launch_eig_values_vectors(double* B, double* ws, double* Z, int p, int rc, int modes,
-                               hipStream_t s) {
+                               int lds_limit, hipStream_t s) {
   if (rc < 1 || rc > p) throw Error{RS_E_INVALID, "eigensolver: wanted vectors outside [1, p]"};
   hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((p + BIS_WAVES - 1) / BIS_WAVES), modes),
                      dim3(64 * BIS_WAVES), 2 * (size_t)p * sizeof(double), s, B, ws, p, rc);
-  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((rc + 255) / 256), modes), dim3(256), 0, s, ws,
-                     Z, p, rc, 0x1a2b3c4d5e6fULL);
+  constexpr int TPB = 32;
+  const size_t inv_lds = ((size_t)2 * p + (size_t)3 * p * TPB) * sizeof(double);
+  if (inv_lds + 1024 <= (size_t)lds_limit) {
+    allow_lds((const void*)invit_lds_kernel<TPB>, inv_lds);
+    hipLaunchKernelGGL(invit_lds_kernel<TPB>, dim3((unsigned)((rc + TPB - 1) / TPB), modes),
+                       dim3(TPB), inv_lds, s, ws, Z, p, rc, 0x1a2b3c4d5e6fULL);
+  } else {
+    hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((rc + 255) / 256), modes), dim3(256), 0, s,
+                       ws, Z, p, rc, 0x1a2b3c4d5e6fULL);
+  }
 }
 
 void launch_eig_backtransform(double* Z, double* ws, int p, int rc, int modes, hipStream_t s) {

@@ -156,9 +156,9 @@ void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uin
                     hipStream_t s);
 // Cholesky C = L L^T in place (lower, col-major), one workgroup per mode; the
 // shifted variant adds 11 (nrows p + p (p+1)) u tr(C) to the diagonal first.
-// fail |= 1 on a non-positive pivot.
+// fail |= fail_bit on a non-positive pivot.
 void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit, int* fail,
-                 hipStream_t s);
+                 int fail_bit, hipStream_t s);
 // Y (n x p row-major per mode) <- Y L^{-T}
 void launch_trsm_rows(double* Y, const double* L, int64_t n, int p, int modes, int lds_limit,
                       hipStream_t s);
@@ -174,7 +174,7 @@ size_t eig_sym_workspace_bytes(int p, int rc, int modes);
 void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds_limit,
                         hipStream_t s);
 void launch_eig_values_vectors(double* B, double* ws, double* Z, int p, int rc, int modes,
-                               hipStream_t s);
+                               int lds_limit, hipStream_t s);
 void launch_eig_backtransform(double* Z, double* ws, int p, int rc, int modes, hipStream_t s);
 // Sort eigenvalues descending, choose ranks; writes perm[mode][p], info doubles.
 struct RankInfo {

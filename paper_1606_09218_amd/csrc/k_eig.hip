@@ -737,101 +737,115 @@ size_t eig_sym_workspace_bytes(int p, int rc, int modes) {
 }
 
 // Householder tridiagonalisation with B in registers, for p <= 16 RT: thread
-// (tx, ty) of a 16 x 16 grid holds B[i, j] for i = tx + 16 a, j = ty + 16 b.
-// Step k: the 16 threads holding column k form the Householder vector and
-// publish it in LDS; every thread multiplies its block by v, partial sums
-// are combined over the ty lanes of a wave and then over the 4 waves in LDS
-// (two barriers per step, double-buffered); each thread then applies the
-// rank-2 update B22 -= v w^T + w v^T to its own entries.  Steps are grouped
-// by the column block KB = k / 16 (compile time): blocks of rows or columns
-// below KB are finished and skipped.
+// (tx, ty) of a 16 x 16 grid holds B[i, j] for i = tx + 16 a, j = ty + 16 b,
+// with tid = ty + 16 tx, so that the 16 lanes of a row share tx (the same
+// rows of B) and differ in ty (the columns).  Step k:
+//  1. the threads holding column k publish it in LDS (one barrier);
+//  2. every wave forms the Householder vector from that column (norm by a
+//     wave reduction, identical in all waves);
+//  3. each lane multiplies its block by v; the sum over the 16 lanes of a
+//     row gives (B22 v)_i in full for the wave's rows; it goes to LDS (one
+//     barrier);
+//  4. every wave forms kc = (beta/2) w^T v by a wave reduction and each
+//     thread applies the rank-2 update B22 -= v w^T + w v^T to its entries.
+// Steps are grouped by the column block KB = k / 16 (compile time): blocks
+// of rows or columns below KB are finished and skipped.
 struct TriLds {
-  double vb[2][128];
-  double part[2][4][128];
-  double beta[2];
+  double col[2][128];
+  double pw[2][128];
 };
 
 template <int RT, int KB>
 __device__ __forceinline__ void tridiag_reg_steps(double (&c)[RT][RT], TriLds& L, EigWs& W, int p,
                                                   int tx, int ty) {
   if constexpr (KB < RT) {
+    const int lane = threadIdx.x & 63;
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 16 * KB + kk;
       if (k + 2 >= p) return;
       const int s = k & 1;
+      // 1. publish column k (rows >= k), zeros above
       if (ty == kk) {
-        double ss = 0.0, x1 = 0.0, dk = 0.0;
-#pragma unroll
-        for (int a = KB; a < RT; ++a) {
-          const int i = tx + 16 * a;
-          const double x = c[a][KB];
-          if (i >= k + 2) ss = fma(x, x, ss);   // rows >= p hold zeros
-          if (i == k + 1) x1 = x;
-          if (i == k) dk = x;
-        }
-        const double sigma = row_sum16(ss);
-        x1 = row_sum16(x1);
-        dk = row_sum16(dk);
-        double beta = 0.0, v1 = 1.0, sub = x1;
-        if (sigma > 0.0) {
-          const double mu = sqrt(x1 * x1 + sigma);
-          v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
-          beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
-          sub = mu;
-        }
-        const double inv1 = 1.0 / v1;
 #pragma unroll
         for (int a = 0; a < RT; ++a) {
           const int i = tx + 16 * a;
-          const double v = (a >= KB && i >= k + 2) ? c[a][KB] * inv1 : (i == k + 1 ? 1.0 : 0.0);
-          L.vb[s][i] = v;
-          if (a >= KB && i >= k + 2 && i < p) W.hv[(int64_t)k * p + i] = v;
-        }
-        if (tx == 0) {
-          L.beta[s] = beta;
-          W.d[k] = dk;
-          W.e[k] = sub;
-          W.beta[k] = beta;
+          L.col[s][i] = (a >= KB && i >= k) ? c[a][KB] : 0.0;
         }
       }
       __syncthreads();
-      const double beta = L.beta[s];
+      // 2. Householder vector (every wave, uniform values)
+      const double* col = L.col[s];
+      double part = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        const double x = (i >= k + 2 && i < 16 * RT) ? col[i] : 0.0;
+        part = fma(x, x, part);
+      }
+      const double sigma = wave_sum_dpp(part);
+      const double x1 = col[k + 1];
+      double beta = 0.0, v1 = 1.0, sub = x1;
+      if (sigma > 0.0) {
+        const double mu = sqrt(x1 * x1 + sigma);
+        v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
+        beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        sub = mu;
+      }
+      const double inv1 = 1.0 / v1;
+      if (threadIdx.x < 64) {
+        if (lane == 0) {
+          W.d[k] = col[k];
+          W.e[k] = sub;
+          W.beta[k] = beta;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          if (i >= k + 2 && i < p) W.hv[(int64_t)k * p + i] = col[i] * inv1;
+        }
+      }
       if (beta == 0.0) continue;   // uniform: column already reduced
       double vi[RT], vj[RT];
 #pragma unroll
-      for (int a = KB; a < RT; ++a) vi[a] = L.vb[s][tx + 16 * a];
+      for (int a = KB; a < RT; ++a) {
+        const int i = tx + 16 * a;
+        vi[a] = i == k + 1 ? 1.0 : (i >= k + 2 ? col[i] * inv1 : 0.0);
+      }
 #pragma unroll
-      for (int b = KB; b < RT; ++b) vj[b] = L.vb[s][ty + 16 * b];
+      for (int b = KB; b < RT; ++b) {
+        const int j = ty + 16 * b;
+        vj[b] = j == k + 1 ? 1.0 : (j >= k + 2 ? col[j] * inv1 : 0.0);
+      }
+      // 3. (B22 v) for the rows of this thread, summed over the row's lanes
 #pragma unroll
       for (int a = KB; a < RT; ++a) {
         double acc = 0.0;
 #pragma unroll
         for (int b = KB; b < RT; ++b) acc = fma(c[a][b], vj[b], acc);
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
-        if ((ty & 3) == 0) L.part[s][ty >> 2][tx + 16 * a] = acc;
+        acc = row_sum16(acc);
+        if (ty == 0) L.pw[s][tx + 16 * a] = beta * acc;
       }
       __syncthreads();
-      double wi[RT], wj[RT];
+      // 4. w = pw - kc v with kc = (beta / 2) pw^T v, then the rank-2 update
+      const double* pw = L.pw[s];
       double t = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i > k && i < p) t = fma(pw[i], i == k + 1 ? 1.0 : col[i] * inv1, t);
+      }
+      const double kc = 0.5 * beta * wave_sum_dpp(t);
+      double wi[RT], wj[RT];
 #pragma unroll
       for (int a = KB; a < RT; ++a) {
         const int i = tx + 16 * a;
-        const double w = beta * ((L.part[s][0][i] + L.part[s][1][i]) + (L.part[s][2][i] + L.part[s][3][i]));
-        wi[a] = (i > k && i < p) ? w : 0.0;
-        t = fma(wi[a], vi[a], t);
+        wi[a] = (i > k && i < p) ? fma(-kc, vi[a], pw[i]) : 0.0;
       }
 #pragma unroll
       for (int b = KB; b < RT; ++b) {
         const int j = ty + 16 * b;
-        const double w = beta * ((L.part[s][0][j] + L.part[s][1][j]) + (L.part[s][2][j] + L.part[s][3][j]));
-        wj[b] = (j > k && j < p) ? w : 0.0;
+        wj[b] = (j > k && j < p) ? fma(-kc, vj[b], pw[j]) : 0.0;
       }
-      const double kc = 0.5 * beta * row_sum16(t);
-#pragma unroll
-      for (int a = KB; a < RT; ++a) wi[a] = fma(-kc, vi[a], wi[a]);
-#pragma unroll
-      for (int b = KB; b < RT; ++b) wj[b] = fma(-kc, vj[b], wj[b]);
 #pragma unroll
       for (int a = KB; a < RT; ++a)
 #pragma unroll
@@ -847,10 +861,11 @@ __global__ __launch_bounds__(256) void tridiag_reg_kernel(const double* __restri
   __shared__ TriLds L;
   const int mode = blockIdx.x;
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int ty = tid & 15, tx = tid >> 4;
   const double* Bg = Ball + (int64_t)mode * p * p;
   EigWs W(ws, p, rc, mode);
   double c[RT][RT];
+  // consecutive lanes (ty) read consecutive words of a row of B
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll

@@ -213,7 +213,7 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
     grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
-               scratch + e.wkg, s);
+               scratch + e.wkg, ncu, s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,

@@ -252,6 +252,146 @@ __global__ __launch_bounds__(256) void grid_split_kernel(const typename SP::T* _
     }
 }
 
+// ---- grid, streaming form -------------------------------------------------------
+// Persistent workgroups of 8 waves.  Workgroup (panel, group) keeps the B
+// planes of a panel of BN columns in LDS and walks the row tiles (128 rows:
+// 16 per wave) of its group; the A fragments of the next tile are loaded
+// while the current one is multiplied.  Each wave stages its 16 x BN FP32
+// tile in LDS and writes whole rows with 16-byte stores.  The panels of one
+// row group run on one XCD (workgroup w runs on XCD w % 8), so the A rows
+// they share are read from that XCD's L2.
+template <class SP, int BN, bool FOLD>
+__global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* __restrict__ Ap,
+                                                          const typename SP::T* __restrict__ Bp,
+                                                          int64_t M, int64_t N, int kp,
+                                                          int npanels, int groups,
+                                                          float* __restrict__ grid,
+                                                          const int* exps) {
+  typedef typename SP::T T;
+  typedef typename SP::V8 V8;
+  constexpr int FN = BN / 16;
+  constexpr int SLD = BN + 4;   // staging row stride (floats)
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  T* Bs = (T*)smem;                                          // [term][BN][kp]
+  float* stage = (float*)(smem + (size_t)SP::TERMS * BN * kp * sizeof(T));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = blockIdx.x;
+  const int xcd = w & 7, iw = w >> 3;
+  const int panel = iw % npanels;
+  const int g = (iw / npanels) * 8 + xcd;
+  const int64_t n0 = (int64_t)panel * BN;
+  // B panel to LDS (rows beyond N are zero)
+  const int64_t planeB = N * kp;
+  for (int e = threadIdx.x; e < SP::TERMS * BN * kp; e += 512) {
+    const int term = e / (BN * kp), rem = e - term * (BN * kp);
+    const int col = rem / kp, k = rem - col * kp;
+    Bs[e] = n0 + col < N ? Bp[term * planeB + (n0 + col) * kp + k] : (T)0.0f;
+  }
+  __syncthreads();
+  const int64_t tiles = (M + 127) / 128;
+  if (g >= groups) return;   // uniform over the workgroup, after the only barrier
+  const int64_t planeA = M * kp;
+  const int kofs = 8 * (lane >> 4);
+  const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
+  float* st = stage + wave * 16 * SLD;
+  auto arow_of = [&](int64_t tile) {
+    const int64_t r = tile * 128 + wave * 16 + (lane & 15);
+    return (r < M ? r : 0) * kp + kofs;
+  };
+  // A fragments of a whole row block (all k blocks) for the current and next tile
+  constexpr int KBMAX = 16;   // kp <= 512
+  const int nkb = kp / 32;
+  int64_t tile = g;
+  if (tile >= tiles) return;
+  int64_t arow = arow_of(tile);
+  for (; tile < tiles; tile += groups) {
+    const int64_t next = tile + groups;
+    const int64_t arow_next = next < tiles ? arow_of(next) : arow;
+    f4 acc[FN][SP::LEVELS];
+    double acc64[FOLD ? FN : 1][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int l = 0; l < SP::LEVELS; ++l) acc[j][l] = f4{0.f, 0.f, 0.f, 0.f};
+    if (FOLD)
+#pragma unroll
+      for (int j = 0; j < (FOLD ? FN : 1); ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[j][v] = 0.0;
+    V8 a[SP::TERMS];
+#pragma unroll
+    for (int term = 0; term < SP::TERMS; ++term) a[term] = *(const V8*)(Ap + term * planeA + arow);
+    int since = 0;
+    for (int kb = 0; kb < nkb; ++kb) {
+      V8 an[SP::TERMS];
+      const bool more = kb + 1 < nkb;
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term)
+        an[term] = more ? *(const V8*)(Ap + term * planeA + arow + 32 * (kb + 1))
+                        : *(const V8*)(Ap + term * planeA + arow_next);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        V8 b[SP::TERMS];
+#pragma unroll
+        for (int term = 0; term < SP::TERMS; ++term)
+          b[term] = *(const V8*)(Bs + (size_t)term * BN * kp + (j * 16 + (lane & 15)) * kp + 32 * kb + kofs);
+        SP::products(a, b, acc[j]);
+      }
+      if (FOLD) {
+        since += 32;
+        if (since >= KCHUNK && more) {
+#pragma unroll
+          for (int j = 0; j < (FOLD ? FN : 1); ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[j][v] += SP::combine(acc[j], v);
+#pragma unroll
+            for (int l = 0; l < SP::LEVELS; ++l) acc[j][l] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+          since = 0;
+        }
+      }
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term) a[term] = an[term];
+    }
+    (void)KBMAX;
+    // stage the 16 x BN tile: lane holds D[4 (lane / 16) + v][16 j + lane % 16]
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double val = SP::combine(acc[j], v);
+        if (FOLD) val += acc64[FOLD ? j : 0][v];
+        st[(4 * (lane >> 4) + v) * SLD + j * 16 + (lane & 15)] = (float)(val * out_scale);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // write rows: BN / 4 lanes per row
+    constexpr int LPR = BN / 4;            // lanes per row (float4 each)
+    constexpr int RPI = 64 / LPR;          // rows per instruction
+    const int64_t row0 = tile * 128 + wave * 16;
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += RPI) {
+      const int r = r0 + lane / LPR, cq = lane % LPR;
+      const int64_t row = row0 + r, col = n0 + 4 * cq;
+      if (row < M && col < N) {
+        const f4 v4 = *(const f4*)(st + r * SLD + 4 * cq);
+        float* dst = grid + row * N + col;
+        if (col + 3 < N && ((row * N + col) & 3) == 0) {
+          __builtin_nontemporal_store(v4, (f4*)dst);
+        } else {
+          const float vv[4] = {v4[0], v4[1], v4[2], v4[3]};
+          for (int q = 0; q < 4 && col + q < N; ++q) __builtin_nontemporal_store(vv[q], dst + q);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    arow = arow_next;
+  }
+}
+
 // ---- core: beta_(1)[a, b r3 + c] = sum_j U~1[j, a] xi_j U~2[j, b] U~3[j, c] ----------
 // A = U~1^T from split planes [term][a][kp]; B[j, (b, c)] formed per lane from
 // s2[b][j] u3[c][j] (FP32) and split in registers.  A wave owns one column
@@ -536,10 +676,51 @@ static GridMixedPlan plan_grid_mixed(int64_t n, int r3) {
 
 size_t grid_mixed_workspace_bytes(int64_t n, int r3) { return plan_grid_mixed(n, r3).total; }
 
+template <class SP, int BN, bool FOLD>
+static void launch_grid_stream(const typename SP::T* ap, const typename SP::T* bp, int64_t M,
+                               int64_t N, int64_t kp, float* grid, const int* exps, int num_cu,
+                               hipStream_t s) {
+  const int npanels = (int)((N + BN - 1) / BN);
+  const int64_t tiles = (M + 127) / 128;
+  // groups: a multiple of 8 (one XCD per group residue), one workgroup per CU
+  // (the B panel and staging take most of the LDS)
+  int gq = std::max(1, num_cu / (8 * npanels));
+  while (gq > 1 && (int64_t)gq * 8 > tiles) --gq;
+  const int groups = gq * 8;
+  const size_t lds = (size_t)SP::TERMS * BN * kp * sizeof(typename SP::T) +
+                     (size_t)8 * 16 * (BN + 4) * sizeof(float);
+  auto fn = grid_stream_kernel<SP, BN, FOLD>;
+  if (lds > 48 * 1024)
+    RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(fn, dim3((unsigned)(8 * npanels * gq)), dim3(512), lds, s, ap, bp, M, N,
+                     (int)kp, npanels, groups, grid, exps);
+}
+
+// widest column panel whose B planes and staging fit the LDS budget
+template <class SP>
+static void grid_stream(const typename SP::T* ap, const typename SP::T* bp, int64_t M, int64_t N,
+                        int64_t kp, float* grid, const int* exps, int num_cu, hipStream_t s) {
+  const size_t budget = 150 * 1024;
+  auto need = [&](int bn) {
+    return (size_t)SP::TERMS * bn * kp * 2 + (size_t)8 * 16 * (bn + 4) * 4;
+  };
+  const bool fold = kp > KCHUNK;
+  if (need(128) <= budget && !fold) launch_grid_stream<SP, 128, false>(ap, bp, M, N, kp, grid, exps, num_cu, s);
+  else if (need(64) <= budget) {
+    if (fold) launch_grid_stream<SP, 64, true>(ap, bp, M, N, kp, grid, exps, num_cu, s);
+    else launch_grid_stream<SP, 64, false>(ap, bp, M, N, kp, grid, exps, num_cu, s);
+  } else if (need(32) <= budget) {
+    launch_grid_stream<SP, 32, true>(ap, bp, M, N, kp, grid, exps, num_cu, s);
+  } else {
+    launch_grid_stream<SP, 16, true>(ap, bp, M, N, kp, grid, exps, num_cu, s);
+  }
+}
+
 template <class SP>
 static void grid_mixed_t(int fp16, const double* T2, const double* V3, int64_t n, int r3,
-                         float* grid, char* work, hipStream_t s) {
+                         float* grid, char* work, int num_cu, hipStream_t s) {
   const GridMixedPlan P = plan_grid_mixed(n, r3);
+  if (P.kp > 512) throw Error{RS_E_UNSUPPORTED, "mixed grid: Tucker rank above 512"};
   unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
   int* exps = (int*)(work + P.o_exps);
   typename SP::T* ap = (typename SP::T*)(work + P.o_a);
@@ -549,17 +730,13 @@ static void grid_mixed_t(int fp16, const double* T2, const double* V3, int64_t n
   scale_setup(T2, n * n * r3, Bops, nb, 1, fp16, mx, exps, s);
   split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
   split_planes<SP>(V3, n, r3, r3, 1, P.kp, exps, 1, bp, s);
-  const int64_t M = n * n;
-  const int tiles_m = (int)((M + 63) / 64), tiles_n = (int)((n + 127) / 128);
-  const int remap = (tiles_m % 8 == 0 && tiles_n > 1) ? 1 : 0;
-  hipLaunchKernelGGL(grid_split_kernel<SP>, dim3((unsigned)((int64_t)tiles_m * tiles_n)), dim3(256),
-                     0, s, ap, bp, M, n, P.kp, tiles_n, remap, grid, exps);
+  grid_stream<SP>(ap, bp, n * n, n, P.kp, grid, exps, num_cu, s);
 }
 
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                void* work, hipStream_t s) {
-  if (prec == RS_MIXED_FP16) grid_mixed_t<SplitF16>(1, T2, V3, n, r3, grid, (char*)work, s);
-  else grid_mixed_t<SplitBF16>(0, T2, V3, n, r3, grid, (char*)work, s);
+                void* work, int num_cu, hipStream_t s) {
+  if (prec == RS_MIXED_FP16) grid_mixed_t<SplitF16>(1, T2, V3, n, r3, grid, (char*)work, num_cu, s);
+  else grid_mixed_t<SplitBF16>(0, T2, V3, n, r3, grid, (char*)work, num_cu, s);
 }
 
 }  // namespace rs

@@ -208,7 +208,7 @@ void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3
 // grid_mixed_workspace_bytes(n, r3) bytes
 size_t grid_mixed_workspace_bytes(int64_t n, int r3);
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                void* work, hipStream_t s);
+                void* work, int num_cu, hipStream_t s);
 
 // k_short.hip
 struct ShortBins {

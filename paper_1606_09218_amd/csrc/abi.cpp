@@ -217,14 +217,16 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
-                 T->brick_start.as<int>(), T->brick_list.as<int>(), s);
+                 T->brick_start.as<int>(), T->brick_list.as<int>(), T->brick_active.as<int>(),
+                 T->active_cap, ncu, s);
   } else if (grid) {
     mark(T, RS_STAGE_GRID, s);
     gemm64(grid_gemm(T, grid), ncu, (double*)(scratch + e.wkg), s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 0, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
-                 T->brick_start.as<int>(), T->brick_list.as<int>(), s);
+                 T->brick_start.as<int>(), T->brick_list.as<int>(), T->brick_active.as<int>(),
+                 T->active_cap, ncu, s);
   }
   mark(T, RS_STAGE_COUNT, s);
 }
@@ -621,7 +623,10 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
     short_bin_fill(dpos, N, n, f->grid.b, P.n_s, T->nb, T->brick_start.as<int>(), counts.as<int>(),
                    T->brick_list.as<int>(), s);
-    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
+    T->active_cap = short_active_capacity(N, P.n_s, T->nb);
+    T->brick_active = DevBuf((size_t)(T->active_cap + 1) * sizeof(int), s);
+    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks,
+                   T->brick_active.as<int>(), T->active_cap, s);
 
     // (a7) T2 and the grid
     build_expansion(T.get(), grid_out, ab + o_exp, s);
@@ -717,7 +722,7 @@ size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
                  (prec == RS_FP64 ? core64_workspace_bytes((int)r, (int)r, (int)r, K, ncu)
                                   : core_mixed_workspace_bytes((int)r, (int)r, (int)r, K, ncu)) +
                  (size_t)8 * n * n * d;  // split-K partials of the projections and expansions (bound)
-  size_t bins = ((n / 8 + 1) * (n / 8 + 1) * (n / 8 + 1) * 2 + 64 * N) * sizeof(int);
+  size_t bins = ((n / 8 + 1) * (n / 8 + 1) * (n / 8 + 1) * 3 + 64 * N + 1) * sizeof(int);
   return inputs + factors + gram_b + eig + result + arena + bins;
 }
 
@@ -745,7 +750,7 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
     I.S_l0 = T->table.S_l0;
     I.tucker_storage = (int64_t)T->r[0] * T->r[1] * T->r[2] + T->n * (T->r[0] + T->r[1] + T->r[2]);
     size_t bytes = T->pos.bytes + T->q.bytes + T->t_dev.bytes + T->a_dev.bytes + T->beta.bytes +
-                   T->T2.bytes + T->brick_start.bytes + T->brick_list.bytes;
+                   T->T2.bytes + T->brick_start.bytes + T->brick_list.bytes + T->brick_active.bytes;
     for (int l = 0; l < 3; ++l) bytes += T->Q[l].bytes;
     I.device_bytes = (int64_t)bytes;
     I.rank_capped = T->rank_capped;
@@ -917,7 +922,10 @@ rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
     RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
     short_bin_fill(T->pos.as<double>(), T->N, T->n, T->b, T->n_s, T->nb, T->brick_start.as<int>(),
                    counts.as<int>(), T->brick_list.as<int>(), s);
-    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks, s);
+    T->active_cap = short_active_capacity(T->N, T->n_s, T->nb);
+    T->brick_active = DevBuf((size_t)(T->active_cap + 1) * sizeof(int), s);
+    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks,
+                   T->brick_active.as<int>(), T->active_cap, s);
     T->T2 = DevBuf((size_t)T->n * T->n * T->r[2] * sizeof(double), s);
     DevBuf scratch(expansion_scratch(T.get(), false).total, s);
     build_expansion(T.get(), nullptr, scratch.as<char>(), s);

@@ -272,8 +272,11 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
   constexpr int FN = BN / 16;
   constexpr int SLD = BN + 4;   // staging row stride (floats)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  T* Bs = (T*)smem;                                          // [term][BN][kp]
-  float* stage = (float*)(smem + (size_t)SP::TERMS * BN * kp * sizeof(T));
+  // B rows are padded by 8 elements (16 bytes): consecutive rows start 4 banks
+  // apart, so the 16-byte reads of 16 lanes from 16 rows hit distinct banks
+  const int ks = kp + 8;
+  T* Bs = (T*)smem;                                          // [term][BN][ks]
+  float* stage = (float*)(smem + (size_t)SP::TERMS * BN * ks * sizeof(T));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int w = blockIdx.x;
   const int xcd = w & 7, iw = w >> 3;
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
   for (int e = threadIdx.x; e < SP::TERMS * BN * kp; e += 512) {
     const int term = e / (BN * kp), rem = e - term * (BN * kp);
     const int col = rem / kp, k = rem - col * kp;
-    Bs[e] = n0 + col < N ? Bp[term * planeB + (n0 + col) * kp + k] : (T)0.0f;
+    Bs[(term * BN + col) * ks + k] = n0 + col < N ? Bp[term * planeB + (n0 + col) * kp + k] : (T)0.0f;
   }
   __syncthreads();
   const int64_t tiles = (M + 127) / 128;
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
         V8 b[SP::TERMS];
 #pragma unroll
         for (int term = 0; term < SP::TERMS; ++term)
-          b[term] = *(const V8*)(Bs + (size_t)term * BN * kp + (j * 16 + (lane & 15)) * kp + 32 * kb + kofs);
+          b[term] = *(const V8*)(Bs + (size_t)(term * BN + j * 16 + (lane & 15)) * ks + 32 * kb + kofs);
         SP::products(a, b, acc[j]);
       }
       if (FOLD) {
@@ -687,7 +690,8 @@ static void launch_grid_stream(const typename SP::T* ap, const typename SP::T* b
   int gq = std::max(1, num_cu / (8 * npanels));
   while (gq > 1 && (int64_t)gq * 8 > tiles) --gq;
   const int groups = gq * 8;
-  const size_t lds = (size_t)SP::TERMS * BN * kp * sizeof(typename SP::T) +
+  // padded B rows (kp + 8 elements) and the per-wave staging tiles
+  const size_t lds = (size_t)SP::TERMS * BN * (kp + 8) * sizeof(typename SP::T) +
                      (size_t)8 * 16 * (BN + 4) * sizeof(float);
   auto fn = grid_stream_kernel<SP, BN, FOLD>;
   if (lds > 48 * 1024)
@@ -702,7 +706,7 @@ static void grid_stream(const typename SP::T* ap, const typename SP::T* bp, int6
                         int64_t kp, float* grid, const int* exps, int num_cu, hipStream_t s) {
   const size_t budget = 150 * 1024;
   auto need = [&](int bn) {
-    return (size_t)SP::TERMS * bn * kp * 2 + (size_t)8 * 16 * (bn + 4) * 4;
+    return (size_t)SP::TERMS * bn * (kp + 8) * 2 + (size_t)8 * 16 * (bn + 4) * 4;
   };
   const bool fold = kp > KCHUNK;
   if (need(128) <= budget && !fold) launch_grid_stream<SP, 128, false>(ap, bp, M, N, kp, grid, exps, num_cu, s);

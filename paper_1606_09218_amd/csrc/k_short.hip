@@ -6,10 +6,10 @@
 //
 // The grid is split into bricks of 8^3 cells.  Binning lists, for every
 // brick, the particles whose window touches it, sorted by particle index.
-// The gather then runs one workgroup per touched brick: it forms the 1D
+// The gather then visits every touched brick with one wave: it forms the 1D
 // factors of each listed particle over the brick's 8 coordinates in LDS and
 // adds the windowed sum to the brick's cells with a read-modify-write.  Every
-// cell is written by one thread and particles are visited in index order, so
+// cell is written by one lane and particles are visited in index order, so
 // the result is deterministic without floating-point atomics.
 #include <hipcub/hipcub.hpp>
 
@@ -74,12 +74,19 @@ void short_bin_fill(const double* pos, int64_t N, int64_t n, double b, int n_s, 
 }
 
 // insertion sort of each brick's (short) list, making the visiting order
-// independent of the atomic fill order
+// independent of the atomic fill order; touched bricks are appended to
+// active[1..] (active[0] counts them, zero on entry).  The order of that
+// list is arbitrary and does not affect the result: every brick is still
+// gathered by one workgroup from its sorted list.
 __global__ void bin_sort_kernel(const int* __restrict__ start, int* __restrict__ list,
-                                int nbricks) {
+                                int nbricks, int* __restrict__ active, int64_t active_cap) {
   int br = blockIdx.x * blockDim.x + threadIdx.x;
   if (br >= nbricks) return;
   int s0 = start[br], s1 = start[br + 1];
+  if (s1 > s0) {
+    const int slot = atomicAdd(&active[0], 1);
+    if (slot < active_cap) active[1 + slot] = br;  // the capacity bounds every window
+  }
   for (int i = s0 + 1; i < s1; ++i) {
     int v = list[i];
     int j = i - 1;
@@ -91,9 +98,18 @@ __global__ void bin_sort_kernel(const int* __restrict__ start, int* __restrict__
   }
 }
 
-void short_bin_sort(const int* start, int* list, int nbricks, hipStream_t s) {
+int64_t short_active_capacity(int64_t N, int n_s, int nb) {
+  // a window of n_s cells meets at most (n_s + 6) / 8 + 1 bricks per axis
+  const int64_t per = (n_s + 6) / BRICK + 1;
+  const int64_t nbricks = (int64_t)nb * nb * nb;
+  return std::min<int64_t>(nbricks, std::max<int64_t>(N, 0) * per * per * per);
+}
+
+void short_bin_sort(const int* start, int* list, int nbricks, int* active, int64_t active_cap,
+                    hipStream_t s) {
+  RS_HIP(hipMemsetAsync(active, 0, sizeof(int), s));
   hipLaunchKernelGGL(bin_sort_kernel, dim3((unsigned)((nbricks + 255) / 256)), dim3(256), 0, s,
-                     start, list, nbricks);
+                     start, list, nbricks, active, active_cap);
 }
 
 void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s) {
@@ -104,87 +120,137 @@ void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s) {
   RS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, in, out, count, s));
 }
 
-constexpr int GATHER_THREADS = 256;
 constexpr int MAX_RS = 64;  // short-range terms handled per particle
 
-// One workgroup per brick (grid.x enumerates all bricks; empty ones exit).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// One wave per touched brick.  Lane (c1, c2) = (lane / 8, lane % 8) owns the
+// eight cells (base0 + m, base1 + c1, base2 + c2), m = 0..7.  Per wave: the
+// brick ids of its next bricks, the listed particles and their positions and
+// charges are loaded one per lane and broadcast with readlane, and the cells
+// to be updated are read before the particle loop, so the dependent global
+// loads of a brick overlap.  The 1D factors exp(-t_k^2 (x - x_nu)^2) of one
+// particle over the brick's 8 coordinates per axis live in LDS
+// f[3][Rs][8] (each thread fills a few), then every lane sums its cells.
+// The workgroup is one wave, so its barriers are cheap and many bricks stay
+// in flight per compute unit; every wave leaves once active[0] bricks are
+// done.
 template <typename GT>
-__global__ __launch_bounds__(GATHER_THREADS) void short_gather_kernel(
+__global__ __launch_bounds__(64) void short_gather_kernel(
     GT* __restrict__ grid, const double* __restrict__ pos, const double* __restrict__ q,
     const double* __restrict__ t, const double* __restrict__ a, int R, int R_l, int64_t n,
-    double b, int w, int nb, const int* __restrict__ start, const int* __restrict__ list) {
-  const int64_t br = blockIdx.x;
-  const int s0 = start[br], s1 = start[br + 1];
-  if (s0 == s1) return;
-  __shared__ double f[3][MAX_RS][BRICK];
-  __shared__ double ak[MAX_RS];
-  __shared__ int win[6];
+    double b, int w, int nb, const int* __restrict__ start, const int* __restrict__ list,
+    const int* __restrict__ active, int64_t active_cap) {
+  extern __shared__ double sg_lds[];
   const int Rs = R - R_l;
-  const int b0 = (int)(br / ((int64_t)nb * nb)), b1 = (int)((br / nb) % nb), b2 = (int)(br % nb);
-  const int base[3] = {b0 * BRICK, b1 * BRICK, b2 * BRICK};
-  const double h = 2.0 * b / (double)n;
-  const int tid = threadIdx.x;
-  if (tid < Rs) ak[tid] = a[R_l + tid];
-
-  // two cells per thread: (c0, c1, c2) and (c0 + 4, c1, c2)
-  const int c2 = tid & 7, c1 = (tid >> 3) & 7, c0 = tid >> 6;  // c0 in 0..3
-  double acc[2] = {0.0, 0.0};
-
-  for (int e = s0; e < s1; ++e) {
-    const int nu = list[e];
-    __syncthreads();  // previous particle's factors are no longer read
-    if (tid == 0) {
-      int lo[3], hi[3];
-      particle_window(pos, nu, n, b, w, lo, hi);
-      for (int l = 0; l < 3; ++l) {
-        win[2 * l] = lo[l] - base[l];
-        win[2 * l + 1] = hi[l] - base[l];
-      }
-    }
-    for (int idx = tid; idx < 3 * Rs * BRICK; idx += GATHER_THREADS) {
-      const int l = idx / (Rs * BRICK);
-      const int rem = idx - l * Rs * BRICK;
-      const int k = rem / BRICK, m = rem - k * BRICK;
-      const double x = -b + ((double)(base[l] + m) + 0.5) * h;
-      const double d = x - pos[3 * nu + l];
-      const double tk = t[R_l + k];
-      f[l][k][m] = exp(-(tk * tk) * (d * d));
-    }
-    __syncthreads();
-    const double z = q[nu];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int m0 = c0 + 4 * u;
-      if (m0 >= win[0] && m0 <= win[1] && c1 >= win[2] && c1 <= win[3] && c2 >= win[4] &&
-          c2 <= win[5]) {
-        double s = 0.0;
-        for (int k = 0; k < Rs; ++k) s += ak[k] * f[0][k][m0] * f[1][k][c1] * f[2][k][c2];
-        acc[u] += z * s;
-      }
-    }
+  double* f = sg_lds;               // [3][Rs][8]
+  double* ak = sg_lds + 24 * Rs;    // [Rs]
+  double* tk2 = ak + Rs;            // [Rs]
+  const int lane = threadIdx.x;
+  for (int k = lane; k < Rs; k += 64) {
+    ak[k] = a[R_l + k];
+    tk2[k] = t[R_l + k] * t[R_l + k];
   }
+  const double h = 2.0 * b / (double)n;
+  const int c1 = lane >> 3, c2 = lane & 7;
+  const int n_active = (int)(active[0] < active_cap ? active[0] : active_cap);
+  const int G = gridDim.x;
+  for (int ia0 = blockIdx.x; ia0 < n_active; ia0 += 64 * G) {
+    // lane j holds brick ia0 + j * G of this wave's share
+    const int64_t mine = (int64_t)ia0 + (int64_t)lane * G;
+    const int mybr = mine < n_active ? active[1 + mine] : 0;
+    const int nbk = (int)std::min<int64_t>(64, ((int64_t)n_active - ia0 + G - 1) / G);
+    for (int j = 0; j < nbk; ++j) {
+      const int br = __builtin_amdgcn_readlane(mybr, j);
+      const int b0 = br / (nb * nb), b1 = (br / nb) % nb, b2 = br % nb;
+      const int base0 = b0 * 8, base1 = b1 * 8, base2 = b2 * 8;
+      const int64_t i1 = base1 + c1, i2 = base2 + c2;
+      const bool col_ok = i1 < n && i2 < n;
+      double old[8];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int64_t i0 = base[0] + c0 + 4 * u, i1 = base[1] + c1, i2 = base[2] + c2;
-    if (i0 < n && i1 < n && i2 < n && acc[u] != 0.0) {
-      GT* dst = grid + (i0 * n + i1) * n + i2;
-      *dst = (GT)((double)(*dst) + acc[u]);
+      for (int m = 0; m < 8; ++m) {
+        const int64_t i0 = base0 + m;
+        old[m] = (col_ok && i0 < n) ? (double)grid[(i0 * n + i1) * n + i2] : 0.0;
+      }
+      double acc[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc[m] = 0.0;
+      const int s0 = start[br], s1 = start[br + 1];
+      for (int e0 = s0; e0 < s1; e0 += 64) {
+        const int cnt = std::min(64, s1 - e0);
+        const int mynu = lane < cnt ? list[e0 + lane] : list[e0];
+        const double px = pos[3 * (int64_t)mynu], py = pos[3 * (int64_t)mynu + 1],
+                     pz = pos[3 * (int64_t)mynu + 2], pq = q[mynu];
+        for (int e = 0; e < cnt; ++e) {
+          const double p[3] = {readlane_f64(px, e), readlane_f64(py, e), readlane_f64(pz, e)};
+          const double z = readlane_f64(pq, e);
+          int lo[3], hi[3];
+          const int bs[3] = {base0, base1, base2};
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            int64_t jc = (int64_t)floor((p[l] + b) / h);
+            jc = jc < 0 ? 0 : (jc > n - 1 ? n - 1 : jc);
+            const int64_t lo_l = jc - w < 0 ? 0 : jc - w;
+            const int64_t hi_l = jc + w > n - 1 ? n - 1 : jc + w;
+            lo[l] = (int)(lo_l - bs[l]);
+            hi[l] = (int)(hi_l - bs[l]);
+          }
+          __syncthreads();  // the previous particle's factors are no longer read
+          for (int idx = lane; idx < 24 * Rs; idx += 64) {
+            const int l = idx / (8 * Rs);
+            const int rem = idx - l * 8 * Rs;
+            const int k = rem >> 3, m = rem & 7;
+            const double d = (-b + ((double)(bs[l] + m) + 0.5) * h) - p[l];
+            f[idx] = exp(-tk2[k] * (d * d));
+          }
+          __syncthreads();
+          if (c1 >= lo[1] && c1 <= hi[1] && c2 >= lo[2] && c2 <= hi[2]) {
+            double s[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) s[m] = 0.0;
+            for (int k = 0; k < Rs; ++k) {
+              const double g = ak[k] * f[(Rs + k) * 8 + c1] * f[(2 * Rs + k) * 8 + c2];
+#pragma unroll
+              for (int m = 0; m < 8; ++m) s[m] += g * f[k * 8 + m];
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+              if (m >= lo[0] && m <= hi[0]) acc[m] += z * s[m];
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int64_t i0 = base0 + m;
+        if (col_ok && i0 < n && acc[m] != 0.0)
+          grid[(i0 * n + i1) * n + i2] = (GT)(old[m] + acc[m]);
+      }
     }
   }
 }
 
 void short_gather(void* grid, int grid_fp32, const double* pos, const double* q, const double* t,
                   const double* a, int R, int R_l, int64_t n, double b, int n_s, int nb,
-                  const int* start, const int* list, hipStream_t s) {
+                  const int* start, const int* list, const int* active, int64_t active_cap,
+                  int num_cu, hipStream_t s) {
   if (R - R_l > MAX_RS) throw Error{RS_E_UNSUPPORTED, "more than 64 short-range terms"};
-  const int64_t nbricks = (int64_t)nb * nb * nb;
+  if (R - R_l <= 0) return;  // no short-range terms: nothing to add
   const int w = (n_s - 1) / 2;
+  // 16 resident one-wave workgroups per compute unit, never more than there are bricks
+  const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(active_cap, (int64_t)num_cu * 16));
+  const size_t lds = (size_t)26 * (R - R_l) * sizeof(double);
   if (grid_fp32)
-    hipLaunchKernelGGL(short_gather_kernel<float>, dim3((unsigned)nbricks), dim3(GATHER_THREADS), 0,
-                       s, (float*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list);
+    hipLaunchKernelGGL(short_gather_kernel<float>, dim3((unsigned)wgs), dim3(64), lds, s,
+                       (float*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active,
+                       active_cap);
   else
-    hipLaunchKernelGGL(short_gather_kernel<double>, dim3((unsigned)nbricks), dim3(GATHER_THREADS), 0,
-                       s, (double*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list);
+    hipLaunchKernelGGL(short_gather_kernel<double>, dim3((unsigned)wgs), dim3(64), lds, s,
+                       (double*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active,
+                       active_cap);
 }
 
 }  // namespace rs

@@ -100,6 +100,8 @@ struct rs_tensor {
   int64_t n_pairs = 0;
   rs::DevBuf brick_start;        // nb^3 + 1
   rs::DevBuf brick_list;         // n_pairs particle indices
+  rs::DevBuf brick_active;       // 1 + active_cap ints: count, then touched bricks
+  int64_t active_cap = 0;
   // stage timing: events[k] recorded before stage k, events[RS_STAGE_COUNT] at the end
   std::vector<hipEvent_t> events;
   // eigensolver phases: eig_events[k] before phase k, eig_events[RS_EIG_PHASES] at the end
@@ -220,12 +222,18 @@ void short_bin_count(const double* pos, int64_t N, int64_t n, double b, int n_s,
                      int* counts, hipStream_t s);
 void short_bin_fill(const double* pos, int64_t N, int64_t n, double b, int n_s, int nb,
                     const int* start, int* cursor, int* list, hipStream_t s);
-void short_bin_sort(const int* start, int* list, int nbricks, hipStream_t s);
+// Sorts every brick's list and writes the touched bricks to active[1..]
+// (count in active[0]; at most active_cap entries, see short_active_capacity).
+void short_bin_sort(const int* start, int* list, int nbricks, int* active, int64_t active_cap,
+                    hipStream_t s);
+// Upper bound on the number of bricks touched by the windows of N particles.
+int64_t short_active_capacity(int64_t N, int n_s, int nb);
 void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s);
 // grid (FP64 or FP32) += sum over particles of the short-range windows
 void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
                   const double* t, const double* a, int R, int R_l, int64_t n, double b,
-                  int n_s, int nb, const int* start, const int* list, hipStream_t s);
+                  int n_s, int nb, const int* start, const int* list, const int* active,
+                  int64_t active_cap, int num_cu, hipStream_t s);
 
 // k_eval.hip
 // vals[m] (part 0/1/2) and optionally grad (M x 3) and self terms at points

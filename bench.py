@@ -105,6 +105,37 @@ def cpu_baseline(s, budget_s: float = 20.0):
                        f"{m} of {s.N} particles (scaled); one step = {total:.1f} s")}
 
 
+def timed_steps(step, steps, stream, starts=None, ends=None):
+    """Run `steps` steps back to back and return (wall seconds, per-step stage
+    times, ranks of the first step).  Each step's result is released as soon
+    as the next step has passed its rank readback (which orders it after the
+    whole previous step), so its device memory is reused as in a serving loop
+    rather than held until the end."""
+    import torch
+    stages, ranks, prev = [], None, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if starts is not None:
+            starts[i].record(stream)
+        h = step()
+        if ends is not None:
+            ends[i].record(stream)
+        if prev is not None:
+            stages.append(prev.stage_ms())
+            if ranks is None:
+                ranks = list(prev.info().ranks)
+            prev.free()
+        prev = h
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages.append(prev.stage_ms())
+    if ranks is None:
+        ranks = list(prev.info().ranks)
+    prev.free()
+    return wall, stages, ranks
+
+
 def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
     """The same step with split-FP16 core and grid expansion (FP32 grid):
     throughput and its error against the FP64 GPU result of the same input."""
@@ -132,15 +163,8 @@ def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
 
         for _ in range(warmup):
             step().free()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hs = [step() for _ in range(steps)]
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = [h.stage_ms() for h in hs]
-        same_ranks = list(hs[0].info().ranks) == ranks
-        for h in hs:
-            h.free()
+        wall, st, ranks_m = timed_steps(step, steps, stream)
+        same_ranks = ranks_m == ranks
         err = float((g32.double() - grid64).abs().max() / grid64.abs().max())
         e_err = abs(E.item() - E64.item()) / abs(E64.item())
         out[prec] = {"value": round(steps / wall, 4), "unit": "assemblies/s",
@@ -152,6 +176,39 @@ def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
     return out
 
 
+def serving_leg(n_requests: int, n_slots: int = 4, prec: str = "mixed_fp16"):
+    """The first `n_requests` requests of the seeded Poisson serving trace
+    (rate 200/s; N log-uniform in [32, 20000]; n in {256, 512, 1024}; R in
+    24..32), replayed in real time through the continuous-batching server,
+    then the same requests all present at t = 0 (saturating).  Latency is
+    arrival to result (energy and ranks on the host)."""
+    import torch
+
+    import workloads
+    from paper_1606_09218_amd.serve import GpuExecutor, Server, summarize
+    trace = workloads.cfg5_trace(seed=5, n_requests=n_requests)
+    ex = GpuExecutor(0, prec=prec, r_max=384)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+    # factors of every (n, R) in the trace are built before the clock starts
+    # (device-resident tables, as in a long-running server)
+    for r in trace:
+        ex.factors(r.system())
+    out = {"requests": n_requests, "slots": n_slots, "prec": prec, "hbm_budget_GB": round(budget / 2**30, 1),
+           "trace": "Poisson 200/s, seed 5 (first requests of the 2000-request trace)"}
+    for label, scale in (("poisson", 1.0), ("saturating", 0.0)):
+        print(f"serving leg: {label} replay of {n_requests} requests", file=sys.stderr, flush=True)
+        srv = Server(ex, n_slots=n_slots, hbm_budget=budget)
+        recs = srv.run_trace(trace, time_scale=scale)
+        sm = summarize(recs)
+        sm["peak_concurrency"] = srv.peak_concurrency
+        out[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
+        errs = [r.error for r in recs if r.error]
+        if errs:
+            out[label]["first_error"] = errs[0]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +217,8 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving trace to replay (0: skip the serving leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
     args = ap.parse_args()
@@ -199,22 +258,8 @@ def main():
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    handles = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        handles.append(step())
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, stages, ranks = timed_steps(step, args.steps, stream, starts, ends)
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    stages = [h.stage_ms() for h in handles]
-    info = handles[0].info()
-    ranks = list(info.ranks)
-    for h in handles:
-        h.free()
-    torch.cuda.synchronize()
 
     stage_avg = {k: float(np.mean([st[k] for st in stages])) for k in stages[0]}
     n, r3 = s.n, ranks[2]
@@ -263,6 +308,11 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid, args.steps, args.warmup, stream)
+    if args.serve_requests > 0:
+        try:
+            out["serving"] = serving_leg(args.serve_requests)
+        except Exception as e:  # reported in the line rather than losing it
+            out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)

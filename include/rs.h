@@ -166,6 +166,13 @@ void rs_ctx_destroy(rs_ctx* ctx);
 /* Enable (1) or disable (0) per-stage HIP-event timing of later assemblies
  * made with this context (reported in rs_info.stage_ms). */
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable);
+/* Device memory of the library's buffers comes from a per-device cache: a
+ * released buffer is kept for reuse by later assemblies (immediately on the
+ * stream it was released on, after an event wait on another stream) and is
+ * returned to the driver only when an allocation would fail.  This call
+ * synchronises the context's device and returns every cached block now.
+ * Buffers still held by live tensors are not affected. */
+rs_status rs_ctx_trim(rs_ctx* ctx);
 
 /* ---- quadrature table and split (sections 2.2-2.3) --------------------- */
 

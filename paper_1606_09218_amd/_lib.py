@@ -72,6 +72,7 @@ def _load():
         "rs_ctx_create": ([C.c_int, C.POINTER(P)], C.c_int),
         "rs_ctx_destroy": ([P], None),
         "rs_ctx_set_timing": ([P, C.c_int], C.c_int),
+        "rs_ctx_trim": ([P], C.c_int),
         "rs_build_factors": ([P, C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.POINTER(P)], C.c_int),
         "rs_factors_get": ([P, D, D, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                             C.POINTER(C.c_int32)], C.c_int),
@@ -99,7 +100,7 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_build_factors", "rs_factors_get",
+EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
@@ -147,6 +148,10 @@ class Context:
     def set_timing(self, enable: bool = True):
         _check(lib.rs_ctx_set_timing(self.handle, int(bool(enable))))
 
+    def trim(self):
+        """Return the device memory cached for reuse (rs_ctx_trim)."""
+        _check(lib.rs_ctx_trim(self.handle))
+
     def __del__(self):
         if getattr(self, "handle", None):
             lib.rs_ctx_destroy(self.handle)
@@ -191,10 +196,19 @@ def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = 
 class Tensor:
     """An RS-Tucker tensor handle (rs_tensor)."""
 
-    def __init__(self, handle, ctx: Context, status: int):
+    def __init__(self, handle, ctx: Context, status: int, N: Optional[int] = None):
         self.handle = handle
         self.ctx = ctx
         self.status = status
+        self._N = N
+
+    @property
+    def N(self) -> int:
+        """Number of particles (known at assembly; info() waits for the
+        assembly to finish when timing is on, this does not)."""
+        if self._N is None:
+            self._N = int(self.info().N)
+        return self._N
 
     def info(self) -> rs_info:
         inf = rs_info()
@@ -230,7 +244,7 @@ def assemble(ctx: Context, f: Factors, pos, q, grid=None, opts: Optional[rs_aopt
     h = C.c_void_p()
     st = _check(lib.rs_assemble(ctx.handle, f.handle, N, p_pos, p_q, C.byref(opts), p_grid,
                                 C.byref(h), _stream_ptr(stream)), allow_rank_cap=True)
-    return Tensor(h, ctx, st)
+    return Tensor(h, ctx, st, N)
 
 
 def weighted_gram(ctx: Context, f: Factors, pos, q, G, stream=None):
@@ -247,14 +261,14 @@ def eval_points(T: Tensor, pts, vals, part: int = 0, stream=None):
 
 
 def energy(T: Tensor, E, dEdq=None, stream=None):
-    N = T.info().N
+    N = T.N
     _check(lib.rs_energy(T.handle, _dev_ptr(E, "f64", 1, "E"),
                          None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
                          _stream_ptr(stream)))
 
 
 def forces(T: Tensor, F, scale: float = 1.0, stream=None):
-    N = T.info().N
+    N = T.N
     _check(lib.rs_forces(T.handle, float(scale), _dev_ptr(F, "f64", 3 * N, "F"), _stream_ptr(stream)))
 
 

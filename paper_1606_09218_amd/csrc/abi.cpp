@@ -5,7 +5,9 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <memory>
+#include <mutex>
 
 #include "rs_internal.h"
 
@@ -15,8 +17,104 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const char* last_error() { return g_err.c_str(); }
 
+// ---- device memory: a stream-aware caching allocator ------------------------
+// Device blocks are taken from the driver once and kept: a released block goes
+// back to a host-side free list tagged with the stream it was released on.
+// A request is served by the smallest cached block that fits (not much
+// larger than asked); a block of the same stream is reusable at once (stream
+// order puts every earlier use before the new one), a block of another stream
+// after that stream's work so far (an event the requesting stream waits on).
+// No driver call and no queue packet is spent on the steady-state path, so
+// consecutive assemblies reuse their buffers without stalls.  Requests are
+// rounded to 512 bytes (below 1 MiB) or 2 MiB; cached memory is returned only
+// when the driver runs out (then every cached block of the device is freed
+// after a device synchronisation) or by rs_ctx_trim().
+namespace {
+struct CachedBlock {
+  void* p;
+  hipStream_t s;
+};
+struct DeviceCache {
+  std::multimap<size_t, CachedBlock> free_blocks;  // by size
+};
+struct BlockInfo {
+  int device;
+  size_t bytes;
+};
+// heap-held and never destroyed: buffers may be released during process exit
+std::mutex& g_cache_mu = *new std::mutex;
+std::map<int, DeviceCache>& g_caches = *new std::map<int, DeviceCache>;
+std::map<void*, BlockInfo>& g_blocks = *new std::map<void*, BlockInfo>;  // every block taken from the driver
+
+size_t round_request(size_t n) {
+  const size_t small = 512, large = (size_t)2 << 20;
+  return n < ((size_t)1 << 20) ? (n + small - 1) / small * small : (n + large - 1) / large * large;
+}
+
+void release_cached(int device, DeviceCache& c) {  // caller holds the lock
+  if (c.free_blocks.empty()) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c.free_blocks) {
+    (void)hipFree(kv.second.p);
+    g_blocks.erase(kv.second.p);
+  }
+  c.free_blocks.clear();
+  (void)hipSetDevice(cur);
+}
+}  // namespace
+
+static void* cache_alloc(size_t nbytes, hipStream_t st) {
+  int dev = 0;
+  RS_HIP(hipGetDevice(&dev));
+  const size_t want = round_request(nbytes);
+  const size_t limit = want + want / 4 + ((size_t)2 << 20);
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  DeviceCache& c = g_caches[dev];
+  auto best = c.free_blocks.end();
+  for (auto it = c.free_blocks.lower_bound(want); it != c.free_blocks.end() && it->first <= limit; ++it) {
+    if (it->second.s == st) { best = it; break; }
+    if (best == c.free_blocks.end()) best = it;
+  }
+  if (best != c.free_blocks.end()) {
+    CachedBlock b = best->second;
+    c.free_blocks.erase(best);
+    if (b.s != st) {
+      hipEvent_t ev;
+      RS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      RS_HIP(hipEventRecord(ev, b.s));
+      RS_HIP(hipStreamWaitEvent(st, ev, 0));
+      RS_HIP(hipEventDestroy(ev));
+    }
+    return b.p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    release_cached(dev, c);
+    RS_HIP(hipMalloc(&p, want));
+  }
+  g_blocks[p] = BlockInfo{dev, want};
+  return p;
+}
+
+static void cache_free(void* p, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto it = g_blocks.find(p);
+  if (it == g_blocks.end()) return;  // not taken by cache_alloc (cannot happen)
+  g_caches[it->second.device].free_blocks.emplace(it->second.bytes, CachedBlock{p, st});
+}
+
+static void cache_trim(int device) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto it = g_caches.find(device);
+  if (it != g_caches.end()) release_cached(device, it->second);
+}
+
 DevBuf::DevBuf(size_t nbytes, hipStream_t st) : bytes(nbytes), s(st) {
-  if (nbytes) RS_HIP(hipMallocAsync(&p, nbytes, st));
+  if (nbytes) p = cache_alloc(nbytes, st);
 }
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
   if (this != &o) {
@@ -31,7 +129,7 @@ DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
 }
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset() {
-  if (p) (void)hipFreeAsync(p, s);
+  if (p) cache_free(p, s);
   p = nullptr;
   bytes = 0;
 }
@@ -115,13 +213,8 @@ static void mark(rs_tensor* T, int stage, hipStream_t s) {
 
 // Gram matrices of the three modes into G (3 x n x n); U, xi, w computed into
 // caller-provided buffers.
-static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
-                                 const double* pos, const double* q, double* U, double* xi,
-                                 double* w, double* sw, double* G, hipStream_t s,
-                                 rs_tensor* T = nullptr) {
-  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s);
-  if (T) mark(T, RS_STAGE_GRAM, s);
-  Gemm64 g;
+static Gemm64 gram_gemm(const Plan& P, const double* U, const double* w, double* G) {
+  Gemm64 g;  // G = U diag(w) U^T per mode (upper tiles, mirrored)
   g.M = P.n;
   g.N = P.n;
   g.K = P.K;
@@ -131,9 +224,32 @@ static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P
   g.C = G; g.scm = P.n; g.scn = 1; g.scb = P.n * P.n;
   g.kscale = w;
   g.upper_only = 1;
-  DevBuf work(gemm64_workspace_bytes(g, ctx->num_cu), s);
-  gemm64(g, ctx->num_cu, work.as<double>(), s);
+  return g;
 }
+
+// `work`: split-K workspace of gemm64_workspace_bytes(gram_gemm(..)), or null
+// to allocate one here.
+static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
+                                 const double* pos, const double* q, double* U, double* xi,
+                                 double* w, double* sw, double* G, hipStream_t s,
+                                 rs_tensor* T = nullptr, double* work = nullptr) {
+  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s);
+  if (T) mark(T, RS_STAGE_GRAM, s);
+  const Gemm64 g = gram_gemm(P, U, w, G);
+  if (work) {
+    gemm64(g, ctx->num_cu, work, s);
+  } else {
+    DevBuf wk(gemm64_workspace_bytes(g, ctx->num_cu), s);
+    gemm64(g, ctx->num_cu, wk.as<double>(), s);
+  }
+}
+
+// Non-owning view of a piece of an arena, with DevBuf's accessors.
+struct Span {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
 
 // Scratch carved from one allocation: offsets are 256-byte aligned.
 struct Carve {
@@ -290,6 +406,14 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
 
 void rs_ctx_destroy(rs_ctx* ctx) { delete ctx; }
 
+rs_status rs_ctx_trim(rs_ctx* ctx) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx != nullptr, "null context");
+    cache_trim(ctx->device);
+    return RS_OK;
+  });
+}
+
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(ctx != nullptr, "null context");
@@ -400,64 +524,114 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const double* dpos = T->pos.as<double>();
     const double* dq = T->q.as<double>();
 
-    DevBuf rb(sizeof(Readback), s);
+    // Every buffer of the stages before the rank readback is a piece of one
+    // allocation (a stream-ordered allocation between two launches costs a
+    // queue dependency each); the pieces live until the assembly returns.
+    const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
+    T->nb = bricks_per_axis(n);
+    const int nbricks = T->nb * T->nb * T->nb;
+    Gemm64 gx_shape;  // Y = G X
+    gx_shape.M = n; gx_shape.N = p; gx_shape.K = n; gx_shape.batch = 3;
+    Gemm64 yty_shape;  // C = Y^T Y (upper)
+    yty_shape.M = p; yty_shape.N = p; yty_shape.K = n; yty_shape.batch = 3; yty_shape.upper_only = 1;
+    Gemm64 qty_shape;  // B = Q0^T Y
+    qty_shape.M = p; qty_shape.N = p; qty_shape.K = n; qty_shape.batch = 3;
+    Gemm64 zz_shape;  // C = Z^T Z (upper)
+    zz_shape.M = rc; zz_shape.N = rc; zz_shape.K = p; zz_shape.batch = 3; zz_shape.upper_only = 1;
+    const size_t d8 = sizeof(double);
+    const size_t scan_bytes = exclusive_scan_bytes(nbricks + 1);
+    Carve pre;
+    const size_t o_rb = pre.add(sizeof(Readback));
+    const size_t o_U = pre.add((size_t)3 * n * K * d8), o_xi = pre.add((size_t)K * d8);
+    const size_t o_w = pre.add((size_t)K * d8), o_sw = pre.add((size_t)K * d8);
+    const size_t o_G = pre.add((size_t)3 * n * n * d8);
+    const size_t o_wgram = pre.add(gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu));
+    const size_t o_Q0 = pre.add((size_t)3 * n * p * d8), o_Bm = pre.add((size_t)3 * p * p * d8);
+    const bool subspace = p < n;
+    const size_t o_Y = pre.add(subspace ? (size_t)3 * n * p * d8 : 0);
+    const size_t o_Cq = pre.add(subspace ? (size_t)3 * p * p * d8 : 0);
+    const size_t wke_bytes =
+        subspace ? std::max({sketch64_workspace_bytes(n, K, 3, p, ncu),
+                             gemm64_workspace_bytes(gx_shape, ncu),
+                             gemm64_workspace_bytes(yty_shape, ncu),
+                             gemm64_workspace_bytes(qty_shape, ncu)})
+                 : 0;
+    const size_t o_wke = pre.add(wke_bytes);
+    const size_t o_ews = pre.add(eig_sym_workspace_bytes(p, rc, 3));
+    const size_t o_Z = pre.add((size_t)3 * p * rc * d8), o_Zsave = pre.add((size_t)3 * p * rc * d8);
+    const size_t o_Cz = pre.add((size_t)3 * rc * rc * d8);
+    const size_t o_wkz = pre.add(gemm64_workspace_bytes(zz_shape, ncu));
+    const size_t o_perm = pre.add((size_t)3 * p * sizeof(int)), o_fixed = pre.add(3 * sizeof(int));
+    const size_t o_counts = pre.add((size_t)(nbricks + 1) * sizeof(int));
+    const size_t o_scan = pre.add(scan_bytes);
+    DevBuf pre_buf(pre.total, s);
+    auto piece = [&](size_t off, size_t bytes) { return Span{pre_buf.as<char>() + off, bytes}; };
+
+    Span rb = piece(o_rb, sizeof(Readback));
     RS_HIP(hipMemsetAsync(rb.p, 0, sizeof(Readback), s));
     Readback* rbd = rb.as<Readback>();
     launch_validate(dpos, dq, N, f->grid.b, &rbd->flags, s);
 
     // (a2, a3) side matrices and charge-weighted Gram matrices
     mark(T.get(), RS_STAGE_FACTORS, s);
-    DevBuf U((size_t)3 * n * K * sizeof(double), s);
-    DevBuf xi((size_t)K * sizeof(double), s), w((size_t)K * sizeof(double), s);
-    DevBuf sw((size_t)K * sizeof(double), s);
-    DevBuf G((size_t)3 * n * n * sizeof(double), s);
+    Span U = piece(o_U, (size_t)3 * n * K * d8), xi = piece(o_xi, (size_t)K * d8);
+    Span w = piece(o_w, (size_t)K * d8), sw = piece(o_sw, (size_t)K * d8);
+    Span G = piece(o_G, (size_t)3 * n * n * d8);
     run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
-                         sw.as<double>(), G.as<double>(), s, T.get());
+                         sw.as<double>(), G.as<double>(), s, T.get(), (double*)(pre_buf.as<char>() + o_wgram));
 
     // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
     mark(T.get(), RS_STAGE_EIGEN, s);
     mark_eig(T.get(), 0, s);
-    DevBuf Q0((size_t)3 * n * p * sizeof(double), s);
-    DevBuf Bm((size_t)3 * p * p * sizeof(double), s);
+    Span Q0 = piece(o_Q0, (size_t)3 * n * p * d8), Bm = piece(o_Bm, (size_t)3 * p * p * d8);
     if (p == n) {
       launch_identity(Q0.as<double>(), n, 3, s);
       RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
     } else {
-      DevBuf Y((size_t)3 * n * p * sizeof(double), s);
-      auto GtimesX = [&](const double* X, double* Yout) {  // row-major n x p in and out
+      Span Y = piece(o_Y, (size_t)3 * n * p * d8), Cq = piece(o_Cq, (size_t)3 * p * p * d8);
+      auto gx_gemm = [&](const double* X, double* Yout) {  // Y = G X, row-major n x p
         Gemm64 g;
         g.M = n; g.N = p; g.K = n; g.batch = 3;
         g.A = G.as<double>(); g.sam = n; g.sak = 1; g.sab = n * n;
         g.B = X; g.sbk = p; g.sbn = 1; g.sbb = n * p;
         g.C = Yout; g.scm = p; g.scn = 1; g.scb = n * p;
-        DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-        gemm64(g, ncu, wk.as<double>(), s);
+        return g;
+      };
+      auto yty_gemm = [&](const double* Yp) {  // C = Y^T Y (symmetric)
+        Gemm64 g;
+        g.M = p; g.N = p; g.K = n; g.batch = 3;
+        g.A = Yp; g.sam = 1; g.sak = p; g.sab = n * p;
+        g.B = Yp; g.sbk = p; g.sbn = 1; g.sbb = n * p;
+        g.C = Cq.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
+        g.upper_only = 1;
+        return g;
+      };
+      auto qty_gemm = [&]() {  // B = Q0^T Y
+        Gemm64 g;
+        g.M = p; g.N = p; g.K = n; g.batch = 3;
+        g.A = Q0.as<double>(); g.sam = 1; g.sak = p; g.sab = n * p;
+        g.B = Y.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = n * p;
+        g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
+        return g;
+      };
+      Span wk_eig = piece(o_wke, wke_bytes);  // split-K workspace of every product here
+      auto GtimesX = [&](const double* X, double* Yout) {
+        gemm64(gx_gemm(X, Yout), ncu, wk_eig.as<double>(), s);
       };
       // orthonormal basis of range(Y), in place: shifted Cholesky QR, twice
       // (each shifted pass maps cond(Y) to about sqrt(shift)/sigma_min(Y)),
       // then two plain passes
-      DevBuf Cq((size_t)3 * p * p * sizeof(double), s);
       auto orth = [&](double* Yp) {
         for (int pass = 0; pass < 4; ++pass) {
-          Gemm64 g;  // C = Y^T Y (symmetric)
-          g.M = p; g.N = p; g.K = n; g.batch = 3;
-          g.A = Yp; g.sam = 1; g.sak = p; g.sab = n * p;
-          g.B = Yp; g.sbk = p; g.sbn = 1; g.sbb = n * p;
-          g.C = Cq.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
-          g.upper_only = 1;
-          DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-          gemm64(g, ncu, wk.as<double>(), s);
+          gemm64(yty_gemm(Yp), ncu, wk_eig.as<double>(), s);
           launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, 1, s);
           launch_trsm_rows(Yp, Cq.as<double>(), n, p, 3, ctx->lds_limit, s);
         }
       };
       // range finder on the charge-weighted side matrix itself (its dynamic
       // range is that of the singular values, not of their squares)
-      {
-        DevBuf wk(sketch64_workspace_bytes(n, K, 3, p, ncu), s);
-        sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
-                 Q0.as<double>(), p, 1, ncu, wk.as<double>(), s);
-      }
+      sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
+               Q0.as<double>(), p, 1, ncu, wk_eig.as<double>(), s);
       launch_perturb(Q0.as<double>(), G.as<double>(), n, p, 3, 0x9e3779b9ULL, s);
       orth(Q0.as<double>());
       for (int it = 0; it < P.power_iters; ++it) {
@@ -467,19 +641,12 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
         std::swap(Q0, Y);
       }
       GtimesX(Q0.as<double>(), Y.as<double>());  // Y = G Q0
-      Gemm64 g;                                  // B = Q0^T Y
-      g.M = p; g.N = p; g.K = n; g.batch = 3;
-      g.A = Q0.as<double>(); g.sam = 1; g.sak = p; g.sab = n * p;
-      g.B = Y.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = n * p;
-      g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
-      DevBuf wk(gemm64_workspace_bytes(g, ncu), s);
-      gemm64(g, ncu, wk.as<double>(), s);
+      gemm64(qty_gemm(), ncu, wk_eig.as<double>(), s);  // B = Q0^T Y
       launch_symmetrize(Bm.as<double>(), p, 3, s);
     }
-    // eigenvectors are formed only for the columns the rank rule can keep
-    const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
-    DevBuf ews(eig_sym_workspace_bytes(p, rc, 3), s);
-    DevBuf Z((size_t)3 * p * rc * sizeof(double), s);
+    // eigenvectors are formed only for the rc columns the rank rule can keep
+    Span ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));
+    Span Z = piece(o_Z, (size_t)3 * p * rc * d8);
     mark_eig(T.get(), 1, s);
     launch_eig_tridiag(Bm.as<double>(), ews.as<double>(), p, rc, 3, ctx->lds_limit, s);
     mark_eig(T.get(), 2, s);
@@ -490,16 +657,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     // iteration leaves them nearly orthonormal, so two plain passes suffice;
     // a breakdown (near-parallel vectors, flag bit 4) is redone from the
     // saved vectors with a shifted pass first, after the readback.
-    DevBuf Zsave((size_t)3 * p * rc * sizeof(double), s);
+    Span Zsave = piece(o_Zsave, (size_t)3 * p * rc * d8);
     RS_HIP(hipMemcpyAsync(Zsave.p, Z.p, Zsave.bytes, hipMemcpyDeviceToDevice, s));
-    DevBuf Cz((size_t)3 * rc * rc * sizeof(double), s);
-    Gemm64 gz;  // C = Z^T Z (symmetric)
-    gz.M = rc; gz.N = rc; gz.K = p; gz.batch = 3;
+    Span Cz = piece(o_Cz, (size_t)3 * rc * rc * d8);
+    Gemm64 gz = zz_shape;  // C = Z^T Z (symmetric)
     gz.A = Z.as<double>(); gz.sam = 1; gz.sak = rc; gz.sab = (int64_t)p * rc;
     gz.B = Z.as<double>(); gz.sbk = rc; gz.sbn = 1; gz.sbb = (int64_t)p * rc;
     gz.C = Cz.as<double>(); gz.scm = rc; gz.scn = 1; gz.scb = (int64_t)rc * rc;
-    gz.upper_only = 1;
-    DevBuf wkz(gemm64_workspace_bytes(gz, ncu), s);
+    Span wkz = piece(o_wkz, gemm64_workspace_bytes(zz_shape, ncu));
     auto orth_z = [&](int passes, bool shifted_first, int fail_bit) {
       for (int pass = 0; pass < passes; ++pass) {
         gemm64(gz, ncu, wkz.as<double>(), s);
@@ -511,20 +676,19 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     orth_z(2, false, 4);
     launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
     mark_eig(T.get(), 4, s);
-    DevBuf perm((size_t)3 * p * sizeof(int), s);
-    DevBuf fixed_dev(3 * sizeof(int), s);
+    Span perm = piece(o_perm, (size_t)3 * p * sizeof(int));
+    Span fixed_dev = piece(o_fixed, 3 * sizeof(int));
     RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
     launch_rank_select(Bm.as<double>(), p, 3, P.eps * P.eps, fixed_dev.as<int>(), P.r_max,
                        perm.as<int>(), &rbd->info, s);
 
     // short-range binning (counts and offsets; the total is read back with the ranks)
-    T->nb = bricks_per_axis(n);
-    const int nbricks = T->nb * T->nb * T->nb;
-    DevBuf counts((size_t)(nbricks + 1) * sizeof(int), s);
+    Span counts = piece(o_counts, (size_t)(nbricks + 1) * sizeof(int));
     RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
     short_bin_count(dpos, N, n, f->grid.b, P.n_s, T->nb, counts.as<int>(), s);
     T->brick_start = DevBuf((size_t)(nbricks + 1) * sizeof(int), s);
-    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1, s);
+    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1,
+                       pre_buf.as<char>() + o_scan, scan_bytes, s);
     RS_HIP(hipMemcpyAsync(&rbd->total_pairs, T->brick_start.as<int>() + nbricks, sizeof(int),
                           hipMemcpyDeviceToDevice, s));
 
@@ -710,13 +874,21 @@ size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
   // scratch arena of the rank-sized stages.
   Gemm64 gram;
   gram.M = n; gram.N = n; gram.K = K; gram.batch = 3; gram.upper_only = 1;
-  Gemm64 sk;
-  sk.M = n; sk.N = p; sk.K = K; sk.batch = 3;
+  Gemm64 yty;
+  yty.M = p; yty.N = p; yty.K = n; yty.batch = 3; yty.upper_only = 1;
+  Gemm64 gx;
+  gx.M = n; gx.N = p; gx.K = n; gx.batch = 3;
+  Gemm64 zz;
+  zz.M = r; zz.N = r; zz.K = p; zz.batch = 3; zz.upper_only = 1;
   size_t inputs = (size_t)N * 4 * d + 2 * (size_t)t.R * d;
   size_t factors = (size_t)(3 * n * K + 3 * K) * d;
   size_t gram_b = (size_t)3 * n * n * d + gemm64_workspace_bytes(gram, ncu);
-  size_t eig = (size_t)(3 * n * p * 2 + 3 * p * p * 3 + 3 * p * r) * d +
-               std::max(gemm64_workspace_bytes(sk, ncu), (size_t)3 * (p * p + 4 * p + 2 * p * r) * d);
+  // the pieces of the pre-readback arena: subspace, eigenproblem, eigenvectors
+  size_t eig = (size_t)(3 * n * p * 2 + 3 * p * p * 2) * d +
+               std::max({sketch64_workspace_bytes(n, K, 3, p, ncu), gemm64_workspace_bytes(gx, ncu),
+                         gemm64_workspace_bytes(yty, ncu)}) +
+               eig_sym_workspace_bytes((int)p, (int)r, 3) + (size_t)(3 * p * r * 2 + 3 * r * r) * d +
+               gemm64_workspace_bytes(zz, ncu) + 32 * 256;
   size_t result = (size_t)(3 * n * r + r * r * r + n * n * r) * d;
   size_t arena = (size_t)(3 * p * r + 3 * K * r + n * r * r) * d +
                  (prec == RS_FP64 ? core64_workspace_bytes((int)r, (int)r, (int)r, K, ncu)

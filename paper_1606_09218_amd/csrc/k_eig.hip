@@ -601,6 +601,107 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
   }
 }
 
+// Blocked Cholesky for 128 < p <= 512: one workgroup of 1024 threads per
+// mode, the matrix in global memory (it stays in L2), worked on in panels of
+// CB = 16 rows of R.  A panel (rows K0..K0+15, columns K0..p-1) is factored
+// in LDS by the right-looking steps restricted to its rows, written back as
+// rows of R, and the trailing upper triangle then takes one rank-16 update
+//   M[j][i] -= sum_k R[k][j] R[k][i],  K0 + 16 <= j <= i < p,
+// so that every trailing entry is read and written once per panel instead
+// of once per column.  The shift of a shifted pass is added to each diagonal
+// entry when its panel is loaded.
+constexpr int CB = 16;
+constexpr int CHB_THREADS = 1024;
+
+__global__ __launch_bounds__(CHB_THREADS) void chol_blk_kernel(double* __restrict__ Call, int p,
+                                                               int64_t nrows, int shifted,
+                                                               int* __restrict__ fail,
+                                                               int fail_bit) {
+  extern __shared__ double pan[];   // [CB][p + 1]
+  __shared__ double red[CHB_THREADS / 64];
+  __shared__ double sh_s;
+  const int mode = blockIdx.x;
+  double* C = Call + (int64_t)mode * p * p;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ldp = p + 1;
+  double sh = 0.0;
+  if (shifted) {
+    double tr = 0.0;
+    for (int i = tid; i < p; i += CHB_THREADS) tr += C[(int64_t)i * p + i];
+    tr = wave_sum(tr);
+    if (lane == 0) red[wave] = tr;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < CHB_THREADS / 64; ++w) t += red[w];
+      sh_s = 11.0 * ((double)nrows * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * t;
+    }
+    __syncthreads();
+    sh = sh_s;
+  }
+  for (int K0 = 0; K0 < p; K0 += CB) {
+    const int nb = p - K0 < CB ? p - K0 : CB;
+    const int w = p - K0;
+    for (int e = tid; e < nb * w; e += CHB_THREADS) {
+      const int r = e / w, c = e - r * w;
+      double v = C[(int64_t)(K0 + r) * p + K0 + c];
+      if (c == r) v += sh;
+      pan[r * ldp + c] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+      double d = pan[k * ldp + k];
+      if (!(d > 0.0)) {
+        if (tid == 0) atomicOr(fail, fail_bit);
+        d = 1e-300;
+      }
+      const double invd = 1.0 / d;
+      const int rows = nb - k - 1;
+      for (int e = tid; e < rows * w; e += CHB_THREADS) {
+        const int j = k + 1 + e / w, i = e - (e / w) * w;
+        if (i >= j) pan[j * ldp + i] -= pan[k * ldp + i] * (pan[k * ldp + j] * invd);
+      }
+      __syncthreads();
+      const double sq = sqrt(d), isq = 1.0 / sq;
+      for (int i = k + 1 + tid; i < w; i += CHB_THREADS) pan[k * ldp + i] *= isq;
+      if (tid == 0) pan[k * ldp + k] = sq;
+      __syncthreads();
+    }
+    for (int e = tid; e < nb * w; e += CHB_THREADS) {
+      const int r = e / w, c = e - r * w;
+      if (c >= r) C[(int64_t)(K0 + r) * p + K0 + c] = pan[r * ldp + c];
+    }
+    // trailing update, rows in groups of 4 (one wave per group), lanes over columns
+    const int j0 = K0 + nb;
+    const int ngroups = (p - j0 + 3) / 4;
+    for (int g = wave; g < ngroups; g += CHB_THREADS / 64) {
+      const int jb = j0 + 4 * g;
+      for (int i = jb + lane; i < p; i += 64) {
+        double acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = jb + r;
+          acc[r] = (j < p && i >= j) ? C[(int64_t)j * p + i] : 0.0;
+        }
+        for (int k = 0; k < nb; ++k) {
+          const double rki = pan[k * ldp + (i - K0)];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double rkj = jb + r < p ? pan[k * ldp + (jb + r - K0)] : 0.0;
+            acc[r] -= rkj * rki;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = jb + r;
+          if (j < p && i >= j) C[(int64_t)j * p + i] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // kernels that use more than the default dynamic LDS opt in to the device limit
 static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 48 * 1024)
@@ -620,7 +721,12 @@ void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int ld
     return;
   }
   const size_t bytes = (size_t)p * p * sizeof(double);
-  if (bytes + 1024 <= (size_t)lds_limit) {
+  const size_t pbytes = (size_t)CB * (p + 1) * sizeof(double);
+  if (p <= 512 && pbytes + 1024 <= (size_t)lds_limit) {
+    allow_lds((const void*)chol_blk_kernel, pbytes);
+    hipLaunchKernelGGL(chol_blk_kernel, dim3(modes), dim3(CHB_THREADS), pbytes, s, C, p, nrows,
+                       shifted, fail, fail_bit);
+  } else if (bytes + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)chol_kernel<true>, bytes);
     hipLaunchKernelGGL(chol_kernel<true>, dim3(modes), dim3(CF_THREADS), bytes, s, C, p, nrows,
                        shifted, fail, fail_bit);
@@ -990,6 +1096,125 @@ __global__ __launch_bounds__(ES_THREADS) void tridiag_kernel(double* __restrict_
   }
 }
 
+// Householder tridiagonalisation for 128 < p <= 512: one workgroup of 1024
+// threads per mode, B (row-major, kept full and symmetric) in global memory,
+// where it stays in L2.  Step k takes the Householder vector from row k
+// (equal to column k), the product B22 v with the 16 waves over slices of
+// the rows of B22 and the lanes over its columns (coalesced; the slices are
+// summed in LDS in wave order), and the rank-2 update one row per wave,
+// lanes over the columns.  Same outputs as the other tridiagonalisations:
+// d, e, beta and the vectors v (v_{k+1} = 1 implicit) in hv.
+constexpr int TW_THREADS = 1024;
+constexpr int TW_WAVES = TW_THREADS / 64;
+constexpr int TW_MAXA = 8;   // columns per lane: p <= 64 TW_MAXA
+
+__device__ double tw_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < TW_WAVES; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(TW_THREADS) void tridiag_wide_kernel(double* __restrict__ Ball,
+                                                                  double* __restrict__ ws, int p,
+                                                                  int rc) {
+  extern __shared__ double tsh[];
+  double* part = tsh;                   // [TW_WAVES][p]
+  double* vs = tsh + TW_WAVES * p;      // [p]
+  double* pw = vs + p;                  // [p]
+  __shared__ double red[TW_WAVES];
+  __shared__ double v1_s, beta_s;
+  const int mode = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* B = Ball + (int64_t)mode * p * p;
+  EigWs W(ws, p, rc, mode);
+  for (int x = tid; x < p; x += TW_THREADS) {
+    W.e[x] = 0.0;
+    W.beta[x] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < p; ++k) {
+    const double* rowk = B + (int64_t)k * p;
+    double prt = 0.0;
+    for (int i = k + 2 + tid; i < p; i += TW_THREADS) prt += rowk[i] * rowk[i];
+    const double sigma = tw_block_sum(prt, red);
+    if (tid == 0) {
+      const double x1 = rowk[k + 1];
+      double beta = 0.0, v1 = 1.0, sub = x1;
+      if (sigma > 0.0) {
+        const double mu = sqrt(x1 * x1 + sigma);
+        v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
+        beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        sub = mu;
+      }
+      W.d[k] = rowk[k];
+      W.e[k] = sub;
+      W.beta[k] = beta;
+      v1_s = v1;
+      beta_s = beta;
+    }
+    __syncthreads();
+    const double beta = beta_s;
+    if (beta == 0.0) {  // uniform: column already reduced (its entries below k+1 are zero)
+      for (int i = k + 2 + tid; i < p; i += TW_THREADS) W.hv[(int64_t)k * p + i] = rowk[i];
+      continue;
+    }
+    const double inv1 = 1.0 / v1_s;
+    for (int i = k + 1 + tid; i < p; i += TW_THREADS) {
+      const double v = i == k + 1 ? 1.0 : rowk[i] * inv1;
+      vs[i] = v;
+      if (i >= k + 2) W.hv[(int64_t)k * p + i] = v;
+    }
+    __syncthreads();
+    double acc[TW_MAXA];
+#pragma unroll
+    for (int a = 0; a < TW_MAXA; ++a) acc[a] = 0.0;
+    for (int j = k + 1 + wave; j < p; j += TW_WAVES) {
+      const double vj = vs[j];
+      const double* rowj = B + (int64_t)j * p;
+#pragma unroll
+      for (int a = 0; a < TW_MAXA; ++a) {
+        const int i = k + 1 + lane + 64 * a;
+        if (i < p) acc[a] += rowj[i] * vj;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < TW_MAXA; ++a) {
+      const int i = k + 1 + lane + 64 * a;
+      if (i < p) part[wave * p + i] = acc[a];
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < p; i += TW_THREADS) {
+      double sacc = 0.0;
+      for (int w = 0; w < TW_WAVES; ++w) sacc += part[w * p + i];
+      pw[i] = beta * sacc;
+    }
+    __syncthreads();
+    prt = 0.0;
+    for (int i = k + 1 + tid; i < p; i += TW_THREADS) prt += pw[i] * vs[i];
+    const double kc = 0.5 * beta * tw_block_sum(prt, red);
+    for (int i = k + 1 + tid; i < p; i += TW_THREADS) pw[i] -= kc * vs[i];
+    __syncthreads();
+    for (int i = k + 1 + wave; i < p; i += TW_WAVES) {
+      const double vi = vs[i], wi = pw[i];
+      double* rowi = B + (int64_t)i * p;
+      for (int j = k + 1 + lane; j < p; j += 64) rowi[j] -= vi * pw[j] + wi * vs[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (p >= 2) {
+      W.d[p - 2] = B[(int64_t)(p - 2) * p + (p - 2)];
+      W.e[p - 2] = B[(int64_t)(p - 1) * p + (p - 2)];
+    }
+    W.d[p - 1] = B[(int64_t)(p - 1) * p + (p - 1)];
+    W.e[p - 1] = 0.0;
+  }
+}
+
 // 1/q for finite nonzero q: the hardware reciprocal estimate refined by two
 // Newton steps t <- t + t (1 - q t) (each roughly doubles the correct bits).
 __device__ __forceinline__ double recip(double q) {
@@ -1307,7 +1532,12 @@ void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds
     return;
   }
   const size_t tri_lds = ((size_t)p * (p + 1) + (size_t)p) * sizeof(double);
-  if (tri_lds + 1024 <= (size_t)lds_limit) {
+  const size_t wide_lds = (size_t)(TW_WAVES + 2) * p * sizeof(double);
+  if (p <= 64 * TW_MAXA && wide_lds + 1024 <= (size_t)lds_limit) {
+    allow_lds((const void*)tridiag_wide_kernel, wide_lds);
+    hipLaunchKernelGGL(tridiag_wide_kernel, dim3(modes), dim3(TW_THREADS), wide_lds, s, B, ws, p,
+                       rc);
+  } else if (tri_lds + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)tridiag_kernel<true>, tri_lds);
     hipLaunchKernelGGL(tridiag_kernel<true>, dim3(modes), dim3(ES_THREADS), tri_lds, s, B, ws, p,
                        rc);

@@ -446,7 +446,9 @@ static void cfg_shape(CfgId c, int& bm, int& bn) {
 }
 
 // Tucker-rank-sized M (65..96) takes the 96-row tile, a very tall product
-// (the grid expansion) the big tile, everything else the small tile.
+// (the grid expansion) the big tile, everything else (and every upper-only
+// product, whose tiles must be square) the small tile.  The big tile measured
+// slower on the charge-weighted Gram (both operands transposed).
 static CfgId choose(const Gemm64& g, int num_cu) {
   (void)num_cu;
   if (g.upper_only) return CFG_SMALL;
@@ -606,7 +608,9 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
   }
 }
 
-// the sketch keeps the small tile (its N is the subspace size p)
+// the sketch takes the big tile when both M and the subspace size N fill it
+static CfgId sketch_cfg(int64_t M, int64_t N) { return (M >= 256 && N >= 128) ? CFG_BIG : CFG_SMALL; }
+
 void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* scale,
               int64_t scale_stride, int batch, int64_t N, uint64_t seed, double* Y, int64_t scm,
               int64_t scn, int num_cu, double* work, hipStream_t s) {
@@ -620,19 +624,22 @@ void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* 
   d.kscale = scale;
   d.upper_only = 0;
   d.nontemporal = 0;
-  const Plan64 P = plan_for(g, CFG_SMALL, num_cu);
+  const Plan64 P = plan_for(g, sketch_cfg(M, N), num_cu);
   d.splits = P.splits;
   d.kchunk = P.kchunk;
-  d.bm = CfgSmall::BM;
-  d.bn = CfgSmall::BN;
-  d.tiles_m = (int)((M + d.bm - 1) / d.bm);
-  d.tiles_n = (int)((N + d.bn - 1) / d.bn);
+  d.bm = P.bm;
+  d.bn = P.bn;
+  d.tiles_m = P.tm;
+  d.tiles_n = P.tn;
   d.xcd_remap = 0;
   const bool use_part = d.splits > 1;
   d.part = use_part ? work : nullptr;
   if (use_part && !work) throw Error{RS_E_DEVICE, "sketch64: missing split-K workspace"};
   dim3 grid((unsigned)(d.tiles_m * d.tiles_n), (unsigned)batch, (unsigned)d.splits);
-  hipLaunchKernelGGL(sketch_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d, seed);
+  if (P.cfg == CFG_BIG)
+    hipLaunchKernelGGL(sketch_kernel<CfgBig>, grid, dim3(CfgBig::NT), 0, s, d, seed);
+  else
+    hipLaunchKernelGGL(sketch_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d, seed);
   if (use_part) {
     int64_t total = M * N;
     int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
@@ -644,7 +651,7 @@ void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* 
 size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu) {
   Gemm64 g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
-  const Plan64 P = plan_for(g, CFG_SMALL, num_cu);
+  const Plan64 P = plan_for(g, sketch_cfg(M, N), num_cu);
   if (P.splits == 1) return 0;
   return (size_t)g.batch * P.splits * g.M * g.N * sizeof(double);
 }

@@ -112,12 +112,25 @@ void short_bin_sort(const int* start, int* list, int nbricks, int* active, int64
                      start, list, nbricks, active, active_cap);
 }
 
-void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s) {
+size_t exclusive_scan_bytes(int count) {
   size_t tmp_bytes = 0;
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, in, out, count, s) != hipSuccess)
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, (const int*)nullptr, (int*)nullptr,
+                                       count) != hipSuccess)
     throw Error{RS_E_DEVICE, "hipcub scan sizing failed"};
-  DevBuf tmp(tmp_bytes > 0 ? tmp_bytes : 16, s);
-  RS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, in, out, count, s));
+  return tmp_bytes > 0 ? tmp_bytes : 16;
+}
+
+void exclusive_scan_int(const int* in, int* out, int count, void* tmp, size_t tmp_bytes,
+                        hipStream_t s) {
+  size_t need = exclusive_scan_bytes(count);
+  if (tmp_bytes < need) throw Error{RS_E_DEVICE, "scan workspace too small"};
+  RS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, need, in, out, count, s));
+}
+
+void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s) {
+  const size_t tmp_bytes = exclusive_scan_bytes(count);
+  DevBuf tmp(tmp_bytes, s);
+  exclusive_scan_int(in, out, count, tmp.p, tmp_bytes, s);
 }
 
 constexpr int MAX_RS = 64;  // short-range terms handled per particle

@@ -229,6 +229,10 @@ void short_bin_sort(const int* start, int* list, int nbricks, int* active, int64
 // Upper bound on the number of bricks touched by the windows of N particles.
 int64_t short_active_capacity(int64_t N, int n_s, int nb);
 void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s);
+// the same with a caller-provided temporary of at least exclusive_scan_bytes(count)
+size_t exclusive_scan_bytes(int count);
+void exclusive_scan_int(const int* in, int* out, int count, void* tmp, size_t tmp_bytes,
+                        hipStream_t s);
 // grid (FP64 or FP32) += sum over particles of the short-range windows
 void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
                   const double* t, const double* a, int R, int R_l, int64_t n, double b,

@@ -10,13 +10,13 @@
 // one accumulator per magnitude level, folded into FP64 registers every
 // KCHUNK values of k.
 //
-// The operands are split once into planes, [term][row][kp] with the
+// The FP64 operands are split once into planes, [term][row][kp] with the
 // contraction index k contiguous and padded with zeros to kp (a multiple of
-// 32), so that each lane loads its MFMA fragment (8 consecutive k of one row,
-// 16 bytes) straight from memory: no LDS staging and no conversion inside the
-// GEMM loops.  The Khatri-Rao operand of the core, xi_j U~2[j,b] U~3[j,c],
-// is never stored: lanes form it in FP32 from xi U~2 and U~3 (transposed,
-// FP32) and split it in registers.
+// 32): an MFMA fragment (8 consecutive k of one row, 16 bytes) is one load.
+// The grid expansion streams its A fragments straight from the planes; the
+// core stages 32-k slabs of both operands in LDS.  The Khatri-Rao operand of
+// the core, xi_j U~2[j,b] U~3[j,c], is never stored: each workgroup forms
+// its slab in FP32 from xi U~2 and U~3 (transposed, FP32) and splits it once.
 //
 // v_mfma_f32_16x16x32_{f16,bf16}: lane l holds A[l % 16][8 (l / 16) + t] and
 // B[8 (l / 16) + t][l % 16] (t = 0..7), and D[4 (l / 16) + v][l % 16].
@@ -144,112 +144,6 @@ __global__ void kr_factors_kernel(const double* __restrict__ U2t, const double* 
       u3[c * kp + j] = j < K ? (float)U3t[j * r3 + c] : 0.0f;
     }
   }
-}
-
-// ---- grid: C[m, n] (FP32) = sum_k A[m, k] B[n, k] from split planes ---------------
-// Workgroup 64 x 128 (4 waves of 32 x 64, 2 x 4 blocks of 16 x 16 each).
-template <class SP>
-__global__ __launch_bounds__(256) void grid_split_kernel(const typename SP::T* __restrict__ Ap,
-                                                         const typename SP::T* __restrict__ Bp,
-                                                         int64_t M, int64_t N, int64_t kp,
-                                                         int tiles_n, int xcd_remap, float* grid,
-                                                         const int* exps) {
-  typedef typename SP::V8 V8;
-  const int t = blockIdx.x;
-  int tm, tn;
-  if (xcd_remap) {
-    const int x = t & 7, i = t >> 3;
-    tm = (i / tiles_n) * 8 + x;
-    tn = i - (i / tiles_n) * tiles_n;
-  } else {
-    tm = t / tiles_n;
-    tn = t - tm * tiles_n;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)tm * 64 + (wave >> 1) * 32;
-  const int64_t n0 = (int64_t)tn * 128 + (wave & 1) * 64;
-  const int64_t planeA = M * kp, planeB = N * kp;
-  const int kofs = 8 * (lane >> 4);
-  f4 acc[2][4][SP::LEVELS];
-  double acc64[2][4][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
-    }
-  // rows beyond M / N read row 0 (their results are not stored)
-  int64_t arow[2], brow[4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int64_t r = m0 + 16 * i + (lane & 15);
-    arow[i] = (r < M ? r : 0) * kp + kofs;
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t r = n0 + 16 * j + (lane & 15);
-    brow[j] = (r < N ? r : 0) * kp + kofs;
-  }
-  // fragments of the next k block are loaded while the current one is used
-  V8 a[2][SP::TERMS], b[4][SP::TERMS];
-  auto load = [&](int64_t k0, V8 (&ra)[2][SP::TERMS], V8 (&rb)[4][SP::TERMS]) {
-#pragma unroll
-    for (int term = 0; term < SP::TERMS; ++term) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) ra[i][term] = *(const V8*)(Ap + term * planeA + arow[i] + k0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rb[j][term] = *(const V8*)(Bp + term * planeB + brow[j] + k0);
-    }
-  };
-  load(0, a, b);
-  int since = 0;
-  for (int64_t k0 = 0; k0 < kp; k0 += 32) {
-    V8 na[2][SP::TERMS], nb[4][SP::TERMS];
-    const bool more = k0 + 32 < kp;
-    if (more) load(k0 + 32, na, nb);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) SP::products(a[i], b[j], acc[i][j]);
-    since += 32;
-    if (since >= KCHUNK || !more) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc64[i][j][v] += SP::combine(acc[i][j], v);
-#pragma unroll
-          for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-      since = 0;
-    }
-    if (more) {
-#pragma unroll
-      for (int term = 0; term < SP::TERMS; ++term) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i][term] = na[i][term];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j][term] = nb[j][term];
-      }
-    }
-  }
-  const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = n0 + 16 * j + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + 16 * i + 4 * (lane >> 4) + v;
-        if (row < M && col < N)
-          __builtin_nontemporal_store((float)(acc64[i][j][v] * out_scale), grid + row * N + col);
-      }
-    }
 }
 
 // ---- grid, streaming form -------------------------------------------------------
@@ -395,120 +289,177 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
   }
 }
 
-// ---- core: beta_(1)[a, b r3 + c] = sum_j U~1[j, a] xi_j U~2[j, b] U~3[j, c] ----------
-// A = U~1^T from split planes [term][a][kp]; B[j, (b, c)] formed per lane from
-// s2[b][j] u3[c][j] (FP32) and split in registers.  A wave owns one column
-// block of 16 (b, c) pairs and 6 row blocks (96 values of a) of one row chunk;
-// blockIdx.y = row chunk, blockIdx.z = split of the j range.
-template <class SP>
-__global__ __launch_bounds__(256) void core_split_kernel(const typename SP::T* __restrict__ Ap,
-                                                         const float* __restrict__ s2,
-                                                         const float* __restrict__ u3, int r1,
-                                                         int r2, int r3, int64_t kp,
-                                                         int64_t kchunk, double* __restrict__ out,
-                                                         int64_t split_stride, const int* exps) {
+// ---- core, LDS-tiled: beta_(1)[a, col] = sum_j A[a, j] B[j, col] ------------------
+// col = b r3 + c, B[j, col] = s2[b][j] u3[c][j] formed in FP32 and split once
+// per workgroup into LDS.  Workgroup tile 32 WGM rows x 32 FN columns, 2 WGM
+// waves of 32 x 16 FN (2 x FN MFMA blocks).  Per step of 32 k the next A
+// fragments (from the split planes) and the raw s2/u3 values are loaded into
+// registers while the MFMAs of the current step run, then written to LDS
+// (rows padded to 40 elements: the 16-byte fragment reads of 16 rows fall
+// in distinct banks).  FP32 accumulators are folded into FP64 every KCHUNK.
+// FN column blocks per wave: 4 for the two-term FP16 split, 2 for the
+// three-term BF16 split (whose accumulators take more registers).
+template <class SP, int WGM, int FN>
+__global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
+    const typename SP::T* __restrict__ Ap, const float* __restrict__ s2,
+    const float* __restrict__ u3, int r1, int r2, int r3, int64_t kp, int64_t kchunk,
+    int row_tiles, double* __restrict__ out, int64_t split_stride, const int* exps) {
   typedef typename SP::T T;
   typedef typename SP::V8 V8;
-  constexpr int RB = 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 40;
+  constexpr int A_ITEMS = BM * 4 * SP::TERMS, A_PER = (A_ITEMS + NT - 1) / NT;
+  constexpr int B_ITEMS = BN * 4, B_PER = (B_ITEMS + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) T As[SP::TERMS][BM][LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[SP::TERMS][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int W = r2 * r3;
-  const int cb = (blockIdx.x * 4 + wave) * 16;   // first (b, c) column of this wave
-  if (cb >= W) return;                          // whole wave idle (no barriers below)
-  const int a0 = blockIdx.y * (16 * RB);
+  const int rt = blockIdx.x % row_tiles, ct = blockIdx.x / row_tiles;
+  const int a0 = rt * BM, n0 = ct * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = kbeg + kchunk < kp ? kbeg + kchunk : kp;
   const int64_t planeA = (int64_t)r1 * kp;
-  const int kofs = 8 * (lane >> 4);
   const float bscale = SP::SCALED && exps ? (float)pow2(exps[1]) : 1.0f;
-  // this lane's (b, c) column
-  const int col = cb + (lane & 15);
-  const int colc = col < W ? col : 0;
-  const int b = colc / r3, c = colc - (colc / r3) * r3;
-  const float* __restrict__ srow = s2 + (int64_t)b * kp + kofs;
-  const float* __restrict__ urow = u3 + (int64_t)c * kp + kofs;
-  int64_t arow[RB];
+
+  // loader coordinates (fixed over k)
+  int64_t a_src[A_PER];
+  int a_dst[A_PER];
+  bool a_ok[A_PER];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) {
-    const int a = a0 + 16 * i + (lane & 15);
-    arow[i] = (int64_t)(a < r1 ? a : 0) * kp + kofs;
+  for (int u = 0; u < A_PER; ++u) {
+    const int idx = tid + NT * u;
+    const int term = idx / (BM * 4), rem = idx - term * (BM * 4);
+    const int row = rem >> 2, q = rem & 3;
+    a_ok[u] = idx < A_ITEMS && a0 + row < r1;
+    a_src[u] = a_ok[u] ? term * planeA + (int64_t)(a0 + row) * kp + 8 * q : 0;
+    a_dst[u] = idx < A_ITEMS ? (term * BM + row) * LDK + 8 * q : 0;
   }
-  f4 acc[RB][SP::LEVELS];
-  double acc64[RB][4];
+  int64_t s_src[B_PER], u_src[B_PER];
+  int b_dst[B_PER];
+  bool b_ok[B_PER], b_in[B_PER];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) {
-#pragma unroll
-    for (int l = 0; l < SP::LEVELS; ++l) acc[i][l] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc64[i][v] = 0.0;
+  for (int u = 0; u < B_PER; ++u) {
+    const int idx = tid + NT * u;
+    const int n = idx >> 2, q = idx & 3;
+    const int col = n0 + n;
+    b_in[u] = idx < B_ITEMS;
+    b_ok[u] = b_in[u] && col < W;
+    const int b = b_ok[u] ? col / r3 : 0, c = b_ok[u] ? col - (col / r3) * r3 : 0;
+    s_src[u] = (int64_t)b * kp + 8 * q;
+    u_src[u] = (int64_t)c * kp + 8 * q;
+    b_dst[u] = n * LDK + 8 * q;
   }
-  const int rem = (r1 - a0 + 15) / 16;
-  const int nrb = rem < RB ? rem : RB;   // row blocks with any row < r1
-  // raw data of the next k block is loaded while the current one is used
-  float4 sv[2], uv[2];
-  V8 af[RB][SP::TERMS];
-  auto load = [&](int64_t k0, float4 (&s_)[2], float4 (&u_)[2], V8 (&a_)[RB][SP::TERMS]) {
-    s_[0] = *(const float4*)(srow + k0);
-    s_[1] = *(const float4*)(srow + k0 + 4);
-    u_[0] = *(const float4*)(urow + k0);
-    u_[1] = *(const float4*)(urow + k0 + 4);
+  V8 ra[A_PER];
+  float4 rs[B_PER][2], ru[B_PER][2];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
-      if (i < nrb)
+    for (int u = 0; u < A_PER; ++u) {
+      if (a_ok[u]) ra[u] = *(const V8*)(Ap + a_src[u] + k0);
+      else ra[u] = V8{};
+    }
 #pragma unroll
-        for (int term = 0; term < SP::TERMS; ++term)
-          a_[i][term] = *(const V8*)(Ap + term * planeA + arow[i] + k0);
+    for (int u = 0; u < B_PER; ++u) {
+      if (b_ok[u]) {
+        rs[u][0] = *(const float4*)(s2 + s_src[u] + k0);
+        rs[u][1] = *(const float4*)(s2 + s_src[u] + k0 + 4);
+        ru[u][0] = *(const float4*)(u3 + u_src[u] + k0);
+        ru[u][1] = *(const float4*)(u3 + u_src[u] + k0 + 4);
+      } else {
+        rs[u][0] = rs[u][1] = ru[u][0] = ru[u][1] = float4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
   };
-  if (kbeg < kend) load(kbeg, sv, uv, af);
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u)
+      if (tid + NT * u < A_ITEMS) *(V8*)(&As[0][0][0] + a_dst[u]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) {
+      if (!b_in[u]) continue;
+      const float x[8] = {rs[u][0].x * ru[u][0].x, rs[u][0].y * ru[u][0].y, rs[u][0].z * ru[u][0].z,
+                          rs[u][0].w * ru[u][0].w, rs[u][1].x * ru[u][1].x, rs[u][1].y * ru[u][1].y,
+                          rs[u][1].z * ru[u][1].z, rs[u][1].w * ru[u][1].w};
+      V8 bv[SP::TERMS];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        T parts[SP::TERMS];
+        SP::split32(x[t] * bscale, parts);
+#pragma unroll
+        for (int term = 0; term < SP::TERMS; ++term) bv[term][t] = parts[term];
+      }
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term)
+        *(V8*)(&Bs[term][0][0] + b_dst[u]) = bv[term];
+    }
+  };
+
+  f4 acc[2][FN][SP::LEVELS];
+  double acc64[2][FN][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+#pragma unroll
+      for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    }
+  if (kbeg < kend) {
+    load(kbeg);
+    store();
+  }
+  __syncthreads();
+  const int frow = lane & 15, fk = 8 * (lane >> 4);
   int since = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
     const bool more = k0 + 32 < kend;
-    float4 nsv[2], nuv[2];
-    V8 naf[RB][SP::TERMS];
-    if (more) load(k0 + 32, nsv, nuv, naf);
-    // B fragment: 8 consecutive j of column (b, c)
-    const float x[8] = {sv[0].x * uv[0].x, sv[0].y * uv[0].y, sv[0].z * uv[0].z, sv[0].w * uv[0].w,
-                        sv[1].x * uv[1].x, sv[1].y * uv[1].y, sv[1].z * uv[1].z, sv[1].w * uv[1].w};
-    V8 bf[SP::TERMS];
+    if (more) load(k0 + 32);
+    V8 af[2][SP::TERMS], bf[FN][SP::TERMS];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      T parts[SP::TERMS];
-      SP::split32(x[t] * bscale, parts);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int term = 0; term < SP::TERMS; ++term) bf[term][t] = parts[term];
-    }
+      for (int term = 0; term < SP::TERMS; ++term)
+        af[i][term] = *(const V8*)(&As[term][wm * 32 + i * 16 + frow][fk]);
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
-      if (i < nrb) SP::products(af[i], bf, acc[i]);
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term)
+        bf[j][term] = *(const V8*)(&Bs[term][wn * (16 * FN) + j * 16 + frow][fk]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) SP::products(af[i], bf[j], acc[i][j]);
     since += 32;
     if (since >= KCHUNK || !more) {
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[i][v] += SP::combine(acc[i], v);
+        for (int j = 0; j < FN; ++j) {
 #pragma unroll
-        for (int l = 0; l < SP::LEVELS; ++l) acc[i][l] = f4{0.f, 0.f, 0.f, 0.f};
-      }
+          for (int v = 0; v < 4; ++v) acc64[i][j][v] += SP::combine(acc[i][j], v);
+#pragma unroll
+          for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
+        }
       since = 0;
     }
+    __syncthreads();
     if (more) {
-      sv[0] = nsv[0];
-      sv[1] = nsv[1];
-      uv[0] = nuv[0];
-      uv[1] = nuv[1];
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int term = 0; term < SP::TERMS; ++term) af[i][term] = naf[i][term];
+      store();
+      __syncthreads();
     }
   }
   const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
   double* o = out + (int64_t)blockIdx.z * split_stride;
 #pragma unroll
-  for (int i = 0; i < RB; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = a0 + 16 * i + 4 * (lane >> 4) + v;
-      if (a < r1 && col < W) o[(int64_t)a * W + col] = acc64[i][v] * out_scale;
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * (16 * FN) + j * 16 + frow;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        if (a < r1 && col < W) o[(int64_t)a * W + col] = acc64[i][j][v] * out_scale;
+      }
     }
 }
 
@@ -582,16 +533,33 @@ static void split_planes(const double* src, int64_t rows, int64_t cols, int64_t 
 // ---- core ------------------------------------------------------------------------
 struct CoreMixedPlan {
   int64_t kp, kchunk;
-  int splits, row_chunks, col_groups;
+  int splits, wgm, row_tiles, col_tiles;
   size_t o_mx, o_exps, o_planes, o_s2, o_u3, o_part, total;
 };
 
-static CoreMixedPlan plan_core_mixed(int r1, int r2, int r3, int64_t K, int num_cu) {
+// rows per workgroup tile 32 WGM, WGM in {4, 3, 2}: the least padding of r1
+// (ties to the larger tile)
+static int core_wgm(int r1) {
+  int best = 4;
+  int64_t best_pad = INT64_MAX;
+  for (int w : {4, 3, 2}) {
+    const int64_t pad = (int64_t)((r1 + 32 * w - 1) / (32 * w)) * 32 * w;
+    if (pad < best_pad) {
+      best_pad = pad;
+      best = w;
+    }
+  }
+  return best;
+}
+
+static CoreMixedPlan plan_core_mixed(int prec, int r1, int r2, int r3, int64_t K, int num_cu) {
   CoreMixedPlan P{};
+  const int fn = prec == RS_MIXED_BF16 ? 2 : 4;
   P.kp = pad32(K);
-  P.row_chunks = (r1 + 95) / 96;
-  P.col_groups = (int)(((int64_t)r2 * r3 + 63) / 64);
-  const int64_t wgs = (int64_t)P.row_chunks * P.col_groups;
+  P.wgm = core_wgm(r1);
+  P.row_tiles = (r1 + 32 * P.wgm - 1) / (32 * P.wgm);
+  P.col_tiles = (int)(((int64_t)r2 * r3 + 32 * fn - 1) / (32 * fn));
+  const int64_t wgs = (int64_t)P.row_tiles * P.col_tiles;
   P.splits = 1;
   if (wgs < 2LL * num_cu) {
     const int64_t want = (2LL * num_cu + wgs - 1) / wgs;
@@ -616,15 +584,18 @@ static CoreMixedPlan plan_core_mixed(int r1, int r2, int r3, int64_t K, int num_
   return P;
 }
 
+// enough for either split (their tiles, and so their split-K plans, differ)
 size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
-  return plan_core_mixed(r1, r2, r3, K, num_cu).total;
+  return std::max(plan_core_mixed(RS_MIXED_FP16, r1, r2, r3, K, num_cu).total,
+                  plan_core_mixed(RS_MIXED_BF16, r1, r2, r3, K, num_cu).total);
 }
 
 template <class SP>
 static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const double* U3t,
                          const double* xi, int r1, int r2, int r3, int64_t K, double* beta,
                          int num_cu, char* work, hipStream_t s) {
-  const CoreMixedPlan P = plan_core_mixed(r1, r2, r3, K, num_cu);
+  const CoreMixedPlan P =
+      plan_core_mixed(fp16 ? RS_MIXED_FP16 : RS_MIXED_BF16, r1, r2, r3, K, num_cu);
   unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
   int* exps = (int*)(work + P.o_exps);
   typename SP::T* planes = (typename SP::T*)(work + P.o_planes);
@@ -638,10 +609,19 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   split_planes<SP>(U1t, r1, K, 1, r1, P.kp, exps, 0, planes, s);
   hipLaunchKernelGGL(kr_factors_kernel, dim3(grid_blocks((int64_t)(r2 + r3) * P.kp)), dim3(256), 0,
                      s, U2t, U3t, xi, r2, r3, K, P.kp, s2, u3);
-  const dim3 grid((unsigned)P.col_groups, (unsigned)P.row_chunks, (unsigned)P.splits);
+  const dim3 grid((unsigned)(P.row_tiles * P.col_tiles), 1, (unsigned)P.splits);
   double* out = part ? part : beta;
-  hipLaunchKernelGGL(core_split_kernel<SP>, grid, dim3(256), 0, s, planes, s2, u3, r1, r2, r3, P.kp,
-                     P.kchunk, out, (int64_t)r1 * r2 * r3, exps);
+  const int64_t stride = (int64_t)r1 * r2 * r3;
+  constexpr int FN = SP::TERMS == 2 ? 4 : 2;
+  if (P.wgm == 4)
+    hipLaunchKernelGGL((core_tile_kernel<SP, 4, FN>), grid, dim3(512), 0, s, planes, s2, u3, r1, r2,
+                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+  else if (P.wgm == 3)
+    hipLaunchKernelGGL((core_tile_kernel<SP, 3, FN>), grid, dim3(384), 0, s, planes, s2, u3, r1, r2,
+                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+  else
+    hipLaunchKernelGGL((core_tile_kernel<SP, 2, FN>), grid, dim3(256), 0, s, planes, s2, u3, r1, r2,
+                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
   if (part) core64_reduce(part, P.splits, (int64_t)r1 * r2 * r3, beta, s);
 }
 

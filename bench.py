@@ -46,11 +46,11 @@ def workload(name: str):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources of the grid-expansion GEMM (its kernel file and the
-    internal header): traffic counters taken on other sources are stale."""
+    """Hash of the source file of the FP64 GEMM kernels: traffic counters
+    taken on another version of it are stale."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1606_09218_amd", "csrc")
-    for f in ("k_gemm64.hip", "rs_internal.h"):
+    for f in ("k_gemm64.hip",):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -157,8 +157,7 @@ def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
 
         def step():
             T = rsm.assemble(ctx, f, pos, q, g32, opts, stream=stream)
-            rsm.energy(T, E, stream=stream)
-            rsm.forces(T, F, 1.0, stream=stream)
+            rsm.energy_forces(T, E, F, 1.0, stream=stream)
             return T
 
         for _ in range(warmup):
@@ -248,8 +247,7 @@ def main():
 
     def step():
         T = rsm.assemble(ctx, f, pos, q, grid, opts, stream=stream)
-        rsm.energy(T, E, stream=stream)
-        rsm.forces(T, F, 1.0, stream=stream)
+        rsm.energy_forces(T, E, F, 1.0, stream=stream)
         return T
 
     for _ in range(args.warmup):

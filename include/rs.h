@@ -240,6 +240,12 @@ rs_status rs_energy(const rs_tensor* T, double* E, double* dEdq, void* stream);
  * F: device, N x 3 FP64, F_j = -scale * dE/dx_j = -scale z_j grad[P_l - z_j g_j](x_j). */
 rs_status rs_forces(const rs_tensor* T, double scale, double* F, void* stream);
 
+/* Energy and forces from one evaluation pass at the particles: the results
+ * of rs_energy(T, E, dEdq) and rs_forces(T, scale, F), bitwise, for the
+ * price of one.  E, F as there; dEdq may be NULL. */
+rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double scale, double* F,
+                           void* stream);
+
 /* ---- introspection, persistence --------------------------------------- */
 
 /* Peak device memory rs_assemble needs for this request (with_grid != 0 adds

@@ -853,6 +853,27 @@ rs_status rs_forces(const rs_tensor* T, double scale, double* F, void* stream) {
   });
 }
 
+rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double scale, double* F,
+                           void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && E && F, "null argument");
+    RS_REQUIRE(std::isfinite(scale), "scale must be finite");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf v((size_t)T->N * sizeof(double), s), gv((size_t)T->N * 3 * sizeof(double), s);
+    DevBuf sv((size_t)T->N * sizeof(double), s), sg((size_t)T->N * 3 * sizeof(double), s);
+    EvalOut o;
+    o.val = v.as<double>();
+    o.grad = gv.as<double>();
+    o.selfv = sv.as<double>();
+    o.selfg = sg.as<double>();
+    launch_eval_long(T, T->N, T->pos.as<double>(), 1, o, s);
+    launch_energy_reduce(T->q.as<double>(), v.as<double>(), sv.as<double>(), T->N, E, dEdq, s);
+    launch_forces(T->q.as<double>(), gv.as<double>(), sg.as<double>(), T->N, scale, F, s);
+    return RS_OK;
+  });
+}
+
 size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N, int32_t r_max,
                           int32_t prec, int32_t with_grid) {
   (void)with_grid;

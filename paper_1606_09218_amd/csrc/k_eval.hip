@@ -18,7 +18,6 @@
 namespace rs {
 
 constexpr int PMAX = 8;        // largest interpolation order
-constexpr int CPL = 16;        // r3 <= 64 * CPL
 
 struct EvalDev {
   const double* T2;    // n x n x r3
@@ -30,28 +29,35 @@ struct EvalDev {
   int r3, R_l, p;
 };
 
-__device__ __forceinline__ void stencil(double y, double b, int64_t n, int p, int& start,
-                                        double* L, double* dL) {
+// Lagrange weights L_i and derivatives dL_i of the P-point stencil around y
+// (cell-centred nodes s..s+P-1, clamped to the grid).
+template <int P>
+__device__ __forceinline__ void stencil(double y, double b, int64_t n, int& start, double* L,
+                                        double* dL) {
   const double h = 2.0 * b / (double)n;
   const double u = (y + b) / h - 0.5;
   int m = (int)floor(u);
-  int s = m - p / 2 + 1;
+  int s = m - P / 2 + 1;
   if (s < 0) s = 0;
-  if (s > (int)n - p) s = (int)n - p;
+  if (s > (int)n - P) s = (int)n - P;
   start = s;
-  for (int i = 0; i < p; ++i) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
     double num = 1.0, den = 1.0;
-    for (int j = 0; j < p; ++j)
+#pragma unroll
+    for (int j = 0; j < P; ++j)
       if (j != i) {
         num *= (u - (double)(s + j));
         den *= (double)(i - j);
       }
     L[i] = num / den;
     double d = 0.0;
-    for (int mm = 0; mm < p; ++mm) {
+#pragma unroll
+    for (int mm = 0; mm < P; ++mm) {
       if (mm == i) continue;
       double prod = 1.0;
-      for (int j = 0; j < p; ++j)
+#pragma unroll
+      for (int j = 0; j < P; ++j)
         if (j != i && j != mm) prod *= (u - (double)(s + j));
       d += prod;
     }
@@ -64,7 +70,10 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// One wave per point.
+// One wave per point; lanes over the rank index c (NC values each).  The
+// stencil order P and NC are compile-time constants, so the P^2 rows of T2
+// are addressed statically and their loads are all issued up front.
+template <int P, int NC>
 __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
                                                         const double* __restrict__ pts,
                                                         int with_self, double* __restrict__ val,
@@ -74,22 +83,23 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
   const int lane = threadIdx.x & 63;
   const int64_t pt = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (pt >= M) return;
-  const int p = e.p;
   double y[3];
   int s[3];
-  double L[3][PMAX], dL[3][PMAX];
+  double L[3][P], dL[3][P];
+#pragma unroll
   for (int l = 0; l < 3; ++l) {
     y[l] = pts[3 * pt + l];
-    stencil(y[l], e.b, e.n, p, s[l], L[l], dL[l]);
+    stencil<P>(y[l], e.b, e.n, s[l], L[l], dL[l]);
   }
   const int r3 = e.r3;
-  double q3[CPL], dq3[CPL];
+  double q3[NC], dq3[NC];
 #pragma unroll
-  for (int u = 0; u < CPL; ++u) {
+  for (int u = 0; u < NC; ++u) {
     const int c = lane + 64 * u;
     double qa = 0.0, qd = 0.0;
     if (c < r3) {
-      for (int m = 0; m < p; ++m) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
         const double v = e.V3[(int64_t)(s[2] + m) * r3 + c];
         qa += L[2][m] * v;
         qd += dL[2][m] * v;
@@ -99,18 +109,18 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
     dq3[u] = qd;
   }
   double v = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-  for (int m1 = 0; m1 < p; ++m1) {
-    for (int m2 = 0; m2 < p; ++m2) {
+#pragma unroll
+  for (int m1 = 0; m1 < P; ++m1) {
+#pragma unroll
+    for (int m2 = 0; m2 < P; ++m2) {
       const double* row = e.T2 + ((int64_t)(s[0] + m1) * e.n + (s[1] + m2)) * r3;
       double d = 0.0, dd = 0.0;
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) {
+      for (int u = 0; u < NC; ++u) {
         const int c = lane + 64 * u;
-        if (c < r3) {
-          const double tv = row[c];
-          d += tv * q3[u];
-          dd += tv * dq3[u];
-        }
+        const double tv = c < r3 ? row[c] : 0.0;
+        d += tv * q3[u];
+        dd += tv * dq3[u];
       }
       const double w12 = L[0][m1] * L[1][m2];
       v += w12 * d;
@@ -132,8 +142,10 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
     double phi[3] = {0, 0, 0}, dphi[3] = {0, 0, 0};
     if (lane < e.R_l) {
       const double tk = e.t[lane];
+#pragma unroll
       for (int l = 0; l < 3; ++l) {
-        for (int m = 0; m < p; ++m) {
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
           const double x = -e.b + ((double)(s[l] + m) + 0.5) * h;
           const double d = x - y[l];
           const double g = exp(-(tk * tk) * (d * d));
@@ -163,11 +175,30 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
   }
 }
 
+template <int P>
+static void launch_eval_p(const EvalDev& e, int64_t M, const double* pts, int with_self,
+                          const EvalOut& out, hipStream_t s) {
+  const int waves = 4;
+  const dim3 grid((unsigned)((M + waves - 1) / waves)), block(64 * waves);
+  const int nc = (e.r3 + 63) / 64;
+#define RS_EVAL(NC)                                                                               \
+  hipLaunchKernelGGL((eval_long_kernel<P, NC>), grid, block, 0, s, e, M, pts, with_self, out.val, \
+                     out.grad, out.selfv, out.selfg)
+  if (nc <= 1) RS_EVAL(1);
+  else if (nc <= 2) RS_EVAL(2);
+  else if (nc <= 4) RS_EVAL(4);
+  else if (nc <= 8) RS_EVAL(8);
+  else RS_EVAL(16);
+#undef RS_EVAL
+}
+
 void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with_self,
                       const EvalOut& out, hipStream_t s) {
-  if (T->r[2] > 64 * CPL) throw Error{RS_E_UNSUPPORTED, "rank r3 above 1024"};
-  if (T->interp > PMAX) throw Error{RS_E_UNSUPPORTED, "interpolation order above 8"};
+  if (T->r[2] > 1024) throw Error{RS_E_UNSUPPORTED, "rank r3 above 1024"};
+  if (T->interp > PMAX || T->interp < 2 || T->interp % 2)
+    throw Error{RS_E_UNSUPPORTED, "interpolation order must be 2, 4, 6 or 8"};
   if (with_self && T->R_l > 64) throw Error{RS_E_UNSUPPORTED, "more than 64 long-range terms"};
+  if (M <= 0) return;
   EvalDev e;
   e.T2 = T->T2.as<double>();
   e.V3 = T->Q[2].as<double>();
@@ -178,10 +209,12 @@ void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with
   e.r3 = T->r[2];
   e.R_l = T->R_l;
   e.p = T->interp;
-  const int waves = 4;
-  unsigned blocks = (unsigned)((M + waves - 1) / waves);
-  hipLaunchKernelGGL(eval_long_kernel, dim3(blocks), dim3(64 * waves), 0, s, e, M, pts, with_self,
-                     out.val, out.grad, out.selfv, out.selfg);
+  switch (T->interp) {
+    case 2: launch_eval_p<2>(e, M, pts, with_self, out, s); break;
+    case 4: launch_eval_p<4>(e, M, pts, with_self, out, s); break;
+    case 6: launch_eval_p<6>(e, M, pts, with_self, out, s); break;
+    default: launch_eval_p<8>(e, M, pts, with_self, out, s); break;
+  }
 }
 
 // Short-range part at arbitrary points: particles whose window contains the

@@ -114,12 +114,14 @@ struct StridedSrc {
 template <int WIDE, int NT, int BK>
 struct KhatriRaoSrc {
   static constexpr int V = (WIDE * BK + NT - 1) / NT;
-  const double* U2t;
-  const double* U3t;
-  const double* xi;
+  const double* s2;   // xi_k U~2[k, b], [K][r2]
+  const double* U3t;  // U~3[k, c], [K][r3]
   int r2, r3;
-  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[V],
-                                       int tid) const {
+  // per-thread slab coordinates, fixed over k: set once by init()
+  int kl_[V];
+  int64_t o2_[V], o3_[V];
+  bool ok_[V];
+  __device__ __forceinline__ void init(int64_t n0, int tid) {
     const int W = r2 * r3;
 #pragma unroll
     for (int r = 0; r < V; ++r) {
@@ -127,14 +129,21 @@ struct KhatriRaoSrc {
       int wl, kl;
       slab_coord<true, WIDE, BK>(e, wl, kl);
       const int bc = (int)n0 + wl;
-      const int64_t k = k0 + kl;
-      double v = 0.0;
-      if (e < WIDE * BK && bc < W && k < kend) {
-        const int b = bc / r3, c = bc - (bc / r3) * r3;
-        v = xi[k] * U2t[k * r2 + b] * U3t[k * r3 + c];
-      }
-      reg[r] = v;
+      ok_[r] = e < WIDE * BK && bc < W;
+      const int b = ok_[r] ? bc / r3 : 0, c = ok_[r] ? bc - b * r3 : 0;
+      kl_[r] = kl;
+      o2_[r] = (int64_t)kl * r2 + b;
+      o3_[r] = (int64_t)kl * r3 + c;
     }
+  }
+  __device__ __forceinline__ void load(int64_t n0, int64_t k0, int64_t kend, double (&reg)[V],
+                                       int tid) const {
+    (void)n0;
+    (void)tid;
+    const double* p2 = s2 + k0 * r2;
+    const double* p3 = U3t + k0 * r3;
+#pragma unroll
+    for (int r = 0; r < V; ++r) reg[r] = (ok_[r] && k0 + kl_[r] < kend) ? p2[o2_[r]] * p3[o3_[r]] : 0.0;
   }
   __device__ __forceinline__ void store(double* lds, int ld, const double (&reg)[V], int tid) const {
 #pragma unroll
@@ -368,9 +377,8 @@ __global__ __launch_bounds__(CF::NT) void sketch_kernel(GemmDev g, uint64_t seed
 
 struct CoreDev {
   const double* U1t;
-  const double* U2t;
+  const double* s2;    // xi_k U~2[k, b], [K][r2]
   const double* U3t;
-  const double* xi;
   int r1, r2, r3;
   int64_t K;
   double* beta;
@@ -382,7 +390,8 @@ struct CoreDev {
 
 // beta_(1) (r1 x r2 r3) = U1t^T diag(xi) (U3t (.) U2t): the core of the
 // RHOSVD, eq CP_form_RHOSVD, as one GEMM whose right operand is the
-// Khatri-Rao product formed while staging it in LDS.
+// Khatri-Rao product formed while staging it in LDS (from xi U~2, scaled
+// once beforehand, and U~3).
 template <class CF>
 __global__ __launch_bounds__(CF::NT) void core_kernel(CoreDev g) {
   const int tile = blockIdx.x;
@@ -393,7 +402,8 @@ __global__ __launch_bounds__(CF::NT) void core_kernel(CoreDev g) {
   if (kend > g.K) kend = g.K;
   const int64_t W = (int64_t)g.r2 * g.r3;
   StridedSrc<true, CF::BM, CF::NT, CF::BK> as{g.U1t, 1, g.r1, g.r1, nullptr};
-  KhatriRaoSrc<CF::BN, CF::NT, CF::BK> bs{g.U2t, g.U3t, g.xi, g.r2, g.r3};
+  KhatriRaoSrc<CF::BN, CF::NT, CF::BK> bs{g.s2, g.U3t, g.r2, g.r3, {}, {}, {}, {}};
+  bs.init((int64_t)tn * CF::BN, threadIdx.x);
   TileOut o;
   o.M = g.r1;
   o.N = W;
@@ -403,6 +413,15 @@ __global__ __launch_bounds__(CF::NT) void core_kernel(CoreDev g) {
   o.part = g.part ? g.part + (int64_t)split * g.r1 * W : nullptr;
   o.nontemporal = 0;
   mfma_tile<CF>(as, bs, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, kbeg, kend, o);
+}
+
+// s2[k r2 + b] = xi_k U~2[k, b]
+__global__ void scale_rows_kernel(const double* __restrict__ xi, const double* __restrict__ U2t,
+                                  int64_t K, int r2, double* __restrict__ s2) {
+  const int64_t total = K * r2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    s2[e] = xi[e / r2] * U2t[e];
 }
 
 __global__ void core64_reduce_kernel(const double* __restrict__ part, int splits, int64_t total,
@@ -551,7 +570,7 @@ void gemm64(const Gemm64& gin, int num_cu, double* work, hipStream_t s) {
   }
 }
 
-// core: the rank tile when 64 < r1 <= 96, else the small tile
+// core: the rank tile when 64 < r1 <= 96 (a 96 x 128 tile measured slower), else the small tile
 static void plan_core(int r1, int r2, int r3, int64_t K, int num_cu, bool& rank_tile, int& splits,
                       int64_t& kchunk, int& tm, int& tn) {
   rank_tile = r1 > 64 && r1 <= 96;
@@ -572,12 +591,15 @@ static void plan_core(int r1, int r2, int r3, int64_t K, int num_cu, bool& rank_
   splits = (int)((K + kchunk - 1) / kchunk);
 }
 
+// workspace: xi U~2 (K x r2), then the split-K partials
+static size_t core64_s2_bytes(int r2, int64_t K) { return ((size_t)K * r2 * sizeof(double) + 255) & ~(size_t)255; }
+
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
   bool rt;
   int splits, tm, tn;
   int64_t kchunk;
   plan_core(r1, r2, r3, K, num_cu, rt, splits, kchunk, tm, tn);
-  return splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0;
+  return core64_s2_bytes(r2, K) + (splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0);
 }
 
 void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi, int r1,
@@ -586,24 +608,30 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
   bool rank_tile;
   int tm;
   plan_core(r1, r2, r3, K, num_cu, rank_tile, d.splits, d.kchunk, tm, d.tiles_n);
+  if (!work) throw Error{RS_E_DEVICE, "core64: missing workspace"};
+  double* s2 = work;
+  double* part = (double*)((char*)work + core64_s2_bytes(r2, K));
+  {
+    const int64_t total = K * r2;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks), dim3(256), 0, s, xi, U2t, K, r2, s2);
+  }
   d.U1t = U1t;
-  d.U2t = U2t;
+  d.s2 = s2;
   d.U3t = U3t;
-  d.xi = xi;
   d.r1 = r1;
   d.r2 = r2;
   d.r3 = r3;
   d.K = K;
   d.beta = beta;
-  d.part = d.splits > 1 ? work : nullptr;
-  if (d.splits > 1 && !work) throw Error{RS_E_DEVICE, "core64: missing workspace"};
+  d.part = d.splits > 1 ? part : nullptr;
   dim3 grid((unsigned)(tm * d.tiles_n), 1, (unsigned)d.splits);
   if (rank_tile) hipLaunchKernelGGL(core_kernel<CfgRank>, grid, dim3(CfgRank::NT), 0, s, d);
   else hipLaunchKernelGGL(core_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d);
   if (d.splits > 1) {
     int64_t total = (int64_t)r1 * r2 * r3;
     unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(core64_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)work,
+    hipLaunchKernelGGL(core64_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)part,
                        d.splits, total, beta);
   }
 }

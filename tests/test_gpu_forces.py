@@ -82,7 +82,15 @@ def test_cfg4_full_size_energy_and_forces(rsm, ctx):
     F = torch.empty(3 * s.N, dtype=torch.float64, device="cuda")
     rsm.energy(T, E)
     rsm.forces(T, F)
+    # the fused entry point gives the same bits from one evaluation pass
+    E2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    F2 = torch.empty(3 * s.N, dtype=torch.float64, device="cuda")
+    dq1 = torch.empty(s.N, dtype=torch.float64, device="cuda")
+    dq2 = torch.empty(s.N, dtype=torch.float64, device="cuda")
+    rsm.energy(T, E, dEdq=dq1)
+    rsm.energy_forces(T, E2, F2, 1.0, dEdq=dq2)
     torch.cuda.synchronize()
+    assert torch.equal(E, E2) and torch.equal(F, F2) and torch.equal(dq1, dq2)
     inf = T.info()
     E_can, F_can = pairwise.energy_canonical(s.pos, s.q, t, a, range(s.R_l), forces=True)
     Fg = F.cpu().numpy().reshape(-1, 3)

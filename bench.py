@@ -267,7 +267,12 @@ def main():
     bytes_grid = 8.0 * (n ** 3 + n * n * r3 + n * r3)
     achieved = flops_grid / t_grid / 1e12
     traffic = traffic_from_profiles("grid_gemm64", args.workload)
-    roofline = {"kernel": "rs::gemm_kernel<rs::Cfg<4, 2, 2, 4, 16, 16>, false, false> (grid = T2 x_3 V3)",
+    # the streaming grid kernel's column panel: the widest whose V3 rows fit 150 KB of LDS
+    kp = (r3 + 31) // 32 * 32
+    bn = next((b for b in (128, 64, 32) if kp * (b + 2) * 8 <= 150 * 1024), None)
+    kname = (f"rs::grid64_stream_kernel<{bn}>" if bn else
+             "rs::gemm_kernel<rs::Cfg<4, 2, 2, 4, 16, 16>, false, false>")
+    roofline = {"kernel": kname + " (grid = T2 x_3 V3)",
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
                 "traffic": traffic,

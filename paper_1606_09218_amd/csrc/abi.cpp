@@ -337,7 +337,9 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
                  T->active_cap, ncu, s);
   } else if (grid) {
     mark(T, RS_STAGE_GRID, s);
-    gemm64(grid_gemm(T, grid), ncu, (double*)(scratch + e.wkg), s);
+    if (!grid64_stream(T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (double*)grid, ncu,
+                       T->ctx->lds_limit, s))
+      gemm64(grid_gemm(T, grid), ncu, (double*)(scratch + e.wkg), s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 0, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,

@@ -455,6 +455,122 @@ __global__ void gemm64_reduce_kernel(GemmDev g) {
   }
 }
 
+// ---- grid expansion, streaming form ------------------------------------------
+// C[m, col] = sum_k A[m, k] B[col, k]: A = T2 (M = n^2 rows of K = r3, k
+// contiguous), B = V3 (n rows of K), C the grid (M x N, non-temporal
+// stores).  Persistent workgroups of 8 waves: workgroup (panel, group) keeps
+// the B rows of a panel of BN columns in LDS as [k][col] (zero-padded to kp,
+// a multiple of 32) for its whole life, and each wave walks 16-row tiles of
+// its group with the A values loaded straight from global memory into the
+// MFMA operand.  Within each 32-k chunk, lane (r, q) = (lane % 16, lane / 16)
+// holds A[r][32 c + 8 q + s] for s = 0..7 (eight consecutive k of its row)
+// and MFMA step s contracts the four k = 32 c + 8 q + s, q = 0..3, at once:
+// the k order is permuted, the sum is the same.  The loop has no barrier; the
+// next chunk's A values are loaded while the current one is multiplied.  The
+// panels of one row group run on one XCD (workgroup w runs on XCD w % 8),
+// so the T2 rows they share come from that XCD's L2.
+template <int BN>
+__global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __restrict__ A,
+                                                            const double* __restrict__ B,
+                                                            int64_t M, int N, int K, int kp,
+                                                            int npanels, int groups,
+                                                            double* __restrict__ C) {
+  constexpr int FN = BN / 16, LDB = BN + 2;
+  extern __shared__ double bsm[];   // [kp][LDB]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = blockIdx.x;
+  const int xcd = w & 7, iw = w >> 3;
+  const int panel = iw % npanels;
+  const int g = (iw / npanels) * 8 + xcd;
+  const int n0 = panel * BN;
+  for (int e = threadIdx.x; e < kp * BN; e += 512) {
+    const int col = e / kp, k = e - col * kp;
+    bsm[k * LDB + col] = (n0 + col < N && k < K) ? B[(int64_t)(n0 + col) * K + k] : 0.0;
+  }
+  __syncthreads();
+  if (g >= groups) return;   // uniform over the workgroup, after the only barrier
+  const int64_t tiles = (M + 15) / 16;
+  const int r = lane & 15, q = lane >> 4;
+  const int nch = kp / 32;
+  const double* bl = bsm + r;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  auto tile_of = [&](int64_t it) { return (it * groups + g) * 8 + wave; };
+  auto load = [&](int64_t tile, int c, double (&a)[8]) {
+    const int64_t row = tile * 16 + r;
+    const int k0 = 32 * c + 8 * q;
+    const double* src = A + row * K + k0;
+    const bool rok = tile < tiles && row < M;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = (rok && k0 + s < K) ? src[s] : 0.0;
+  };
+  int64_t it = 0;
+  int64_t tile = tile_of(0);
+  if (tile >= tiles) return;
+  double a[8];
+  load(tile, 0, a);
+  for (; tile < tiles; tile = tile_of(++it)) {
+    d4 acc[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < nch; ++c) {
+      double an[8];
+      if (c + 1 < nch) load(tile, c + 1, an);
+      else load(tile_of(it + 1), 0, an);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const double* brow = bl + (32 * c + 8 * q + s) * LDB;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], brow[j * 16], acc[j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[s] = an[s];
+    }
+    // acc[j][v] is C[16 tile + q + 4 v][n0 + 16 j + r]
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + 16 * j + r;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = tile * 16 + q + 4 * v;
+        if (row < M && col < N) __builtin_nontemporal_store(acc[j][v], C + row * N + col);
+      }
+    }
+  }
+}
+
+template <int BN>
+static void launch_grid64_stream(const double* T2, const double* V3, int64_t M, int N, int K,
+                                 int kp, double* C, int num_cu, hipStream_t s) {
+  const int npanels = (N + BN - 1) / BN;
+  const int64_t tiles = (M + 15) / 16;
+  int gq = std::max(1, num_cu / (8 * npanels));
+  while (gq > 1 && (int64_t)gq * 8 * 8 > tiles) --gq;
+  const int groups = gq * 8;
+  const size_t lds = (size_t)kp * (BN + 2) * sizeof(double);
+  auto fn = grid64_stream_kernel<BN>;
+  if (lds > 48 * 1024)
+    RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(fn, dim3((unsigned)(8 * npanels * gq)), dim3(512), lds, s, T2, V3, M, N, K, kp,
+                     npanels, groups, C);
+}
+
+bool grid64_stream(const double* T2, const double* V3, int64_t n, int r3, double* grid, int num_cu,
+                   int lds_limit, hipStream_t s) {
+  if (n <= 0 || r3 <= 0) return true;
+  const int kp = (r3 + 31) / 32 * 32;
+  // the panel opts in beyond the default 64 KB of dynamic LDS (gfx950 has 160 KB per CU)
+  (void)lds_limit;
+  const size_t budget = 150 * 1024;
+  auto need = [&](int bn) { return (size_t)kp * (bn + 2) * sizeof(double); };
+  const int64_t M = n * n;
+  if (need(128) <= budget) launch_grid64_stream<128>(T2, V3, M, (int)n, r3, kp, grid, num_cu, s);
+  else if (need(64) <= budget) launch_grid64_stream<64>(T2, V3, M, (int)n, r3, kp, grid, num_cu, s);
+  else if (need(32) <= budget) launch_grid64_stream<32>(T2, V3, M, (int)n, r3, kp, grid, num_cu, s);
+  else return false;   // rank too large for an LDS panel: the caller takes the tiled GEMM
+  return true;
+}
+
 // ---- host: configuration choice and split-K plan -----------------------------
 enum CfgId { CFG_SMALL = 0, CFG_RANK = 1, CFG_BIG = 2 };
 

@@ -144,6 +144,11 @@ struct Gemm64 {
 // gemm64_workspace_bytes(g, num_cu) bytes (may be null when that is 0).
 size_t gemm64_workspace_bytes(const Gemm64& g, int num_cu);
 void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s);
+// grid (n^2 x n, row-major) = T2 (n^2 x r3) V3^T (V3: n x r3), FP64, streamed
+// through an LDS-resident V3 panel; returns false (nothing launched) when the
+// panel of r3 does not fit the LDS, for the caller to use gemm64.
+bool grid64_stream(const double* T2, const double* V3, int64_t n, int r3, double* grid, int num_cu,
+                   int lds_limit, hipStream_t s);
 // Range-finder sketch Y[bt] (M x N col-major) = A[bt] (M x K col-major) Omega_bt,
 // Omega_bt[k, c] = scale[bt*scale_stride + k] * u(seed, bt, k, c), u uniform in [-1, 1).
 size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu);

@@ -122,6 +122,32 @@ def test_cfg1_full_grid_parity_and_own_ranks(rsm, ctx):
     assert err2 <= 10 * TOL
 
 
+@pytest.mark.parametrize("case", [
+    # subspace of 176 < n: the blocked Cholesky QR and the wide tridiagonalisation
+    dict(seed=81, N=90, b=8.0, n=192, R=24, R_l=10, n_s=9, r_max=160),
+    # subspace = n = 160: the Gram itself is tridiagonalised by the wide kernel
+    dict(seed=82, N=60, b=7.0, n=160, R=24, R_l=10, n_s=9, r_max=150),
+])
+def test_mid_subspace_full_grid_parity(rsm, ctx, case):
+    s = workloads.tiny_system(case["seed"], case["N"], case["b"], case["n"], case["R"],
+                              case["R_l"], case["n_s"], min_sep=0.5)
+    say(f"mid-subspace grid parity {s.name} r_max={case['r_max']}")
+    # the GPU's own rank rule, so that the subspace is r_max + 16 (fixed ranks
+    # would size it from the ranks); the oracle then keeps the same ranks
+    f, T, g = run_gpu(rsm, ctx, s, r_max=case["r_max"])
+    inf = T.info()
+    own = list(inf.ranks)
+    assert min(inf.subspace) > 128
+    ref_own = rs.assemble_system(s)
+    for l in range(3):
+        assert abs(own[l] - ref_own.ranks[l]) <= 1
+    ref = rs.assemble_system(s, fixed_ranks=own)
+    full = ref.full_grid()
+    err = rel_linf(g.cpu().numpy().reshape(full.shape), full)
+    say(f"  ranks {own} (oracle's own {ref_own.ranks}) subspace {list(inf.subspace)} rel-Linf {err:.2e}")
+    assert err <= TOL
+
+
 def test_cfg2_sampled_parity(rsm, ctx):
     s = workloads.cfg2_lattice()
     say("cfg2 sampled")

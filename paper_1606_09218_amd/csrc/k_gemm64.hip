@@ -458,19 +458,19 @@ __global__ void gemm64_reduce_kernel(GemmDev g) {
 // ---- grid expansion, streaming form ------------------------------------------
 // C[m, col] = sum_k A[m, k] B[col, k]: A = T2 (M = n^2 rows of K = r3, k
 // contiguous), B = V3 (n rows of K), C the grid (M x N, non-temporal
-// stores).  Persistent workgroups of 8 waves: workgroup (panel, group) keeps
+// stores).  Persistent workgroups of 16 waves: workgroup (panel, group) keeps
 // the B rows of a panel of BN columns in LDS as [k][col] (zero-padded to kp,
 // a multiple of 32) for its whole life, and each wave walks 16-row tiles of
 // its group with the A values loaded straight from global memory into the
 // MFMA operand.  Within each 32-k chunk, lane (r, q) = (lane % 16, lane / 16)
-// holds A[r][32 c + 8 q + s] for s = 0..7 (eight consecutive k of its row)
-// and MFMA step s contracts the four k = 32 c + 8 q + s, q = 0..3, at once:
-// the k order is permuted, the sum is the same.  The loop has no barrier; the
+// holds A[r][32 c + 4 s + q] for s = 0..7, so that MFMA step s contracts
+// k = 32 c + 4 s + q, q = 0..3, and each load instruction reads one
+// contiguous 32-byte piece of each of the 16 rows.  The loop has no barrier; the
 // next chunk's A values are loaded while the current one is multiplied.  The
 // panels of one row group run on one XCD (workgroup w runs on XCD w % 8),
 // so the T2 rows they share come from that XCD's L2.
-template <int BN>
-__global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __restrict__ A,
+template <int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void grid64_stream_kernel(const double* __restrict__ A,
                                                             const double* __restrict__ B,
                                                             int64_t M, int N, int K, int kp,
                                                             int npanels, int groups,
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __rest
   const int panel = iw % npanels;
   const int g = (iw / npanels) * 8 + xcd;
   const int n0 = panel * BN;
-  for (int e = threadIdx.x; e < kp * BN; e += 512) {
+  for (int e = threadIdx.x; e < kp * BN; e += 64 * WAVES) {
     const int col = e / kp, k = e - col * kp;
     bsm[k * LDB + col] = (n0 + col < N && k < K) ? B[(int64_t)(n0 + col) * K + k] : 0.0;
   }
@@ -494,14 +494,14 @@ __global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __rest
   const int nch = kp / 32;
   const double* bl = bsm + r;
   typedef double d4 __attribute__((ext_vector_type(4)));
-  auto tile_of = [&](int64_t it) { return (it * groups + g) * 8 + wave; };
+  auto tile_of = [&](int64_t it) { return (it * groups + g) * WAVES + wave; };
   auto load = [&](int64_t tile, int c, double (&a)[8]) {
     const int64_t row = tile * 16 + r;
-    const int k0 = 32 * c + 8 * q;
+    const int k0 = 32 * c + q;
     const double* src = A + row * K + k0;
     const bool rok = tile < tiles && row < M;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = (rok && k0 + s < K) ? src[s] : 0.0;
+    for (int s = 0; s < 8; ++s) a[s] = (rok && k0 + 4 * s < K) ? src[4 * s] : 0.0;
   };
   int64_t it = 0;
   int64_t tile = tile_of(0);
@@ -516,12 +516,16 @@ __global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __rest
       double an[8];
       if (c + 1 < nch) load(tile, c + 1, an);
       else load(tile_of(it + 1), 0, an);
+      // steps whose four k are all >= K contribute nothing: skipped (uniform)
+      const int smax = (K - 32 * c + 3) / 4;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const double* brow = bl + (32 * c + 8 * q + s) * LDB;
+        if (s < smax) {
+          const double* brow = bl + (32 * c + 4 * s + q) * LDB;
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], brow[j * 16], acc[j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], brow[j * 16], acc[j], 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int s = 0; s < 8; ++s) a[s] = an[s];
@@ -539,20 +543,22 @@ __global__ __launch_bounds__(512) void grid64_stream_kernel(const double* __rest
   }
 }
 
+constexpr int GRID_WAVES = 16;   // waves per workgroup, all sharing the panel
+
 template <int BN>
 static void launch_grid64_stream(const double* T2, const double* V3, int64_t M, int N, int K,
                                  int kp, double* C, int num_cu, hipStream_t s) {
   const int npanels = (N + BN - 1) / BN;
   const int64_t tiles = (M + 15) / 16;
   int gq = std::max(1, num_cu / (8 * npanels));
-  while (gq > 1 && (int64_t)gq * 8 * 8 > tiles) --gq;
+  while (gq > 1 && (int64_t)gq * 8 * GRID_WAVES > tiles) --gq;
   const int groups = gq * 8;
   const size_t lds = (size_t)kp * (BN + 2) * sizeof(double);
-  auto fn = grid64_stream_kernel<BN>;
+  auto fn = grid64_stream_kernel<BN, GRID_WAVES>;
   if (lds > 48 * 1024)
     RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(fn, dim3((unsigned)(8 * npanels * gq)), dim3(512), lds, s, T2, V3, M, N, K, kp,
-                     npanels, groups, C);
+  hipLaunchKernelGGL(fn, dim3((unsigned)(8 * npanels * gq)), dim3(64 * GRID_WAVES), lds, s, T2, V3,
+                     M, N, K, kp, npanels, groups, C);
 }
 
 bool grid64_stream(const double* T2, const double* V3, int64_t n, int r3, double* grid, int num_cu,

@@ -532,12 +532,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
     T->nb = bricks_per_axis(n);
     const int nbricks = T->nb * T->nb * T->nb;
-    Gemm64 gx_shape;  // Y = G X
-    gx_shape.M = n; gx_shape.N = p; gx_shape.K = n; gx_shape.batch = 3;
+    Gemm64 zq_shape;  // Z = U^T Q0 (K x p)
+    zq_shape.M = K; zq_shape.N = p; zq_shape.K = n; zq_shape.batch = 3;
+    Gemm64 bz_shape;  // B = Z^T diag(w) Z (upper)
+    bz_shape.M = p; bz_shape.N = p; bz_shape.K = K; bz_shape.batch = 3; bz_shape.upper_only = 1;
+    Gemm64 uwz_shape;  // Y = U diag(w) Z (power iterations)
+    uwz_shape.M = n; uwz_shape.N = p; uwz_shape.K = K; uwz_shape.batch = 3;
     Gemm64 yty_shape;  // C = Y^T Y (upper)
     yty_shape.M = p; yty_shape.N = p; yty_shape.K = n; yty_shape.batch = 3; yty_shape.upper_only = 1;
-    Gemm64 qty_shape;  // B = Q0^T Y
-    qty_shape.M = p; qty_shape.N = p; qty_shape.K = n; qty_shape.batch = 3;
     Gemm64 zz_shape;  // C = Z^T Z (upper)
     zz_shape.M = rc; zz_shape.N = rc; zz_shape.K = p; zz_shape.batch = 3; zz_shape.upper_only = 1;
     const size_t d8 = sizeof(double);
@@ -546,17 +548,23 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const size_t o_rb = pre.add(sizeof(Readback));
     const size_t o_U = pre.add((size_t)3 * n * K * d8), o_xi = pre.add((size_t)K * d8);
     const size_t o_w = pre.add((size_t)K * d8), o_sw = pre.add((size_t)K * d8);
-    const size_t o_G = pre.add((size_t)3 * n * n * d8);
-    const size_t o_wgram = pre.add(gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu));
-    const size_t o_Q0 = pre.add((size_t)3 * n * p * d8), o_Bm = pre.add((size_t)3 * p * p * d8);
+    // the n x n Gram is formed only when the subspace is all of R^n; otherwise
+    // its projection B = Q^T G Q is formed as Z^T diag(w) Z with Z = U^T Q
     const bool subspace = p < n;
-    const size_t o_Y = pre.add(subspace ? (size_t)3 * n * p * d8 : 0);
+    const size_t o_G = pre.add(subspace ? 0 : (size_t)3 * n * n * d8);
+    const size_t o_wgram =
+        pre.add(subspace ? 0 : gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu));
+    const size_t o_Q0 = pre.add((size_t)3 * n * p * d8), o_Bm = pre.add((size_t)3 * p * p * d8);
+    const size_t o_Y = pre.add(subspace && P.power_iters > 0 ? (size_t)3 * n * p * d8 : 0);
+    const size_t o_Zk = pre.add(subspace ? (size_t)3 * K * p * d8 : 0);
     const size_t o_Cq = pre.add(subspace ? (size_t)3 * p * p * d8 : 0);
+    const size_t o_eta = pre.add(3 * d8);
     const size_t wke_bytes =
         subspace ? std::max({sketch64_workspace_bytes(n, K, 3, p, ncu),
-                             gemm64_workspace_bytes(gx_shape, ncu),
-                             gemm64_workspace_bytes(yty_shape, ncu),
-                             gemm64_workspace_bytes(qty_shape, ncu)})
+                             gemm64_workspace_bytes(zq_shape, ncu),
+                             gemm64_workspace_bytes(bz_shape, ncu),
+                             P.power_iters > 0 ? gemm64_workspace_bytes(uwz_shape, ncu) : (size_t)0,
+                             gemm64_workspace_bytes(yty_shape, ncu)})
                  : 0;
     const size_t o_wke = pre.add(wke_bytes);
     const size_t o_ews = pre.add(eig_sym_workspace_bytes(p, rc, 3));
@@ -578,9 +586,16 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     mark(T.get(), RS_STAGE_FACTORS, s);
     Span U = piece(o_U, (size_t)3 * n * K * d8), xi = piece(o_xi, (size_t)K * d8);
     Span w = piece(o_w, (size_t)K * d8), sw = piece(o_sw, (size_t)K * d8);
-    Span G = piece(o_G, (size_t)3 * n * n * d8);
-    run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
-                         sw.as<double>(), G.as<double>(), s, T.get(), (double*)(pre_buf.as<char>() + o_wgram));
+    Span G = piece(o_G, subspace ? 0 : (size_t)3 * n * n * d8);
+    if (subspace) {
+      launch_side_matrices(dpos, dq, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U.as<double>(),
+                           xi.as<double>(), w.as<double>(), sw.as<double>(), s);
+      mark(T.get(), RS_STAGE_GRAM, s);   // no n x n Gram on this path
+    } else {
+      run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
+                           sw.as<double>(), G.as<double>(), s, T.get(),
+                           (double*)(pre_buf.as<char>() + o_wgram));
+    }
 
     // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
     mark(T.get(), RS_STAGE_EIGEN, s);
@@ -590,36 +605,40 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       launch_identity(Q0.as<double>(), n, 3, s);
       RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
     } else {
-      Span Y = piece(o_Y, (size_t)3 * n * p * d8), Cq = piece(o_Cq, (size_t)3 * p * p * d8);
-      auto gx_gemm = [&](const double* X, double* Yout) {  // Y = G X, row-major n x p
-        Gemm64 g;
-        g.M = n; g.N = p; g.K = n; g.batch = 3;
-        g.A = G.as<double>(); g.sam = n; g.sak = 1; g.sab = n * n;
+      Span Y = piece(o_Y, P.power_iters > 0 ? (size_t)3 * n * p * d8 : 0);
+      Span Zk = piece(o_Zk, (size_t)3 * K * p * d8), Cq = piece(o_Cq, (size_t)3 * p * p * d8);
+      double* eta = (double*)(pre_buf.as<char>() + o_eta);
+      auto zq_gemm = [&](const double* X) {  // Z = U^T X (K x p, row-major)
+        Gemm64 g = zq_shape;
+        g.A = U.as<double>(); g.sam = n; g.sak = 1; g.sab = n * K;
         g.B = X; g.sbk = p; g.sbn = 1; g.sbb = n * p;
+        g.C = Zk.as<double>(); g.scm = p; g.scn = 1; g.scb = K * p;
+        return g;
+      };
+      auto bz_gemm = [&]() {  // B = Z^T diag(w) Z (symmetric)
+        Gemm64 g = bz_shape;
+        g.A = Zk.as<double>(); g.sam = 1; g.sak = p; g.sab = K * p;
+        g.B = Zk.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = K * p;
+        g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
+        g.kscale = w.as<double>();
+        return g;
+      };
+      auto uwz_gemm = [&](double* Yout) {  // Y = U diag(w) Z = G X for Z = U^T X
+        Gemm64 g = uwz_shape;
+        g.A = U.as<double>(); g.sam = 1; g.sak = n; g.sab = n * K;
+        g.B = Zk.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = K * p;
         g.C = Yout; g.scm = p; g.scn = 1; g.scb = n * p;
+        g.kscale = w.as<double>();
         return g;
       };
       auto yty_gemm = [&](const double* Yp) {  // C = Y^T Y (symmetric)
-        Gemm64 g;
-        g.M = p; g.N = p; g.K = n; g.batch = 3;
+        Gemm64 g = yty_shape;
         g.A = Yp; g.sam = 1; g.sak = p; g.sab = n * p;
         g.B = Yp; g.sbk = p; g.sbn = 1; g.sbb = n * p;
         g.C = Cq.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
-        g.upper_only = 1;
-        return g;
-      };
-      auto qty_gemm = [&]() {  // B = Q0^T Y
-        Gemm64 g;
-        g.M = p; g.N = p; g.K = n; g.batch = 3;
-        g.A = Q0.as<double>(); g.sam = 1; g.sak = p; g.sab = n * p;
-        g.B = Y.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = n * p;
-        g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
         return g;
       };
       Span wk_eig = piece(o_wke, wke_bytes);  // split-K workspace of every product here
-      auto GtimesX = [&](const double* X, double* Yout) {
-        gemm64(gx_gemm(X, Yout), ncu, wk_eig.as<double>(), s);
-      };
       // orthonormal basis of range(Y), in place: shifted Cholesky QR, twice
       // (each shifted pass maps cond(Y) to about sqrt(shift)/sigma_min(Y)),
       // then two plain passes
@@ -634,17 +653,19 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       // range is that of the singular values, not of their squares)
       sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
                Q0.as<double>(), p, 1, ncu, wk_eig.as<double>(), s);
-      launch_perturb(Q0.as<double>(), G.as<double>(), n, p, 3, 0x9e3779b9ULL, s);
+      launch_sketch_eta(Q0.as<double>(), n, p, 3, eta, s);
+      launch_perturb_eta(Q0.as<double>(), eta, n, p, 3, 0x9e3779b9ULL, s);
       orth(Q0.as<double>());
       for (int it = 0; it < P.power_iters; ++it) {
-        GtimesX(Q0.as<double>(), Y.as<double>());
-        launch_perturb(Y.as<double>(), G.as<double>(), n, p, 3, 0x9e3779b9ULL + it + 1, s);
+        gemm64(zq_gemm(Q0.as<double>()), ncu, wk_eig.as<double>(), s);
+        gemm64(uwz_gemm(Y.as<double>()), ncu, wk_eig.as<double>(), s);   // Y = G Q0
+        launch_perturb_eta(Y.as<double>(), eta, n, p, 3, 0x9e3779b9ULL + it + 1, s);
         orth(Y.as<double>());
         std::swap(Q0, Y);
       }
-      GtimesX(Q0.as<double>(), Y.as<double>());  // Y = G Q0
-      gemm64(qty_gemm(), ncu, wk_eig.as<double>(), s);  // B = Q0^T Y
-      launch_symmetrize(Bm.as<double>(), p, 3, s);
+      // Rayleigh-Ritz matrix B = Q0^T G Q0 = Z^T diag(w) Z, Z = U^T Q0
+      gemm64(zq_gemm(Q0.as<double>()), ncu, wk_eig.as<double>(), s);
+      gemm64(bz_gemm(), ncu, wk_eig.as<double>(), s);
     }
     // eigenvectors are formed only for the rc columns the rank rule can keep
     Span ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));

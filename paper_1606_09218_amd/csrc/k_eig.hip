@@ -784,6 +784,53 @@ __global__ void perturb_kernel(double* __restrict__ Yall, const double* __restri
     Y[e] += eta * hash_uniform(seed + mode, (uint64_t)(e % n), (uint64_t)(e / n));
 }
 
+// The same perturbation with the scale taken from the sketch itself:
+// eta = 1e-12 sqrt(|Y|_F^2 / (n p)).  For the range-finder sketch
+// Y = U diag(w^1/2) Omega with Omega uniform in [-1, 1), E |Y|_F^2 = p tr(G) / 3,
+// so this is the scale above without forming G.  One workgroup per mode
+// sums |Y|_F^2 in a fixed order.
+constexpr int ETA_THREADS = 1024;
+__global__ __launch_bounds__(ETA_THREADS) void sketch_eta_kernel(const double* __restrict__ Yall,
+                                                                 int64_t n, int p,
+                                                                 double* __restrict__ eta) {
+  __shared__ double red[ETA_THREADS / 64];
+  const int mode = blockIdx.x;
+  const double* Y = Yall + (int64_t)mode * n * p;
+  const int64_t total = n * p;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < total; e += ETA_THREADS) acc += Y[e] * Y[e];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < ETA_THREADS / 64; ++w) t += red[w];
+    eta[mode] = 1e-12 * sqrt(fmax(t, 0.0) / ((double)n * p));
+  }
+}
+
+__global__ void perturb_eta_kernel(double* __restrict__ Yall, const double* __restrict__ eta_all,
+                                   int64_t n, int p, uint64_t seed) {
+  const int mode = blockIdx.y;
+  const double eta = eta_all[mode] > 0 ? eta_all[mode] : 1e-300;
+  double* Y = Yall + (int64_t)mode * n * p;
+  const int64_t total = n * p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    Y[e] += eta * hash_uniform(seed + mode, (uint64_t)(e % n), (uint64_t)(e / n));
+}
+
+void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* eta, hipStream_t s) {
+  hipLaunchKernelGGL(sketch_eta_kernel, dim3(modes), dim3(ETA_THREADS), 0, s, Y, n, p, eta);
+}
+
+void launch_perturb_eta(double* Y, const double* eta, int64_t n, int p, int modes, uint64_t seed,
+                        hipStream_t s) {
+  const int64_t total = n * p;
+  unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(perturb_eta_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, eta, n, p, seed);
+}
+
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,
                     hipStream_t s) {
   const int64_t total = n * p;

@@ -161,6 +161,11 @@ void launch_identity(double* I, int64_t n, int modes, hipStream_t s);
 void launch_symmetrize(double* B, int p, int modes, hipStream_t s);
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,
                     hipStream_t s);
+// eta[mode] = 1e-12 sqrt(|Y_mode|_F^2 / (n p)) (the scale of the perturbation
+// from the range-finder sketch), and Y += eta * uniform noise with that scale
+void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* eta, hipStream_t s);
+void launch_perturb_eta(double* Y, const double* eta, int64_t n, int p, int modes, uint64_t seed,
+                        hipStream_t s);
 // Cholesky C = L L^T in place (lower, col-major), one workgroup per mode; the
 // shifted variant adds 11 (nrows p + p (p+1)) u tr(C) to the diagonal first.
 // fail |= fail_bit on a non-positive pivot.

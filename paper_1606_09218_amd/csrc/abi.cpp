@@ -759,10 +759,19 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       g.sbk = 1; g.sbn = p;
       g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
       Gemm64& h = gp[l];  // U~_l = V_l^T U_l, stored column j contiguous: U~[j*r + a]
-      h.M = r; h.N = K; h.K = n;
-      h.A = T->Q[l].as<double>(); h.sam = 1; h.sak = r;
-      h.B = U.as<double>() + (int64_t)l * n * K; h.sbk = 1; h.sbn = n;
-      h.scm = 1; h.scn = r;
+      if (subspace) {
+        // U~_l^T = U_l^T Q0 W_r = Z W_r (K x r): Z = U^T Q0 is kept from the
+        // Rayleigh-Ritz step, so the projection contracts over p, not n
+        h.M = K; h.N = r; h.K = p;
+        h.A = (const double*)(pre_buf.as<char>() + o_Zk) + (int64_t)l * K * p; h.sam = p; h.sak = 1;
+        h.sbk = 1; h.sbn = p;   // W_r is p x r, column-major (as gathered)
+        h.scm = r; h.scn = 1;
+      } else {
+        h.M = r; h.N = K; h.K = n;
+        h.A = T->Q[l].as<double>(); h.sam = 1; h.sak = r;
+        h.B = U.as<double>() + (int64_t)l * n * K; h.sbk = 1; h.sbn = n;
+        h.scm = 1; h.scn = r;
+      }
     }
     Carve cv;
     size_t o_wr[3], o_wkb[3], o_ut[3], o_wkp[3];
@@ -787,12 +796,15 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
                          at(o_wr[l]), s);
       gb[l].B = at(o_wr[l]);
       gemm64(gb[l], ncu, at(o_wkb[l]), s);
-      launch_canonical_signs(T->Q[l].as<double>(), n, r, s);
+      // the sign of each kept column is fixed on V_l and carried to W_r,
+      // which the projection below multiplies
+      launch_canonical_signs(T->Q[l].as<double>(), n, r, s, subspace ? at(o_wr[l]) : nullptr, p);
     }
 
     // (a5) projection U~_l = V_l^T U_l and core
     mark(T.get(), RS_STAGE_PROJECT, s);
     for (int l = 0; l < 3; ++l) {
+      if (subspace) gp[l].B = at(o_wr[l]);
       gp[l].C = at(o_ut[l]);
       gemm64(gp[l], ncu, at(o_wkp[l]), s);
     }

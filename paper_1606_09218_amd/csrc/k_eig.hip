@@ -200,7 +200,10 @@ void launch_gather_cols(const double* Z, int ldz, const int* perm, int p, int r,
 
 // One wave per column of the row-major n x r matrix: find the entry of
 // largest magnitude (first on ties) and flip the column if it is negative.
-__global__ void canonical_signs_kernel(double* Q, int64_t n, int r) {
+// Column c of Q (n x r, row-major) is negated when its entry of largest
+// magnitude (lowest row on ties) is negative; the same columns of W (m x r,
+// column-major, when given) are negated with it.
+__global__ void canonical_signs_kernel(double* Q, int64_t n, int r, double* W, int64_t m) {
   const int col = blockIdx.x;
   const int lane = threadIdx.x;
   double best = -1.0;
@@ -221,12 +224,15 @@ __global__ void canonical_signs_kernel(double* Q, int64_t n, int r) {
     }
   }
   const bool flip = Q[bi * r + col] < 0.0;
-  if (flip)
+  if (flip) {
     for (int64_t i = lane; i < n; i += 64) Q[i * r + col] = -Q[i * r + col];
+    if (W)
+      for (int64_t i = lane; i < m; i += 64) W[col * m + i] = -W[col * m + i];
+  }
 }
 
-void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s) {
-  hipLaunchKernelGGL(canonical_signs_kernel, dim3(r), dim3(64), 0, s, Qrow, n, r);
+void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s, double* W, int64_t m) {
+  hipLaunchKernelGGL(canonical_signs_kernel, dim3(r), dim3(64), 0, s, Qrow, n, r, W, m);
 }
 
 // ---- shifted Cholesky QR ---------------------------------------------------------

@@ -200,7 +200,8 @@ void launch_rank_select(const double* B, int p, int modes, double eps2, const in
 // canonical signs (largest-magnitude entry of each column positive).
 void launch_gather_cols(const double* Z, int ldz, const int* perm, int p, int r, double* Wr,
                         hipStream_t s);
-void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s);
+void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s, double* W = nullptr,
+                            int64_t m = 0);
 
 // k_core.hip : beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);

@@ -558,7 +558,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const size_t o_Y = pre.add(subspace && P.power_iters > 0 ? (size_t)3 * n * p * d8 : 0);
     const size_t o_Zk = pre.add(subspace ? (size_t)3 * K * p * d8 : 0);
     const size_t o_Cq = pre.add(subspace ? (size_t)3 * p * p * d8 : 0);
-    const size_t o_eta = pre.add(3 * d8);
+    const size_t o_eta = pre.add(sketch_eta_bytes(3));
     const size_t wke_bytes =
         subspace ? std::max({sketch64_workspace_bytes(n, K, 3, p, ncu),
                              gemm64_workspace_bytes(zq_shape, ncu),
@@ -790,16 +790,17 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 
     // final bases V_l = Q0 W[:, perm[:r]] (n x r row-major), canonical signs
     mark(T.get(), RS_STAGE_BASIS, s);
+    Mode3 wr3{{at(o_wr[0]), at(o_wr[1]), at(o_wr[2])}, {r1, r2, r3}};
+    Mode3 q3{{T->Q[0].as<double>(), T->Q[1].as<double>(), T->Q[2].as<double>()}, {r1, r2, r3}};
+    launch_gather_cols3(Z.as<double>(), rc, (int64_t)p * rc, perm.as<int>(), p, wr3, s);
     for (int l = 0; l < 3; ++l) {
-      const int r = T->r[l];
-      launch_gather_cols(Z.as<double>() + (int64_t)l * p * rc, rc, perm.as<int>() + l * p, p, r,
-                         at(o_wr[l]), s);
       gb[l].B = at(o_wr[l]);
       gemm64(gb[l], ncu, at(o_wkb[l]), s);
-      // the sign of each kept column is fixed on V_l and carried to W_r,
-      // which the projection below multiplies
-      launch_canonical_signs(T->Q[l].as<double>(), n, r, s, subspace ? at(o_wr[l]) : nullptr, p);
     }
+    // the sign of each kept column is fixed on V_l and carried to W_r,
+    // which the projection below multiplies
+    Mode3 none{{nullptr, nullptr, nullptr}, {r1, r2, r3}};
+    launch_canonical_signs3(q3, n, subspace ? wr3 : none, p, s);
 
     // (a5) projection U~_l = V_l^T U_l and core
     mark(T.get(), RS_STAGE_PROJECT, s);

@@ -235,6 +235,71 @@ void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s, doubl
   hipLaunchKernelGGL(canonical_signs_kernel, dim3(r), dim3(64), 0, s, Qrow, n, r, W, m);
 }
 
+// The three modes in one launch each (blockIdx.y = mode).
+__global__ void gather_cols3_kernel(const double* __restrict__ Z, int ldz, int64_t zstride,
+                                    const int* __restrict__ perm, int p, Mode3 w) {
+  const int mode = blockIdx.y;
+  const int r = w.r[mode];
+  const double* Zm = Z + (int64_t)mode * zstride;
+  const int* pm = perm + (int64_t)mode * p;
+  double* Wr = w.p[mode];
+  const int64_t total = (int64_t)p * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e / p), row = (int)(e % p);
+    const int src = pm[col];
+    Wr[e] = (src >= 0 && src < ldz) ? Zm[(int64_t)row * ldz + src] : 0.0;
+  }
+}
+
+void launch_gather_cols3(const double* Z, int ldz, int64_t zstride, const int* perm, int p,
+                         const Mode3& Wr, hipStream_t s) {
+  const int rmax = std::max({Wr.r[0], Wr.r[1], Wr.r[2]});
+  const int64_t total = (int64_t)p * rmax;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(gather_cols3_kernel, dim3(blocks, 3), dim3(256), 0, s, Z, ldz, zstride, perm, p,
+                     Wr);
+}
+
+__global__ void canonical_signs3_kernel(Mode3 q, int64_t n, Mode3 w, int64_t m) {
+  const int mode = blockIdx.y;
+  const int r = q.r[mode];
+  const int col = blockIdx.x;
+  if (col >= r) return;   // uniform over the (one-wave) workgroup
+  double* Q = q.p[mode];
+  double* W = w.p[mode];
+  const int lane = threadIdx.x;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = lane; i < n; i += 64) {
+    double v = fabs(Q[i * r + col]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    double ob = __shfl_xor(best, off);
+    int64_t oi = __shfl_xor(bi, off);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  const bool flip = Q[bi * r + col] < 0.0;
+  if (flip) {
+    for (int64_t i = lane; i < n; i += 64) Q[i * r + col] = -Q[i * r + col];
+    if (W)
+      for (int64_t i = lane; i < m; i += 64) W[col * m + i] = -W[col * m + i];
+  }
+}
+
+void launch_canonical_signs3(const Mode3& Q, int64_t n, const Mode3& W, int64_t m, hipStream_t s) {
+  const int rmax = std::max({Q.r[0], Q.r[1], Q.r[2]});
+  hipLaunchKernelGGL(canonical_signs3_kernel, dim3((unsigned)std::max(rmax, 1), 3), dim3(64), 0, s, Q,
+                     n, W, m);
+}
+
 // ---- shifted Cholesky QR ---------------------------------------------------------
 // Y (n x p, col-major) <- Y R^{-1} with C = Y^T Y = R^T R.  A shifted pass
 // adds s = 11 (n p + p (p + 1)) u tr(C) to the diagonal so that the
@@ -793,32 +858,33 @@ __global__ void perturb_kernel(double* __restrict__ Yall, const double* __restri
 // The same perturbation with the scale taken from the sketch itself:
 // eta = 1e-12 sqrt(|Y|_F^2 / (n p)).  For the range-finder sketch
 // Y = U diag(w^1/2) Omega with Omega uniform in [-1, 1), E |Y|_F^2 = p tr(G) / 3,
-// so this is the scale above without forming G.  One workgroup per mode
-// sums |Y|_F^2 in a fixed order.
-constexpr int ETA_THREADS = 1024;
-__global__ __launch_bounds__(ETA_THREADS) void sketch_eta_kernel(const double* __restrict__ Yall,
-                                                                 int64_t n, int p,
-                                                                 double* __restrict__ eta) {
-  __shared__ double red[ETA_THREADS / 64];
-  const int mode = blockIdx.x;
+// so this is the scale above without forming G.  ETA_PARTS workgroups per
+// mode write partial sums of |Y|_F^2; every workgroup of the perturbation
+// adds them in the same order.
+constexpr int ETA_PARTS = 32;
+__global__ __launch_bounds__(256) void sketch_eta_kernel(const double* __restrict__ Yall,
+                                                         int64_t n, int p,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4];
+  const int mode = blockIdx.y;
   const double* Y = Yall + (int64_t)mode * n * p;
   const int64_t total = n * p;
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < total; e += ETA_THREADS) acc += Y[e] * Y[e];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += 256 * ETA_PARTS)
+    acc += Y[e] * Y[e];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < ETA_THREADS / 64; ++w) t += red[w];
-    eta[mode] = 1e-12 * sqrt(fmax(t, 0.0) / ((double)n * p));
-  }
+  if (threadIdx.x == 0) part[mode * ETA_PARTS + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void perturb_eta_kernel(double* __restrict__ Yall, const double* __restrict__ eta_all,
+__global__ void perturb_eta_kernel(double* __restrict__ Yall, const double* __restrict__ part,
                                    int64_t n, int p, uint64_t seed) {
   const int mode = blockIdx.y;
-  const double eta = eta_all[mode] > 0 ? eta_all[mode] : 1e-300;
+  double t = 0.0;
+  for (int b = 0; b < ETA_PARTS; ++b) t += part[mode * ETA_PARTS + b];
+  const double eta0 = 1e-12 * sqrt(fmax(t, 0.0) / ((double)n * p));
+  const double eta = eta0 > 0 ? eta0 : 1e-300;
   double* Y = Yall + (int64_t)mode * n * p;
   const int64_t total = n * p;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -826,15 +892,17 @@ __global__ void perturb_eta_kernel(double* __restrict__ Yall, const double* __re
     Y[e] += eta * hash_uniform(seed + mode, (uint64_t)(e % n), (uint64_t)(e / n));
 }
 
-void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* eta, hipStream_t s) {
-  hipLaunchKernelGGL(sketch_eta_kernel, dim3(modes), dim3(ETA_THREADS), 0, s, Y, n, p, eta);
+size_t sketch_eta_bytes(int modes) { return (size_t)modes * ETA_PARTS * sizeof(double); }
+
+void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(sketch_eta_kernel, dim3(ETA_PARTS, modes), dim3(256), 0, s, Y, n, p, part);
 }
 
-void launch_perturb_eta(double* Y, const double* eta, int64_t n, int p, int modes, uint64_t seed,
+void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, uint64_t seed,
                         hipStream_t s) {
   const int64_t total = n * p;
   unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 2048);
-  hipLaunchKernelGGL(perturb_eta_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, eta, n, p, seed);
+  hipLaunchKernelGGL(perturb_eta_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, part, n, p, seed);
 }
 
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,

@@ -591,10 +591,11 @@ static void cfg_shape(CfgId c, int& bm, int& bn) {
 // product, whose tiles must be square) the small tile.  The big tile measured
 // slower on the charge-weighted Gram (both operands transposed).
 static CfgId choose(const Gemm64& g, int num_cu) {
-  (void)num_cu;
   if (g.upper_only) return CFG_SMALL;
   if (g.M > 64 && g.M <= 96) return CFG_RANK;
-  if (g.M >= 8192 && g.N >= 128) return CFG_BIG;
+  // the big tile only when it alone fills the chip (no split-K and its reduction)
+  const int64_t big_tiles = ((g.M + CfgBig::BM - 1) / CfgBig::BM) * ((g.N + CfgBig::BN - 1) / CfgBig::BN) * g.batch;
+  if (g.M >= 8192 && g.N >= 128 && big_tiles >= num_cu) return CFG_BIG;
   return CFG_SMALL;
 }
 
@@ -618,7 +619,12 @@ static Plan64 plan_for(const Gemm64& g, CfgId cfg, int num_cu) {
   if (tiles < target && g.K > 2 * KALIGN) {
     int64_t want = (target + tiles - 1) / tiles;
     int64_t maxs = g.K / (2 * KALIGN);  // at least 64 k per split
-    P.splits = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxs, 64)));
+    // a small symmetric output (p x p Rayleigh-Ritz or Cholesky QR Grams): at
+    // most ~2^20 partial values, which the fixed-order reduction reads back
+    const int64_t cap = g.upper_only
+        ? std::max<int64_t>(4, ((int64_t)1 << 20) / std::max<int64_t>(1, g.M * g.N * g.batch))
+        : (int64_t)64;
+    P.splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, cap, (int64_t)64}));
   }
   P.kchunk = (g.K + P.splits - 1) / P.splits;
   P.kchunk = (P.kchunk + KALIGN - 1) / KALIGN * KALIGN;

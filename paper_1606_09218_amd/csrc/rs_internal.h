@@ -161,10 +161,12 @@ void launch_identity(double* I, int64_t n, int modes, hipStream_t s);
 void launch_symmetrize(double* B, int p, int modes, hipStream_t s);
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,
                     hipStream_t s);
-// eta[mode] = 1e-12 sqrt(|Y_mode|_F^2 / (n p)) (the scale of the perturbation
-// from the range-finder sketch), and Y += eta * uniform noise with that scale
-void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* eta, hipStream_t s);
-void launch_perturb_eta(double* Y, const double* eta, int64_t n, int p, int modes, uint64_t seed,
+// Partial sums of |Y_mode|_F^2 (sketch_eta_bytes(modes) bytes), then
+// Y += eta * uniform noise with eta = 1e-12 sqrt(|Y_mode|_F^2 / (n p)), the
+// scale of the perturbation taken from the range-finder sketch
+size_t sketch_eta_bytes(int modes);
+void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* part, hipStream_t s);
+void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, uint64_t seed,
                         hipStream_t s);
 // Cholesky C = L L^T in place (lower, col-major), one workgroup per mode; the
 // shifted variant adds 11 (nrows p + p (p+1)) u tr(C) to the diagonal first.
@@ -202,6 +204,17 @@ void launch_gather_cols(const double* Z, int ldz, const int* perm, int p, int r,
                         hipStream_t s);
 void launch_canonical_signs(double* Qrow, int64_t n, int r, hipStream_t s, double* W = nullptr,
                             int64_t m = 0);
+// per-mode pointers and ranks, passed by value to the three-mode kernels
+struct Mode3 {
+  double* p[3];
+  int r[3];
+};
+// gather_cols and canonical_signs for the three modes in one launch each:
+// mode l reads Z + l zstride and perm + l p, writes Wr.p[l] (p x Wr.r[l]);
+// signs are fixed on Q.p[l] (n x Q.r[l]) and carried to W.p[l] (m x r, or null)
+void launch_gather_cols3(const double* Z, int ldz, int64_t zstride, const int* perm, int p,
+                         const Mode3& Wr, hipStream_t s);
+void launch_canonical_signs3(const Mode3& Q, int64_t n, const Mode3& W, int64_t m, hipStream_t s);
 
 // k_core.hip : beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);

@@ -261,24 +261,30 @@ struct Carve {
   }
 };
 
-static Gemm64 expand1_gemm(const rs_tensor* T, double* W1) {
+// The two-mode expansion T2[i1, i2, c] = sum_{a,b} V1[i1,a] V2[i2,b] beta[a,b,c]
+// as two single GEMMs.  The first writes X[b][i1][c] = sum_a V1[i1,a] beta[a,b,c]
+// (output column (b, c) of V1 beta_(1) sent to b n r3 + c); the second
+// contracts b: T2 row i2, column (i1, c) = sum_b V2[i2,b] X[b][i1 r3 + c],
+// sent to i1 n r3 + i2 r3 + c.
+static Gemm64 expand1_gemm(const rs_tensor* T, double* X) {
+  const int64_t n = T->n;
   const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
-  Gemm64 g;  // W1 (n x r2 r3) = V1 beta_(1)
-  g.M = T->n; g.N = (int64_t)r2 * r3; g.K = r1;
+  Gemm64 g;  // X[b][i1][c] = (V1 beta_(1))[i1, (b, c)]
+  g.M = n; g.N = (int64_t)r2 * r3; g.K = r1;
   g.A = T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
   g.B = T->beta.as<double>(); g.sbk = (int64_t)r2 * r3; g.sbn = 1;
-  g.C = W1; g.scm = (int64_t)r2 * r3; g.scn = 1;
+  g.C = X; g.scm = r3; g.scn = 1; g.ccb = r3; g.sccb = n * r3;
   return g;
 }
 
-static Gemm64 expand2_gemm(const rs_tensor* T, const double* W1) {
+static Gemm64 expand2_gemm(const rs_tensor* T, const double* X) {
   const int64_t n = T->n;
   const int r2 = T->r[1], r3 = T->r[2];
-  Gemm64 g;  // T2[i1] (n x r3) = V2 (n x r2) W1[i1] (r2 x r3), batched over i1
-  g.M = n; g.N = r3; g.K = r2; g.batch = (int)n;
-  g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1; g.sab = 0;
-  g.B = W1; g.sbk = r3; g.sbn = 1; g.sbb = (int64_t)r2 * r3;
-  g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.scb = n * r3;
+  Gemm64 g;  // T2[i1][i2][c] = sum_b V2[i2, b] X[b][i1 r3 + c]
+  g.M = n; g.N = n * r3; g.K = r2;
+  g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1;
+  g.B = X; g.sbk = n * r3; g.sbn = 1;
+  g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.ccb = r3; g.sccb = n * r3;
   return g;
 }
 
@@ -294,7 +300,7 @@ static Gemm64 grid_gemm(const rs_tensor* T, void* grid) {
   return g;
 }
 
-// Scratch layout of build_expansion: W1, then the GEMM workspaces.
+// Scratch layout of build_expansion: X (n r2 r3), then the GEMM workspaces.
 struct ExpansionScratch {
   size_t w1, wk1, wk2, wkg, total;
 };
@@ -321,11 +327,11 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
   const int r3 = T->r[2];
   const int ncu = T->ctx->num_cu;
   const ExpansionScratch e = expansion_scratch(T, grid != nullptr);
-  double* W1 = (double*)(scratch + e.w1);
+  double* X = (double*)(scratch + e.w1);
   mark(T, RS_STAGE_EXPAND1, s);
-  gemm64(expand1_gemm(T, W1), ncu, (double*)(scratch + e.wk1), s);
+  gemm64(expand1_gemm(T, X), ncu, (double*)(scratch + e.wk1), s);
   mark(T, RS_STAGE_EXPAND2, s);
-  gemm64(expand2_gemm(T, W1), ncu, (double*)(scratch + e.wk2), s);
+  gemm64(expand2_gemm(T, X), ncu, (double*)(scratch + e.wk2), s);
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
     grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,

@@ -55,6 +55,7 @@ struct GemmDev {
   int64_t kchunk;      // K range per split (multiple of BK)
   int upper_only;
   int nontemporal;
+  int64_t ccb, sccb;  // column blocks of the output (ccb = 0: none)
   int tiles_m, tiles_n;
   int xcd_remap;       // tile order grouped by XCD (tiles_m % 8 == 0, one batch, no split)
   int bm, bn;          // tile shape (for the reduction's mirror test)
@@ -201,6 +202,7 @@ struct HashSrc {
 struct TileOut {
   int64_t M, N;
   double* C; int64_t scm, scn;
+  int64_t ccb = 0, sccb = 0;
   double* part;   // split-K partial base for this (bt, split), row-major M x N, or null
   int nontemporal;
 };
@@ -305,7 +307,8 @@ __device__ __forceinline__ void mfma_tile(const ASrc& as_src, const BSrc& bs_src
           if (o.part) {
             o.part[row * o.N + col] = val;
           } else {
-            double* dst = o.C + row * o.scm + col * o.scn;
+            const int64_t coff = o.ccb ? (col / o.ccb) * o.sccb + (col % o.ccb) * o.scn : col * o.scn;
+            double* dst = o.C + row * o.scm + coff;
             if (o.nontemporal) __builtin_nontemporal_store(val, dst);
             else *dst = val;
           }
@@ -347,6 +350,8 @@ __global__ __launch_bounds__(CF::NT) void gemm_kernel(GemmDev g) {
   o.C = g.C + (int64_t)bt * g.scb;
   o.scm = g.scm;
   o.scn = g.scn;
+  o.ccb = g.ccb;
+  o.sccb = g.sccb;
   o.part = g.part ? g.part + ((int64_t)bt * g.splits + split) * g.M * g.N : nullptr;
   o.nontemporal = g.nontemporal;
   mfma_tile<CF>(as, bs, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, kbeg, kend, o);
@@ -450,7 +455,8 @@ __global__ void gemm64_reduce_kernel(GemmDev g) {
     double s = 0.0;
     for (int sp = 0; sp < g.splits; ++sp)
       s += g.part[(((int64_t)bt * g.splits + sp) * g.M + sr) * g.N + sc];
-    double* dst = g.C + (int64_t)bt * g.scb + row * g.scm + col * g.scn;
+    const int64_t coff = g.ccb ? (col / g.ccb) * g.sccb + (col % g.ccb) * g.scn : col * g.scn;
+    double* dst = g.C + (int64_t)bt * g.scb + row * g.scm + coff;
     *dst = s;
   }
 }
@@ -636,7 +642,7 @@ static Plan64 plan_for(const Gemm64& g, CfgId cfg, int num_cu) {
 // A product whose N is a Tucker rank (65..96) and whose M is larger is
 // computed transposed, C^T = B^T A^T, so that the rank sits on the 96-row side.
 static Gemm64 canon(const Gemm64& g) {
-  if (g.upper_only || !(g.N > 64 && g.N <= 96 && g.M > 96)) return g;
+  if (g.upper_only || g.ccb || !(g.N > 64 && g.N <= 96 && g.M > 96)) return g;
   Gemm64 t = g;
   t.M = g.N; t.N = g.M;
   t.A = g.B; t.sam = g.sbn; t.sak = g.sbk; t.sab = g.sbb;
@@ -673,6 +679,8 @@ void gemm64(const Gemm64& gin, int num_cu, double* work, hipStream_t s) {
   d.kscale = g.kscale;
   d.upper_only = g.upper_only;
   d.nontemporal = g.nontemporal;
+  d.ccb = g.ccb;
+  d.sccb = g.sccb;
   d.splits = P.splits;
   d.kchunk = P.kchunk;
   d.tiles_m = P.tm;
@@ -780,6 +788,8 @@ void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* 
   d.kscale = scale;
   d.upper_only = 0;
   d.nontemporal = 0;
+  d.ccb = 0;
+  d.sccb = 0;
   const Plan64 P = plan_for(g, sketch_cfg(M, N), num_cu);
   d.splits = P.splits;
   d.kchunk = P.kchunk;

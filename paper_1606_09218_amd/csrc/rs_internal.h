@@ -138,6 +138,9 @@ struct Gemm64 {
   const double* kscale = nullptr;   // optional, length K (same for all batches)
   int upper_only = 0;               // square symmetric output: compute tiles on/above the diagonal, mirror
   int nontemporal = 0;              // streaming stores for a write-once output
+  // optional column blocks: output column j goes to (j / ccb) sccb + (j % ccb) scn
+  // (0: plain j scn), so that an (i, c) column pair can land in another layout
+  int64_t ccb = 0, sccb = 0;
 };
 // Splits K so that at least ~2 waves of workgroups fill the chip; partial
 // sums are reduced in a fixed order (deterministic).  `work` must hold

@@ -162,7 +162,10 @@ def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
 
         for _ in range(warmup):
             step().free()
+        ctx.set_timing(2)
         wall, st, ranks_m = timed_steps(step, steps, stream)
+        ctx.set_timing(1)
+        _, st1, _ = timed_steps(step, min(steps, 5), stream)
         same_ranks = ranks_m == ranks
         err = float((g32.double() - grid64).abs().max() / grid64.abs().max())
         e_err = abs(E.item() - E64.item()) / abs(E64.item())
@@ -170,7 +173,7 @@ def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
                      "ms_per_step": round(wall / steps * 1e3, 3),
                      "grid_rel_linf_vs_fp64": err, "energy_rel_err_vs_fp64": e_err,
                      "meets_1e-5": bool(err <= 1e-5), "same_ranks_as_fp64": same_ranks,
-                     "core_ms": round(float(np.mean([x["core"] for x in st])), 4),
+                     "core_ms": round(float(np.mean([x["core"] for x in st1])), 4),
                      "grid_ms": round(float(np.mean([x["grid"] for x in st])), 4)}
     return out
 
@@ -254,15 +257,22 @@ def main():
         step().free()
     torch.cuda.synchronize()
 
+    # the timed steps carry only the two events around the grid kernel (the
+    # roofline kernel); the per-stage breakdown comes from separate steps
+    # after the timed region, so that its markers do not slow the value
+    ctx.set_timing(2)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    wall, stages, ranks = timed_steps(step, args.steps, stream, starts, ends)
+    wall, grid_stages, ranks = timed_steps(step, args.steps, stream, starts, ends)
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    ctx.set_timing(1)
+    _, stages, _ = timed_steps(step, min(args.steps, 5), stream)
 
     stage_avg = {k: float(np.mean([st[k] for st in stages])) for k in stages[0]}
     n, r3 = s.n, ranks[2]
-    # dominant single-kernel stage: the grid expansion GEMM (one launch)
-    t_grid = stage_avg["grid"] * 1e-3
+    # dominant single kernel: the grid expansion (one launch), timed over the timed steps
+    grid_ms = float(np.mean([st["grid"] for st in grid_stages]))
+    t_grid = grid_ms * 1e-3
     flops_grid = 2.0 * n ** 3 * r3
     bytes_grid = 8.0 * (n ** 3 + n * n * r3 + n * r3)
     achieved = flops_grid / t_grid / 1e12
@@ -279,7 +289,7 @@ def main():
                 "algorithmic_flops_per_launch": flops_grid,
                 "algorithmic_bytes_per_launch": bytes_grid,
                 "achieved_hbm_GBs_algorithmic": round(bytes_grid / t_grid / 1e9, 1),
-                "avg_launch_ms": round(stage_avg["grid"], 4)}
+                "avg_launch_ms": round(grid_ms, 4)}
 
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB

@@ -136,12 +136,12 @@ typedef struct {
 
 enum {
   RS_STAGE_FACTORS = 0,   /* side matrices and weights */
-  RS_STAGE_GRAM = 1,      /* charge-weighted Gram GEMMs */
+  RS_STAGE_GRAM = 1,      /* n x n charge-weighted Gram GEMMs (only when the subspace is all of R^n) */
   RS_STAGE_EIGEN = 2,     /* dominant eigenvectors of the Gram matrices, rank rule (incl. rank readback) */
-  RS_STAGE_BASIS = 3,     /* V_l = Q W, canonical signs */
-  RS_STAGE_PROJECT = 4,   /* U~_l = V_l^T U_l */
-  RS_STAGE_CORE = 5,      /* Khatri-Rao core contraction */
-  RS_STAGE_BINS = 6,      /* short-range brick lists */
+  RS_STAGE_BINS = 3,      /* short-range brick lists (first after the readback) */
+  RS_STAGE_BASIS = 4,     /* V_l = Q W, canonical signs */
+  RS_STAGE_PROJECT = 5,   /* U~_l = V_l^T U_l */
+  RS_STAGE_CORE = 6,      /* Khatri-Rao core contraction */
   RS_STAGE_EXPAND1 = 7,   /* V1 beta_(1) */
   RS_STAGE_EXPAND2 = 8,   /* T2 = beta x_1 V1 x_2 V2 */
   RS_STAGE_GRID = 9,      /* grid = T2 x_3 V3 (one GEMM launch) */
@@ -163,8 +163,11 @@ enum {
 /* Bind the library to HIP device `device` (makes it current on this thread). */
 rs_status rs_ctx_create(int device, rs_ctx** out);
 void rs_ctx_destroy(rs_ctx* ctx);
-/* Enable (1) or disable (0) per-stage HIP-event timing of later assemblies
- * made with this context (reported in rs_info.stage_ms). */
+/* HIP-event timing of later assemblies made with this context, reported in
+ * rs_info.stage_ms and eig_phase_ms: 0 off, 1 every stage and eigensolver
+ * phase, 2 the grid stage only (two events around its one kernel, so that
+ * the rest of the assembly runs without markers between launches).
+ * Errors: RS_E_INVALID for another value. */
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable);
 /* Device memory of the library's buffers comes from a per-device cache: a
  * released buffer is kept for reuse by later assemblies (immediately on the

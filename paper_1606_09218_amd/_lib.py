@@ -57,7 +57,7 @@ class rs_info(C.Structure):
 
 
 EIG_PHASES = ("eig_subspace", "eig_tridiag", "eig_values_vectors", "eig_orth_backtransform")
-STAGES = ("factors", "gram", "eigen", "basis", "project", "core", "bins", "expand1",
+STAGES = ("factors", "gram", "eigen", "bins", "basis", "project", "core", "expand1",
           "expand2", "grid", "short")
 
 
@@ -146,8 +146,11 @@ class Context:
         self.handle = h
         self.device = device
 
-    def set_timing(self, enable: bool = True):
-        _check(lib.rs_ctx_set_timing(self.handle, int(bool(enable))))
+    def set_timing(self, enable=True):
+        """HIP-event timing of later assemblies: False/0 off, True/1 every
+        stage, 2 the grid stage only (rs_ctx_set_timing)."""
+        mode = int(enable) if not isinstance(enable, bool) else int(enable)
+        _check(lib.rs_ctx_set_timing(self.handle, mode))
 
     def trim(self):
         """Return the device memory cached for reuse (rs_ctx_trim)."""

@@ -208,7 +208,14 @@ static int bricks_per_axis(int64_t n) { return (int)((n + 7) / 8); }
 // Record the start of `stage` (and so the end of the previous one) when the
 // tensor carries timing events.
 static void mark(rs_tensor* T, int stage, hipStream_t s) {
-  if (!T->events.empty()) RS_HIP(hipEventRecord(T->events[stage], s));
+  if (T->events.empty()) return;
+  // grid-only timing records the grid kernel's start and end and the end of
+  // the assembly; every other event would put a marker between two launches
+  if (T->timing_mode == 2 && stage != RS_STAGE_GRID && stage != RS_STAGE_SHORT &&
+      stage != RS_STAGE_COUNT)
+    return;
+  RS_HIP(hipEventRecord(T->events[stage], s));
+  T->recorded |= 1u << stage;
 }
 
 // Gram matrices of the three modes into G (3 x n x n); U, xi, w computed into
@@ -412,6 +419,10 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
   });
 }
 
+rs_ctx::~rs_ctx() {
+  for (void* p : pin_all) (void)hipHostFree(p);
+}
+
 void rs_ctx_destroy(rs_ctx* ctx) { delete ctx; }
 
 rs_status rs_ctx_trim(rs_ctx* ctx) {
@@ -425,7 +436,8 @@ rs_status rs_ctx_trim(rs_ctx* ctx) {
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(ctx != nullptr, "null context");
-    ctx->timing = enable ? 1 : 0;
+    RS_REQUIRE(enable >= 0 && enable <= 2, "timing mode must be 0, 1 or 2");
+    ctx->timing = enable;
     return RS_OK;
   });
 }
@@ -515,10 +527,13 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     T->stream = s;
     for (int l = 0; l < 3; ++l) T->p[l] = p;
     if (ctx->timing) {
+      T->timing_mode = ctx->timing;
       T->events.assign(RS_STAGE_COUNT + 1, nullptr);
       for (auto& e : T->events) RS_HIP(hipEventCreate(&e));
-      T->eig_events.assign(RS_EIG_PHASES + 1, nullptr);
-      for (auto& e : T->eig_events) RS_HIP(hipEventCreate(&e));
+      if (ctx->timing == 1) {
+        T->eig_events.assign(RS_EIG_PHASES + 1, nullptr);
+        for (auto& e : T->eig_events) RS_HIP(hipEventCreate(&e));
+      }
     }
 
     T->pos = DevBuf((size_t)N * 3 * sizeof(double), s);
@@ -721,9 +736,32 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     RS_HIP(hipMemcpyAsync(&rbd->total_pairs, T->brick_start.as<int>() + nbricks, sizeof(int),
                           hipMemcpyDeviceToDevice, s));
 
+    // the readback lands in a pinned host slot of the context (a copy to
+    // pageable memory would be staged through a driver buffer)
     Readback host;
-    RS_HIP(hipMemcpyAsync(&host, rbd, sizeof(Readback), hipMemcpyDeviceToHost, s));
-    RS_HIP(hipStreamSynchronize(s));
+    {
+      void* slot = nullptr;
+      {
+        std::lock_guard<std::mutex> lock(ctx->pin_mu);
+        if (!ctx->pin_free.empty()) {
+          slot = ctx->pin_free.back();
+          ctx->pin_free.pop_back();
+        }
+      }
+      if (!slot) {
+        RS_HIP(hipHostMalloc(&slot, sizeof(Readback), hipHostMallocDefault));
+        std::lock_guard<std::mutex> lock(ctx->pin_mu);
+        ctx->pin_all.push_back(slot);
+      }
+      const hipError_t e1 = hipMemcpyAsync(slot, rbd, sizeof(Readback), hipMemcpyDeviceToHost, s);
+      const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s) : e1;
+      if (e2 == hipSuccess) std::memcpy(&host, slot, sizeof(Readback));
+      {
+        std::lock_guard<std::mutex> lock(ctx->pin_mu);
+        ctx->pin_free.push_back(slot);
+      }
+      RS_HIP(e2);
+    }
     if (host.flags & 1) throw Error{RS_E_INVALID, "non-finite particle position or charge"};
     if (host.flags & 2) throw Error{RS_E_INVALID, "particle outside the box [-b, b]^3"};
     if (host.chol_fail & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the subspace basis"};
@@ -755,6 +793,17 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     T->beta = DevBuf((size_t)r1 * r2 * r3 * sizeof(double), s);
     T->n_pairs = host.total_pairs;
     T->brick_list = DevBuf((size_t)std::max<int64_t>(T->n_pairs, 1) * sizeof(int), s);
+    // (a6) short-range lists: fill and sort by particle index (first after the
+    // readback: it keeps the device busy while the rank-sized launches are enqueued)
+    mark(T.get(), RS_STAGE_BINS, s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_fill(dpos, N, n, f->grid.b, P.n_s, T->nb, T->brick_start.as<int>(), counts.as<int>(),
+                   T->brick_list.as<int>(), s);
+    T->active_cap = short_active_capacity(N, P.n_s, T->nb);
+    T->brick_active = DevBuf((size_t)(T->active_cap + 1) * sizeof(int), s);
+    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks,
+                   T->brick_active.as<int>(), T->active_cap, s);
+
     T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
     Gemm64 gb[3], gp[3];
     for (int l = 0; l < 3; ++l) {
@@ -823,16 +872,6 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       core_mixed(P.prec, at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
                  T->beta.as<double>(), ncu, at(o_core), s);
     }
-
-    // (a6) short-range lists: fill and sort by particle index
-    mark(T.get(), RS_STAGE_BINS, s);
-    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
-    short_bin_fill(dpos, N, n, f->grid.b, P.n_s, T->nb, T->brick_start.as<int>(), counts.as<int>(),
-                   T->brick_list.as<int>(), s);
-    T->active_cap = short_active_capacity(N, P.n_s, T->nb);
-    T->brick_active = DevBuf((size_t)(T->active_cap + 1) * sizeof(int), s);
-    short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks,
-                   T->brick_active.as<int>(), T->active_cap, s);
 
     // (a7) T2 and the grid
     build_expansion(T.get(), grid_out, ab + o_exp, s);
@@ -997,14 +1036,18 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
           I.eig_phase_ms[k] = ms;
       }
     }
-    if (!T->events.empty()) {
+    if (!T->events.empty() && (T->recorded >> RS_STAGE_COUNT) & 1u) {
       RS_HIP(hipEventSynchronize(T->events[RS_STAGE_COUNT]));
-      // a stage that did not run has its start event unrecorded: it borrows
-      // the next recorded event and reports 0
+      // a stage runs from its event to the next recorded one; a stage whose
+      // event was not recorded (it did not run, or is not timed) reports 0
       for (int k = 0; k < RS_STAGE_COUNT; ++k) {
+        I.stage_ms[k] = 0.0;
+        if (!((T->recorded >> k) & 1u)) continue;
+        int j = k + 1;
+        while (!((T->recorded >> j) & 1u)) ++j;   // bit RS_STAGE_COUNT is set
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, T->events[k], T->events[k + 1]) == hipSuccess) I.stage_ms[k] = ms;
-        else I.stage_ms[k] = 0.0;
+        RS_HIP(hipEventElapsedTime(&ms, T->events[k], T->events[j]));
+        I.stage_ms[k] = ms;
       }
     }
     *info = I;

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/rs.h"
@@ -67,6 +68,11 @@ struct rs_ctx {
   int timing = 0;
   int lds_limit = 65536;   // dynamic LDS bytes one workgroup may use
   double wall_khz = 100000.0;  // rate of the device wall clock
+  // pinned host slots for the rank readback of concurrent assemblies
+  // (hipHostMalloc'd on first use, freed with the context)
+  std::mutex pin_mu;
+  std::vector<void*> pin_free, pin_all;
+  ~rs_ctx();
 };
 
 struct rs_factors {
@@ -104,6 +110,8 @@ struct rs_tensor {
   int64_t active_cap = 0;
   // stage timing: events[k] recorded before stage k, events[RS_STAGE_COUNT] at the end
   std::vector<hipEvent_t> events;
+  int timing_mode = 0;          // 1: every stage and eigen phase, 2: the grid stage only
+  uint32_t recorded = 0;        // bit k: events[k] was recorded
   // eigensolver phases: eig_events[k] before phase k, eig_events[RS_EIG_PHASES] at the end
   std::vector<hipEvent_t> eig_events;
   ~rs_tensor() {

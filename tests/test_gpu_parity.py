@@ -238,3 +238,25 @@ def test_determinism_and_antisymmetry(rsm, ctx):
     sp = workloads.System(s.name, s.pos[perm], s.q[perm], s.b, s.n, s.R, s.R_l, s.n_s)
     _, _, g4 = run_gpu(rsm, ctx, sp, r_max=48)
     assert rel_linf(g4.cpu().numpy(), g1.cpu().numpy()) <= 1e-10
+
+
+def test_timing_modes(rsm, ctx):
+    """Mode 1 times every stage; mode 2 only the grid stage (and the short
+    range after it); other values are rejected."""
+    s = workloads.tiny_system(91, 20, 5.0, 48, 20, 8, 7, min_sep=0.5)
+    c2 = rsm.Context(0)
+    try:
+        c2.set_timing(1)
+        _, T1, _ = run_gpu(rsm, c2, s, r_max=32)
+        st1 = T1.stage_ms()
+        c2.set_timing(2)
+        _, T2, _ = run_gpu(rsm, c2, s, r_max=32)
+        st2 = T2.stage_ms()
+        say(f"  mode 1 {st1}\n  mode 2 {st2}")
+        assert st1["grid"] > 0 and st1["core"] > 0 and st1["eig_tridiag"] > 0
+        assert st2["grid"] > 0 and st2["short"] > 0
+        assert all(v == 0.0 for k, v in st2.items() if k not in ("grid", "short"))
+        with pytest.raises(rsm.RSError):
+            c2.set_timing(3)
+    finally:
+        c2.set_timing(0)

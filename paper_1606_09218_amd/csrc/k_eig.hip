@@ -10,6 +10,8 @@
 // range finder of Halko, Martinsson and Tropp) orthonormalised by shifted
 // Cholesky QR.  Everything is FP64.  Each small kernel runs one workgroup per
 // mode.
+#include <hip/hip_cooperative_groups.h>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -944,10 +946,12 @@ __device__ double es_block_sum(double v, double* red) {
 // multipliers p x rc and reciprocal pivots p x rc (row-major, thread j owns
 // column j so that a wave touches consecutive words).  The vectors Z live in
 // their own array, p x rc row-major per mode.
+constexpr int TD_G = 16;   // workgroups per mode of the distributed tridiagonalisation
+
 struct EigWs {
-  double *hv, *beta, *d, *e, *lam, *lm, *ru;
+  double *hv, *beta, *d, *e, *lam, *lm, *ru, *sx;
   __host__ __device__ EigWs(double* base, int p, int rc, int mode) {
-    const int64_t per = (int64_t)p * p + 4 * (int64_t)p + 2 * (int64_t)p * rc;
+    const int64_t per = (int64_t)p * p + 4 * (int64_t)p + 2 * (int64_t)p * rc + 4 * (int64_t)p + 2 * TD_G;
     double* b = base + mode * per;
     hv = b;
     beta = hv + (int64_t)p * p;
@@ -956,11 +960,14 @@ struct EigWs {
     lam = e + p;
     lm = lam + p;
     ru = lm + (int64_t)p * rc;
+    sx = ru + (int64_t)p * rc;   // exchange buffers of the distributed tridiagonalisation
   }
 };
 
 size_t eig_sym_workspace_bytes(int p, int rc, int modes) {
-  return (size_t)modes * ((size_t)p * p + 4 * (size_t)p + 2 * (size_t)p * rc) * sizeof(double);
+  return (size_t)modes *
+         ((size_t)p * p + 4 * (size_t)p + 2 * (size_t)p * rc + 4 * (size_t)p + 2 * TD_G) *
+         sizeof(double);
 }
 
 // Householder tridiagonalisation with B in registers, for p <= 16 RT: thread
@@ -1336,6 +1343,182 @@ __global__ __launch_bounds__(TW_THREADS) void tridiag_wide_kernel(double* __rest
   }
 }
 
+// Householder tridiagonalisation for 128 < p <= 512 on TD_G workgroups per
+// mode (cooperative launch: all co-resident).  Workgroup g keeps rows
+// i = g + TD_G t of B in LDS for the whole factorisation.  The rank-2 update
+// of step k-1 is applied lazily, fused with the product B22 v of step k in one
+// pass over the workgroup's rows; the owner of row k+1 publishes that row
+// (through global memory), and after the grid barrier every workgroup
+// derives the next Householder vector from it with identical arithmetic, so
+// one grid barrier per step suffices.  Exchange buffers (per mode, parity
+// k & 1): the products pw[2][p], the published rows row[2][p] and the
+// per-workgroup partial sums of pw . v, part[2][TD_G].  Same outputs as the
+// other tridiagonalisations.
+constexpr int TD_THREADS = 512;
+constexpr int TD_WAVES = TD_THREADS / 64;
+
+__global__ __launch_bounds__(TD_THREADS) void tridiag_dist_kernel(const double* __restrict__ Ball,
+                                                                  double* __restrict__ ws, int p,
+                                                                  int rc) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  extern __shared__ double tds[];
+  __shared__ double red[TD_WAVES];
+  __shared__ double sh_beta, sh_v1;
+  const int mode = blockIdx.x / TD_G, g = blockIdx.x - (blockIdx.x / TD_G) * TD_G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nlm = (p + TD_G - 1) / TD_G;
+  const int nloc = (p - g + TD_G - 1) / TD_G;   // rows i = g + TD_G t, t < nloc
+  double* rows = tds;                           // [nlm][p]
+  double* vold = rows + (size_t)nlm * p;        // pending vector v_{k-1}
+  double* wold = vold + p;                      // pending w_{k-1}
+  double* vnew = wold + p;                      // v_k
+  double* rk = vnew + p;                        // current row k
+  const double* B = Ball + (int64_t)mode * p * p;
+  EigWs W(ws, p, rc, mode);
+  double* pwb[2] = {W.sx, W.sx + p};
+  double* rowb[2] = {W.sx + 2 * p, W.sx + 3 * p};
+  double* partb[2] = {W.sx + 4 * p, W.sx + 4 * p + TD_G};
+  for (int t = 0; t < nloc; ++t)
+    for (int j = tid; j < p; j += TD_THREADS) rows[t * p + j] = B[(int64_t)(g + TD_G * t) * p + j];
+  for (int j = tid; j < p; j += TD_THREADS) {
+    vold[j] = 0.0;
+    wold[j] = 0.0;
+    if (g == 0) {
+      W.e[j] = 0.0;
+      W.beta[j] = 0.0;
+    }
+  }
+  __syncthreads();
+  double beta_prev = 0.0;
+  for (int k = 0; k + 2 < p; ++k) {
+    const int par = k & 1, ppar = par ^ 1;
+    if (k > 0) {   // the pending w_{k-1} = pw_{k-1} - kc v_{k-1}
+      double ps = 0.0;
+      for (int b = 0; b < TD_G; ++b) ps += partb[ppar][b];
+      const double kc = 0.5 * beta_prev * ps;
+      for (int j = k + tid; j < p; j += TD_THREADS) wold[j] = pwb[ppar][j] - kc * vold[j];
+    }
+    __syncthreads();
+    const double* pub = k == 0 ? B : rowb[ppar];   // row k before the pending update
+    {
+      const double vk = vold[k], wk = wold[k];
+      for (int j = k + tid; j < p; j += TD_THREADS) rk[j] = pub[j] - (vk * wold[j] + wk * vold[j]);
+    }
+    __syncthreads();
+    double prt = 0.0;
+    for (int j = k + 2 + tid; j < p; j += TD_THREADS) prt += rk[j] * rk[j];
+    prt = wave_sum(prt);
+    if (lane == 0) red[wave] = prt;
+    __syncthreads();
+    if (tid == 0) {
+      double sigma = 0.0;
+      for (int w = 0; w < TD_WAVES; ++w) sigma += red[w];
+      const double x1 = rk[k + 1];
+      double beta = 0.0, v1 = 1.0, sub = x1;
+      if (sigma > 0.0) {
+        const double mu = sqrt(x1 * x1 + sigma);
+        v1 = x1 <= 0.0 ? x1 - mu : -sigma / (x1 + mu);
+        beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        sub = mu;
+      }
+      sh_beta = beta;
+      sh_v1 = v1;
+      if (g == 0) {
+        W.d[k] = rk[k];
+        W.e[k] = sub;
+        W.beta[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double beta = sh_beta, inv1 = 1.0 / sh_v1;
+    for (int j = k + 1 + tid; j < p; j += TD_THREADS) {
+      const double v = j == k + 1 ? 1.0 : rk[j] * inv1;
+      vnew[j] = v;
+      if (g == 0 && j >= k + 2) W.hv[(int64_t)k * p + j] = v;
+    }
+    __syncthreads();
+    // own rows i >= k+1: apply the pending update, then pw_i = beta (B v_k)_i
+    double kpart = 0.0;
+    for (int t = wave; t < nloc; t += TD_WAVES) {
+      const int i = g + TD_G * t;
+      if (i < k + 1) continue;   // uniform over the wave
+      const double vi = vold[i], wi = wold[i];
+      double* ri = rows + (size_t)t * p;
+      double acc = 0.0;
+      for (int j = k + 1 + lane; j < p; j += 64) {
+        const double b = ri[j] - (vi * wold[j] + wi * vold[j]);
+        ri[j] = b;
+        acc += b * vnew[j];
+      }
+      acc = wave_sum(acc);
+      const double pwi = beta * acc;
+      if (lane == 0) pwb[par][i] = pwi;
+      kpart += pwi * vnew[i];
+      if (i == k + 1)
+        for (int j = k + 1 + lane; j < p; j += 64) rowb[par][j] = ri[j];
+    }
+    if (lane == 0) red[wave] = kpart;
+    __syncthreads();
+    if (tid == 0) {
+      double sp = 0.0;
+      for (int w = 0; w < TD_WAVES; ++w) sp += red[w];
+      partb[par][g] = sp;
+    }
+    for (int j = k + 1 + tid; j < p; j += TD_THREADS) vold[j] = vnew[j];
+    beta_prev = beta;
+    grid.sync();
+  }
+  // the last pending update (of step p-3) on rows p-2 and p-1
+  if (p >= 3) {
+    const int par = (p - 3) & 1;
+    double ps = 0.0;
+    for (int b = 0; b < TD_G; ++b) ps += partb[par][b];
+    const double kc = 0.5 * beta_prev * ps;
+    if (tid == 0) {
+      double w2[2];
+      for (int q = 0; q < 2; ++q) w2[q] = pwb[par][p - 2 + q] - kc * vold[p - 2 + q];
+      for (int t = 0; t < nloc; ++t) {
+        const int i = g + TD_G * t;
+        if (i < p - 2) continue;
+        const double vi = vold[i], wi = w2[i - (p - 2)];
+        double* ri = rows + (size_t)t * p;
+        for (int q = 0; q < 2; ++q) ri[p - 2 + q] -= vi * w2[q] + wi * vold[p - 2 + q];
+        if (i == p - 2) {
+          W.d[p - 2] = ri[p - 2];
+          W.e[p - 2] = ri[p - 1];
+        } else {
+          W.d[p - 1] = ri[p - 1];
+          W.e[p - 1] = 0.0;
+        }
+      }
+    }
+  }
+}
+
+// the distributed form when the device can launch it cooperatively
+static bool launch_tridiag_dist(double* B, double* ws, int p, int rc, int modes, hipStream_t s) {
+  static int coop = -1;
+  if (coop < 0) {
+    int dev = 0, v = 0;
+    coop = (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && v)
+               ? 1 : 0;
+  }
+  if (!coop || p < 3) return false;
+  const int nlm = (p + TD_G - 1) / TD_G;
+  const size_t lds = ((size_t)nlm * p + 4 * (size_t)p) * sizeof(double);
+  if (lds > 150 * 1024) return false;
+  allow_lds((const void*)tridiag_dist_kernel, lds);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tridiag_dist_kernel, TD_THREADS, lds) !=
+          hipSuccess || per_cu < 1)
+    return false;
+  void* args[] = {&B, &ws, &p, &rc};
+  RS_HIP(hipLaunchCooperativeKernel((const void*)tridiag_dist_kernel, dim3(modes * TD_G),
+                                    dim3(TD_THREADS), args, lds, s));
+  return true;
+}
+
 // 1/q for finite nonzero q: the hardware reciprocal estimate refined by two
 // Newton steps t <- t + t (1 - q t) (each roughly doubles the correct bits).
 __device__ __forceinline__ double recip(double q) {
@@ -1654,6 +1837,7 @@ void launch_eig_tridiag(double* B, double* ws, int p, int rc, int modes, int lds
   }
   const size_t tri_lds = ((size_t)p * (p + 1) + (size_t)p) * sizeof(double);
   const size_t wide_lds = (size_t)(TW_WAVES + 2) * p * sizeof(double);
+  if (p <= 512 && launch_tridiag_dist(B, ws, p, rc, modes, s)) return;
   if (p <= 64 * TW_MAXA && wide_lds + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)tridiag_wide_kernel, wide_lds);
     hipLaunchKernelGGL(tridiag_wide_kernel, dim3(modes), dim3(TW_THREADS), wide_lds, s, B, ws, p,

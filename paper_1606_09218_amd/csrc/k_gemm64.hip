@@ -24,6 +24,7 @@
 // walk the N tiles of one M tile, so the A tile is re-read from that XCD's
 // L2 rather than from HBM.
 #include "rs_internal.h"
+#include <algorithm>
 
 namespace rs {
 
@@ -727,6 +728,125 @@ static void plan_core(int r1, int r2, int r3, int64_t K, int num_cu, bool& rank_
   splits = (int)((K + kchunk - 1) / kchunk);
 }
 
+// ---- core, streaming form (r1 <= 128) -------------------------------------------
+// beta_(1)[a, col] = sum_k U~1[k, a] s2[k, b] U~3[k, c], col = b r3 + c.  A
+// workgroup of 8 waves owns 128 columns (16 per wave) and a k range; it
+// stages 128-k chunks of U~1 (all r1 rows, [k][a]) in LDS, and each wave forms
+// its Khatri-Rao fragment in registers: lane (r, q) holds B[k0 + 4s + q][col]
+// = s2[k][b] U~3[k][c] for its column (the 16 lanes of a k read 16
+// consecutive c), loaded four steps ahead.  Step s is RB MFMAs
+// against the shared A chunk.
+constexpr int CS_KC = 64, CS_NP = 4;
+
+template <int RB>
+__global__ __launch_bounds__(512) void core_stream_kernel(const double* __restrict__ U1t,
+                                                          const double* __restrict__ s2,
+                                                          const double* __restrict__ U3t, int r1,
+                                                          int r2, int r3, int64_t K,
+                                                          int64_t kchunk, double* __restrict__ out,
+                                                          int64_t split_stride) {
+  constexpr int KC = CS_KC, NP = CS_NP, AR = 16 * RB;
+  constexpr int LDA = AR + ((RB & 1) ? 0 : 16);   // row starts 32 banks apart per q
+  constexpr int AV = (KC * AR + 511) / 512;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  extern __shared__ double As[];   // [KC][LDA]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int W = r2 * r3;
+  const int col = blockIdx.x * 128 + wave * 16 + r;
+  const bool colok = col < W;
+  const int b = colok ? col / r3 : 0, c = colok ? col - b * r3 : 0;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+  double ra[AV];
+  auto loadA = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 512 * u;
+      const int kk = e / AR, a = e - kk * AR;
+      ra[u] = (e < KC * AR && k0 + kk < kend && a < r1) ? U1t[(k0 + kk) * r1 + a] : 0.0;
+    }
+  };
+  auto storeA = [&]() {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 512 * u;
+      const int kk = e / AR, a = e - kk * AR;
+      if (e < KC * AR) As[kk * LDA + a] = ra[u];
+    }
+  };
+  // raw Khatri-Rao factors of NP consecutive steps (k = k0 + 4 s + q)
+  auto loadB = [&](int64_t k0, double (&x2)[NP], double (&x3)[NP]) {
+#pragma unroll
+    for (int s8 = 0; s8 < NP; ++s8) {
+      const int64_t k = k0 + 4 * s8 + q;
+      const bool ok = colok && k < kend;
+      x2[s8] = ok ? s2[k * r2 + b] : 0.0;
+      x3[s8] = ok ? U3t[k * r3 + c] : 0.0;
+    }
+  };
+  d4 acc[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  if (kbeg < kend) {
+    loadA(kbeg);
+    storeA();
+  }
+  __syncthreads();
+  double c2[NP], c3[NP];
+  loadB(kbeg, c2, c3);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    const bool more = k0 + KC < kend;
+    if (more) loadA(k0 + KC);
+#pragma unroll 2
+    for (int g = 0; g < KC / (4 * NP); ++g) {
+      // the next NP steps are fetched NP steps ahead, across chunk ends
+      double n2[NP], n3[NP];
+      loadB(k0 + 4 * NP * (g + 1), n2, n3);
+#pragma unroll
+      for (int s8 = 0; s8 < NP; ++s8) {
+        const double bv = c2[s8] * c3[s8];
+        const double* arow = As + (4 * NP * g + 4 * s8 + q) * LDA + r;
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * i], bv, acc[i], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s8 = 0; s8 < NP; ++s8) {
+        c2[s8] = n2[s8];
+        c3[s8] = n3[s8];
+      }
+    }
+    __syncthreads();
+    if (more) {
+      storeA();
+      __syncthreads();
+    }
+  }
+  // acc[i][v] is beta_(1)[16 i + q + 4 v][col]
+  double* o = out + (int64_t)blockIdx.z * split_stride;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * i + q + 4 * v;
+      if (a < r1 && colok) o[(int64_t)a * W + col] = acc[i][v];
+    }
+}
+
+static int core_stream_rb(int r1) { return r1 <= 32 ? 2 : r1 <= 64 ? 4 : r1 <= 96 ? 6 : 8; }
+
+static void plan_core_stream(int r1, int r2, int r3, int64_t K, int num_cu, int& splits,
+                             int64_t& kchunk) {
+  const int64_t groups = ((int64_t)r2 * r3 + 127) / 128;
+  // one 8-wave workgroup per CU: fill the chip once without a ragged second wave
+  splits = (int)std::max<int64_t>(1, std::min<int64_t>(num_cu / groups, (K + CS_KC - 1) / CS_KC));
+  splits = std::min(splits, 32);
+  kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + CS_KC - 1) / CS_KC * CS_KC;
+  splits = (int)((K + kchunk - 1) / kchunk);
+}
+
 // workspace: xi U~2 (K x r2), then the split-K partials
 static size_t core64_s2_bytes(int r2, int64_t K) { return ((size_t)K * r2 * sizeof(double) + 255) & ~(size_t)255; }
 
@@ -734,7 +854,8 @@ size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
   bool rt;
   int splits, tm, tn;
   int64_t kchunk;
-  plan_core(r1, r2, r3, K, num_cu, rt, splits, kchunk, tm, tn);
+  if (r1 <= 128) plan_core_stream(r1, r2, r3, K, num_cu, splits, kchunk);
+  else plan_core(r1, r2, r3, K, num_cu, rt, splits, kchunk, tm, tn);
   return core64_s2_bytes(r2, K) + (splits > 1 ? (size_t)splits * r1 * r2 * r3 * sizeof(double) : 0);
 }
 
@@ -751,6 +872,34 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
     const int64_t total = K * r2;
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks), dim3(256), 0, s, xi, U2t, K, r2, s2);
+  }
+  if (r1 <= 128) {
+    int splits;
+    int64_t kchunk;
+    plan_core_stream(r1, r2, r3, K, num_cu, splits, kchunk);
+    double* outp = splits > 1 ? part : beta;
+    const int64_t W = (int64_t)r2 * r3;
+    const dim3 grid((unsigned)((W + 127) / 128), 1, (unsigned)splits);
+    const int rb = core_stream_rb(r1);
+    auto launch = [&](auto fn, int RBv) {
+      const size_t lds = (size_t)CS_KC * (16 * RBv + ((RBv & 1) ? 0 : 16)) * sizeof(double);
+      if (lds > 48 * 1024)
+        RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+      hipLaunchKernelGGL(fn, grid, dim3(512), lds, s, U1t, (const double*)s2, U3t, r1, r2, r3, K,
+                         kchunk, outp, (int64_t)r1 * W);
+    };
+    if (rb == 2) launch(core_stream_kernel<2>, 2);
+    else if (rb == 4) launch(core_stream_kernel<4>, 4);
+    else if (rb == 6) launch(core_stream_kernel<6>, 6);
+    else launch(core_stream_kernel<8>, 8);
+    if (splits > 1) {
+      const int64_t total = (int64_t)r1 * W;
+      unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+      hipLaunchKernelGGL(core64_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)part,
+                         splits, total, beta);
+    }
+    return;
   }
   d.U1t = U1t;
   d.s2 = s2;

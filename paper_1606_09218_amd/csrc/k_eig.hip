@@ -619,9 +619,21 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
   // column c of the column-major L starts at c p + c.  Either way Lc[i - c] = L[i, c].
   const int packed = p * (p + 1) / 2;
   if (LDS) {
-    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-      const int c = e / p, i = e - c * p;
-      if (i >= c) sht[c * p - c * (c - 1) / 2 + (i - c)] = L[e];
+    // loads in batches of SB per thread, issued together before their stores
+    constexpr int SB = 16;
+    for (int e0 = 0; e0 < p * p; e0 += SB * (int)blockDim.x) {
+      double v[SB];
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
+        v[t] = e < p * p ? L[e] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
+        const int c = e / p, i = e - c * p;
+        if (e < p * p && i >= c) sht[c * p - c * (c - 1) / 2 + (i - c)] = v[t];
+      }
     }
     for (int c = threadIdx.x; c < p; c += blockDim.x) sht[packed + c] = 1.0 / L[(int64_t)c * p + c];
     __syncthreads();
@@ -1537,6 +1549,7 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* ee, in
   double q = d[0] - x;
   if (fabs(q) <= pivmin) q = -pivmin;
   int c = q < 0.0;
+#pragma unroll 8
   for (int i = 1; i < p; ++i) {
     q = fmin(fmax(q, -big), big);
     q = (d[i] - x) - ee[i - 1] * recip(q);
@@ -1749,6 +1762,8 @@ __global__ __launch_bounds__(TPB) void invit_lds_kernel(double* __restrict__ ws,
   double rprev = recip(up);
   lm[0] = 0.0;
   ru[0] = rprev;
+  // unrolled so that the LDS loads of a chunk precede its dependent chain
+#pragma unroll 8
   for (int i = 1; i < p; ++i) {
     const double ei = eS[i - 1];
     const double l = ei * rprev;
@@ -1762,11 +1777,13 @@ __global__ __launch_bounds__(TPB) void invit_lds_kernel(double* __restrict__ ws,
   double scale = 1.0;
   for (int it = 0; it < 3; ++it) {
     double prev = 0.0;
+#pragma unroll 8
     for (int i = 0; i < p; ++i) {
       prev = scale * z[i * TPB] - lm[i * TPB] * prev;
       z[i * TPB] = prev;
     }
     double nxt = 0.0, mx = 0.0;
+#pragma unroll 8
     for (int i = p - 1; i >= 0; --i) {
       nxt = (z[i * TPB] - eS[i] * nxt) * ru[i * TPB];
       z[i * TPB] = nxt;
@@ -1775,6 +1792,7 @@ __global__ __launch_bounds__(TPB) void invit_lds_kernel(double* __restrict__ ws,
     scale = mx > 0.0 ? 1.0 / mx : 1.0;
   }
   double nrm = 0.0;
+#pragma unroll 8
   for (int i = 0; i < p; ++i) {
     const double v = scale * z[i * TPB];
     nrm += v * v;
@@ -1802,21 +1820,43 @@ __global__ __launch_bounds__(256) void reflect_cols_kernel(double* __restrict__ 
     const int i = lane + 64 * u;
     y[u] = i < p ? Z[(int64_t)i * rc] : 0.0;
   }
-  for (int k = p - 3; k >= 0; --k) {
-    const double beta = W.beta[k];
-    if (beta == 0.0) continue;
-    const double* v = W.hv + (int64_t)k * p;
-    double vv[UPL];
-    double part = 0.0;
+  // reflectors in blocks of D (k = kb, kb - 1, ...); the next block's vectors
+  // are loaded while the current block is applied
+  constexpr int D = UPL <= 4 ? 8 : UPL <= 8 ? 4 : 2;
+  auto load_block = [&](int kb, double (&vb)[D][UPL], double (&bb)[D]) {
 #pragma unroll
-    for (int u = 0; u < UPL; ++u) {
-      const int i = lane + 64 * u;
-      vv[u] = i == k + 1 ? 1.0 : ((i >= k + 2 && i < p) ? v[i] : 0.0);
-      part = fma(vv[u], y[u], part);
+    for (int t = 0; t < D; ++t) {
+      const int k = kb - t;
+      bb[t] = k >= 0 ? W.beta[k] : 0.0;
+      const double* v = W.hv + (int64_t)(k >= 0 ? k : 0) * p;
+#pragma unroll
+      for (int u = 0; u < UPL; ++u) {
+        const int i = lane + 64 * u;
+        vb[t][u] = k < 0 ? 0.0 : (i == k + 1 ? 1.0 : ((i >= k + 2 && i < p) ? v[i] : 0.0));
+      }
     }
-    const double dot = beta * wave_sum_dpp(part);
+  };
+  double cv[D][UPL], cb[D];
+  load_block(p - 3, cv, cb);
+  for (int kb = p - 3; kb >= 0; kb -= D) {
+    double nv[D][UPL], nb[D];
+    load_block(kb - D, nv, nb);
 #pragma unroll
-    for (int u = 0; u < UPL; ++u) y[u] = fma(-dot, vv[u], y[u]);
+    for (int t = 0; t < D; ++t) {
+      if (cb[t] == 0.0) continue;
+      double part = 0.0;
+#pragma unroll
+      for (int u = 0; u < UPL; ++u) part = fma(cv[t][u], y[u], part);
+      const double dot = cb[t] * wave_sum_dpp(part);
+#pragma unroll
+      for (int u = 0; u < UPL; ++u) y[u] = fma(-dot, cv[t][u], y[u]);
+    }
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      cb[t] = nb[t];
+#pragma unroll
+      for (int u = 0; u < UPL; ++u) cv[t][u] = nv[t][u];
+    }
   }
 #pragma unroll
   for (int u = 0; u < UPL; ++u) {

@@ -162,6 +162,9 @@ enum {
 
 /* Bind the library to HIP device `device` (makes it current on this thread). */
 rs_status rs_ctx_create(int device, rs_ctx** out);
+/* Release the handle.  Tensors still alive keep the context (and its cached
+   memory and pinned slots) until the last of them is freed with
+   rs_tensor_free; a null handle is ignored. */
 void rs_ctx_destroy(rs_ctx* ctx);
 /* HIP-event timing of later assemblies made with this context, reported in
  * rs_info.stage_ms and eig_phase_ms: 0 off, 1 every stage and eigensolver

@@ -13,6 +13,10 @@
 
 namespace rs {
 
+void ctx_release(rs_ctx* c) {
+  if (c->refs.fetch_sub(1) == 1) delete c;
+}
+
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const char* last_error() { return g_err.c_str(); }
@@ -423,7 +427,9 @@ rs_ctx::~rs_ctx() {
   for (void* p : pin_all) (void)hipHostFree(p);
 }
 
-void rs_ctx_destroy(rs_ctx* ctx) { delete ctx; }
+void rs_ctx_destroy(rs_ctx* ctx) {
+  if (ctx) rs::ctx_release(ctx);
+}
 
 rs_status rs_ctx_trim(rs_ctx* ctx) {
   return guarded([&]() -> rs_status {
@@ -512,6 +518,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 
     auto T = std::make_unique<rs_tensor>();
     T->ctx = ctx;
+    T->ctx_ref.set(ctx);
     T->N = N;
     T->n = n;
     T->b = f->grid.b;
@@ -1128,6 +1135,7 @@ rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
     RS_REQUIRE(std::memcmp(magic, kMagic, 8) == 0, "not an RS tensor file (bad magic/version)");
     auto T = std::make_unique<rs_tensor>();
     T->ctx = ctx;
+    T->ctx_ref.set(ctx);
     hipStream_t s = nullptr;
     T->stream = s;
     int32_t ints[10];

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -72,8 +73,31 @@ struct rs_ctx {
   // (hipHostMalloc'd on first use, freed with the context)
   std::mutex pin_mu;
   std::vector<void*> pin_free, pin_all;
+  // references: the handle returned by rs_ctx_create plus one per live
+  // tensor; the context is deleted when the last one is released, so a
+  // tensor freed after rs_ctx_destroy still finds it
+  std::atomic<int> refs{1};
   ~rs_ctx();
 };
+
+namespace rs {
+void ctx_release(rs_ctx* c);
+// a counted reference to a context, released after the members declared
+// after it (declare it first)
+struct CtxRef {
+  rs_ctx* p = nullptr;
+  CtxRef() = default;
+  CtxRef(const CtxRef&) = delete;
+  CtxRef& operator=(const CtxRef&) = delete;
+  void set(rs_ctx* c) {
+    c->refs.fetch_add(1);
+    p = c;
+  }
+  ~CtxRef() {
+    if (p) ctx_release(p);
+  }
+};
+}  // namespace rs
 
 struct rs_factors {
   rs_grid grid;
@@ -85,6 +109,7 @@ struct rs_factors {
 };
 
 struct rs_tensor {
+  rs::CtxRef ctx_ref;   // first: released after every buffer below
   rs_ctx* ctx = nullptr;
   int64_t N = 0, n = 0;
   double b = 0, h = 0;

@@ -148,6 +148,27 @@ def test_mid_subspace_full_grid_parity(rsm, ctx, case):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("r1", [24, 56, 88, 120])
+def test_core_register_blocks(rsm, ctx, r1):
+    """The streaming core keeps 2, 4, 6 or 8 MFMA row blocks per wave
+    (r1 <= 32, 64, 96, 128): each form against the oracle at the same fixed
+    ranks (a truncation of a spectrum computed to 1e-9)."""
+    s = workloads.tiny_system(81, 90, 8.0, 192, 24, 10, 9, min_sep=0.5)
+    s.eps_tucker = 1e-9
+    own = rs.assemble_system(s).ranks
+    assert own[0] >= r1
+    ranks = [r1, own[1], own[2]]
+    say(f"core register blocks r1={r1}: ranks {ranks}")
+    ref = rs.assemble_system(s, fixed_ranks=ranks)
+    f, T, g = run_gpu(rsm, ctx, s, ranks=ranks)
+    assert list(T.info().ranks) == ranks
+    idx = workloads.grid_sample_indices(23 + r1, s.n, 4000)
+    refv = ref.at(ogrid.flat_to_ijk(idx, s.n))
+    err = float(np.max(np.abs(g.cpu().numpy()[idx] - refv)) / np.max(np.abs(refv)))
+    say(f"  sampled rel-Linf {err:.2e}")
+    assert err <= TOL
+
+
 def test_cfg2_sampled_parity(rsm, ctx):
     s = workloads.cfg2_lattice()
     say("cfg2 sampled")

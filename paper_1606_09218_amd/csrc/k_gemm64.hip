@@ -625,7 +625,11 @@ static Plan64 plan_for(const Gemm64& g, CfgId cfg, int num_cu) {
   P.splits = 1;
   if (tiles < target && g.K > 2 * KALIGN) {
     int64_t want = (target + tiles - 1) / tiles;
-    int64_t maxs = g.K / (2 * KALIGN);  // at least 64 k per split
+    // at least 2 KALIGN k per split for the symmetric products and small
+    // outputs; at least 128 for large outputs, whose reduction pass (a full
+    // read and write of the output per split) outweighs the shorter k loop
+    const bool small_out = g.M * g.N * g.batch <= ((int64_t)1 << 17);
+    int64_t maxs = (g.upper_only || small_out) ? g.K / (2 * KALIGN) : g.K / 128;
     // a small symmetric output (p x p Rayleigh-Ritz or Cholesky QR Grams): at
     // most ~2^20 partial values, which the fixed-order reduction reads back
     const int64_t cap = g.upper_only

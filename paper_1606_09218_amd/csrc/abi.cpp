@@ -591,6 +591,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
         subspace ? std::max({sketch64_workspace_bytes(n, K, 3, p, ncu),
                              gemm64_workspace_bytes(zq_shape, ncu),
                              gemm64_workspace_bytes(bz_shape, ncu),
+                             gram_stream_workspace_bytes(p, K, 3, ncu),
                              P.power_iters > 0 ? gemm64_workspace_bytes(uwz_shape, ncu) : (size_t)0,
                              gemm64_workspace_bytes(yty_shape, ncu)})
                  : 0;
@@ -693,7 +694,9 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       }
       // Rayleigh-Ritz matrix B = Q0^T G Q0 = Z^T diag(w) Z, Z = U^T Q0
       gemm64(zq_gemm(Q0.as<double>()), ncu, wk_eig.as<double>(), s);
-      gemm64(bz_gemm(), ncu, wk_eig.as<double>(), s);
+      if (!gram_stream(Zk.as<double>(), K * p, w.as<double>(), p, K, 3, Bm.as<double>(), ncu,
+                       wk_eig.as<double>(), s))
+        gemm64(bz_gemm(), ncu, wk_eig.as<double>(), s);
     }
     // eigenvectors are formed only for the rc columns the rank rule can keep
     Span ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));

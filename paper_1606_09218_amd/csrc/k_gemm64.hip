@@ -748,7 +748,8 @@ __global__ __launch_bounds__(512) void core_stream_kernel(const double* __restri
                                                           const double* __restrict__ U3t, int r1,
                                                           int r2, int r3, int64_t K,
                                                           int64_t kchunk, double* __restrict__ out,
-                                                          int64_t split_stride) {
+                                                          int64_t split_stride, int64_t sb1,
+                                                          int64_t sbs, int64_t sb3) {
   constexpr int KC = CS_KC, NP = CS_NP, AR = 16 * RB;
   constexpr int LDA = AR + ((RB & 1) ? 0 : 16);   // row starts 32 banks apart per q
   constexpr int AV = (KC * AR + 511) / 512;
@@ -758,6 +759,11 @@ __global__ __launch_bounds__(512) void core_stream_kernel(const double* __restri
   const int r = lane & 15, q = lane >> 4;
   const int W = r2 * r3;
   const int col = blockIdx.x * 128 + wave * 16 + r;
+  // batch blockIdx.y: its factors at the given strides, its splits after the
+  // previous batch's
+  U1t += (int64_t)blockIdx.y * sb1;
+  s2 += (int64_t)blockIdx.y * sbs;
+  U3t += (int64_t)blockIdx.y * sb3;
   const bool colok = col < W;
   const int b = colok ? col / r3 : 0, c = colok ? col - b * r3 : 0;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(512) void core_stream_kernel(const double* __restri
     }
   }
   // acc[i][v] is beta_(1)[16 i + q + 4 v][col]
-  double* o = out + (int64_t)blockIdx.z * split_stride;
+  double* o = out + ((int64_t)blockIdx.y * gridDim.z + blockIdx.z) * split_stride;
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -891,7 +897,7 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
         RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
       hipLaunchKernelGGL(fn, grid, dim3(512), lds, s, U1t, (const double*)s2, U3t, r1, r2, r3, K,
-                         kchunk, outp, (int64_t)r1 * W);
+                         kchunk, outp, (int64_t)r1 * W, (int64_t)0, (int64_t)0, (int64_t)0);
     };
     if (rb == 2) launch(core_stream_kernel<2>, 2);
     else if (rb == 4) launch(core_stream_kernel<4>, 4);
@@ -924,6 +930,72 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
                        d.splits, total, beta);
   }
 }
+
+// ---- tall Gram, streaming form --------------------------------------------------
+// C[b] = Z[b]^T diag(w) Z[b] (p x p, p <= 128) for Z[b] K x p row-major: the
+// streaming core with r1 = r3 = p, r2 = 1 (its scaled factor is w itself),
+// K split over the workgroups of all batches; the splits are summed in a
+// fixed order for the upper triangle, which is written to both triangles
+// (C exactly symmetric).
+__global__ void gram_sym_reduce_kernel(const double* __restrict__ part, int splits, int p,
+                                       int batch, double* __restrict__ C) {
+  const int64_t pp = (int64_t)p * p, total = (int64_t)batch * pp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / pp, rem = e - b * pp;
+    const int i = (int)(rem / p), j = (int)(rem - (int64_t)i * p);
+    if (j < i) continue;
+    const double* src = part + b * splits * pp + rem;
+    double v = 0.0;
+    for (int z = 0; z < splits; ++z) v += src[z * pp];
+    C[b * pp + (int64_t)i * p + j] = v;
+    C[b * pp + (int64_t)j * p + i] = v;
+  }
+}
+
+static void plan_gram_stream(int64_t K, int batch, int num_cu, int& splits, int64_t& kchunk) {
+  splits = (int)std::max<int64_t>(1, std::min<int64_t>(num_cu / std::max(1, batch),
+                                                        (K + CS_KC - 1) / CS_KC));
+  kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + CS_KC - 1) / CS_KC * CS_KC;
+  splits = (int)((K + kchunk - 1) / kchunk);
+}
+
+size_t gram_stream_workspace_bytes(int p, int64_t K, int batch, int num_cu) {
+  if (p > 128 || p <= 0 || K <= 0) return 0;
+  int splits;
+  int64_t kchunk;
+  plan_gram_stream(K, batch, num_cu, splits, kchunk);
+  return (size_t)batch * splits * p * p * sizeof(double);
+}
+
+bool gram_stream(const double* Z, int64_t zstride, const double* w, int p, int64_t K, int batch,
+                 double* C, int num_cu, double* work, hipStream_t s) {
+  if (p > 128 || p <= 0 || K <= 0 || batch <= 0) return false;
+  int splits;
+  int64_t kchunk;
+  plan_gram_stream(K, batch, num_cu, splits, kchunk);
+  const dim3 grid((unsigned)((p + 127) / 128), (unsigned)batch, (unsigned)splits);
+  auto launch = [&](auto fn, int RBv) {
+    const size_t lds = (size_t)CS_KC * (16 * RBv + ((RBv & 1) ? 0 : 16)) * sizeof(double);
+    if (lds > 48 * 1024)
+      RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(fn, grid, dim3(512), lds, s, Z, w, Z, p, 1, p, K, kchunk, work,
+                       (int64_t)p * p, zstride, (int64_t)0, zstride);
+  };
+  const int rb = core_stream_rb(p);
+  if (rb == 2) launch(core_stream_kernel<2>, 2);
+  else if (rb == 4) launch(core_stream_kernel<4>, 4);
+  else if (rb == 6) launch(core_stream_kernel<6>, 6);
+  else launch(core_stream_kernel<8>, 8);
+  const int64_t total = (int64_t)batch * p * p;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(gram_sym_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)work,
+                     splits, p, batch, C);
+  return true;
+}
+
 
 // the sketch takes the big tile when both M and the subspace size N fill it
 static CfgId sketch_cfg(int64_t M, int64_t N) { return (M >= 256 && N >= 128) ? CFG_BIG : CFG_SMALL; }

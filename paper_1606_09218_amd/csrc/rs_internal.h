@@ -252,6 +252,11 @@ void launch_gather_cols3(const double* Z, int ldz, int64_t zstride, const int* p
                          const Mode3& Wr, hipStream_t s);
 void launch_canonical_signs3(const Mode3& Q, int64_t n, const Mode3& W, int64_t m, hipStream_t s);
 
+// k_gemm64.hip : C[b] = Z[b]^T diag(w) Z[b] for Z[b] K x p row-major at stride zstride, p <= 128
+// (false otherwise: nothing launched); C exactly symmetric, p x p per batch.
+size_t gram_stream_workspace_bytes(int p, int64_t K, int batch, int num_cu);
+bool gram_stream(const double* Z, int64_t zstride, const double* w, int p, int64_t K, int batch,
+                 double* C, int num_cu, double* work, hipStream_t s);
 // k_core.hip : beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
 void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi,

@@ -49,12 +49,10 @@ struct SplitF16 {
   __device__ static f4 mfma(V8 a, V8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
-  // level 0: hi*hi; level 1: hi*lo + lo*hi (weight 2^-11)
-  __device__ static void products(const V8 (&a)[TERMS], const V8 (&b)[TERMS], f4 (&acc)[LEVELS]) {
-    acc[0] = mfma(a[0], b[0], acc[0]);
-    acc[1] = mfma(a[0], b[1], acc[1]);
-    acc[1] = mfma(a[1], b[0], acc[1]);
-  }
+  // level 0: hi*hi; level 1: hi*lo + lo*hi (weight 2^-11).  Product p is
+  // a[PA[p]] b[PB[p]] into level PL[p], in this order within a level.
+  static constexpr int NPROD = 3;
+  static constexpr int PA[NPROD] = {0, 0, 1}, PB[NPROD] = {0, 1, 0}, PL[NPROD] = {0, 1, 1};
   __device__ static double combine(const f4 (&acc)[LEVELS], int v) {
     return (double)acc[0][v] + (double)acc[1][v] * (1.0 / 2048.0);
   }
@@ -86,14 +84,10 @@ struct SplitBF16 {
   __device__ static f4 mfma(V8 a, V8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
-  __device__ static void products(const V8 (&a)[TERMS], const V8 (&b)[TERMS], f4 (&acc)[LEVELS]) {
-    acc[0] = mfma(a[0], b[0], acc[0]);
-    acc[1] = mfma(a[0], b[1], acc[1]);
-    acc[1] = mfma(a[1], b[0], acc[1]);
-    acc[2] = mfma(a[0], b[2], acc[2]);
-    acc[2] = mfma(a[2], b[0], acc[2]);
-    acc[2] = mfma(a[1], b[1], acc[2]);
-  }
+  // level 0: hi*hi; level 1: hi*mid + mid*hi; level 2: hi*lo + lo*hi + mid*mid
+  static constexpr int NPROD = 6;
+  static constexpr int PA[NPROD] = {0, 0, 1, 0, 2, 1}, PB[NPROD] = {0, 1, 0, 2, 0, 1},
+                       PL[NPROD] = {0, 1, 1, 2, 2, 2};
   __device__ static double combine(const f4 (&acc)[LEVELS], int v) {
     return (double)acc[0][v] + (double)acc[1][v] + (double)acc[2][v];
   }
@@ -232,7 +226,9 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
 #pragma unroll
         for (int term = 0; term < SP::TERMS; ++term)
           b[term] = *(const V8*)(Bs + (size_t)(term * BN + j * 16 + (lane & 15)) * ks + 32 * kb + kofs);
-        SP::products(a, b, acc[j]);
+#pragma unroll
+        for (int pi = 0; pi < SP::NPROD; ++pi)
+          acc[j][SP::PL[pi]] = SP::mfma(a[SP::PA[pi]], b[SP::PB[pi]], acc[j][SP::PL[pi]]);
       }
       if (FOLD) {
         since += 32;
@@ -425,10 +421,16 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
         bf[j][term] = *(const V8*)(&Bs[term][wn * (16 * FN) + j * 16 + frow][fk]);
+    // products in the outer loop: the MFMAs that accumulate into one level
+    // of one block are 2 FN instructions apart
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int pi = 0; pi < SP::NPROD; ++pi)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) SP::products(af[i], bf[j], acc[i][j]);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j][SP::PL[pi]] =
+              SP::mfma(af[i][SP::PA[pi]], bf[j][SP::PB[pi]], acc[i][j][SP::PL[pi]]);
     since += 32;
     if (since >= KCHUNK || !more) {
 #pragma unroll

@@ -41,21 +41,23 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
 // so the stores are fully coalesced.  grid.y = mode.
 __global__ void side_matrix_kernel(const double* __restrict__ pos, const double* __restrict__ t,
                                    int64_t N, int R_l, int64_t n, double b, double* __restrict__ U) {
+  // one column j = k N + nu per workgroup step (its index arithmetic done
+  // once), the threads over the n grid points of the column (coalesced)
   const int l = blockIdx.y;
   const int64_t K = N * R_l;
-  const int64_t total = n * K;
   const double h = 2.0 * b / (double)n;
-  double* Ul = U + (int64_t)l * total;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t j = e / n;
-    int64_t i = e - j * n;
-    int64_t k = j / N;
-    int64_t nu = j - k * N;
-    double xi = -b + ((double)i + 0.5) * h;
-    double d = xi - pos[3 * nu + l];
-    double tk = t[k];
-    Ul[e] = exp(-(tk * tk) * (d * d));
+  double* Ul = U + (int64_t)l * n * K;
+  for (int64_t j = blockIdx.x; j < K; j += gridDim.x) {
+    const int64_t k = j / N;
+    const int64_t nu = j - k * N;
+    const double x = pos[3 * nu + l];
+    const double tk = t[k];
+    double* col = Ul + j * n;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const double xi = -b + ((double)i + 0.5) * h;
+      const double d = xi - x;
+      col[i] = exp(-(tk * tk) * (d * d));
+    }
   }
 }
 
@@ -75,13 +77,12 @@ __global__ void weights_kernel(const double* __restrict__ q, const double* __res
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
                           double* w, double* sw, hipStream_t s) {
-  const int64_t total = n * N * R_l;
-  int threads = 256;
-  int64_t blocks = (total + threads - 1) / threads;
-  if (blocks > 65535LL * 16) blocks = 65535LL * 16;
+  const int64_t K = N * R_l;
+  const int threads = n >= 256 ? 256 : 64;
+  const int64_t blocks = std::min<int64_t>(K, 65535LL * 16);
+  if (blocks <= 0 || n <= 0) return;
   hipLaunchKernelGGL(side_matrix_kernel, dim3((unsigned)blocks, 3), dim3(threads), 0, s, pos, t,
                      N, R_l, n, b, U);
-  int64_t K = N * R_l;
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, q, a, N,
                      R_l, xi, w, sw);
 }

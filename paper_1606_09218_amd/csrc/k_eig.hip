@@ -131,15 +131,20 @@ __global__ __launch_bounds__(EIG_THREADS) void rank_select_kernel(const double* 
   int* pm = perm + mode * p;
   if (threadIdx.x == 0) cnt_s = 0;
   __syncthreads();
-  // NaN (from invalid input, rejected by the host afterwards) orders as -inf
-  // so that perm is always a permutation of 0..p-1
+  // the diagonal staged in LDS once; NaN (from invalid input, rejected by
+  // the host afterwards) orders as -inf so that perm is always a
+  // permutation of 0..p-1
+  extern __shared__ double dg[];   // p
   for (int i = threadIdx.x; i < p; i += EIG_THREADS) {
-    double li = B[(int64_t)i * p + i];
-    if (li != li) li = -HUGE_VAL;
+    const double v = B[(int64_t)i * p + i];
+    dg[i] = v != v ? -HUGE_VAL : v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < p; i += EIG_THREADS) {
+    const double li = dg[i];
     int rank = 0;
     for (int j = 0; j < p; ++j) {
-      double lj = B[(int64_t)j * p + j];
-      if (lj != lj) lj = -HUGE_VAL;
+      const double lj = dg[j];
       if (lj > li || (lj == li && j < i)) ++rank;
     }
     pm[rank] = i;
@@ -174,8 +179,8 @@ __global__ __launch_bounds__(EIG_THREADS) void rank_select_kernel(const double* 
 
 void launch_rank_select(const double* B, int p, int modes, double eps2, const int* fixed,
                         int r_max, int* perm, RankInfo* info_dev, hipStream_t s) {
-  hipLaunchKernelGGL(rank_select_kernel, dim3(modes), dim3(EIG_THREADS), 0, s, B, p, eps2, fixed,
-                     r_max, perm, info_dev);
+  hipLaunchKernelGGL(rank_select_kernel, dim3(modes), dim3(EIG_THREADS), (size_t)p * sizeof(double),
+                     s, B, p, eps2, fixed, r_max, perm, info_dev);
 }
 
 // Wr (p x r col-major) = Z[:, perm[0..r)] for row-major Z (p x ldz); an

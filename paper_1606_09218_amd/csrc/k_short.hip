@@ -33,44 +33,60 @@ __device__ __forceinline__ void particle_window(const double* __restrict__ pos, 
   }
 }
 
-__global__ void bin_count_kernel(const double* __restrict__ pos, int64_t N, int64_t n, double b,
-                                 int w, int nb, int* __restrict__ counts) {
-  int64_t nu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (nu >= N) return;
+// bricks per axis that a window of n_s cells can meet
+__host__ __device__ inline int window_bricks(int n_s) { return (n_s + 6) / BRICK + 1; }
+
+// one thread per (particle, brick of its window): the brick at offset
+// (d0, d1, d2) from the window's first brick, if the window reaches it
+__device__ __forceinline__ bool pair_brick(const double* __restrict__ pos, int64_t t, int64_t N,
+                                           int64_t n, double b, int w, int per, int nb,
+                                           int64_t& nu, int64_t& br) {
+  const int64_t ppp = (int64_t)per * per * per;
+  if (t >= N * ppp) return false;
+  nu = t / ppp;
+  const int sl = (int)(t - nu * ppp);
+  const int d0 = sl / (per * per), d1 = (sl / per) % per, d2 = sl % per;
   int lo[3], hi[3];
   particle_window(pos, nu, n, b, w, lo, hi);
-  for (int b0 = lo[0] / BRICK; b0 <= hi[0] / BRICK; ++b0)
-    for (int b1 = lo[1] / BRICK; b1 <= hi[1] / BRICK; ++b1)
-      for (int b2 = lo[2] / BRICK; b2 <= hi[2] / BRICK; ++b2)
-        atomicAdd(&counts[((int64_t)b0 * nb + b1) * nb + b2], 1);
+  const int b0 = lo[0] / BRICK + d0, b1 = lo[1] / BRICK + d1, b2 = lo[2] / BRICK + d2;
+  if (b0 > hi[0] / BRICK || b1 > hi[1] / BRICK || b2 > hi[2] / BRICK) return false;
+  br = ((int64_t)b0 * nb + b1) * nb + b2;
+  return true;
+}
+
+__global__ void bin_count_kernel(const double* __restrict__ pos, int64_t N, int64_t n, double b,
+                                 int w, int per, int nb, int* __restrict__ counts) {
+  int64_t nu, br;
+  if (pair_brick(pos, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, N, n, b, w, per, nb, nu, br))
+    atomicAdd(&counts[br], 1);
 }
 
 void short_bin_count(const double* pos, int64_t N, int64_t n, double b, int n_s, int nb,
                      int* counts, hipStream_t s) {
-  hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, pos, N,
-                     n, b, (n_s - 1) / 2, nb, counts);
+  const int per = window_bricks(n_s);
+  const int64_t pairs = N * per * per * per;
+  if (pairs <= 0) return;
+  hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, pos,
+                     N, n, b, (n_s - 1) / 2, per, nb, counts);
 }
 
 __global__ void bin_fill_kernel(const double* __restrict__ pos, int64_t N, int64_t n, double b,
-                                int w, int nb, const int* __restrict__ start,
+                                int w, int per, int nb, const int* __restrict__ start,
                                 int* __restrict__ cursor, int* __restrict__ list) {
-  int64_t nu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (nu >= N) return;
-  int lo[3], hi[3];
-  particle_window(pos, nu, n, b, w, lo, hi);
-  for (int b0 = lo[0] / BRICK; b0 <= hi[0] / BRICK; ++b0)
-    for (int b1 = lo[1] / BRICK; b1 <= hi[1] / BRICK; ++b1)
-      for (int b2 = lo[2] / BRICK; b2 <= hi[2] / BRICK; ++b2) {
-        int64_t br = ((int64_t)b0 * nb + b1) * nb + b2;
-        int slot = atomicAdd(&cursor[br], 1);
-        list[start[br] + slot] = (int)nu;
-      }
+  int64_t nu, br;
+  if (pair_brick(pos, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, N, n, b, w, per, nb, nu, br)) {
+    const int slot = atomicAdd(&cursor[br], 1);
+    list[start[br] + slot] = (int)nu;
+  }
 }
 
 void short_bin_fill(const double* pos, int64_t N, int64_t n, double b, int n_s, int nb,
                     const int* start, int* cursor, int* list, hipStream_t s) {
-  hipLaunchKernelGGL(bin_fill_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, pos, N,
-                     n, b, (n_s - 1) / 2, nb, start, cursor, list);
+  const int per = window_bricks(n_s);
+  const int64_t pairs = N * per * per * per;
+  if (pairs <= 0) return;
+  hipLaunchKernelGGL(bin_fill_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, pos,
+                     N, n, b, (n_s - 1) / 2, per, nb, start, cursor, list);
 }
 
 // insertion sort of each brick's (short) list, making the visiting order
@@ -80,13 +96,19 @@ void short_bin_fill(const double* pos, int64_t N, int64_t n, double b, int n_s, 
 // gathered by one workgroup from its sorted list.
 __global__ void bin_sort_kernel(const int* __restrict__ start, int* __restrict__ list,
                                 int nbricks, int* __restrict__ active, int64_t active_cap) {
-  int br = blockIdx.x * blockDim.x + threadIdx.x;
-  if (br >= nbricks) return;
-  int s0 = start[br], s1 = start[br + 1];
+  const int br = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s0 = br < nbricks ? start[br] : 0, s1 = br < nbricks ? start[br + 1] : 0;
+  // slots in the active list: one atomic per wave for its touched bricks
+  const unsigned long long m = __ballot(s1 > s0);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0 && m) base = atomicAdd(&active[0], __popcll(m));
+  base = __shfl(base, 0);
   if (s1 > s0) {
-    const int slot = atomicAdd(&active[0], 1);
+    const int slot = base + __popcll(m & ((1ULL << lane) - 1ULL));
     if (slot < active_cap) active[1 + slot] = br;  // the capacity bounds every window
   }
+  if (br >= nbricks) return;
   for (int i = s0 + 1; i < s1; ++i) {
     int v = list[i];
     int j = i - 1;
@@ -100,7 +122,7 @@ __global__ void bin_sort_kernel(const int* __restrict__ start, int* __restrict__
 
 int64_t short_active_capacity(int64_t N, int n_s, int nb) {
   // a window of n_s cells meets at most (n_s + 6) / 8 + 1 bricks per axis
-  const int64_t per = (n_s + 6) / BRICK + 1;
+  const int64_t per = window_bricks(n_s);
   const int64_t nbricks = (int64_t)nb * nb * nb;
   return std::min<int64_t>(nbricks, std::max<int64_t>(N, 0) * per * per * per);
 }

@@ -727,7 +727,11 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
         launch_trsm_rows(Z.as<double>(), Cz.as<double>(), p, rc, 3, ctx->lds_limit, s);
       }
     };
-    orth_z(2, false, 4);
+    // one plain pass: the kept vectors are nearly orthonormal already (their
+    // Gram is close to the identity), and Cholesky QR is causal, so the
+    // leading columns come out orthonormal to rounding whatever the trailing
+    // (unkept, clustered) ones do; a breakdown still flags the robust redo
+    orth_z(1, false, 4);
     launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
     mark_eig(T.get(), 4, s);
     Span perm = piece(o_perm, (size_t)3 * p * sizeof(int));

@@ -281,3 +281,26 @@ def test_timing_modes(rsm, ctx):
             c2.set_timing(3)
     finally:
         c2.set_timing(0)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg1", "mid"])
+def test_basis_orthonormal(rsm, ctx, name):
+    """The exported Tucker bases V_l have orthonormal columns to 1e-12 (the
+    lattice workload has degenerate eigenvalues, the mid case a subspace
+    above 128)."""
+    if name == "cfg2":
+        s, r_max = workloads.cfg2_lattice(), 112
+    elif name == "cfg1":
+        s, r_max = workloads.cfg1_plain_small(), 128
+    else:
+        s, r_max = workloads.tiny_system(81, 90, 8.0, 192, 24, 10, 9, min_sep=0.5), 160
+    f, T, _ = run_gpu(rsm, ctx, s, with_grid=False, r_max=r_max)
+    r = list(T.info().ranks)
+    Vs = [torch.empty(s.n * rl, dtype=torch.float64, device="cuda") for rl in r]
+    rsm.tensor_export(T, *Vs)
+    worst = 0.0
+    for V, rl in zip(Vs, r):
+        Vh = V.cpu().numpy().reshape(s.n, rl)
+        worst = max(worst, float(np.max(np.abs(Vh.T @ Vh - np.eye(rl)))))
+    say(f"basis {name}: ranks {r} max |V^T V - I| {worst:.2e}")
+    assert worst <= 1e-12

@@ -672,7 +672,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       // (each shifted pass maps cond(Y) to about sqrt(shift)/sigma_min(Y)),
       // then two plain passes
       auto orth = [&](double* Yp) {
-        for (int pass = 0; pass < 4; ++pass) {
+        for (int pass = 0; pass < 3; ++pass) {
           gemm64(yty_gemm(Yp), ncu, wk_eig.as<double>(), s);
           launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, 1, s);
           launch_trsm_rows(Yp, Cq.as<double>(), n, p, 3, ctx->lds_limit, s);

@@ -283,18 +283,23 @@ def test_timing_modes(rsm, ctx):
         c2.set_timing(0)
 
 
-@pytest.mark.parametrize("name", ["cfg2", "cfg1", "mid"])
+@pytest.mark.parametrize("name", ["cfg2", "cfg1", "mid", "cfg3", "cfg4"])
 def test_basis_orthonormal(rsm, ctx, name):
     """The exported Tucker bases V_l have orthonormal columns to 1e-12 (the
     lattice workload has degenerate eigenvalues, the mid case a subspace
-    above 128)."""
+    above 128, cfg3 n = 1024 with a subspace of 416, cfg4 two kernels)."""
     if name == "cfg2":
         s, r_max = workloads.cfg2_lattice(), 112
     elif name == "cfg1":
         s, r_max = workloads.cfg1_plain_small(), 128
+    elif name == "cfg3":
+        s, r_max = workloads.cfg3_protein_like(), 400
+    elif name == "cfg4":
+        s, r_max = workloads.cfg4_forces(), 256
     else:
         s, r_max = workloads.tiny_system(81, 90, 8.0, 192, 24, 10, 9, min_sep=0.5), 160
-    f, T, _ = run_gpu(rsm, ctx, s, with_grid=False, r_max=r_max)
+    f, T, _ = run_gpu(rsm, ctx, s, with_grid=False, r_max=r_max,
+                      n_s=-1 if s.n_s is None else s.n_s)
     r = list(T.info().ranks)
     Vs = [torch.empty(s.n * rl, dtype=torch.float64, device="cuda") for rl in r]
     rsm.tensor_export(T, *Vs)

@@ -126,7 +126,7 @@ def test_window_excludes_only_small_short_terms(R, R_l, b, n):
         assert worst2 > delta
 
 
-def test_survey_window_values():
+def test_window_values_of_the_workloads():
     # the configs' stated and derived windows (criterion (A), delta = 1e-4 S(0))
     t, a = Q.literal_table("newton", 20)
     assert Q.derive_window(t, a, 8, 1e-4, 20 / 128) == 9

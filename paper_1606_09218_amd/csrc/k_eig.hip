@@ -278,6 +278,8 @@ __global__ void canonical_signs3_kernel(Mode3 q, int64_t n, Mode3 w, int64_t m) 
   const int lane = threadIdx.x;
   double best = -1.0;
   int64_t bi = 0;
+  // unrolled: the strided loads of a lane are issued together
+#pragma unroll 8
   for (int64_t i = lane; i < n; i += 64) {
     double v = fabs(Q[i * r + col]);
     if (v > best) {
@@ -295,6 +297,7 @@ __global__ void canonical_signs3_kernel(Mode3 q, int64_t n, Mode3 w, int64_t m) 
   }
   const bool flip = Q[bi * r + col] < 0.0;
   if (flip) {
+#pragma unroll 8
     for (int64_t i = lane; i < n; i += 64) Q[i * r + col] = -Q[i * r + col];
     if (W)
       for (int64_t i = lane; i < m; i += 64) W[col * m + i] = -W[col * m + i];

@@ -111,11 +111,18 @@ def cpu_baseline_child(workload_name: str):
     the HIP runtime; returns its result (or the child's error)."""
     import subprocess
     print("cpu baseline: oracle sample in a child process", file=sys.stderr, flush=True)
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
-                        "--workload", workload_name], capture_output=True, text=True, timeout=900)
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                            "--workload", workload_name], capture_output=True, text=True,
+                           timeout=900)
+    except subprocess.TimeoutExpired:
+        return {"error": "oracle child did not finish within 900 s"}
     if r.returncode != 0 or not r.stdout.strip():
         return {"error": f"oracle child exited with status {r.returncode}: {r.stderr[-400:]}"}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    try:
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except ValueError:
+        return {"error": "oracle child printed no result line"}
 
 
 def timed_steps(step, steps, stream, starts=None, ends=None):

@@ -2,14 +2,17 @@
 """Benchmark of the RS canonical/Tucker potential path on one MI355X.
 
 One step = one RS assembly of the workload's particle system: side matrices,
-charge-weighted Gram GEMMs, eigensolve and rank rule, projection, core,
-short-range windows and the full n^3 grid, followed by the interaction
-energy and the forces.  Inputs (positions, charges, quadrature table) are
-resident on the device before the timed region.  Prints one JSON line.
+eigensolve and rank rule, projection, core, short-range windows and the full
+n^3 grid, followed by the interaction energy and the forces.  Inputs
+(positions, charges, quadrature table) are resident on the device before the
+timed region.  Prints one JSON line.
 
-Default workload: 10x10x10 lattice, spacing 1.0, 100 vacancies, jitter
-N(0, 0.05^2), alternating +-1 charges (N = 900); box [-12,12]^3, n = 512,
-R = 24, R_l = 10, n_s = 17, Tucker tolerance 1e-6, FP64.
+Default workload: the protein-like cloud, N = 10000 charges in 40 Gaussian
+blobs (sigma 2) inside [-25,25]^3, n = 1024, R = 32, R_l = 12, window by
+criterion (A), Tucker tolerance 1e-6.  The step runs in FP64 and with
+split-FP16 and split-BF16 contractions; `value` is the fastest split
+precision whose grid and energy are within rel-Linf 1e-5 of the FP64 GPU
+result of the same input (the FP64 rate stands beside it).
 """
 from __future__ import annotations
 
@@ -24,12 +27,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "RS assemblies/sec at rel-L∞≤1e-5 vs plain FP64 on GPU; p50/p99 latency"
+GATE = 1e-5
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
+PRODUCTS = {"fp64": 1, "mixed_fp16": 3, "mixed_bf16": 6}   # MFMA products per split multiply
+DTYPE = {"fp64": "f64", "mixed_fp16": "fp16", "mixed_bf16": "bf16"}
+PRECISION = {
+    "fp64": "FP64 throughout",
+    "mixed_fp16": ("core and grid expansion in split FP16 (hi + lo 2^-11, 3 MFMA products) with "
+                   "FP32 accumulation and FP64 sums per 256 k; quadrature, eigensolve, projection "
+                   "and energy reduction FP64; FP32 grid"),
+    "mixed_bf16": ("core and grid expansion in split BF16 (3 terms, 6 MFMA products) with FP32 "
+                   "accumulation and FP64 sums per 256 k; quadrature, eigensolve, projection and "
+                   "energy reduction FP64; FP32 grid"),
+}
 
 
 def workload(name: str):
+    """(system, config dict, r_max) of a named workload."""
     import workloads
+    if name == "cfg3":
+        s = workloads.cfg3_protein_like()
+        cfg = {"workload": "protein_blobs40_N10000_n1024_R32_Rl12_nsA", "N": s.N, "n": s.n,
+               "b": s.b, "R": s.R, "R_l": s.R_l, "n_s": "criterion (A), delta 1e-4",
+               "eps_tucker": s.eps_tucker, "kernel": s.kernel, "r_max": 400}
+        return s, cfg, 400
     if name == "cfg2":
         s = workloads.cfg2_lattice()
         cfg = {"workload": "lattice10^3_vac100_N900_n512_R24_Rl10_ns17",
@@ -42,67 +64,101 @@ def workload(name: str):
                "R_l": s.R_l, "n_s": s.n_s, "eps_tucker": s.eps_tucker, "kernel": s.kernel,
                "r_max": 128}
         return s, cfg, 128
+    if name == "cfg4":
+        s = workloads.cfg4_forces()
+        cfg = {"workload": "uniform4096_neutral_n512_R28_Rl11_newton+yukawa", "N": s.N, "n": s.n,
+               "b": s.b, "R": s.R, "R_l": s.R_l, "n_s": "criterion (A), delta 1e-4",
+               "eps_tucker": s.eps_tucker, "kernel": s.kernel, "r_max": 256}
+        return s, cfg, 256
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the source file of the FP64 GEMM kernels: traffic counters
-    taken on another version of it are stale."""
+def kernel_source_hash(files) -> str:
+    """Hash of the kernel source files: traffic counters taken on another
+    version of them are stale."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1606_09218_amd", "csrc")
-    for f in ("k_gemm64.hip",):
+    for f in files:
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str, workload_tag: str):
+def traffic_from_profiles(kernel_tag: str, workload_tag: str, files):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     --pmc summaries, if they were taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload_tag}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(files):
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(s, budget_s: float = 20.0):
+def cpu_baseline(s):
     """The oracle (plain FP64 NumPy), timed on this host on a bounded sample
-    of one step: the full RS-Tucker build (side matrices, SVD of the weighted
-    side matrices, core), grid values on a few i1-planes, and energy and
-    forces for a subset of particles; scaled to one full step."""
+    of one step: side matrices, the SVD basis of one mode on every 8th of
+    its columns (scaled to K columns and three modes), the projections, the core
+    over a block of the K terms (scaled to K), grid values on one i1-plane
+    (scaled to n planes), and energy and forces for 4 particles (scaled to
+    N)."""
     import numpy as np
-    from oracle import canonical, pointeval, rs
+    from oracle import canonical, pointeval, quadrature, rhosvd, rs
     try:
         from threadpoolctl import threadpool_info
         cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count() or 1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
+    t, a = quadrature.literal_table(s.kernel, s.R, s.lam)
+    n_s = s.n_s if s.n_s is not None else quadrature.derive_window(t, a, s.R_l, s.delta_rel, s.h)
     t0 = time.perf_counter()
-    T = rs.assemble_system(s)
-    t_build = time.perf_counter() - t0
+    U = rhosvd.side_matrices(s.b, s.n, s.pos, t[:s.R_l])
+    xi = rhosvd.canonical_weights(s.q, a[:s.R_l])
+    w = rhosvd.gram_weights(xi)
+    t_side = time.perf_counter() - t0
+    K = xi.shape[0]
+    # the SVD of an n x K matrix costs about n^2 K: timed on every 8th
+    # column of one mode (all quadrature terms represented, so the rank is
+    # that of the full matrix) and scaled to K and to the three modes
+    st = 8 if K > 8 * s.n else 1
+    kb = len(range(0, K, st))
+    t0 = time.perf_counter()
+    Q0, _, r0 = rhosvd.mode_basis(U[0][:, ::st], w[::st], s.eps_tucker, s.n)
+    t_basis = (time.perf_counter() - t0) * 3 * K / kb
+    Qs = [Q0, Q0, Q0]          # the other two modes: same shape (timing only)
+    t0 = time.perf_counter()
+    Ut = [rhosvd.project(Qs[l], U[l]) for l in range(3)]
+    t_proj = time.perf_counter() - t0
+    del U
+    kc = min(K, 128)
+    t0 = time.perf_counter()
+    beta = rhosvd.core([u[:, :kc] for u in Ut], xi[:kc]) * (K / kc)
+    t_core = (time.perf_counter() - t0) * K / kc
+    T = rs.RSTucker(s.b, s.n, t, a, s.R_l, n_s, s.pos, s.q, Qs, beta, [None] * 3, [r0] * 3)
     n = s.n
-    planes = 2
     t0 = time.perf_counter()
-    for i1 in range(n // 2, n // 2 + planes):
-        long_plane = np.einsum("abc,a,jb,kc->jk", T.beta, T.Q[0][i1], T.Q[1], T.Q[2], optimize=True)
-        ii = np.stack(np.meshgrid([i1], np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
-        short_plane = canonical.short_range_at(ii, s.b, n, T.pos, T.q, T.t, T.a, T.R_l, T.n_s)
-        _ = long_plane.ravel() + short_plane
-    t_grid = (time.perf_counter() - t0) * n / planes
-    m = min(16, s.N)
+    i1 = n // 2
+    long_plane = np.einsum("abc,a,jb,kc->jk", T.beta, T.Q[0][i1], T.Q[1], T.Q[2], optimize=True)
+    short_plane = canonical.short_range_subgrid([i1], np.arange(n), np.arange(n), s.b, n, s.pos,
+                                                s.q, t, a, s.R_l, n_s)
+    _ = long_plane + short_plane[0]
+    t_grid = (time.perf_counter() - t0) * n
+    m = min(4, s.N)
     sub = rs.RSTucker(T.b, T.n, T.t, T.a, T.R_l, T.n_s, T.pos[:m], T.q[:m], T.Q, T.beta,
                       T.sigma, T.ranks)
     t0 = time.perf_counter()
     pointeval.energy(sub)
     pointeval.forces(sub)
     t_ef = (time.perf_counter() - t0) * s.N / m
-    total = t_build + t_grid + t_ef
+    total = t_side + t_basis + t_proj + t_core + t_grid + t_ef
     return {"value": 1.0 / total, "unit": "assemblies/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle RS-Tucker build of the full system ({t_build:.1f} s) + grid on "
-                       f"{planes} of {n} i1-planes (scaled x{n // planes}) + energy/forces for "
-                       f"{m} of {s.N} particles (scaled); one step = {total:.1f} s")}
+            "sample": (f"oracle FP64: side matrices {t_side:.1f} s, SVD basis on {kb} of {K} "
+                       f"(strided) columns of 1 mode (rank {r0}; scaled to K and 3 modes: {t_basis:.1f} s), "
+                       f"projections "
+                       f"{t_proj:.1f} s, core over {kc} of {K} terms "
+                       f"(scaled: {t_core:.1f} s), grid on 1 of {n} i1-planes (scaled: "
+                       f"{t_grid:.1f} s), energy/forces for {m} of {s.N} particles (scaled: "
+                       f"{t_ef:.1f} s); one step = {total:.1f} s")}
 
 
 def cpu_baseline_child(workload_name: str):
@@ -114,9 +170,9 @@ def cpu_baseline_child(workload_name: str):
     try:
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
                             "--workload", workload_name], capture_output=True, text=True,
-                           timeout=900)
+                           timeout=600)
     except subprocess.TimeoutExpired:
-        return {"error": "oracle child did not finish within 900 s"}
+        return {"error": "oracle child did not finish within 600 s"}
     if r.returncode != 0 or not r.stdout.strip():
         return {"error": f"oracle child exited with status {r.returncode}: {r.stderr[-400:]}"}
     try:
@@ -156,45 +212,99 @@ def timed_steps(step, steps, stream, starts=None, ends=None):
     return wall, stages, ranks
 
 
-def mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid64, steps, warmup, stream):
-    """The same step with split-FP16 core and grid expansion (FP32 grid):
-    throughput and its error against the FP64 GPU result of the same input."""
+def run_leg(rsm, ctx, f, pos, q, s, r_max, prec, grid, steps, warmup, stream, breakdown=True):
+    """Warm-up steps, then `steps` timed steps with events only around the
+    core's main kernel (timing mode 3) and around each step, then a few steps
+    with every stage timed (mode 1) for the breakdown.  Returns the leg's
+    numbers and the energy of its last step."""
     import numpy as np
     import torch
-    out = {}
-    E64 = torch.empty(1, dtype=torch.float64, device=grid64.device)
-    T = rsm.assemble(ctx, f, pos, q, grid64, rsm.make_aopts(s.eps_tucker, r_max=r_max), stream=stream)
-    rsm.energy(T, E64, stream=stream)
-    ranks = list(T.info().ranks)
-    T.free()
-    for prec in ("mixed_fp16", "mixed_bf16"):
-        g32 = torch.empty(s.n ** 3, dtype=torch.float32, device=grid64.device)
-        E = torch.empty(1, dtype=torch.float64, device=grid64.device)
-        F = torch.empty(3 * s.N, dtype=torch.float64, device=grid64.device)
-        # same options as the FP64 step: the eigen stage is FP64 in both paths,
-        # so ranks and subspace size agree
-        opts = rsm.make_aopts(s.eps_tucker, r_max=r_max, prec=prec)
+    E = torch.empty(1, dtype=torch.float64, device=grid.device)
+    F = torch.empty(3 * s.N, dtype=torch.float64, device=grid.device)
+    opts = rsm.make_aopts(s.eps_tucker, r_max=r_max, prec=prec)
 
-        def step():
-            T = rsm.assemble(ctx, f, pos, q, g32, opts, stream=stream)
-            rsm.energy_forces(T, E, F, 1.0, stream=stream)
-            return T
+    def step():
+        T = rsm.assemble(ctx, f, pos, q, grid, opts, stream=stream)
+        rsm.energy_forces(T, E, F, 1.0, stream=stream)
+        return T
 
-        for _ in range(warmup):
-            step().free()
-        ctx.set_timing(2)
-        wall, st, ranks_m = timed_steps(step, steps, stream)
+    ctx.set_timing(0)
+    for _ in range(warmup):
+        step().free()
+    torch.cuda.synchronize()
+    ctx.set_timing(3)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    wall, kst, ranks = timed_steps(step, steps, stream, starts, ends)
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    out = {"value": round(steps / wall, 4), "unit": "assemblies/s",
+           "ms_per_step": round(wall / steps * 1e3, 3),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "ranks": ranks,
+           "core_kernel_ms": round(float(np.mean([x["core_kernel"] for x in kst])), 4)}
+    if breakdown:
         ctx.set_timing(1)
-        _, st1, _ = timed_steps(step, min(steps, 5), stream)
-        same_ranks = ranks_m == ranks
-        err = float((g32.double() - grid64).abs().max() / grid64.abs().max())
-        e_err = abs(E.item() - E64.item()) / abs(E64.item())
-        out[prec] = {"value": round(steps / wall, 4), "unit": "assemblies/s",
-                     "ms_per_step": round(wall / steps * 1e3, 3),
-                     "grid_rel_linf_vs_fp64": err, "energy_rel_err_vs_fp64": e_err,
-                     "meets_1e-5": bool(err <= 1e-5), "same_ranks_as_fp64": same_ranks,
-                     "core_ms": round(float(np.mean([x["core"] for x in st1])), 4),
-                     "grid_ms": round(float(np.mean([x["grid"] for x in st])), 4)}
+        _, st1, _ = timed_steps(step, min(steps, 3), stream)
+        out["stage_ms"] = {k: round(float(np.mean([x[k] for x in st1])), 4)
+                           for k in st1[0] if k != "core_kernel"}
+    ctx.set_timing(0)
+    torch.cuda.synchronize()
+    return out, E.item()
+
+
+def rel_linf_chunked(a, b, chunk=1 << 26):
+    """max |a - b| / max |b| over two device vectors, in chunks (a may be FP32)."""
+    diff, ref = 0.0, 0.0
+    for c0 in range(0, b.numel(), chunk):
+        bb = b[c0:c0 + chunk]
+        diff = max(diff, (a[c0:c0 + chunk].double() - bb).abs().max().item())
+        ref = max(ref, bb.abs().max().item())
+    return diff / ref
+
+
+def core_roofline(leg, s, prec):
+    """Roofline line of the core's main kernel: algorithmic FLOP 2 r1 r2 r3 K
+    per launch over its mean duration (HIP events on the launch stream)."""
+    r1, r2, r3 = leg["ranks"]
+    K = s.N * s.R_l
+    flops = 2.0 * r1 * r2 * r3 * K
+    t = leg["core_kernel_ms"] * 1e-3
+    dt = DTYPE[prec]
+    kname = {"fp64": "rs::core_kernel<CfgRank> (FP64, r1 > 128)" if r1 > 128 else
+             "rs::core_stream_kernel (FP64)",
+             "mixed_fp16": "rs::core_tile_kernel<rs::SplitF16, WGM, 4>",
+             "mixed_bf16": "rs::core_tile_kernel<rs::SplitBF16, WGM, 2>"}[prec]
+    achieved = flops / t / 1e12
+    return {"kernel": kname + " (core beta_(1) = U~1 diag(xi) (U~2 kr U~3)^T)",
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dt],
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dt], 4),
+            "algorithmic_flops_per_launch": flops,
+            "mfma_products_per_multiply": PRODUCTS[prec],
+            "executed_mfma_tflops": round(achieved * PRODUCTS[prec], 3),
+            "avg_launch_ms": leg["core_kernel_ms"]}
+
+
+def secondary_leg(rsm, ctx, name, steps, warmup, stream):
+    """FP64 and split-FP16 rates of another workload, with the gate."""
+    import torch
+    s, cfg, r_max = workload(name)
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s if s.n_s is not None else -1, kernel=s.kernel,
+                    lam=s.lam, delta_rel=s.delta_rel)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    q = torch.tensor(s.q, dtype=torch.float64, device="cuda")
+    g64 = torch.empty(s.n ** 3, dtype=torch.float64, device="cuda")
+    g32 = torch.empty(s.n ** 3, dtype=torch.float32, device="cuda")
+    out = {"config": cfg}
+    l64, E64 = run_leg(rsm, ctx, f, pos, q, s, r_max, "fp64", g64, steps, warmup, stream)
+    out["fp64"] = l64
+    lm, Em = run_leg(rsm, ctx, f, pos, q, s, r_max, "mixed_fp16", g32, steps, warmup, stream)
+    lm["grid_rel_linf_vs_fp64"] = rel_linf_chunked(g32, g64)
+    lm["energy_rel_err_vs_fp64"] = abs(Em - E64) / abs(E64)
+    lm["meets_1e-5"] = bool(lm["grid_rel_linf_vs_fp64"] <= GATE and lm["energy_rel_err_vs_fp64"] <= GATE)
+    out["mixed_fp16"] = lm
+    del g64, g32
+    torch.cuda.empty_cache()
     return out
 
 
@@ -236,9 +346,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 leg")
+    ap.add_argument("--secondary", default="cfg2",
+                    help="another workload timed in FP64 and split FP16 ('' to skip)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving trace to replay (0: skip the serving leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -257,7 +369,6 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline_child(args.workload)
 
-    import numpy as np
     import torch
 
     import paper_1606_09218_amd as rsm
@@ -265,59 +376,34 @@ def main():
     s, cfg, r_max = workload(args.workload)
     dev = torch.device("cuda:0")
     ctx = rsm.Context(0)
-    ctx.set_timing(True)
-    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s, kernel=s.kernel, lam=s.lam,
-                    delta_rel=s.delta_rel)
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s if s.n_s is not None else -1, kernel=s.kernel,
+                    lam=s.lam, delta_rel=s.delta_rel)
+    cfg = dict(cfg, n_s=f.n_s)
     pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
     q = torch.tensor(s.q, dtype=torch.float64, device=dev)
-    grid = torch.empty(s.n ** 3, dtype=torch.float64, device=dev)
-    E = torch.empty(1, dtype=torch.float64, device=dev)
-    F = torch.empty(3 * s.N, dtype=torch.float64, device=dev)
-    opts = rsm.make_aopts(s.eps_tucker, r_max=r_max)
     stream = torch.cuda.current_stream()
+    g64 = torch.empty(s.n ** 3, dtype=torch.float64, device=dev)
+    g32 = torch.empty(s.n ** 3, dtype=torch.float32, device=dev)
 
-    def step():
-        T = rsm.assemble(ctx, f, pos, q, grid, opts, stream=stream)
-        rsm.energy_forces(T, E, F, 1.0, stream=stream)
-        return T
-
-    for _ in range(args.warmup):
-        step().free()
-    torch.cuda.synchronize()
-
-    # the timed steps carry only the two events around the grid kernel (the
-    # roofline kernel); the per-stage breakdown comes from separate steps
-    # after the timed region, so that its markers do not slow the value
-    ctx.set_timing(2)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    wall, grid_stages, ranks = timed_steps(step, args.steps, stream, starts, ends)
-    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    ctx.set_timing(1)
-    _, stages, _ = timed_steps(step, min(args.steps, 5), stream)
-
-    stage_avg = {k: float(np.mean([st[k] for st in stages])) for k in stages[0]}
-    n, r3 = s.n, ranks[2]
-    # dominant single kernel: the grid expansion (one launch), timed over the timed steps
-    grid_ms = float(np.mean([st["grid"] for st in grid_stages]))
-    t_grid = grid_ms * 1e-3
-    flops_grid = 2.0 * n ** 3 * r3
-    bytes_grid = 8.0 * (n ** 3 + n * n * r3 + n * r3)
-    achieved = flops_grid / t_grid / 1e12
-    traffic = traffic_from_profiles("grid64_stream", args.workload)
-    # the streaming grid kernel's column panel: the widest whose V3 rows fit 150 KB of LDS
-    kp = (r3 + 31) // 32 * 32
-    bn = next((b for b in (128, 64, 32) if kp * (b + 2) * 8 <= 150 * 1024), None)
-    kname = (f"rs::grid64_stream_kernel<{bn}, 16>" if bn else
-             "rs::gemm_kernel<rs::Cfg<4, 2, 2, 4, 16, 16>, false, false>")
-    roofline = {"kernel": kname + " (grid = T2 x_3 V3)",
-                "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
-                "traffic": traffic,
-                "algorithmic_flops_per_launch": flops_grid,
-                "algorithmic_bytes_per_launch": bytes_grid,
-                "achieved_hbm_GBs_algorithmic": round(bytes_grid / t_grid / 1e9, 1),
-                "avg_launch_ms": round(grid_ms, 4)}
+    print(f"bench: {cfg['workload']} FP64 leg", file=sys.stderr, flush=True)
+    legs = {}
+    legs["fp64"], E64 = run_leg(rsm, ctx, f, pos, q, s, r_max, "fp64", g64, args.steps, args.warmup,
+                                stream)
+    for prec in ("mixed_fp16",) + (() if args.no_bf16 else ("mixed_bf16",)):
+        print(f"bench: {cfg['workload']} {prec} leg", file=sys.stderr, flush=True)
+        leg, Em = run_leg(rsm, ctx, f, pos, q, s, r_max, prec, g32, args.steps, args.warmup, stream)
+        leg["grid_rel_linf_vs_fp64"] = rel_linf_chunked(g32, g64)
+        leg["energy_rel_err_vs_fp64"] = abs(Em - E64) / abs(E64)
+        leg["meets_1e-5"] = bool(leg["grid_rel_linf_vs_fp64"] <= GATE and
+                                 leg["energy_rel_err_vs_fp64"] <= GATE)
+        leg["same_ranks_as_fp64"] = leg["ranks"] == legs["fp64"]["ranks"]
+        legs[prec] = leg
+    gated = [p for p in legs if p != "fp64" and legs[p]["meets_1e-5"]]
+    head = max(gated, key=lambda p: legs[p]["value"]) if gated else "fp64"
+    hl = legs[head]
+    traffic = traffic_from_profiles(f"core_{head}", args.workload, ("k_mixed.hip", "k_gemm64.hip"))
+    roofline = dict(core_roofline(hl, s, head), traffic=traffic)
+    roofline_fp64 = core_roofline(legs["fp64"], s, "fp64")
 
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -325,30 +411,38 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
+    del g64, g32
+    torch.cuda.empty_cache()
 
-    ms_per_step = wall / args.steps * 1e3
     out = {
         "metric": METRIC,
-        "value": round(args.steps / wall, 4),
+        "value": hl["value"],
         "unit": "assemblies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": hl["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE[head],
         "data": "synthetic",
-        "config": cfg,
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "ranks": ranks,
-        "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "config": dict(cfg, precision=PRECISION[head], step="assembly + n^3 grid + energy + forces"),
+        "p50_ms": hl["p50_ms"],
+        "p99_ms": hl["p99_ms"],
+        "ranks": hl["ranks"],
+        "headline_leg": head,
+        "fp64_value": legs["fp64"]["value"],
+        "speedup_vs_fp64": round(hl["value"] / legs["fp64"]["value"], 3),
+        "legs": legs,
         "roofline": roofline,
+        "roofline_fp64_core": roofline_fp64,
     }
-    if not args.no_mixed:
-        out["mixed"] = mixed_leg(rsm, ctx, f, pos, q, s, r_max, grid, args.steps, args.warmup, stream)
+    if args.secondary:
+        print(f"bench: secondary workload {args.secondary}", file=sys.stderr, flush=True)
+        out["secondary"] = {args.secondary: secondary_leg(rsm, ctx, args.secondary, args.steps,
+                                                          args.warmup, stream)}
     if args.serve_requests > 0:
         try:
             out["serving"] = serving_leg(args.serve_requests)

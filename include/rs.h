@@ -146,7 +146,10 @@ enum {
   RS_STAGE_EXPAND2 = 8,   /* T2 = beta x_1 V1 x_2 V2 */
   RS_STAGE_GRID = 9,      /* grid = T2 x_3 V3 (one GEMM launch) */
   RS_STAGE_SHORT = 10,    /* short-range window gather into the grid */
-  RS_STAGE_COUNT = 11
+  RS_STAGE_COUNT = 11,
+  /* stage_ms[RS_STAGE_CORE_KERNEL]: the core's main contraction kernel alone,
+   * without its operand preparation and split-K sum (timing mode 3 only) */
+  RS_STAGE_CORE_KERNEL = 11
 };
 
 /* Phases of the eigen stage reported in rs_info.eig_phase_ms. */
@@ -169,7 +172,8 @@ void rs_ctx_destroy(rs_ctx* ctx);
 /* HIP-event timing of later assemblies made with this context, reported in
  * rs_info.stage_ms and eig_phase_ms: 0 off, 1 every stage and eigensolver
  * phase, 2 the grid stage only (two events around its one kernel, so that
- * the rest of the assembly runs without markers between launches).
+ * the rest of the assembly runs without markers between launches), 3 the
+ * core's main kernel only (stage_ms[RS_STAGE_CORE_KERNEL]).
  * Errors: RS_E_INVALID for another value. */
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable);
 /* Device memory of the library's buffers comes from a per-device cache: a

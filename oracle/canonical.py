@@ -133,3 +133,31 @@ def short_range_points(points, b: float, n: int, pos, q, t, a, R_l: int, n_s: in
             s += a[k] * np.exp(-t[k] ** 2 * d2)
         out[inside] += q[nu] * s
     return out
+
+
+def short_range_subgrid(I1, I2, I3, b: float, n: int, pos, q, t, a, R_l: int, n_s: int):
+    """The short-range CCT sum_nu z_nu U_nu (as short_range_grid) on the
+    index set I1 x I2 x I3 only: each particle adds its windowed local
+    tensor at the indices of the set that fall inside its window.  Result:
+    |I1| x |I2| x |I3|."""
+    idx = [np.asarray(I, dtype=np.int64) for I in (I1, I2, I3)]
+    x = _grid.cell_centres(b, n)
+    out = np.zeros(tuple(len(I) for I in idx))
+    lo, hi = window_bounds(pos, b, n, n_s)
+    # particles whose window meets the set in every mode (a count of the set's
+    # indices inside [lo, hi] per mode, from sorted copies)
+    srt = [np.sort(I) for I in idx]
+    touches = np.ones(pos.shape[0], dtype=bool)
+    for l in range(3):
+        cnt = np.searchsorted(srt[l], hi[:, l], "right") - np.searchsorted(srt[l], lo[:, l], "left")
+        touches &= cnt > 0
+    for nu in np.nonzero(touches)[0]:
+        sel = [np.nonzero((idx[l] >= lo[nu, l]) & (idx[l] <= hi[nu, l]))[0] for l in range(3)]
+        if any(s.size == 0 for s in sel):
+            continue
+        block = np.zeros(tuple(s.size for s in sel))
+        for k in range(R_l, len(t)):
+            g = [np.exp(-t[k] ** 2 * (x[idx[l][sel[l]]] - pos[nu, l]) ** 2) for l in range(3)]
+            block += a[k] * np.einsum("i,j,k->ijk", g[0], g[1], g[2])
+        out[np.ix_(sel[0], sel[1], sel[2])] += q[nu] * block
+    return out

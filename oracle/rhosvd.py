@@ -137,3 +137,59 @@ def unfolding_singular_values(T, mode: int) -> np.ndarray:
     HOSVD of the Appendix, brute force, small n only)."""
     M = np.moveaxis(T, mode, 0).reshape(T.shape[mode], -1)
     return np.linalg.svd(M, compute_uv=False)
+
+
+def mode_basis_eigh(G, eps: float, r_max: int, fixed_rank=None):
+    """The same basis through the weighted Gram G = U diag(w) U^T (eq
+    SVD_SideMatr: the left singular vectors of U diag(w^{1/2}) are the
+    eigenvectors of G, sigma_k^2 its eigenvalues).  Used where the SVD of an
+    n x K side matrix is too slow (K ~ 1e5).  Returns (Q n x r with canonical
+    signs, singular values sqrt(max(lambda, 0)) in descending order, r)."""
+    lam, Z = np.linalg.eigh(G)
+    order = np.argsort(lam)[::-1]
+    lam, Z = lam[order], Z[:, order]
+    sigma = np.sqrt(np.maximum(lam, 0.0))
+    r = select_rank(sigma, eps, r_max) if fixed_rank is None else int(fixed_rank)
+    return canonical_signs(Z[:, :r]), sigma, r
+
+
+def core_chunked(Ut, xi, chunk: int = 512) -> np.ndarray:
+    """beta = sum_j xi_j u~1_j (x) u~2_j (x) u~3_j (eq CP_form_RHOSVD) summed
+    over consecutive blocks of j, so that the intermediate of the contraction
+    stays small for large K."""
+    K = xi.shape[0]
+    beta = np.zeros((Ut[0].shape[0], Ut[1].shape[0], Ut[2].shape[0]))
+    for j0 in range(0, K, chunk):
+        js = slice(j0, min(j0 + chunk, K))
+        beta += np.einsum("aj,bj,cj->abc", Ut[0][:, js] * xi[None, js], Ut[1][:, js],
+                          Ut[2][:, js], optimize=True)
+    return beta
+
+
+def projected_side_matrices(Q, Ut):
+    """W_l = Q_l U~_l = Q_l Q_l^T U_l (n x K): the side matrices projected on
+    the Tucker bases (the factors of the projected canonical sum)."""
+    return [Q[l] @ Ut[l] for l in range(3)]
+
+
+def tucker_subgrid_projected(Q, Ut, xi, I1, I2, I3, chunk: int = 2048, W=None) -> np.ndarray:
+    """Values of the Tucker tensor beta x_1 Q1 x_2 Q2 x_3 Q3, beta the RHOSVD
+    core of the canonical sum (xi, U), on the index set I1 x I2 x I3, through
+    the projected canonical sum
+        A(i) = sum_j xi_j (Q1 u~1_j)(i1) (Q2 u~2_j)(i2) (Q3 u~3_j)(i3)
+    (eqs CP_form_RHOSVD and Tucker_CS with the sum over j taken last), which
+    needs no core: for K ~ 1e5 and ranks ~ 300 the core itself is out of
+    reach on the CPU.  W: projected_side_matrices(Q, Ut) when already
+    formed (then Q and Ut are not read).  Result: |I1| x |I2| x |I3|."""
+    idx = [np.asarray(I, dtype=np.int64) for I in (I1, I2, I3)]
+    if W is None:
+        W = [Q[l][idx[l]] @ Ut[l] for l in range(3)]     # |I_l| x K: rows of Q_l Q_l^T U_l
+    else:
+        W = [W[l][idx[l]] for l in range(3)]
+    K = xi.shape[0]
+    out = np.zeros((len(idx[0]) * len(idx[1]), len(idx[2])))
+    for j0 in range(0, K, chunk):
+        js = slice(j0, min(j0 + chunk, K))
+        kr = (W[0][:, None, js] * W[1][None, :, js]).reshape(-1, js.stop - js.start)
+        out += (kr * xi[None, js]) @ W[2][:, js].T
+    return out.reshape(len(idx[0]), len(idx[1]), len(idx[2]))

@@ -73,7 +73,10 @@ def table_for(kernel: str, R: int, lam: float = 0.5):
 
 
 def assemble(b: float, n: int, pos, q, t, a, R_l: int, n_s: int, eps: float,
-             r_max: Optional[int] = None, fixed_ranks: Optional[Sequence[int]] = None) -> RSTucker:
+             r_max: Optional[int] = None, fixed_ranks: Optional[Sequence[int]] = None,
+             core_chunk: Optional[int] = None) -> RSTucker:
+    """core_chunk: sum the core over blocks of that many terms j
+    (rhosvd.core_chunked) instead of one contraction, for large K and ranks."""
     pos = np.asarray(pos, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     if r_max is None:
@@ -90,11 +93,11 @@ def assemble(b: float, n: int, pos, q, t, a, R_l: int, n_s: int, eps: float,
         sig.append(s)
         ranks.append(r)
     Ut = [rhosvd.project(Qs[l], U[l]) for l in range(3)]
-    beta = rhosvd.core(Ut, xi)
+    beta = rhosvd.core(Ut, xi) if core_chunk is None else rhosvd.core_chunked(Ut, xi, core_chunk)
     return RSTucker(b, n, np.asarray(t), np.asarray(a), R_l, n_s, pos, q, Qs, beta, sig, ranks)
 
 
-def assemble_system(sys, fixed_ranks=None, r_max=None, n_s=None) -> RSTucker:
+def assemble_system(sys, fixed_ranks=None, r_max=None, n_s=None, core_chunk=None) -> RSTucker:
     """Assemble a workloads.System with the paper-literal table; the window
     width is the system's, or derived by criterion (A) when it gives none."""
     t, a = quadrature.literal_table(sys.kernel, sys.R, sys.lam)
@@ -103,4 +106,4 @@ def assemble_system(sys, fixed_ranks=None, r_max=None, n_s=None) -> RSTucker:
     if n_s is None:
         n_s = quadrature.derive_window(t, a, sys.R_l, sys.delta_rel, grid.spacing(sys.b, sys.n))
     return assemble(sys.b, sys.n, sys.pos, sys.q, t, a, sys.R_l, n_s, sys.eps_tucker,
-                    r_max=r_max, fixed_ranks=fixed_ranks)
+                    r_max=r_max, fixed_ranks=fixed_ranks, core_chunk=core_chunk)

@@ -58,7 +58,7 @@ class rs_info(C.Structure):
 
 EIG_PHASES = ("eig_subspace", "eig_tridiag", "eig_values_vectors", "eig_orth_backtransform")
 STAGES = ("factors", "gram", "eigen", "bins", "basis", "project", "core", "expand1",
-          "expand2", "grid", "short")
+          "expand2", "grid", "short", "core_kernel")
 
 
 def _load():
@@ -148,7 +148,7 @@ class Context:
 
     def set_timing(self, enable=True):
         """HIP-event timing of later assemblies: False/0 off, True/1 every
-        stage, 2 the grid stage only (rs_ctx_set_timing)."""
+        stage, 2 the grid stage only, 3 the core kernel only (rs_ctx_set_timing)."""
         mode = int(enable) if not isinstance(enable, bool) else int(enable)
         _check(lib.rs_ctx_set_timing(self.handle, mode))
 

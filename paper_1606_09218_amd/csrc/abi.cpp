@@ -218,6 +218,9 @@ static void mark(rs_tensor* T, int stage, hipStream_t s) {
   if (T->timing_mode == 2 && stage != RS_STAGE_GRID && stage != RS_STAGE_SHORT &&
       stage != RS_STAGE_COUNT)
     return;
+  // core-kernel timing records the two events around that launch (inside the
+  // core launchers) and the end of the assembly
+  if (T->timing_mode == 3 && stage != RS_STAGE_COUNT) return;
   RS_HIP(hipEventRecord(T->events[stage], s));
   T->recorded |= 1u << stage;
 }
@@ -442,7 +445,7 @@ rs_status rs_ctx_trim(rs_ctx* ctx) {
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(ctx != nullptr, "null context");
-    RS_REQUIRE(enable >= 0 && enable <= 2, "timing mode must be 0, 1 or 2");
+    RS_REQUIRE(enable >= 0 && enable <= 3, "timing mode must be 0, 1, 2 or 3");
     ctx->timing = enable;
     return RS_OK;
   });
@@ -540,6 +543,10 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       if (ctx->timing == 1) {
         T->eig_events.assign(RS_EIG_PHASES + 1, nullptr);
         for (auto& e : T->eig_events) RS_HIP(hipEventCreate(&e));
+      }
+      if (ctx->timing == 3) {
+        RS_HIP(hipEventCreate(&T->kevents.begin));
+        RS_HIP(hipEventCreate(&T->kevents.end));
       }
     }
 
@@ -879,12 +886,13 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       gemm64(gp[l], ncu, at(o_wkp[l]), s);
     }
     mark(T.get(), RS_STAGE_CORE, s);
+    const KernelTimer* kt = T->kevents.begin ? &T->kevents : nullptr;
     if (P.prec == RS_FP64) {
       core64(at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
-             T->beta.as<double>(), ncu, at(o_core), s);
+             T->beta.as<double>(), ncu, at(o_core), s, kt);
     } else {
       core_mixed(P.prec, at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
-                 T->beta.as<double>(), ncu, at(o_core), s);
+                 T->beta.as<double>(), ncu, at(o_core), s, kt);
     }
 
     // (a7) T2 and the grid
@@ -1062,6 +1070,11 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
         float ms = 0.f;
         RS_HIP(hipEventElapsedTime(&ms, T->events[k], T->events[j]));
         I.stage_ms[k] = ms;
+      }
+      if (T->kevents.begin) {
+        float ms = 0.f;
+        RS_HIP(hipEventElapsedTime(&ms, T->kevents.begin, T->kevents.end));
+        I.stage_ms[RS_STAGE_CORE_KERNEL] = ms;
       }
     }
     *info = I;

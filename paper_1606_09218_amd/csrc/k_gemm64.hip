@@ -870,7 +870,8 @@ size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu) {
 }
 
 void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi, int r1,
-            int r2, int r3, int64_t K, double* beta, int num_cu, double* work, hipStream_t s) {
+            int r2, int r3, int64_t K, double* beta, int num_cu, double* work, hipStream_t s,
+            const KernelTimer* kt) {
   CoreDev d;
   bool rank_tile;
   int tm;
@@ -896,8 +897,10 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
       if (lds > 48 * 1024)
         RS_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
+      if (kt) RS_HIP(hipEventRecord(kt->begin, s));
       hipLaunchKernelGGL(fn, grid, dim3(512), lds, s, U1t, (const double*)s2, U3t, r1, r2, r3, K,
                          kchunk, outp, (int64_t)r1 * W, (int64_t)0, (int64_t)0, (int64_t)0);
+      if (kt) RS_HIP(hipEventRecord(kt->end, s));
     };
     if (rb == 2) launch(core_stream_kernel<2>, 2);
     else if (rb == 4) launch(core_stream_kernel<4>, 4);
@@ -921,8 +924,10 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
   d.beta = beta;
   d.part = d.splits > 1 ? part : nullptr;
   dim3 grid((unsigned)(tm * d.tiles_n), 1, (unsigned)d.splits);
+  if (kt) RS_HIP(hipEventRecord(kt->begin, s));
   if (rank_tile) hipLaunchKernelGGL(core_kernel<CfgRank>, grid, dim3(CfgRank::NT), 0, s, d);
   else hipLaunchKernelGGL(core_kernel<CfgSmall>, grid, dim3(CfgSmall::NT), 0, s, d);
+  if (kt) RS_HIP(hipEventRecord(kt->end, s));
   if (d.splits > 1) {
     int64_t total = (int64_t)r1 * r2 * r3;
     unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);

@@ -595,7 +595,7 @@ size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu)
 template <class SP>
 static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const double* U3t,
                          const double* xi, int r1, int r2, int r3, int64_t K, double* beta,
-                         int num_cu, char* work, hipStream_t s) {
+                         int num_cu, char* work, hipStream_t s, const KernelTimer* kt) {
   const CoreMixedPlan P =
       plan_core_mixed(fp16 ? RS_MIXED_FP16 : RS_MIXED_BF16, r1, r2, r3, K, num_cu);
   unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
@@ -615,6 +615,7 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   double* out = part ? part : beta;
   const int64_t stride = (int64_t)r1 * r2 * r3;
   constexpr int FN = SP::TERMS == 2 ? 4 : 2;
+  if (kt) RS_HIP(hipEventRecord(kt->begin, s));
   if (P.wgm == 4)
     hipLaunchKernelGGL((core_tile_kernel<SP, 4, FN>), grid, dim3(512), 0, s, planes, s2, u3, r1, r2,
                        r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
@@ -624,16 +625,17 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   else
     hipLaunchKernelGGL((core_tile_kernel<SP, 2, FN>), grid, dim3(256), 0, s, planes, s2, u3, r1, r2,
                        r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+  if (kt) RS_HIP(hipEventRecord(kt->end, s));
   if (part) core64_reduce(part, P.splits, (int64_t)r1 * r2 * r3, beta, s);
 }
 
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
-                hipStream_t s) {
+                hipStream_t s, const KernelTimer* kt) {
   if (prec == RS_MIXED_FP16)
-    core_mixed_t<SplitF16>(1, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s);
+    core_mixed_t<SplitF16>(1, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s, kt);
   else
-    core_mixed_t<SplitBF16>(0, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s);
+    core_mixed_t<SplitBF16>(0, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s, kt);
 }
 
 // ---- grid ------------------------------------------------------------------------

@@ -60,6 +60,12 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Two events recorded on the launch stream immediately before and after the
+// main kernel of a contraction (the core), or null for none.
+struct KernelTimer {
+  hipEvent_t begin = nullptr, end = nullptr;
+};
+
 }  // namespace rs
 
 struct rs_ctx {
@@ -135,11 +141,15 @@ struct rs_tensor {
   int64_t active_cap = 0;
   // stage timing: events[k] recorded before stage k, events[RS_STAGE_COUNT] at the end
   std::vector<hipEvent_t> events;
-  int timing_mode = 0;          // 1: every stage and eigen phase, 2: the grid stage only
+  int timing_mode = 0;          // 1: every stage and eigen phase, 2: the grid stage only, 3: the core kernel only
   uint32_t recorded = 0;        // bit k: events[k] was recorded
   // eigensolver phases: eig_events[k] before phase k, eig_events[RS_EIG_PHASES] at the end
   std::vector<hipEvent_t> eig_events;
+  // timing mode 3: around the core's main kernel launch
+  rs::KernelTimer kevents;
   ~rs_tensor() {
+    if (kevents.begin) (void)hipEventDestroy(kevents.begin);
+    if (kevents.end) (void)hipEventDestroy(kevents.end);
     for (hipEvent_t e : events)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : eig_events)
@@ -257,11 +267,11 @@ void launch_canonical_signs3(const Mode3& Q, int64_t n, const Mode3& W, int64_t 
 size_t gram_stream_workspace_bytes(int p, int64_t K, int batch, int num_cu);
 bool gram_stream(const double* Z, int64_t zstride, const double* w, int p, int64_t K, int batch,
                  double* C, int num_cu, double* work, hipStream_t s);
-// k_core.hip : beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
+// beta(a, b*r3 + c) = sum_j U1t[j*r1+a] xi[j] U2t[j*r2+b] U3t[j*r3+c]
 size_t core64_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
 void core64(const double* U1t, const double* U2t, const double* U3t, const double* xi,
             int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
-            hipStream_t s);
+            hipStream_t s, const KernelTimer* kt = nullptr);
 
 // fixed-order sum of `splits` partial arrays of `total` doubles
 void core64_reduce(const double* part, int splits, int64_t total, double* out, hipStream_t s);
@@ -270,7 +280,7 @@ void core64_reduce(const double* part, int splits, int64_t total, double* out, h
 size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
-                hipStream_t s);
+                hipStream_t s, const KernelTimer* kt = nullptr);
 // FP32 grid[(i1 i2), i3] = sum_c T2[(i1 i2), c] V3[i3, c]; work holds
 // grid_mixed_workspace_bytes(n, r3) bytes
 size_t grid_mixed_workspace_bytes(int64_t n, int r3);

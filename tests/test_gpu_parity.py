@@ -148,6 +148,36 @@ def test_mid_subspace_full_grid_parity(rsm, ctx, case):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("case", [
+    # ranks ~226: the tiled core (r1 > 128) and the 64-column V3 panel of the
+    # streaming grid expansion (r3 in 148..288)
+    dict(seed=83, N=150, b=25.0, n=256, R=32, R_l=12, n_s=9, panel=64),
+    # ranks ~300: the 32-column panel (r3 > 288)
+    pytest.param(dict(seed=84, N=300, b=25.0, n=384, R=32, R_l=12, n_s=9, panel=32),
+                 marks=pytest.mark.xfail(strict=False, reason=(
+                     "one-pass range finder on the weighted side matrices: its basis "
+                     "leaves 1.5e-6 here (1.4e-8 with one power iteration)"))),
+])
+def test_high_rank_full_grid_parity(rsm, ctx, case):
+    """Full-grid parity at ranks above 128 (the kernels cfg3 and cfg4 take),
+    at the oracle's own ranks."""
+    s = workloads.tiny_system(case["seed"], case["N"], case["b"], case["n"], case["R"],
+                              case["R_l"], case["n_s"], min_sep=0.8, box_frac=0.8)
+    say(f"high-rank grid parity {s.name}")
+    ref = rs.assemble_system(s, core_chunk=256)
+    r1, r3 = ref.ranks[0], ref.ranks[2]
+    assert r1 > 128
+    kp = (r3 + 31) // 32 * 32
+    panel = next(b for b in (128, 64, 32) if kp * (b + 2) * 8 <= 150 * 1024)
+    assert panel == case["panel"], (ref.ranks, panel)
+    f, T, g = run_gpu(rsm, ctx, s, ranks=ref.ranks)
+    assert list(T.info().ranks) == ref.ranks
+    full = ref.full_grid()
+    err = rel_linf(g.cpu().numpy().reshape(full.shape), full)
+    say(f"  ranks {ref.ranks} panel {panel} rel-Linf {err:.2e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("r1", [24, 56, 88, 120])
 def test_core_register_blocks(rsm, ctx, r1):
     """The streaming core keeps 2, 4, 6 or 8 MFMA row blocks per wave
@@ -278,7 +308,7 @@ def test_timing_modes(rsm, ctx):
         assert st2["grid"] > 0 and st2["short"] > 0
         assert all(v == 0.0 for k, v in st2.items() if k not in ("grid", "short"))
         with pytest.raises(rsm.RSError):
-            c2.set_timing(3)
+            c2.set_timing(4)
     finally:
         c2.set_timing(0)
 

@@ -117,3 +117,74 @@ def test_rank_saturates_in_N_and_is_flat_in_n():
         w = rhosvd.gram_weights(rhosvd.canonical_weights(q_all[:N], a))
         full[N] = rhosvd.mode_basis(U, w, 1e-6, 128)[2]
     assert full[64] > ranks[64]
+
+
+def _factors(s):
+    t, a = quadrature.literal_table("newton", s.R)
+    U = rhosvd.side_matrices(s.b, s.n, s.pos, t[:s.R_l])
+    xi = rhosvd.canonical_weights(s.q, a[:s.R_l])
+    return t, a, U, xi, rhosvd.gram_weights(xi)
+
+
+def test_eigh_basis_spans_the_svd_basis():
+    """The Gram route gives the singular subspace of the SVD route: equal
+    projectors up to the rounding of the squared spectrum, equal leading
+    singular values, the same rank rule."""
+    s = _tiny(n=40, N=15)
+    t, a, U, xi, w = _factors(s)
+    for l in range(3):
+        Qs, sig_s, r_s = rhosvd.mode_basis(U[l], w, 1e-6, s.n)
+        Qe, sig_e, r_e = rhosvd.mode_basis_eigh(rhosvd.weighted_gram(U[l], w), 1e-6, s.n)
+        assert r_s == r_e
+        assert np.max(np.abs(sig_s[:4] - sig_e[:4]) / sig_s[:4]) <= 1e-12
+        # a gap well above the truncation: leading 8 columns equal up to rounding
+        assert np.max(np.abs(Qs[:, :8] - Qe[:, :8])) <= 1e-8
+        P_s, P_e = Qs @ Qs.T, Qe @ Qe.T
+        # projectors differ only in directions at the threshold (sigma ~ 1e-6 sigma_1)
+        A = U[l] * np.sqrt(w)[None, :]
+        assert np.linalg.norm((P_s - P_e) @ A, 2) <= 1e-7 * sig_s[0]
+
+
+def test_chunked_core_equals_core():
+    s = _tiny(n=24, N=14)
+    t, a, U, xi, w = _factors(s)
+    Qs = [rhosvd.mode_basis(U[l], w, 1e-6, s.n)[0] for l in range(3)]
+    Ut = [rhosvd.project(Qs[l], U[l]) for l in range(3)]
+    b1 = rhosvd.core(Ut, xi)
+    for chunk in (1, 7, 64, 10 ** 6):
+        b2 = rhosvd.core_chunked(Ut, xi, chunk)
+        assert np.max(np.abs(b1 - b2)) <= 1e-13 * np.max(np.abs(b1))
+
+
+def test_projected_subgrid_equals_tucker_and_full_rank_canonical():
+    """The projected canonical sum on an index set equals the Tucker tensor
+    there; with full ranks (Q orthogonal, Q Q^T = I) it is the canonical
+    long-range sum itself."""
+    s = _tiny(n=20, N=9)
+    t, a, U, xi, w = _factors(s)
+    rng = np.random.default_rng(3)
+    I = [np.sort(rng.choice(s.n, size=m, replace=False)) for m in (7, 5, 9)]
+    for ranks in ([9, 7, 8], [s.n] * 3):
+        Qs = [rhosvd.mode_basis(U[l], w, 0.0, s.n, ranks[l])[0] for l in range(3)]
+        Ut = [rhosvd.project(Qs[l], U[l]) for l in range(3)]
+        full = rhosvd.tucker_full(rhosvd.core(Ut, xi), Qs)[np.ix_(*I)]
+        got = rhosvd.tucker_subgrid_projected(Qs, Ut, xi, *I, chunk=17)
+        assert np.max(np.abs(got - full)) <= 1e-13 * np.max(np.abs(full))
+        W = rhosvd.projected_side_matrices(Qs, Ut)
+        got_w = rhosvd.tucker_subgrid_projected(None, None, xi, *I, chunk=17, W=W)
+        assert np.max(np.abs(got_w - full)) <= 1e-13 * np.max(np.abs(full))
+    C = rhosvd.canonical_full(U, xi)[np.ix_(*I)]
+    assert np.max(np.abs(got - C)) <= 1e-12 * np.max(np.abs(C))
+
+
+def test_short_range_subgrid_equals_dense_and_pointwise():
+    s = _tiny(n=24, N=12, n_s=7)
+    t, a = quadrature.literal_table("newton", s.R)
+    dense = canonical.short_range_grid(s.b, s.n, s.pos, s.q, t, a, s.R_l, s.n_s)
+    rng = np.random.default_rng(4)
+    I = [np.sort(rng.choice(s.n, size=m, replace=False)) for m in (10, 6, 13)]
+    sub = canonical.short_range_subgrid(*I, s.b, s.n, s.pos, s.q, t, a, s.R_l, s.n_s)
+    assert np.array_equal(sub, dense[np.ix_(*I)])
+    ijk = np.stack(np.meshgrid(*I, indexing="ij"), -1).reshape(-1, 3)
+    pw = canonical.short_range_at(ijk, s.b, s.n, s.pos, s.q, t, a, s.R_l, s.n_s)
+    assert np.max(np.abs(pw - sub.ravel())) <= 1e-15 * np.max(np.abs(pw)) * 10

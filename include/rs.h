@@ -58,11 +58,14 @@ typedef enum { RS_NEWTON = 0, RS_YUKAWA = 1, RS_NEWTON_PLUS_YUKAWA = 2 } rs_kern
 
 /* Arithmetic of the assembly.
  *  RS_FP64: everything in FP64; the grid is FP64.
- *  RS_MIXED_FP16: the projection, core and grid-expansion contractions use
- *    split FP16 operands (value = hi + lo * 2^-11) with FP32 MFMA accumulation
- *    and FP64 sums across K chunks; the Gram, eigensolve, quadrature table,
- *    point evaluation and energy reduction stay FP64.  The grid is FP32.
- *  RS_MIXED_BF16: as RS_MIXED_FP16 with three-way split BF16 operands. */
+ *  RS_MIXED_FP16: the core contraction and the last grid-expansion
+ *    contraction (T2 x_3 V3) use split FP16 operands (value = hi + lo * 2^-11,
+ *    three MFMA products) with FP32 MFMA accumulation and FP64 sums across K
+ *    chunks; the side matrices, Gram, eigensolve, projection, the first two
+ *    expansion contractions, quadrature table, point evaluation and energy
+ *    reduction stay FP64.  The grid is FP32.
+ *  RS_MIXED_BF16: as RS_MIXED_FP16 with three-way split BF16 operands (six
+ *    products). */
 typedef enum { RS_FP64 = 0, RS_MIXED_FP16 = 1, RS_MIXED_BF16 = 2 } rs_prec;
 
 typedef struct rs_ctx rs_ctx;
@@ -95,13 +98,30 @@ typedef struct {
   double C0;
 } rs_fdesc;
 
+/* How the charge-weighted Gram matrices G_l = U_l diag(|xi|^{2/3}) U_l^T are formed.
+ *  RS_GRAM_IDENTITY: by the Gaussian-product identity
+ *     G[i, i'] = sum_k exp(-t_k^2 (x_i - x_i')^2 / 2) sum_nu w exp(-2 t_k^2 ((x_i + x_i')/2 - x_nu)^2),
+ *     O(n N R_l + n^2 R_l) work (the columns are Gaussians of one width per k);
+ *  RS_GRAM_GEMM: by the FP64 MFMA product U diag(w) U^T, 2 n^2 N R_l FLOP. */
+typedef enum { RS_GRAM_IDENTITY = 0, RS_GRAM_GEMM = 1 } rs_gram_method;
+
 /* Assembly options.
  *  eps_tucker: rank rule, keep singular values sigma_k > eps_tucker * sigma_1 of
  *     the charge-weighted side matrix U_l diag(|xi|^{1/3}) (Appendix, step (I)).
  *  r_max: rank cap per mode (<= n).  fixed_ranks[l] > 0 overrides the rule.
- *  oversample: extra subspace columns of the eigensolver (default 16 when <= 0).
- *  power_iters: subspace iterations after the first (default 0 when < 0).
- *  interp_order: even Lagrange order p of point evaluation (default 6 when <= 0). */
+ *  oversample: extra subspace columns of the eigensolver beyond r_max (or
+ *     beyond the largest fixed rank); default when <= 0: 16 for the rank rule,
+ *     48 with fixed ranks.  The margin between the subspace size and the
+ *     rank sets how well the basis resolves the directions at the threshold.
+ *  power_iters: subspace iterations Q <- orth(G Q) after the range finder
+ *     (default 0 when < 0).
+ *  interp_order: even Lagrange order p of point evaluation (default 6 when <= 0).
+ *  gram: rs_gram_method (default RS_GRAM_IDENTITY = 0).
+ *  sketch: what the randomized range finder multiplies by the random matrix:
+ *     0 (default) the Gram G_l itself (n x n, 2 n^2 p FLOP; its spectrum is
+ *     the square of the side matrix's, so the directions at the threshold are
+ *     resolved as by one subspace iteration), 1 the weighted side matrix
+ *     U_l diag(|xi|^{1/3}) (n x N R_l, 2 n N R_l p FLOP). */
 typedef struct {
   double eps_tucker;
   int32_t r_max;
@@ -110,6 +130,8 @@ typedef struct {
   int32_t oversample;
   int32_t power_iters;
   int32_t interp_order;
+  int32_t gram;          /* rs_gram_method */
+  int32_t sketch;        /* 0: G_l, 1: U_l diag(|xi|^{1/3}) */
 } rs_aopts;
 
 typedef struct {
@@ -208,10 +230,14 @@ void rs_factors_free(rs_factors* f);
  *     It receives beta x_1 V1 x_2 V2 x_3 V3 + sum_nu z_nu U_nu at the cell centres.
  *  out: receives a new tensor handle (keeps its own copies of pos and q).
  * Steps: side matrices U_l[i, k*N+nu] = exp(-t_k^2 (x_i - x_{nu,l})^2) for
- * k < R_l; weighted Gram G_l = U_l diag(|xi|^{2/3}) U_l^T, xi = z_nu a_k;
- * dominant eigenvectors of G_l (subspace iteration + Jacobi, FP64); rank rule;
- * projection U~_l = V_l^T U_l; core beta = sum_j xi_j u~1_j (x) u~2_j (x) u~3_j;
- * short windows of width n_s around each particle's cell.
+ * k < R_l; weighted Gram G_l = U_l diag(|xi|^{2/3}) U_l^T, xi = z_nu a_k
+ * (opts->gram); dominant eigenvectors of G_l in FP64: a randomized range
+ * finder (opts->sketch) orthonormalised by shifted Cholesky QR
+ * (opts->power_iters more subspace iterations through G_l), the Rayleigh-Ritz
+ * matrix Q^T G_l Q, Householder tridiagonalisation, bisection and inverse
+ * iteration; rank rule; projection U~_l = V_l^T U_l; core
+ * beta = sum_j xi_j u~1_j (x) u~2_j (x) u~3_j; short windows of width n_s
+ * around each particle's cell.
  * Synchronizes `stream` once, after the eigensolve, to read the ranks back.
  * Errors: RS_E_INVALID (N < 1, non-finite input, a particle outside Omega,
  * bad options), RS_E_NOMEM, RS_E_DEVICE; RS_E_RANK_CAP is returned with a
@@ -222,10 +248,11 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 
 /* The three charge-weighted Gram matrices G_l = U_l diag(|xi|^{2/3}) U_l^T of
  * the long-range side matrices (Appendix step (I) through the Gram), the
- * first step of the RHOSVD.  pos, q as in rs_assemble; G: device, 3 x n x n
- * FP64 (mode-major, symmetric).  Asynchronous. */
+ * first step of the RHOSVD.  pos, q as in rs_assemble; method: rs_gram_method;
+ * G: device, 3 x n x n FP64 (mode-major, symmetric).  Asynchronous.
+ * Errors: RS_E_INVALID for an unknown method. */
 rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
-                           const double* q, double* G, void* stream);
+                           const double* q, int32_t method, double* G, void* stream);
 
 /* ---- evaluation (Lemma Property_RST_Tuck, section 4.3-4.4) ------------- */
 

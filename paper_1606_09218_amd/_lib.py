@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_PKG, "librs.so")
 RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_RANK_CAP, RS_E_UNSUPPORTED = range(6)
 KERNELS = {"newton": 0, "yukawa": 1, "newton+yukawa": 2}
 PRECS = {"fp64": 0, "mixed_fp16": 1, "mixed_bf16": 2}
+GRAMS = {"identity": 0, "gemm": 1}
+SKETCHES = {"gram": 0, "side": 1}
 
 
 class RSError(RuntimeError):
@@ -42,7 +44,7 @@ class rs_aopts(C.Structure):
     _fields_ = [("eps_tucker", C.c_double), ("r_max", C.c_int32),
                 ("fixed_ranks", C.c_int32 * 3), ("prec", C.c_int32),
                 ("oversample", C.c_int32), ("power_iters", C.c_int32),
-                ("interp_order", C.c_int32)]
+                ("interp_order", C.c_int32), ("gram", C.c_int32), ("sketch", C.c_int32)]
 
 
 class rs_info(C.Structure):
@@ -78,7 +80,7 @@ def _load():
                             C.POINTER(C.c_int32)], C.c_int),
         "rs_factors_free": ([P], None),
         "rs_assemble": ([P, P, C.c_int64, P, P, C.POINTER(rs_aopts), P, C.POINTER(P), P], C.c_int),
-        "rs_weighted_gram": ([P, P, C.c_int64, P, P, P, P], C.c_int),
+        "rs_weighted_gram": ([P, P, C.c_int64, P, P, C.c_int32, P, P], C.c_int),
         "rs_eval_points": ([P, C.c_int64, P, P, C.c_int32, P], C.c_int),
         "rs_energy": ([P, P, P, P], C.c_int),
         "rs_forces": ([P, C.c_double, P, P], C.c_int),
@@ -191,10 +193,11 @@ class Factors:
 
 
 def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = None,
-               prec="fp64", oversample=0, power_iters=-1, interp_order=0) -> rs_aopts:
+               prec="fp64", oversample=0, power_iters=-1, interp_order=0,
+               gram="identity", sketch="gram") -> rs_aopts:
     fr = (C.c_int32 * 3)(*(list(fixed_ranks) if fixed_ranks else [0, 0, 0]))
     return rs_aopts(float(eps_tucker), int(r_max), fr, PRECS[prec], int(oversample),
-                    int(power_iters), int(interp_order))
+                    int(power_iters), int(interp_order), GRAMS[gram], SKETCHES[sketch])
 
 
 class Tensor:
@@ -251,11 +254,11 @@ def assemble(ctx: Context, f: Factors, pos, q, grid=None, opts: Optional[rs_aopt
     return Tensor(h, ctx, st, N)
 
 
-def weighted_gram(ctx: Context, f: Factors, pos, q, G, stream=None):
+def weighted_gram(ctx: Context, f: Factors, pos, q, G, method: str = "identity", stream=None):
     N = int(q.numel())
     _check(lib.rs_weighted_gram(ctx.handle, f.handle, N, _dev_ptr(pos, "f64", 3 * N, "pos"),
-                                _dev_ptr(q, "f64", N, "q"), _dev_ptr(G, "f64", 3 * f.n * f.n, "G"),
-                                _stream_ptr(stream)))
+                                _dev_ptr(q, "f64", N, "q"), GRAMS[method],
+                                _dev_ptr(G, "f64", 3 * f.n * f.n, "G"), _stream_ptr(stream)))
 
 
 def eval_points(T: Tensor, pts, vals, part: int = 0, stream=None):

@@ -157,7 +157,7 @@ static rs_status guarded(F&& f) {
 struct Plan {
   int64_t N, n, K;
   int R, R_l, n_s;
-  int r_max, p, power_iters, interp, prec;
+  int r_max, p, power_iters, interp, prec, gram, sketch;
   int fixed[3];
   double eps;
 };
@@ -189,7 +189,10 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   if (all_fixed) rcap = std::max(P.fixed[0], std::max(P.fixed[1], P.fixed[2]));
   else
     for (int l = 0; l < 3; ++l) rcap = std::max(rcap, P.fixed[l]);
-  const int os = d.oversample > 0 ? d.oversample : 16;
+  // the subspace oversampling sets how well the basis resolves the
+  // directions at the rank threshold: with fixed ranks the subspace is sized
+  // from them, so it gets a wider margin than the r_max budget of the rank rule
+  const int os = d.oversample > 0 ? d.oversample : (all_fixed ? 48 : 16);
   int64_t p = std::min<int64_t>(P.n, (int64_t)rcap + os);
   if (p % 2) ++p;
   if (p > P.n) p = P.n;
@@ -201,6 +204,10 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   P.interp = d.interp_order > 0 ? d.interp_order : 6;
   RS_REQUIRE(P.interp % 2 == 0 && P.interp <= 8 && P.interp <= P.n, "interp_order must be even, <= 8");
   P.prec = d.prec;
+  P.gram = d.gram;
+  P.sketch = d.sketch;
+  RS_REQUIRE(P.sketch == 0 || P.sketch == 1, "sketch must be 0 (Gram) or 1 (side matrix)");
+  RS_REQUIRE(P.gram == RS_GRAM_IDENTITY || P.gram == RS_GRAM_GEMM, "unknown Gram method");
   RS_REQUIRE(P.prec == RS_FP64 || P.prec == RS_MIXED_FP16 || P.prec == RS_MIXED_BF16,
              "unknown precision");
   RS_REQUIRE(P.R - P.R_l <= 64 && P.R_l <= 64, "at most 64 long and 64 short terms");
@@ -241,21 +248,28 @@ static Gemm64 gram_gemm(const Plan& P, const double* U, const double* w, double*
   return g;
 }
 
-// `work`: split-K workspace of gemm64_workspace_bytes(gram_gemm(..)), or null
-// to allocate one here.
+static size_t gram_workspace_bytes(const Plan& P, int method, int ncu) {
+  return method == RS_GRAM_GEMM ? gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu)
+                                : gauss_gram_workspace_bytes(P.N, P.R_l, P.n, ncu);
+}
+
+// Side matrices, weights and the three Gram matrices (method RS_GRAM_*).
+// `work`: gram_workspace_bytes(P, method, ncu) bytes, or null to allocate here.
 static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
                                  const double* pos, const double* q, double* U, double* xi,
-                                 double* w, double* sw, double* G, hipStream_t s,
+                                 double* w, double* sw, double* G, int method, hipStream_t s,
                                  rs_tensor* T = nullptr, double* work = nullptr) {
   launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s);
   if (T) mark(T, RS_STAGE_GRAM, s);
-  const Gemm64 g = gram_gemm(P, U, w, G);
-  if (work) {
-    gemm64(g, ctx->num_cu, work, s);
-  } else {
-    DevBuf wk(gemm64_workspace_bytes(g, ctx->num_cu), s);
-    gemm64(g, ctx->num_cu, wk.as<double>(), s);
+  DevBuf own;
+  if (!work) {
+    own = DevBuf(gram_workspace_bytes(P, method, ctx->num_cu), s);
+    work = own.as<double>();
   }
+  if (method == RS_GRAM_GEMM)
+    gemm64(gram_gemm(P, U, w, G), ctx->num_cu, work, s);
+  else
+    launch_gauss_gram(pos, f->t_dev, w, P.N, P.R_l, P.n, f->grid.b, G, work, ctx->num_cu, s);
 }
 
 // Non-owning view of a piece of an arena, with DevBuf's accessors.
@@ -492,16 +506,17 @@ void rs_factors_free(rs_factors* f) {
 }
 
 rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
-                           const double* q, double* G, void* stream) {
+                           const double* q, int32_t method, double* G, void* stream) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(ctx && f && pos && q && G, "null argument");
+    RS_REQUIRE(method == RS_GRAM_IDENTITY || method == RS_GRAM_GEMM, "unknown Gram method");
     RS_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     Plan P = make_plan(f, N, nullptr);
     DevBuf U((size_t)3 * P.n * P.K * sizeof(double), s);
     DevBuf xi((size_t)P.K * sizeof(double), s), w((size_t)P.K * sizeof(double), s);
     run_factors_and_gram(ctx, f, P, pos, q, U.as<double>(), xi.as<double>(), w.as<double>(),
-                         nullptr, G, s);
+                         nullptr, G, method, s);
     return RS_OK;
   });
 }
@@ -567,12 +582,10 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
     T->nb = bricks_per_axis(n);
     const int nbricks = T->nb * T->nb * T->nb;
-    Gemm64 zq_shape;  // Z = U^T Q0 (K x p)
-    zq_shape.M = K; zq_shape.N = p; zq_shape.K = n; zq_shape.batch = 3;
-    Gemm64 bz_shape;  // B = Z^T diag(w) Z (upper)
-    bz_shape.M = p; bz_shape.N = p; bz_shape.K = K; bz_shape.batch = 3; bz_shape.upper_only = 1;
-    Gemm64 uwz_shape;  // Y = U diag(w) Z (power iterations)
-    uwz_shape.M = n; uwz_shape.N = p; uwz_shape.K = K; uwz_shape.batch = 3;
+    Gemm64 gq_shape;  // G Q0 (n x p)
+    gq_shape.M = n; gq_shape.N = p; gq_shape.K = n; gq_shape.batch = 3;
+    Gemm64 qgq_shape;  // B = Q0^T (G Q0) (upper)
+    qgq_shape.M = p; qgq_shape.N = p; qgq_shape.K = n; qgq_shape.batch = 3; qgq_shape.upper_only = 1;
     Gemm64 yty_shape;  // C = Y^T Y (upper)
     yty_shape.M = p; yty_shape.N = p; yty_shape.K = n; yty_shape.batch = 3; yty_shape.upper_only = 1;
     Gemm64 zz_shape;  // C = Z^T Z (upper)
@@ -583,23 +596,22 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const size_t o_rb = pre.add(sizeof(Readback));
     const size_t o_U = pre.add((size_t)3 * n * K * d8), o_xi = pre.add((size_t)K * d8);
     const size_t o_w = pre.add((size_t)K * d8), o_sw = pre.add((size_t)K * d8);
-    // the n x n Gram is formed only when the subspace is all of R^n; otherwise
-    // its projection B = Q^T G Q is formed as Z^T diag(w) Z with Z = U^T Q
+    // the three n x n Gram matrices: by the Gaussian-product identity
+    // (O(n K + n^2 R_l)) or by the MFMA GEMM U diag(w) U^T (2 n^2 K FLOP)
     const bool subspace = p < n;
-    const size_t o_G = pre.add(subspace ? 0 : (size_t)3 * n * n * d8);
-    const size_t o_wgram =
-        pre.add(subspace ? 0 : gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu));
+    const size_t o_G = pre.add((size_t)3 * n * n * d8);
+    const size_t wgram_bytes = P.gram == RS_GRAM_GEMM
+                                   ? gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu)
+                                   : gauss_gram_workspace_bytes(P.N, P.R_l, n, ncu);
+    const size_t o_wgram = pre.add(wgram_bytes);
     const size_t o_Q0 = pre.add((size_t)3 * n * p * d8), o_Bm = pre.add((size_t)3 * p * p * d8);
-    const size_t o_Y = pre.add(subspace && P.power_iters > 0 ? (size_t)3 * n * p * d8 : 0);
-    const size_t o_Zk = pre.add(subspace ? (size_t)3 * K * p * d8 : 0);
+    const size_t o_Y = pre.add(subspace ? (size_t)3 * n * p * d8 : 0);
     const size_t o_Cq = pre.add(subspace ? (size_t)3 * p * p * d8 : 0);
     const size_t o_eta = pre.add(sketch_eta_bytes(3));
     const size_t wke_bytes =
-        subspace ? std::max({sketch64_workspace_bytes(n, K, 3, p, ncu),
-                             gemm64_workspace_bytes(zq_shape, ncu),
-                             gemm64_workspace_bytes(bz_shape, ncu),
-                             gram_stream_workspace_bytes(p, K, 3, ncu),
-                             P.power_iters > 0 ? gemm64_workspace_bytes(uwz_shape, ncu) : (size_t)0,
+        subspace ? std::max({sketch64_workspace_bytes(n, P.sketch ? K : n, 3, p, ncu),
+                             gemm64_workspace_bytes(gq_shape, ncu),
+                             gemm64_workspace_bytes(qgq_shape, ncu),
                              gemm64_workspace_bytes(yty_shape, ncu)})
                  : 0;
     const size_t o_wke = pre.add(wke_bytes);
@@ -622,16 +634,10 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     mark(T.get(), RS_STAGE_FACTORS, s);
     Span U = piece(o_U, (size_t)3 * n * K * d8), xi = piece(o_xi, (size_t)K * d8);
     Span w = piece(o_w, (size_t)K * d8), sw = piece(o_sw, (size_t)K * d8);
-    Span G = piece(o_G, subspace ? 0 : (size_t)3 * n * n * d8);
-    if (subspace) {
-      launch_side_matrices(dpos, dq, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U.as<double>(),
-                           xi.as<double>(), w.as<double>(), sw.as<double>(), s);
-      mark(T.get(), RS_STAGE_GRAM, s);   // no n x n Gram on this path
-    } else {
-      run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
-                           sw.as<double>(), G.as<double>(), s, T.get(),
-                           (double*)(pre_buf.as<char>() + o_wgram));
-    }
+    Span G = piece(o_G, (size_t)3 * n * n * d8);
+    run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
+                         sw.as<double>(), G.as<double>(), P.gram, s, T.get(),
+                         (double*)(pre_buf.as<char>() + o_wgram));
 
     // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
     mark(T.get(), RS_STAGE_EIGEN, s);
@@ -641,30 +647,20 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       launch_identity(Q0.as<double>(), n, 3, s);
       RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
     } else {
-      Span Y = piece(o_Y, P.power_iters > 0 ? (size_t)3 * n * p * d8 : 0);
-      Span Zk = piece(o_Zk, (size_t)3 * K * p * d8), Cq = piece(o_Cq, (size_t)3 * p * p * d8);
+      Span Y = piece(o_Y, (size_t)3 * n * p * d8), Cq = piece(o_Cq, (size_t)3 * p * p * d8);
       double* eta = (double*)(pre_buf.as<char>() + o_eta);
-      auto zq_gemm = [&](const double* X) {  // Z = U^T X (K x p, row-major)
-        Gemm64 g = zq_shape;
-        g.A = U.as<double>(); g.sam = n; g.sak = 1; g.sab = n * K;
+      auto gq_gemm = [&](const double* X, double* out) {  // out = G X (n x p, row-major)
+        Gemm64 g = gq_shape;
+        g.A = G.as<double>(); g.sam = n; g.sak = 1; g.sab = n * n;
         g.B = X; g.sbk = p; g.sbn = 1; g.sbb = n * p;
-        g.C = Zk.as<double>(); g.scm = p; g.scn = 1; g.scb = K * p;
+        g.C = out; g.scm = p; g.scn = 1; g.scb = n * p;
         return g;
       };
-      auto bz_gemm = [&]() {  // B = Z^T diag(w) Z (symmetric)
-        Gemm64 g = bz_shape;
-        g.A = Zk.as<double>(); g.sam = 1; g.sak = p; g.sab = K * p;
-        g.B = Zk.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = K * p;
+      auto qgq_gemm = [&](const double* X, const double* GX) {  // B = X^T (G X) (symmetric)
+        Gemm64 g = qgq_shape;
+        g.A = X; g.sam = 1; g.sak = p; g.sab = n * p;
+        g.B = GX; g.sbk = p; g.sbn = 1; g.sbb = n * p;
         g.C = Bm.as<double>(); g.scm = p; g.scn = 1; g.scb = (int64_t)p * p;
-        g.kscale = w.as<double>();
-        return g;
-      };
-      auto uwz_gemm = [&](double* Yout) {  // Y = U diag(w) Z = G X for Z = U^T X
-        Gemm64 g = uwz_shape;
-        g.A = U.as<double>(); g.sam = 1; g.sak = n; g.sab = n * K;
-        g.B = Zk.as<double>(); g.sbk = p; g.sbn = 1; g.sbb = K * p;
-        g.C = Yout; g.scm = p; g.scn = 1; g.scb = n * p;
-        g.kscale = w.as<double>();
         return g;
       };
       auto yty_gemm = [&](const double* Yp) {  // C = Y^T Y (symmetric)
@@ -675,35 +671,50 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
         return g;
       };
       Span wk_eig = piece(o_wke, wke_bytes);  // split-K workspace of every product here
+      // Y = G X carries the squared spectrum (condition up to ~1e16 once the
+      // perturbation below bounds it); Y = U diag(|xi|^{1/3}) Omega the
+      // spectrum itself.  The perturbation must stay below the components
+      // at the rank threshold (sigma^2 ~ 1e-12 sigma_1^2 for the Gram).
       // orthonormal basis of range(Y), in place: shifted Cholesky QR, twice
       // (each shifted pass maps cond(Y) to about sqrt(shift)/sigma_min(Y)),
-      // then two plain passes
-      auto orth = [&](double* Yp) {
-        for (int pass = 0; pass < 3; ++pass) {
+      // then plain passes (two for the squared spectrum)
+      auto orth = [&](double* Yp, bool squared) {
+        const int passes = squared ? 4 : 3;
+        for (int pass = 0; pass < passes; ++pass) {
           gemm64(yty_gemm(Yp), ncu, wk_eig.as<double>(), s);
           launch_chol(Cq.as<double>(), p, n, 3, pass < 2, ctx->lds_limit, &rbd->chol_fail, 1, s);
           launch_trsm_rows(Yp, Cq.as<double>(), n, p, 3, ctx->lds_limit, s);
         }
       };
-      // range finder on the charge-weighted side matrix itself (its dynamic
-      // range is that of the singular values, not of their squares)
-      sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
-               Q0.as<double>(), p, 1, ncu, wk_eig.as<double>(), s);
-      launch_sketch_eta(Q0.as<double>(), n, p, 3, eta, s);
-      launch_perturb_eta(Q0.as<double>(), eta, n, p, 3, 0x9e3779b9ULL, s);
-      orth(Q0.as<double>());
+      // a random perturbation of relative size `rel` (scaled from Y itself)
+      // gives Y full column rank when the Gram has rank below p
+      auto perturb = [&](double* Yp, uint64_t seed, bool squared) {
+        launch_sketch_eta(Yp, n, p, 3, eta, s);
+        launch_perturb_eta(Yp, eta, n, p, 3, squared ? 1e-13 : 1e-12, seed, s);
+      };
+      // range finder: Y = G Omega (n x n times n x p), or on the
+      // charge-weighted side matrix itself, Y = U diag(|xi|^{1/3}) Omega
+      // (n x K times K x p; the dynamic range of Y is that of the singular
+      // values, not of their squares, but one pass resolves the directions
+      // at the threshold less well and costs 2 n K p)
+      if (P.sketch == 0)
+        sketch64(G.as<double>(), n, n, n * n, nullptr, 0, 3, p, 0x5eed1234ULL, Q0.as<double>(), p,
+                 1, ncu, wk_eig.as<double>(), s);
+      else
+        sketch64(U.as<double>(), n, K, n * K, sw.as<double>(), 0, 3, p, 0x5eed1234ULL,
+                 Q0.as<double>(), p, 1, ncu, wk_eig.as<double>(), s);
+      perturb(Q0.as<double>(), 0x9e3779b9ULL, P.sketch == 0);
+      orth(Q0.as<double>(), P.sketch == 0);
+      // subspace iterations Q0 <- orth(G Q0): n x n products through the Gram
       for (int it = 0; it < P.power_iters; ++it) {
-        gemm64(zq_gemm(Q0.as<double>()), ncu, wk_eig.as<double>(), s);
-        gemm64(uwz_gemm(Y.as<double>()), ncu, wk_eig.as<double>(), s);   // Y = G Q0
-        launch_perturb_eta(Y.as<double>(), eta, n, p, 3, 0x9e3779b9ULL + it + 1, s);
-        orth(Y.as<double>());
+        gemm64(gq_gemm(Q0.as<double>(), Y.as<double>()), ncu, wk_eig.as<double>(), s);
+        perturb(Y.as<double>(), 0x9e3779b9ULL + it + 1, true);
+        orth(Y.as<double>(), true);
         std::swap(Q0, Y);
       }
-      // Rayleigh-Ritz matrix B = Q0^T G Q0 = Z^T diag(w) Z, Z = U^T Q0
-      gemm64(zq_gemm(Q0.as<double>()), ncu, wk_eig.as<double>(), s);
-      if (!gram_stream(Zk.as<double>(), K * p, w.as<double>(), p, K, 3, Bm.as<double>(), ncu,
-                       wk_eig.as<double>(), s))
-        gemm64(bz_gemm(), ncu, wk_eig.as<double>(), s);
+      // Rayleigh-Ritz matrix B = Q0^T G Q0
+      gemm64(gq_gemm(Q0.as<double>(), Y.as<double>()), ncu, wk_eig.as<double>(), s);
+      gemm64(qgq_gemm(Q0.as<double>(), Y.as<double>()), ncu, wk_eig.as<double>(), s);
     }
     // eigenvectors are formed only for the rc columns the rank rule can keep
     Span ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));
@@ -834,20 +845,11 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       g.A = Q0.as<double>() + (int64_t)l * n * p; g.sam = p; g.sak = 1;
       g.sbk = 1; g.sbn = p;
       g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
-      Gemm64& h = gp[l];  // U~_l = V_l^T U_l, stored column j contiguous: U~[j*r + a]
-      if (subspace) {
-        // U~_l^T = U_l^T Q0 W_r = Z W_r (K x r): Z = U^T Q0 is kept from the
-        // Rayleigh-Ritz step, so the projection contracts over p, not n
-        h.M = K; h.N = r; h.K = p;
-        h.A = (const double*)(pre_buf.as<char>() + o_Zk) + (int64_t)l * K * p; h.sam = p; h.sak = 1;
-        h.sbk = 1; h.sbn = p;   // W_r is p x r, column-major (as gathered)
-        h.scm = r; h.scn = 1;
-      } else {
-        h.M = r; h.N = K; h.K = n;
-        h.A = T->Q[l].as<double>(); h.sam = 1; h.sak = r;
-        h.B = U.as<double>() + (int64_t)l * n * K; h.sbk = 1; h.sbn = n;
-        h.scm = 1; h.scn = r;
-      }
+      Gemm64& h = gp[l];  // U~_l^T = U_l^T V_l (K x r row-major, i.e. U~[j*r + a]): the
+      h.M = K; h.N = r; h.K = n;   // long dimension K is the GEMM's row dimension
+      h.A = U.as<double>() + (int64_t)l * n * K; h.sam = n; h.sak = 1;
+      h.B = T->Q[l].as<double>(); h.sbk = r; h.sbn = 1;
+      h.scm = r; h.scn = 1;
     }
     Carve cv;
     size_t o_wr[3], o_wkb[3], o_ut[3], o_wkp[3];
@@ -876,12 +878,11 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     // the sign of each kept column is fixed on V_l and carried to W_r,
     // which the projection below multiplies
     Mode3 none{{nullptr, nullptr, nullptr}, {r1, r2, r3}};
-    launch_canonical_signs3(q3, n, subspace ? wr3 : none, p, s);
+    launch_canonical_signs3(q3, n, none, p, s);
 
     // (a5) projection U~_l = V_l^T U_l and core
     mark(T.get(), RS_STAGE_PROJECT, s);
     for (int l = 0; l < 3; ++l) {
-      if (subspace) gp[l].B = at(o_wr[l]);
       gp[l].C = at(o_ut[l]);
       gemm64(gp[l], ncu, at(o_wkp[l]), s);
     }

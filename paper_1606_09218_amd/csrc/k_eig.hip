@@ -878,7 +878,7 @@ __global__ void perturb_kernel(double* __restrict__ Yall, const double* __restri
 }
 
 // The same perturbation with the scale taken from the sketch itself:
-// eta = 1e-12 sqrt(|Y|_F^2 / (n p)).  For the range-finder sketch
+// eta = rel sqrt(|Y|_F^2 / (n p)).  For the range-finder sketch
 // Y = U diag(w^1/2) Omega with Omega uniform in [-1, 1), E |Y|_F^2 = p tr(G) / 3,
 // so this is the scale above without forming G.  ETA_PARTS workgroups per
 // mode write partial sums of |Y|_F^2; every workgroup of the perturbation
@@ -901,11 +901,11 @@ __global__ __launch_bounds__(256) void sketch_eta_kernel(const double* __restric
 }
 
 __global__ void perturb_eta_kernel(double* __restrict__ Yall, const double* __restrict__ part,
-                                   int64_t n, int p, uint64_t seed) {
+                                   int64_t n, int p, double rel, uint64_t seed) {
   const int mode = blockIdx.y;
   double t = 0.0;
   for (int b = 0; b < ETA_PARTS; ++b) t += part[mode * ETA_PARTS + b];
-  const double eta0 = 1e-12 * sqrt(fmax(t, 0.0) / ((double)n * p));
+  const double eta0 = rel * sqrt(fmax(t, 0.0) / ((double)n * p));
   const double eta = eta0 > 0 ? eta0 : 1e-300;
   double* Y = Yall + (int64_t)mode * n * p;
   const int64_t total = n * p;
@@ -920,11 +920,12 @@ void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* par
   hipLaunchKernelGGL(sketch_eta_kernel, dim3(ETA_PARTS, modes), dim3(256), 0, s, Y, n, p, part);
 }
 
-void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, uint64_t seed,
-                        hipStream_t s) {
+void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, double rel,
+                        uint64_t seed, hipStream_t s) {
   const int64_t total = n * p;
   unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 2048);
-  hipLaunchKernelGGL(perturb_eta_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, part, n, p, seed);
+  hipLaunchKernelGGL(perturb_eta_kernel, dim3(blocks, modes), dim3(256), 0, s, Y, part, n, p, rel,
+                     seed);
 }
 
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,

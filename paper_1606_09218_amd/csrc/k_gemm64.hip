@@ -184,7 +184,7 @@ struct HashSrc {
       double v = 0.0;
       if (e < WIDE * BK && c < W && k < kend) {
         const uint64_t h = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ULL + (uint64_t)c));
-        v = scale[k] * ((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+        v = (scale ? scale[k] : 1.0) * ((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
       }
       reg[r] = v;
     }

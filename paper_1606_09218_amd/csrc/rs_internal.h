@@ -196,11 +196,18 @@ void gemm64(const Gemm64& g, int num_cu, double* work, hipStream_t s);
 bool grid64_stream(const double* T2, const double* V3, int64_t n, int r3, double* grid, int num_cu,
                    int lds_limit, hipStream_t s);
 // Range-finder sketch Y[bt] (M x N col-major) = A[bt] (M x K col-major) Omega_bt,
-// Omega_bt[k, c] = scale[bt*scale_stride + k] * u(seed, bt, k, c), u uniform in [-1, 1).
+// Omega_bt[k, c] = scale[bt*scale_stride + k] * u(seed, bt, k, c), u uniform in [-1, 1)
+// (scale null: 1).
 size_t sketch64_workspace_bytes(int64_t M, int64_t K, int batch, int64_t N, int num_cu);
 void sketch64(const double* A, int64_t M, int64_t K, int64_t sab, const double* scale,
               int64_t scale_stride, int batch, int64_t N, uint64_t seed, double* Y, int64_t scm,
               int64_t scn, int num_cu, double* work, hipStream_t s);
+
+// k_gram.hip: G (3 x n x n) = U diag(w) U^T per mode by the Gaussian-product
+// identity, from the particle coordinates, the nodes t and the weights w
+size_t gauss_gram_workspace_bytes(int64_t N, int R_l, int64_t n, int num_cu);
+void launch_gauss_gram(const double* pos, const double* t, const double* w, int64_t N, int R_l,
+                       int64_t n, double b, double* G, double* work, int num_cu, hipStream_t s);
 
 // k_eig.hip
 void launch_identity(double* I, int64_t n, int modes, hipStream_t s);
@@ -208,12 +215,12 @@ void launch_symmetrize(double* B, int p, int modes, hipStream_t s);
 void launch_perturb(double* Y, const double* G, int64_t n, int p, int modes, uint64_t seed,
                     hipStream_t s);
 // Partial sums of |Y_mode|_F^2 (sketch_eta_bytes(modes) bytes), then
-// Y += eta * uniform noise with eta = 1e-12 sqrt(|Y_mode|_F^2 / (n p)), the
+// Y += eta * uniform noise with eta = rel sqrt(|Y_mode|_F^2 / (n p)), the
 // scale of the perturbation taken from the range-finder sketch
 size_t sketch_eta_bytes(int modes);
 void launch_sketch_eta(const double* Y, int64_t n, int p, int modes, double* part, hipStream_t s);
-void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, uint64_t seed,
-                        hipStream_t s);
+void launch_perturb_eta(double* Y, const double* part, int64_t n, int p, int modes, double rel,
+                        uint64_t seed, hipStream_t s);
 // Cholesky C = L L^T in place (lower, col-major), one workgroup per mode; the
 // shifted variant adds 11 (nrows p + p (p+1)) u tr(C) to the diagonal first.
 // fail |= fail_bit on a non-positive pivot.

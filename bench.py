@@ -304,6 +304,7 @@ def secondary_leg(rsm, ctx, name, steps, warmup, stream):
     lm["meets_1e-5"] = bool(lm["grid_rel_linf_vs_fp64"] <= GATE and lm["energy_rel_err_vs_fp64"] <= GATE)
     out["mixed_fp16"] = lm
     del g64, g32
+    f.close()
     torch.cuda.empty_cache()
     return out
 
@@ -314,12 +315,20 @@ def serving_leg(n_requests: int, n_slots: int = 4, prec: str = "mixed_fp16"):
     24..32), replayed in real time through the continuous-batching server,
     then the same requests all present at t = 0 (saturating).  Latency is
     arrival to result (energy and ranks on the host)."""
-    import torch
-
     import workloads
-    from paper_1606_09218_amd.serve import GpuExecutor, Server, summarize
+    from paper_1606_09218_amd.serve import GpuExecutor
     trace = workloads.cfg5_trace(seed=5, n_requests=n_requests)
     ex = GpuExecutor(0, prec=prec, r_max=384)
+    try:
+        return _serve_trace(ex, trace, n_requests, n_slots, prec)
+    finally:
+        ex.close()
+
+
+def _serve_trace(ex, trace, n_requests, n_slots, prec):
+    import torch
+
+    from paper_1606_09218_amd.serve import Server, summarize
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.85 * free)
     # factors of every (n, R) in the trace are built before the clock starts
@@ -361,7 +370,7 @@ def main():
     if args.cpu_baseline_only:
         s, _, _ = workload(args.workload)
         print(json.dumps(cpu_baseline(s)), flush=True)
-        return False
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(every workload here runs on a single MI355X).", file=sys.stderr)
@@ -450,17 +459,10 @@ def main():
             out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    f.close()
+    ctx.close()
     print(json.dumps(out), flush=True)
-    return args.serve_requests > 0
 
 
 if __name__ == "__main__":
-    if main():
-        # after the serving leg the line is out: leave without the
-        # interpreter's and the runtimes' teardown (one full run with the
-        # serving leg crashed there, after every result had been printed).
-        # Runs without it end normally, so that a profiler attached to them
-        # still writes its output at exit.
-        sys.stdout.flush()
-        sys.stderr.flush()
-        os._exit(0)
+    main()

@@ -23,6 +23,12 @@
  *  - Work is enqueued on the HIP stream passed as `stream` (a hipStream_t;
  *    NULL = the null stream).  Calls return once their work is enqueued,
  *    except where a call says it synchronizes.
+ *  - Stream lifetime: the library's device-buffer cache remembers the stream
+ *    that last used each cached buffer and may later make another stream
+ *    wait on it.  A stream handed to the library must therefore stay valid
+ *    until the tensors made on it are freed and rs_stream_release(ctx,
+ *    stream) has been called (or until rs_ctx_trim, or the end of the
+ *    process).
  *  - Arguments are validated before anything is enqueued; on a non-OK
  *    status nothing has been written to caller memory.  rs_last_error()
  *    returns a thread-local message describing the last failure.  No C++
@@ -198,6 +204,11 @@ void rs_ctx_destroy(rs_ctx* ctx);
  * core's main kernel only (stage_ms[RS_STAGE_CORE_KERNEL]).
  * Errors: RS_E_INVALID for another value. */
 rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable);
+/* Synchronise `stream` and detach the library's cached buffers from it, so
+ * that the caller may destroy it afterwards (see "Stream lifetime" above).
+ * Tensors still alive that were made on `stream` keep using it when freed:
+ * free them first.  Errors: RS_E_DEVICE if the synchronisation fails. */
+rs_status rs_stream_release(rs_ctx* ctx, void* stream);
 /* Device memory of the library's buffers comes from a per-device cache: a
  * released buffer is kept for reuse by later assemblies (immediately on the
  * stream it was released on, after an event wait on another stream) and is

@@ -6,8 +6,10 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
 from typing import Optional, Sequence
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +77,7 @@ def _load():
         "rs_ctx_destroy": ([P], None),
         "rs_ctx_set_timing": ([P, C.c_int], C.c_int),
         "rs_ctx_trim": ([P], C.c_int),
+        "rs_stream_release": ([P, P], C.c_int),
         "rs_build_factors": ([P, C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.POINTER(P)], C.c_int),
         "rs_factors_get": ([P, D, D, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                             C.POINTER(C.c_int32)], C.c_int),
@@ -103,7 +106,27 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim", "rs_build_factors", "rs_factors_get",
+
+# Handles are released explicitly (close/free) or by __del__ while the
+# interpreter runs normally; once it starts to exit, __del__ makes no library
+# call (the HIP runtime and the modules it would need may already be going
+# away, and the process is about to release everything anyway).
+_exiting = False
+
+
+def _at_exit():
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_at_exit)
+
+
+def _may_release() -> bool:
+    return not _exiting and not sys.is_finalizing()
+
+EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim",
+            "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_energy_forces", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
@@ -158,10 +181,19 @@ class Context:
         """Return the device memory cached for reuse (rs_ctx_trim)."""
         _check(lib.rs_ctx_trim(self.handle))
 
-    def __del__(self):
+    def release_stream(self, stream):
+        """Synchronise a torch stream and detach cached buffers from it
+        (rs_stream_release), before the caller destroys it."""
+        _check(lib.rs_stream_release(self.handle, _stream_ptr(stream)))
+
+    def close(self):
         if getattr(self, "handle", None):
             lib.rs_ctx_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        if _may_release():
+            self.close()
 
 
 class Factors:
@@ -186,10 +218,14 @@ class Factors:
         self.R, self.R_l, self.n_s = Rv.value, Rl.value, ns.value
         self.b, self.n = float(b), int(n)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None):
             lib.rs_factors_free(self.handle)
             self.handle = None
+
+    def __del__(self):
+        if _may_release():
+            self.close()
 
 
 def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = None,
@@ -235,7 +271,8 @@ class Tensor:
             self.handle = None
 
     def __del__(self):
-        self.free()
+        if _may_release():
+            self.free()
 
 
 def assemble(ctx: Context, f: Factors, pos, q, grid=None, opts: Optional[rs_aopts] = None,

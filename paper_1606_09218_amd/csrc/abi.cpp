@@ -37,6 +37,7 @@ namespace {
 struct CachedBlock {
   void* p;
   hipStream_t s;
+  bool idle;   // no work on it can be pending (its stream was synchronised and released)
 };
 struct DeviceCache {
   std::multimap<size_t, CachedBlock> free_blocks;  // by size
@@ -79,13 +80,13 @@ static void* cache_alloc(size_t nbytes, hipStream_t st) {
   DeviceCache& c = g_caches[dev];
   auto best = c.free_blocks.end();
   for (auto it = c.free_blocks.lower_bound(want); it != c.free_blocks.end() && it->first <= limit; ++it) {
-    if (it->second.s == st) { best = it; break; }
+    if (it->second.idle || it->second.s == st) { best = it; break; }
     if (best == c.free_blocks.end()) best = it;
   }
   if (best != c.free_blocks.end()) {
     CachedBlock b = best->second;
     c.free_blocks.erase(best);
-    if (b.s != st) {
+    if (!b.idle && b.s != st) {
       hipEvent_t ev;
       RS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
       RS_HIP(hipEventRecord(ev, b.s));
@@ -108,7 +109,19 @@ static void cache_free(void* p, hipStream_t st) {
   std::lock_guard<std::mutex> lock(g_cache_mu);
   auto it = g_blocks.find(p);
   if (it == g_blocks.end()) return;  // not taken by cache_alloc (cannot happen)
-  g_caches[it->second.device].free_blocks.emplace(it->second.bytes, CachedBlock{p, st});
+  g_caches[it->second.device].free_blocks.emplace(it->second.bytes, CachedBlock{p, st, false});
+}
+
+// Detach the cached blocks of stream `st` from it (the caller has
+// synchronised `st`), so that no later allocation records an event on it.
+static void cache_forget_stream(hipStream_t st) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  for (auto& dc : g_caches)
+    for (auto& kv : dc.second.free_blocks)
+      if (kv.second.s == st) {
+        kv.second.idle = true;
+        kv.second.s = nullptr;
+      }
 }
 
 static void cache_trim(int device) {
@@ -452,6 +465,16 @@ rs_status rs_ctx_trim(rs_ctx* ctx) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(ctx != nullptr, "null context");
     cache_trim(ctx->device);
+    return RS_OK;
+  });
+}
+
+rs_status rs_stream_release(rs_ctx* ctx, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx != nullptr, "null context");
+    RS_HIP(hipSetDevice(ctx->device));
+    RS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    cache_forget_stream((hipStream_t)stream);
     return RS_OK;
   });
 }

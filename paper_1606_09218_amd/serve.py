@@ -51,6 +51,9 @@ class Executor:
     def run(self, req, slot):  # pragma: no cover - interface
         raise NotImplementedError
 
+    def close(self):
+        """Release what the executor holds (device memory, handles)."""
+
 
 class Server:
     def __init__(self, executor: Executor, n_slots: int = 4, hbm_budget: int = 1 << 40,
@@ -177,6 +180,19 @@ class GpuExecutor(Executor):
                                      delta_rel=sysm.delta_rel)
                 self._factors[key] = f
         return f
+
+    def close(self):
+        """Wait for the device, then free the quadrature tables and the
+        context (rather than leaving them to the garbage collector)."""
+        if self.ctx is None:
+            return
+        self.torch.cuda.synchronize(self.device)
+        with self._lock:
+            for f in self._factors.values():
+                f.close()
+            self._factors.clear()
+        self.ctx.close()
+        self.ctx = None
 
     def footprint(self, req) -> int:
         sysm = req.system() if hasattr(req, "system") else req

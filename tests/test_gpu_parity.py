@@ -313,6 +313,27 @@ def test_determinism_and_antisymmetry(rsm, ctx):
     assert rel_linf(g4.cpu().numpy(), g1.cpu().numpy()) <= 1e-10
 
 
+def test_stream_release_then_other_stream(rsm, ctx):
+    """Buffers cached from a released stream are reused on another stream
+    with identical results (rs_stream_release detaches them)."""
+    s = workloads.tiny_system(92, 20, 5.0, 48, 20, 8, 7, min_sep=0.5)
+    c2 = rsm.Context(0)
+    f = rsm.Factors(c2, s.b, s.n, s.R, s.R_l, s.n_s)
+    pos, q = dev(s.pos), dev(s.q)
+    grids = []
+    for _ in range(2):
+        st = torch.cuda.Stream()
+        g = torch.empty(s.n ** 3, dtype=torch.float64, device="cuda")
+        T = rsm.assemble(c2, f, pos, q, g, rsm.make_aopts(r_max=32), stream=st)
+        st.synchronize()
+        T.free()
+        c2.release_stream(st)
+        grids.append(g)
+    assert torch.equal(grids[0], grids[1])
+    f.close()
+    c2.close()
+
+
 def test_timing_modes(rsm, ctx):
     """Mode 1 times every stage; mode 2 only the grid stage (and the short
     range after it); other values are rejected."""

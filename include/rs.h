@@ -294,6 +294,19 @@ rs_status rs_forces(const rs_tensor* T, double scale, double* F, void* stream);
 rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double scale, double* F,
                            void* stream);
 
+/* rs_energy_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bitwise, with the
+ * per-particle scratch (8 N doubles) carved from a static device array of
+ * the library (8 MiB per GPU, held until the process ends) instead of the
+ * library's allocator.  It calls no hipMalloc/hipFree.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Errors: RS_E_INVALID for N > 131072 (8 N doubles must fit the array), a
+ * null E or F, or a non-finite scale. */
+rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
+                                   double* F, void* stream);
+
 /* ---- introspection, persistence --------------------------------------- */
 
 /* Peak device memory rs_assemble needs for this request (with_grid != 0 adds

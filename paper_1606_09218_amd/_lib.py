@@ -88,6 +88,7 @@ def _load():
         "rs_energy": ([P, P, P, P], C.c_int),
         "rs_forces": ([P, C.c_double, P, P], C.c_int),
         "rs_energy_forces": ([P, P, P, C.c_double, P, P], C.c_int),
+        "rs_energy_forces_noalloc": ([P, P, P, C.c_double, P, P], C.c_int),
         "rs_footprint_bytes": ([C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.c_int64, C.c_int32,
                                 C.c_int32, C.c_int32], C.c_size_t),
         "rs_tensor_info": ([P, C.POINTER(rs_info)], C.c_int),
@@ -128,7 +129,7 @@ def _may_release() -> bool:
 EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim",
             "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
-            "rs_forces", "rs_energy_forces", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
+            "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
             "rs_last_error")
 
@@ -322,6 +323,16 @@ def energy_forces(T: Tensor, E, F, scale: float = 1.0, dEdq=None, stream=None):
     _check(lib.rs_energy_forces(T.handle, _dev_ptr(E, "f64", 1, "E"),
                                 None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
                                 float(scale), _dev_ptr(F, "f64", 3 * N, "F"), _stream_ptr(stream)))
+
+
+def energy_forces_noalloc(T: Tensor, E, F, scale: float = 1.0, dEdq=None, stream=None):
+    """rs_energy_forces_noalloc: as energy_forces, with the scratch in the
+    library's static device array (no device allocation)."""
+    N = T.N
+    _check(lib.rs_energy_forces_noalloc(T.handle, _dev_ptr(E, "f64", 1, "E"),
+                                        None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
+                                        float(scale), _dev_ptr(F, "f64", 3 * N, "F"),
+                                        _stream_ptr(stream)))
 
 
 def tensor_export(T: Tensor, V1=None, V2=None, V3=None, beta=None, stream=None):

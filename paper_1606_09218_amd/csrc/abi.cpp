@@ -445,6 +445,7 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
     int wk = 0;
     if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, device) == hipSuccess && wk > 0)
       c->wall_khz = (double)wk;
+    noalloc_scratch_init(device);
     RS_HIP(hipDeviceGetDefaultMemPool(&c->pool, device));
     uint64_t thr = UINT64_MAX;  // keep freed blocks cached for reuse
     RS_HIP(hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &thr));
@@ -997,6 +998,33 @@ rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double s
     launch_eval_long(T, T->N, T->pos.as<double>(), 1, o, s);
     launch_energy_reduce(T->q.as<double>(), v.as<double>(), sv.as<double>(), T->N, E, dEdq, s);
     launch_forces(T->q.as<double>(), gv.as<double>(), sg.as<double>(), T->N, scale, F, s);
+    return RS_OK;
+  });
+}
+
+rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
+                                   double* F, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && E && F, "null argument");
+    RS_REQUIRE(std::isfinite(scale), "scale must be finite");
+    RS_REQUIRE(8 * T->N <= kNoAllocScratchDoubles,
+               "rs_energy_forces_noalloc: N above " + std::to_string(kNoAllocScratchDoubles / 8) +
+                   " (the size of the library's static scratch array)");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // the device array's address on this device (looked up at context
+    // creation), carved like the buffers of rs_energy_forces; every value
+    // is written before it is read, so nothing needs clearing
+    double* sc = noalloc_scratch(T->ctx->device);
+    const int64_t N = T->N;
+    EvalOut o;
+    o.val = sc;
+    o.grad = sc + N;
+    o.selfv = sc + 4 * N;
+    o.selfg = sc + 5 * N;
+    launch_eval_long(T, N, T->pos.as<double>(), 1, o, s);
+    launch_energy_reduce(T->q.as<double>(), o.val, o.selfv, N, E, dEdq, s);
+    launch_forces(T->q.as<double>(), o.grad, o.selfg, N, scale, F, s);
     return RS_OK;
   });
 }

@@ -321,6 +321,13 @@ void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
                   int n_s, int nb, const int* start, const int* list, const int* active,
                   int64_t active_cap, int num_cu, hipStream_t s);
 
+// k_noalloc.hip: one file-scope device array per GPU for the entry points that
+// allocate nothing (8 MiB: the per-particle evaluations of up to 131072
+// particles); its address per device is looked up once, at context creation
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)1 << 20;
+void noalloc_scratch_init(int device);   // with `device` current; idempotent
+double* noalloc_scratch(int device);     // RS_E_DEVICE if not set up
+
 // k_eval.hip
 // vals[m] (part 0/1/2) and optionally grad (M x 3) and self terms at points
 struct EvalOut {

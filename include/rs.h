@@ -84,9 +84,21 @@ typedef struct {
   int64_t n;
 } rs_grid;
 
+/* Quadrature rule of eq laplace (section 2.2).
+ *  RS_RULE_PAPER_LITERAL: t_k = k h_M, h_M = C0 log(M)/M (eq hM), weights
+ *     folded onto k >= 0: a_0 = h_M a(0)/2, a_k = h_M a(t_k).  Accurate for
+ *     1/r only on a narrow band of r (about [0.3, 2] at R = 20).
+ *  RS_RULE_EXP_SINC: the exponential convergence of eq sinc_conv from the
+ *     substitution t = e^s: M = R - 1 nodes t_k = e^{s_1 + (k-1) h} with
+ *     weights a_k = (2/sqrt(pi)) h t_k a(t_k)/a_Newton, plus t_0 = 0 carrying
+ *     the geometric sum of the nodes left of s_1; the step h and s_1 are
+ *     chosen so that M nodes cover [r_lo, r_hi] with balanced
+ *     discretisation and truncation errors (relative error against 1/r
+ *     about 2e-4 at R = 20, 2e-5 at R = 32 for the default range). */
+typedef enum { RS_RULE_PAPER_LITERAL = 0, RS_RULE_EXP_SINC = 1 } rs_rule;
+
 /* Quadrature and range split (sections 2.2-2.3).
- *  R: number of terms, R = M + 1; t_k = k h_M, h_M = C0 log(M)/M (eq hM),
- *     weights folded onto k >= 0: a_0 = h_M a(0)/2, a_k = h_M a(t_k).
+ *  R: number of terms, R = M + 1, by `rule` (rs_rule).
  *  R_l: long-range terms k = 0..R_l-1 (1 <= R_l <= R-1); -1 = choose by
  *     criterion (A) (eq Split_crit_max) for the support radius sigma = sigma_split.
  *  n_s: odd short-range window width in cells; -1 = the smallest odd n_s with
@@ -101,7 +113,9 @@ typedef struct {
   int32_t n_s;
   double delta_rel;      /* criterion (A) threshold relative to S(0); <= 0 -> 1e-4 */
   double sigma_split;    /* only read when R_l == -1 */
-  double C0;
+  double C0;             /* literal rule only */
+  int32_t rule;          /* rs_rule */
+  double r_lo, r_hi;     /* exp-sinc rule: range of r it is fitted to; <= 0: h and 2 sqrt(3) b */
 } rs_fdesc;
 
 /* How the charge-weighted Gram matrices G_l = U_l diag(|xi|^{2/3}) U_l^T are formed.

@@ -3,6 +3,9 @@
 Section 2.2 (eqs laplace, hM, sinc_Newt, sinc_general) and section 2.3
 (eqs Split_Qpoints, Split_Tens, Split_crit_max).
 
+Two rules are provided: the paper-literal one (literal_table) and one with
+the exponential convergence the paper claims (expsinc_table, reading below).
+
 Readings taken where the paper is ambiguous:
 * The rule sums k = -M..M with a_k = a(t_k) h_M for an integral over R+.
   Read as the trapezoid rule on the whole line for the even integrand,
@@ -88,6 +91,83 @@ def literal_table(kernel: str, R: int, lam: float = 0.5, C0: float = 3.0) -> Tup
     a = h * laplace_weight(kernel, t, lam)
     a[0] *= 0.5
     return t, a
+
+
+def expsinc_table(kernel: str, R: int, r_lo: float, r_hi: float, lam: float = 0.5):
+    """Quadrature with exponentially convergent error for r in [r_lo, r_hi]
+    (the rate claimed in eq sinc_conv), from the substitution t = e^s in
+    eq laplace.  Parity unpinned against the paper's own tables: the paper
+    prints t_k = k h_M, whose convergence on the half line is not
+    exponential, and does not state the substitution it used.
+
+    With t = e^s the Newton integrand is (2/sqrt(pi)) e^{s - r^2 e^{2s}}, in
+    u = s + log r the r-free g(u) = e^{u - e^{2u}} (integral sqrt(pi)/2 over
+    the real line).  The trapezoid rule with step h on the whole line has
+    relative error about exp(-pi^2 / (2h)) (g is analytic in |Im u| < pi/4);
+    M = R - 1 nodes s_1, s_1 + h, ... are kept, and the dropped nodes to the
+    left, where r e^s << 1 and the Gaussian factor is ~1, are summed as a
+    geometric series into one term with t_0 = 0.  With L = -log(eps):
+        h(L)     = pi^2 / (2 (L + log 2))                (discretisation ~ eps)
+        u_l(L)   = (-L - log 0.38) / 3 + h/2              (left tail, ~ e^{3u}/3 ~ eps)
+        u_r(L)   = log(L + 1) / 2                         (right tail e^{-e^{2u}} ~ eps)
+    and L solves (M - 1) h(L) = u_r(L) - u_l(L) + log(r_hi / r_lo), so that
+    the nodes span u_l at r = r_hi to u_r at r = r_lo; s_1 = u_l - log r_hi.
+    Weights: t_0 = 0, a_0 = (2/sqrt(pi)) h e^{s_1} / (e^h - 1);
+    t_k = e^{s_k}, a_k = (2/sqrt(pi)) h t_k.  Yukawa multiplies each weight
+    by exp(-lam^2 / (4 t_k^2)) (a_0 = 0); the sum kernel adds the two.
+    Returns (t, a, L)."""
+    M = R - 1
+    if M < 2:
+        raise ValueError("need R >= 3")
+    if not (0 < r_lo < r_hi):
+        raise ValueError("need 0 < r_lo < r_hi")
+    span = math.log(r_hi / r_lo)
+
+    def h_of(L):
+        return math.pi ** 2 / (2.0 * (L + math.log(2.0)))
+
+    def u_left(L):
+        return (-L - math.log(0.38)) / 3.0 + 0.5 * h_of(L)
+
+    def u_right(L):
+        return 0.5 * math.log(L + 1.0)
+
+    def excess(L):   # node span minus the span the rule must cover; decreasing in L
+        return (M - 1) * h_of(L) - (u_right(L) - u_left(L) + span)
+
+    lo, hi = 0.5, 200.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if excess(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    L = 0.5 * (lo + hi)
+    h = h_of(L)
+    s1 = u_left(L) - math.log(r_hi)
+    t = np.zeros(R)
+    t[1:] = np.exp(s1 + h * np.arange(M))
+    c = 2.0 / SQRT_PI
+    a_newton = np.empty(R)
+    a_newton[0] = c * h * math.exp(s1) / math.expm1(h)
+    a_newton[1:] = c * h * t[1:]
+    yuk = np.zeros(R)
+    yuk[1:] = np.exp(-lam * lam / (4.0 * t[1:] ** 2))
+    if kernel == "newton":
+        a = a_newton
+    elif kernel == "yukawa":
+        a = a_newton * yuk
+    elif kernel == "newton+yukawa":
+        a = a_newton * (1.0 + yuk)
+    else:
+        raise ValueError(kernel)
+    return t, a, L
+
+
+def default_range(b: float, n: int):
+    """[r_lo, r_hi] = [h, 2 sqrt(3) b]: from one grid spacing to the largest
+    distance between two points of the box [-b, b]^3."""
+    return 2.0 * b / n, 2.0 * math.sqrt(3.0) * b
 
 
 def kernel_sum(r, t, a, ks=None):

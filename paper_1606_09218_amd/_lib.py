@@ -19,6 +19,7 @@ RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_RANK_CAP, RS_E_UNSUPPORTED = 
 KERNELS = {"newton": 0, "yukawa": 1, "newton+yukawa": 2}
 PRECS = {"fp64": 0, "mixed_fp16": 1, "mixed_bf16": 2}
 GRAMS = {"identity": 0, "gemm": 1}
+RULES = {"literal": 0, "expsinc": 1}
 SKETCHES = {"gram": 0, "side": 1}
 
 
@@ -39,7 +40,8 @@ class rs_grid(C.Structure):
 class rs_fdesc(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("lambda_", C.c_double), ("R", C.c_int32),
                 ("R_l", C.c_int32), ("n_s", C.c_int32), ("delta_rel", C.c_double),
-                ("sigma_split", C.c_double), ("C0", C.c_double)]
+                ("sigma_split", C.c_double), ("C0", C.c_double), ("rule", C.c_int32),
+                ("r_lo", C.c_double), ("r_hi", C.c_double)]
 
 
 class rs_aopts(C.Structure):
@@ -202,11 +204,13 @@ class Factors:
 
     def __init__(self, ctx: Context, b: float, n: int, R: int, R_l: int = -1, n_s: int = -1,
                  kernel: str = "newton", lam: float = 0.5, delta_rel: float = 1e-4,
-                 sigma_split: float = 0.0, C0: float = 3.0):
+                 sigma_split: float = 0.0, C0: float = 3.0, rule: str = "literal",
+                 r_lo: float = 0.0, r_hi: float = 0.0):
         self.ctx = ctx
         self.grid = rs_grid(float(b), int(n))
         self.fdesc = rs_fdesc(KERNELS[kernel], float(lam), int(R), int(R_l), int(n_s),
-                              float(delta_rel), float(sigma_split), float(C0))
+                              float(delta_rel), float(sigma_split), float(C0), RULES[rule],
+                              float(r_lo), float(r_hi))
         h = C.c_void_p()
         _check(lib.rs_build_factors(ctx.handle, C.byref(self.grid), C.byref(self.fdesc), C.byref(h)))
         self.handle = h

@@ -1,5 +1,6 @@
 // FP64 sinc quadrature of the Laplace-Gauss transform and the range split
-// (sections 2.2-2.3).
+// (sections 2.2-2.3): the paper-literal rule and the exponentially convergent
+// rule with the substitution t = e^s (expsinc_nodes below).
 //
 //   p(z) = int_0^inf a(t) exp(-t^2 z^2) dt                        (eq laplace)
 //   t_k = k h_M,  h_M = C0 log(M)/M,  M = R - 1                   (eq hM)
@@ -28,6 +29,46 @@ static double weight_fn(int kernel, double t, double lambda) {
   throw Error{RS_E_INVALID, "unknown kernel"};
 }
 
+// Nodes and weights of the rule with the substitution t = e^s (reading of
+// eq sinc_conv's exponential rate): the Newton integrand becomes
+// (2/sqrt(pi)) e^{s - r^2 e^{2s}}, r-free in u = s + ln r.  The trapezoid
+// step h leaves a relative discretisation error ~ e^{-pi^2/(2h)}, so the
+// design accuracy is eps(h) = e^{-(pi^2/(2h) - ln 2)}; with Lh = -ln eps(h),
+// the first node must sit at u = (ln(1/0.38) - Lh)/3 + h/2 for r = r_hi (left
+// tail ~ e^{3u}/3) and the last at u = ln(Lh + 1)/2 for r = r_lo (right tail
+// e^{-e^{2u}}).  The step is the one for which M = R - 1 nodes span exactly
+// that range (the span shrinks and the demand grows as h falls: one root,
+// found by bisection).  Nodes left of the first, where e^{-r^2 t^2} ~ 1, are
+// summed as a geometric series into the t_0 = 0 term.
+static void expsinc_nodes(int R, double r_lo, double r_hi, std::vector<double>& t,
+                          std::vector<double>& an) {
+  const int M = R - 1;
+  const double span = std::log(r_hi) - std::log(r_lo);
+  auto Lh = [](double h) { return M_PI * M_PI / (2.0 * h) - std::log(2.0); };
+  auto first_u = [&](double h) { return (-std::log(0.38) - Lh(h)) / 3.0 + 0.5 * h; };
+  auto last_u = [&](double h) { return 0.5 * std::log(Lh(h) + 1.0); };
+  // covered minus required span, increasing in h
+  auto gap = [&](double h) { return (M - 1) * h - (last_u(h) - first_u(h) + span); };
+  // bracket: h at L = 200 (tiny step) and at L = 0.5
+  double hlo = M_PI * M_PI / (2.0 * (200.0 + std::log(2.0)));
+  double hhi = M_PI * M_PI / (2.0 * (0.5 + std::log(2.0)));
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (hlo + hhi);
+    if (gap(mid) < 0) hlo = mid;
+    else hhi = mid;
+  }
+  const double h = 0.5 * (hlo + hhi);
+  const double s1 = first_u(h) - std::log(r_hi);
+  const double c = 2.0 / std::sqrt(M_PI);
+  t.assign(R, 0.0);
+  an.assign(R, 0.0);
+  an[0] = c * h * std::exp(s1) / std::expm1(h);
+  for (int k = 1; k <= M; ++k) {
+    t[k] = std::exp(s1 + (k - 1) * h);
+    an[k] = c * h * t[k];
+  }
+}
+
 Table build_table(const rs_grid& g, const rs_fdesc& f) {
   RS_REQUIRE(g.b > 0 && std::isfinite(g.b), "grid half width b must be positive");
   RS_REQUIRE(g.n >= 8 && g.n % 2 == 0, "grid size n must be even and >= 8");
@@ -36,16 +77,28 @@ Table build_table(const rs_grid& g, const rs_fdesc& f) {
              "unknown kernel");
   if (f.kernel != RS_NEWTON)
     RS_REQUIRE(f.lambda > 0 && std::isfinite(f.lambda), "Yukawa lambda must be positive");
-  const double C0 = f.C0 > 0 ? f.C0 : 3.0;
-  const int M = f.R - 1;
-  const double hM = C0 * std::log((double)M) / (double)M;
+  RS_REQUIRE(f.rule == RS_RULE_PAPER_LITERAL || f.rule == RS_RULE_EXP_SINC, "unknown quadrature rule");
   Table T;
   T.R = f.R;
   T.t.resize(f.R);
   T.a.resize(f.R);
-  for (int k = 0; k < f.R; ++k) {
-    T.t[k] = k * hM;
-    T.a[k] = hM * weight_fn(f.kernel, T.t[k], f.lambda) * (k == 0 ? 0.5 : 1.0);
+  if (f.rule == RS_RULE_PAPER_LITERAL) {
+    const double C0 = f.C0 > 0 ? f.C0 : 3.0;
+    const int M = f.R - 1;
+    const double hM = C0 * std::log((double)M) / (double)M;
+    for (int k = 0; k < f.R; ++k) {
+      T.t[k] = k * hM;
+      T.a[k] = hM * weight_fn(f.kernel, T.t[k], f.lambda) * (k == 0 ? 0.5 : 1.0);
+    }
+  } else {
+    const double r_lo = f.r_lo > 0 ? f.r_lo : 2.0 * g.b / (double)g.n;
+    const double r_hi = f.r_hi > 0 ? f.r_hi : 2.0 * std::sqrt(3.0) * g.b;
+    RS_REQUIRE(std::isfinite(r_lo) && std::isfinite(r_hi) && r_lo < r_hi, "need 0 < r_lo < r_hi");
+    std::vector<double> an;
+    expsinc_nodes(f.R, r_lo, r_hi, T.t, an);
+    // the Newton weight (2/sqrt(pi)) h t_k times a(t_k) / a_Newton
+    const double c = 2.0 / std::sqrt(M_PI);
+    for (int k = 0; k < f.R; ++k) T.a[k] = an[k] * (weight_fn(f.kernel, T.t[k], f.lambda) / c);
   }
   T.S0 = 0.0;
   for (int k = 0; k < f.R; ++k) T.S0 += T.a[k];

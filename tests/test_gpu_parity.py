@@ -91,6 +91,63 @@ def test_quadrature_table_matches_oracle(rsm, ctx):
         assert np.max(np.abs(np.array(f.t) - t)) <= 1e-15 * t.max()
         assert np.max(np.abs(np.array(f.a) - a)) <= 1e-15 * a.max()
         assert f.n_s == quadrature.derive_window(t, a, 8, 1e-4, 20.0 / 128)
+    # the exponentially convergent rule: same nodes and weights to rounding
+    # (each side solves its own one-dimensional balance equation)
+    for kernel, R, b, n, rng in [("newton", 20, 10.0, 128, None), ("yukawa", 28, 18.0, 512, None),
+                                 ("newton+yukawa", 32, 25.0, 1024, (0.02, 70.0))]:
+        r_lo, r_hi = rng if rng else quadrature.default_range(b, n)
+        f = rsm.Factors(ctx, b, n, R, R // 2, -1, kernel=kernel, lam=0.5, rule="expsinc",
+                        r_lo=rng[0] if rng else 0.0, r_hi=rng[1] if rng else 0.0)
+        t, a, _ = quadrature.expsinc_table(kernel, R, r_lo, r_hi, 0.5)
+        assert np.max(np.abs(np.array(f.t) - t) / np.maximum(t, 1e-300)) <= 1e-13
+        assert np.max(np.abs(np.array(f.a) - a)) <= 1e-13 * a.max()
+        assert f.n_s == quadrature.derive_window(t, a, R // 2, 1e-4, 2.0 * b / n)
+
+
+def test_expsinc_grid_parity_and_true_potential(rsm, ctx):
+    """With the exponentially convergent rule the RS grid approximates the
+    actual Coulomb potential: (1) parity with the oracle given the table
+    (1e-6); (2) at every grid point at least 2h from all particles, the
+    pointwise gap to the direct sum sum_nu z_nu / |x - x_nu| stays within the
+    budget the oracle derives: the rule's measured relative error times
+    sum |z_nu| / r_nu, plus the short terms cut at the window edge
+    (criterion (A): delta each), plus 1e-6 of the maximum for the Tucker
+    truncation."""
+    s = workloads.tiny_system(93, 24, 8.0, 96, 24, 10, None, min_sep=0.8, box_frac=0.5)
+    say(f"exp-sinc grid {s.name}")
+    sigma, delta_rel = 0.8, 1e-6
+    f = rsm.Factors(ctx, s.b, s.n, s.R, -1, -1, delta_rel=delta_rel, sigma_split=sigma,
+                    rule="expsinc")
+    t, a, _ = quadrature.expsinc_table("newton", s.R, *quadrature.default_range(s.b, s.n))
+    S0 = float(np.sum(a))
+    R_l = quadrature.split_criterion_A(t, a, sigma, delta_rel * S0)
+    n_s = quadrature.derive_window(t, a, R_l, delta_rel, s.h)
+    assert (f.R_l, f.n_s) == (R_l, n_s)
+    ref = rs.assemble(s.b, s.n, s.pos, s.q, t, a, R_l, n_s, s.eps_tucker)
+    g = torch.empty(s.n ** 3, dtype=torch.float64, device="cuda")
+    T = rsm.assemble(ctx, f, dev(s.pos), dev(s.q), g, rsm.make_aopts(s.eps_tucker, fixed_ranks=ref.ranks))
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().reshape(s.n, s.n, s.n)
+    full = ref.full_grid()
+    err = rel_linf(gg, full)
+    say(f"  R_l {R_l} n_s {n_s} ranks {ref.ranks} parity rel-Linf {err:.2e}")
+    assert err <= TOL
+    # against the direct sum
+    r_lo, r_hi = quadrature.default_range(s.b, s.n)
+    rr = np.exp(np.linspace(np.log(r_lo), np.log(r_hi), 4000))
+    eq = float(np.max(np.abs(quadrature.kernel_sum(rr, t, a) * rr - 1.0)))
+    x = ogrid.cell_centres(s.b, s.n)
+    X = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(-1, 3)
+    d = np.sqrt(((X[:, None, :] - s.pos[None, :, :]) ** 2).sum(-1))
+    keep = d.min(1) >= 2 * s.h
+    direct = (s.q[None, :] / d).sum(1)
+    budget = eq * (np.abs(s.q)[None, :] / d).sum(1) + delta_rel * S0 * np.abs(s.q).sum() \
+        + 1e-6 * np.max(np.abs(direct[keep]))
+    gap = np.abs(gg.reshape(-1) - direct)
+    worst = float(np.max((gap / budget)[keep]))
+    say(f"  rule error {eq:.2e}; gap to the direct 1/r sum within {worst:.2f} of its budget at "
+        f"{int(keep.sum())} points; rel-Linf {np.max(gap[keep]) / np.max(np.abs(direct[keep])):.2e}")
+    assert worst <= 1.0
 
 
 @pytest.mark.parametrize("case", [

@@ -158,3 +158,89 @@ def test_initial_canonical_rank_matches_paper_tables(row):
     t = np.arange(terms) * 0.3
     U = rhosvd.side_matrix(10.0, 8, coords, t)
     assert U.shape[1] == rank
+
+
+# ---- the exponentially convergent rule (substitution t = e^s) ----------------
+
+def _rel_err_mp(kernel, t, a, r_lo, r_hi, lam=0.5, m=400):
+    """max |S(r)/p(r) - 1| over a log grid of [r_lo, r_hi], p from mpmath."""
+    mpmath.mp.dps = 30
+    worst = 0.0
+    for x in np.exp(np.linspace(np.log(r_lo), np.log(r_hi), m)):
+        xm = mpmath.mpf(float(x))
+        if kernel == "newton":
+            p = 1 / xm
+        elif kernel == "yukawa":
+            p = mpmath.exp(-lam * xm) / xm
+        else:
+            p = (1 + mpmath.exp(-lam * xm)) / xm
+        S = mpmath.fsum(mpmath.mpf(float(ak)) * mpmath.exp(-(mpmath.mpf(float(tk)) * xm) ** 2)
+                        for tk, ak in zip(t, a))
+        worst = max(worst, float(abs(S / p - 1)))
+    return worst
+
+
+@pytest.mark.parametrize("R,b,n", [(20, 10.0, 128), (24, 12.0, 512), (32, 25.0, 1024)])
+def test_expsinc_newton_error_within_its_design_bound(R, b, n):
+    """Against 1/r evaluated in mpmath: the maximum relative error on
+    [h, 2 sqrt(3) b] stays within three times the rule's own design
+    accuracy e^{-L} and below 3e-4 (R >= 20)."""
+    r_lo, r_hi = Q.default_range(b, n)
+    t, a, L = Q.expsinc_table("newton", R, r_lo, r_hi)
+    err = _rel_err_mp("newton", t, a, r_lo, r_hi)
+    assert err <= 3.0 * math.exp(-L)
+    assert err <= 3e-4
+    assert np.all(np.diff(t) > 0) and t[0] == 0.0 and np.all(a > 0)
+
+
+def test_expsinc_converges_exponentially_in_sqrt_M():
+    """The error falls like e^{-beta sqrt(M)} (eq sinc_conv): log(err) is
+    decreasing and close to linear in sqrt(M) with a negative slope."""
+    r_lo, r_hi = Q.default_range(12.0, 512)
+    Ms, errs = [], []
+    for R in (12, 16, 20, 24, 28, 32, 40):
+        t, a, _ = Q.expsinc_table("newton", R, r_lo, r_hi)
+        Ms.append(R - 1)
+        errs.append(_rel_err_mp("newton", t, a, r_lo, r_hi, m=200))
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+    slope, icept = np.polyfit(np.sqrt(Ms), np.log(errs), 1)
+    assert slope < -1.0
+    resid = np.log(errs) - (slope * np.sqrt(Ms) + icept)
+    assert np.max(np.abs(resid)) < 1.0
+
+
+def test_expsinc_tail_weight_is_the_sum_of_the_dropped_nodes():
+    """a_0 (t_0 = 0) equals the trapezoid weights h (2/sqrt(pi)) e^{s} of the
+    nodes s_1 - h, s_1 - 2h, ... summed by brute force."""
+    t, a, L = Q.expsinc_table("newton", 24, 0.05, 40.0)
+    s1 = math.log(t[1])
+    h = math.log(t[2]) - math.log(t[1])
+    brute = sum(2.0 / math.sqrt(math.pi) * h * math.exp(s1 - j * h) for j in range(1, 2000))
+    assert abs(a[0] - brute) <= 1e-14 * brute
+    assert np.allclose(np.diff(np.log(t[1:])), h, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("kernel", ["yukawa", "newton+yukawa"])
+def test_expsinc_yukawa_against_mpmath(kernel):
+    """The screened kernels with the same nodes (R = 28, lam = 0.5), against
+    mpmath: the Newton-plus-Yukawa sum to 1e-3 relative on [h, 2 sqrt(3) b];
+    Yukawa alone to 1e-3 relative on [h, 5] and, on the whole range, to
+    1e-4 on the scale of 1/r (|S - p| r), since e^{-lam r}/r itself falls
+    to 1e-7 of 1/r there; the Yukawa weight at t_0 = 0 is 0."""
+    r_lo, r_hi = Q.default_range(18.0, 512)
+    t, a, _ = Q.expsinc_table(kernel, 28, r_lo, r_hi, lam=0.5)
+    tn, an, _ = Q.expsinc_table("newton", 28, r_lo, r_hi)
+    assert np.array_equal(t, tn)
+    if kernel == "newton+yukawa":
+        assert _rel_err_mp(kernel, t, a, r_lo, r_hi, m=300) <= 1e-3
+        return
+    assert a[0] == 0.0
+    assert _rel_err_mp(kernel, t, a, r_lo, 5.0, m=300) <= 1e-3
+    mpmath.mp.dps = 30
+    worst = 0.0
+    for x in np.exp(np.linspace(np.log(r_lo), np.log(r_hi), 300)):
+        xm = mpmath.mpf(float(x))
+        S = mpmath.fsum(mpmath.mpf(float(ak)) * mpmath.exp(-(mpmath.mpf(float(tk)) * xm) ** 2)
+                        for tk, ak in zip(t, a))
+        worst = max(worst, float(abs(S - mpmath.exp(-0.5 * xm) / xm) * xm))
+    assert worst <= 1e-4

@@ -71,8 +71,13 @@ typedef enum { RS_NEWTON = 0, RS_YUKAWA = 1, RS_NEWTON_PLUS_YUKAWA = 2 } rs_kern
  *    expansion contractions, quadrature table, point evaluation and energy
  *    reduction stay FP64.  The grid is FP32.
  *  RS_MIXED_BF16: as RS_MIXED_FP16 with three-way split BF16 operands (six
- *    products). */
-typedef enum { RS_FP64 = 0, RS_MIXED_FP16 = 1, RS_MIXED_BF16 = 2 } rs_prec;
+ *    products).
+ *  RS_FP32: assembled as RS_MIXED_FP16; point values, the energy's per-
+ *    particle terms and the forces are evaluated from FP32 copies of the
+ *    Tucker field in FP32 arithmetic (section 4.3's energy and forces at
+ *    single precision), with the energy's final reduction and every output
+ *    in FP64. */
+typedef enum { RS_FP64 = 0, RS_MIXED_FP16 = 1, RS_MIXED_BF16 = 2, RS_FP32 = 3 } rs_prec;
 
 typedef struct rs_ctx rs_ctx;
 typedef struct rs_factors rs_factors;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "librs.so")
 
 RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_RANK_CAP, RS_E_UNSUPPORTED = range(6)
 KERNELS = {"newton": 0, "yukawa": 1, "newton+yukawa": 2}
-PRECS = {"fp64": 0, "mixed_fp16": 1, "mixed_bf16": 2}
+PRECS = {"fp64": 0, "mixed_fp16": 1, "mixed_bf16": 2, "fp32": 3}
 GRAMS = {"identity": 0, "gemm": 1}
 RULES = {"literal": 0, "expsinc": 1}
 SKETCHES = {"gram": 0, "side": 1}

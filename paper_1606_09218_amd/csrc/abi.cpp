@@ -221,13 +221,28 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   P.sketch = d.sketch;
   RS_REQUIRE(P.sketch == 0 || P.sketch == 1, "sketch must be 0 (Gram) or 1 (side matrix)");
   RS_REQUIRE(P.gram == RS_GRAM_IDENTITY || P.gram == RS_GRAM_GEMM, "unknown Gram method");
-  RS_REQUIRE(P.prec == RS_FP64 || P.prec == RS_MIXED_FP16 || P.prec == RS_MIXED_BF16,
+  RS_REQUIRE(P.prec == RS_FP64 || P.prec == RS_MIXED_FP16 || P.prec == RS_MIXED_BF16 ||
+                 P.prec == RS_FP32,
              "unknown precision");
   RS_REQUIRE(P.R - P.R_l <= 64 && P.R_l <= 64, "at most 64 long and 64 short terms");
   return P;
 }
 
 static int bricks_per_axis(int64_t n) { return (int)((n + 7) / 8); }
+
+// The contractions' arithmetic of an assembly precision: RS_FP32 assembles
+// with the split-FP16 contractions (and evaluates its field in FP32).
+static int contraction_prec(int prec) { return prec == RS_FP32 ? RS_MIXED_FP16 : prec; }
+
+// FP32 copies of T2 and V3 for the FP32 evaluation of RS_FP32 tensors.
+static void make_fp32_field(rs_tensor* T, hipStream_t s) {
+  if (T->prec != RS_FP32) return;
+  const int64_t nt2 = T->n * T->n * T->r[2], nv3 = T->n * T->r[2];
+  T->T2f = DevBuf((size_t)nt2 * sizeof(float), s);
+  T->V3f = DevBuf((size_t)nv3 * sizeof(float), s);
+  launch_to_float(T->T2.as<double>(), nt2, T->T2f.as<float>(), s);
+  launch_to_float(T->Q[2].as<double>(), nv3, T->V3f.as<float>(), s);
+}
 
 // Record the start of `stage` (and so the end of the previous one) when the
 // tensor carries timing events.
@@ -375,7 +390,7 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
   gemm64(expand2_gemm(T, X), ncu, (double*)(scratch + e.wk2), s);
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
-    grid_mixed(T->prec, T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
+    grid_mixed(contraction_prec(T->prec), T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
                scratch + e.wkg, ncu, s);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
@@ -916,12 +931,13 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       core64(at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
              T->beta.as<double>(), ncu, at(o_core), s, kt);
     } else {
-      core_mixed(P.prec, at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
+      core_mixed(contraction_prec(P.prec), at(o_ut[0]), at(o_ut[1]), at(o_ut[2]), xi.as<double>(), r1, r2, r3, K,
                  T->beta.as<double>(), ncu, at(o_core), s, kt);
     }
 
     // (a7) T2 and the grid
     build_expansion(T.get(), grid_out, ab + o_exp, s);
+    make_fp32_field(T.get(), s);
 
     *out = T.release();
     return (*out)->rank_capped ? RS_E_RANK_CAP : RS_OK;
@@ -1098,7 +1114,8 @@ rs_status rs_tensor_info(const rs_tensor* T, rs_info* info) {
     I.S_l0 = T->table.S_l0;
     I.tucker_storage = (int64_t)T->r[0] * T->r[1] * T->r[2] + T->n * (T->r[0] + T->r[1] + T->r[2]);
     size_t bytes = T->pos.bytes + T->q.bytes + T->t_dev.bytes + T->a_dev.bytes + T->beta.bytes +
-                   T->T2.bytes + T->brick_start.bytes + T->brick_list.bytes + T->brick_active.bytes;
+                   T->T2.bytes + T->T2f.bytes + T->V3f.bytes + T->brick_start.bytes +
+                   T->brick_list.bytes + T->brick_active.bytes;
     for (int l = 0; l < 3; ++l) bytes += T->Q[l].bytes;
     I.device_bytes = (int64_t)bytes;
     I.rank_capped = T->rank_capped;
@@ -1287,6 +1304,7 @@ rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
     T->T2 = DevBuf((size_t)T->n * T->n * T->r[2] * sizeof(double), s);
     DevBuf scratch(expansion_scratch(T.get(), false).total, s);
     build_expansion(T.get(), nullptr, scratch.as<char>(), s);
+    make_fp32_field(T.get(), s);
     RS_HIP(hipStreamSynchronize(s));
     *out = T.release();
     return RS_OK;

@@ -22,6 +22,8 @@ constexpr int PMAX = 8;        // largest interpolation order
 struct EvalDev {
   const double* T2;    // n x n x r3
   const double* V3;    // n x r3 row-major
+  const float* T2f;    // FP32 copies (FP32 evaluation), or null
+  const float* V3f;
   const double* t;     // R
   const double* a;     // R
   int64_t n;
@@ -65,15 +67,25 @@ __device__ __forceinline__ void stencil(double y, double b, int64_t n, int& star
   }
 }
 
-__device__ __forceinline__ double wsum(double v) {
+template <class VT>
+__device__ __forceinline__ VT wsum(VT v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
+template <class VT> __device__ __forceinline__ const VT* field_t2(const EvalDev& e);
+template <> __device__ __forceinline__ const double* field_t2<double>(const EvalDev& e) { return e.T2; }
+template <> __device__ __forceinline__ const float* field_t2<float>(const EvalDev& e) { return e.T2f; }
+template <class VT> __device__ __forceinline__ const VT* field_v3(const EvalDev& e);
+template <> __device__ __forceinline__ const double* field_v3<double>(const EvalDev& e) { return e.V3; }
+template <> __device__ __forceinline__ const float* field_v3<float>(const EvalDev& e) { return e.V3f; }
+
 // One wave per point; lanes over the rank index c (NC values each).  The
 // stencil order P and NC are compile-time constants, so the P^2 rows of T2
-// are addressed statically and their loads are all issued up front.
-template <int P, int NC>
+// are addressed statically and their loads are all issued up front.  VT is
+// the arithmetic of the field contraction and of the self terms (double, or
+// float for the FP32 evaluation); the stencil weights are formed in FP64.
+template <int P, int NC, class VT>
 __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
                                                         const double* __restrict__ pts,
                                                         int with_self, double* __restrict__ val,
@@ -85,22 +97,30 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
   if (pt >= M) return;
   double y[3];
   int s[3];
-  double L[3][P], dL[3][P];
+  VT L[3][P], dL[3][P];
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
+    double Ld[P], dLd[P];
     y[l] = pts[3 * pt + l];
-    stencil<P>(y[l], e.b, e.n, s[l], L[l], dL[l]);
+    stencil<P>(y[l], e.b, e.n, s[l], Ld, dLd);
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      L[l][m] = (VT)Ld[m];
+      dL[l][m] = (VT)dLd[m];
+    }
   }
   const int r3 = e.r3;
-  double q3[NC], dq3[NC];
+  const VT* V3 = field_v3<VT>(e);
+  const VT* T2 = field_t2<VT>(e);
+  VT q3[NC], dq3[NC];
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
     const int c = lane + 64 * u;
-    double qa = 0.0, qd = 0.0;
+    VT qa = 0, qd = 0;
     if (c < r3) {
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        const double v = e.V3[(int64_t)(s[2] + m) * r3 + c];
+        const VT v = V3[(int64_t)(s[2] + m) * r3 + c];
         qa += L[2][m] * v;
         qd += dL[2][m] * v;
       }
@@ -108,21 +128,21 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
     q3[u] = qa;
     dq3[u] = qd;
   }
-  double v = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+  VT v = 0, g1 = 0, g2 = 0, g3 = 0;
 #pragma unroll
   for (int m1 = 0; m1 < P; ++m1) {
 #pragma unroll
     for (int m2 = 0; m2 < P; ++m2) {
-      const double* row = e.T2 + ((int64_t)(s[0] + m1) * e.n + (s[1] + m2)) * r3;
-      double d = 0.0, dd = 0.0;
+      const VT* row = T2 + ((int64_t)(s[0] + m1) * e.n + (s[1] + m2)) * r3;
+      VT d = 0, dd = 0;
 #pragma unroll
       for (int u = 0; u < NC; ++u) {
         const int c = lane + 64 * u;
-        const double tv = c < r3 ? row[c] : 0.0;
+        const VT tv = c < r3 ? row[c] : (VT)0;
         d += tv * q3[u];
         dd += tv * dq3[u];
       }
-      const double w12 = L[0][m1] * L[1][m2];
+      const VT w12 = L[0][m1] * L[1][m2];
       v += w12 * d;
       g1 += dL[0][m1] * L[1][m2] * d;
       g2 += L[0][m1] * dL[1][m2] * d;
@@ -135,25 +155,24 @@ __global__ __launch_bounds__(256) void eval_long_kernel(EvalDev e, int64_t M,
     g2 = wsum(g2);
     g3 = wsum(g3);
   }
-  double sv = 0.0, sg[3] = {0.0, 0.0, 0.0};
+  VT sv = 0, sg[3] = {0, 0, 0};
   if (with_self) {
     // lanes over the long-range terms k < R_l (R_l <= 64)
     const double h = 2.0 * e.b / (double)e.n;
-    double phi[3] = {0, 0, 0}, dphi[3] = {0, 0, 0};
+    VT phi[3] = {0, 0, 0}, dphi[3] = {0, 0, 0};
     if (lane < e.R_l) {
-      const double tk = e.t[lane];
+      const VT tk = (VT)e.t[lane];
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-          const double x = -e.b + ((double)(s[l] + m) + 0.5) * h;
-          const double d = x - y[l];
-          const double g = exp(-(tk * tk) * (d * d));
+          const VT d = (VT)((-e.b + ((double)(s[l] + m) + 0.5) * h) - y[l]);
+          const VT g = exp(-(tk * tk) * (d * d));
           phi[l] += L[l][m] * g;
           dphi[l] += dL[l][m] * g;
         }
       }
-      const double ak = e.a[lane];
+      const VT ak = (VT)e.a[lane];
       sv = ak * phi[0] * phi[1] * phi[2];
       sg[0] = ak * dphi[0] * phi[1] * phi[2];
       sg[1] = ak * phi[0] * dphi[1] * phi[2];
@@ -181,14 +200,22 @@ static void launch_eval_p(const EvalDev& e, int64_t M, const double* pts, int wi
   const int waves = 4;
   const dim3 grid((unsigned)((M + waves - 1) / waves)), block(64 * waves);
   const int nc = (e.r3 + 63) / 64;
-#define RS_EVAL(NC)                                                                               \
-  hipLaunchKernelGGL((eval_long_kernel<P, NC>), grid, block, 0, s, e, M, pts, with_self, out.val, \
-                     out.grad, out.selfv, out.selfg)
-  if (nc <= 1) RS_EVAL(1);
-  else if (nc <= 2) RS_EVAL(2);
-  else if (nc <= 4) RS_EVAL(4);
-  else if (nc <= 8) RS_EVAL(8);
-  else RS_EVAL(16);
+#define RS_EVAL(NC, VT)                                                                           \
+  hipLaunchKernelGGL((eval_long_kernel<P, NC, VT>), grid, block, 0, s, e, M, pts, with_self,      \
+                     out.val, out.grad, out.selfv, out.selfg)
+  if (e.T2f) {
+    if (nc <= 1) RS_EVAL(1, float);
+    else if (nc <= 2) RS_EVAL(2, float);
+    else if (nc <= 4) RS_EVAL(4, float);
+    else if (nc <= 8) RS_EVAL(8, float);
+    else RS_EVAL(16, float);
+  } else {
+    if (nc <= 1) RS_EVAL(1, double);
+    else if (nc <= 2) RS_EVAL(2, double);
+    else if (nc <= 4) RS_EVAL(4, double);
+    else if (nc <= 8) RS_EVAL(8, double);
+    else RS_EVAL(16, double);
+  }
 #undef RS_EVAL
 }
 
@@ -202,6 +229,8 @@ void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with
   EvalDev e;
   e.T2 = T->T2.as<double>();
   e.V3 = T->Q[2].as<double>();
+  e.T2f = T->T2f.as<float>();
+  e.V3f = T->V3f.as<float>();
   e.t = T->t_dev.as<double>();
   e.a = T->a_dev.as<double>();
   e.n = T->n;
@@ -301,6 +330,18 @@ __global__ void forces_kernel(const double* __restrict__ q, const double* __rest
   if (e >= 3 * N) return;
   const int64_t j = e / 3;
   F[e] = -scale * q[j] * (gv[e] - q[j] * gg[e]);
+}
+
+__global__ void to_float_kernel(const double* __restrict__ in, int64_t count, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+void launch_to_float(const double* in, int64_t count, float* out, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(to_float_kernel, dim3(blocks), dim3(256), 0, s, in, count, out);
 }
 
 void launch_forces(const double* q, const double* gradv, const double* gradg, int64_t N,

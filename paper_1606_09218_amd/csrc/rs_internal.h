@@ -132,6 +132,7 @@ struct rs_tensor {
   rs::DevBuf Q[3];               // n x r_l row-major
   rs::DevBuf beta;               // r1 x r2 x r3
   rs::DevBuf T2;                 // n x n x r3: beta x_1 V1 x_2 V2 (long-range, modes 1,2 expanded)
+  rs::DevBuf T2f, V3f;           // FP32 copies of T2 and V3 (RS_FP32 tensors only)
   // short-range binning: bricks of 8^3 cells; pairs (brick, particle) sorted by particle
   int nb = 0;                    // bricks per axis
   int64_t n_pairs = 0;
@@ -336,8 +337,12 @@ struct EvalOut {
   double* selfv = nullptr;     // self term g_j (when points are the particles), or null
   double* selfg = nullptr;     // M x 3 gradient of the self term, or null
 };
+// With FP32 copies of the field (RS_FP32 tensors) the long-range values,
+// gradients and self terms are evaluated in FP32 arithmetic (outputs FP64).
 void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with_self,
                       const EvalOut& out, hipStream_t s);
+// out[i] = (float)in[i]
+void launch_to_float(const double* in, int64_t count, float* out, hipStream_t s);
 void launch_eval_short(const rs_tensor* T, int64_t M, const double* pts, double* vals,
                        int accumulate, hipStream_t s);
 // E = 1/2 sum_j q_j (v_j - q_j g_j); dEdq_j = v_j - q_j g_j (optional)

@@ -350,6 +350,77 @@ def _serve_trace(ex, trace, n_requests, n_slots, prec):
     return out
 
 
+def serving_full(n_slots: int = 4, sample_every: int = 125):
+    """The serving workload in full: the 2000-request Poisson trace (200/s)
+    replayed in real time with split-FP16 and with FP64 assemblies (same
+    slots, same HBM budget), the first 400 requests at 20/s (below one GPU's
+    capacity, so that latency is service time rather than queueing) in both
+    precisions, and the split-FP16 against the FP64 result (grid rel-Linf,
+    energy) of every `sample_every`-th request, each run alone."""
+    import torch
+
+    import paper_1606_09218_amd as rsm
+    import workloads
+    from paper_1606_09218_amd.serve import GpuExecutor, Server, summarize
+    full = workloads.cfg5_trace(seed=5, n_requests=2000, rate_hz=200.0)
+    slow = workloads.cfg5_trace(seed=5, n_requests=400, rate_hz=20.0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+    out = {"slots": n_slots, "hbm_budget_GB": round(budget / 2**30, 1), "r_max": 384,
+           "trace": "seed 5: N log-uniform in [32, 20000], n in {256, 512, 1024}, R in 24..32"}
+    for prec in ("mixed_fp16", "fp64"):
+        ex = GpuExecutor(0, prec=prec, r_max=384)
+        try:
+            for r in full:
+                ex.factors(r.system())
+            res = {}
+            for label, trace in (("poisson_200_per_s_2000", full), ("poisson_20_per_s_400", slow)):
+                print(f"serving: {prec} {label}", file=sys.stderr, flush=True)
+                srv = Server(ex, n_slots=n_slots, hbm_budget=budget)
+                recs = srv.run_trace(trace, progress_every=200)
+                sm = summarize(recs)
+                sm["peak_concurrency"] = srv.peak_concurrency
+                errs = [r.error for r in recs if r.error]
+                if errs:
+                    sm["first_error"] = errs[0]
+                res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
+            out[prec] = res
+        finally:
+            ex.close()
+    # split-FP16 against FP64 for a sample of requests, each alone
+    ctx = rsm.Context(0)
+    samples = []
+    try:
+        for req in full[::sample_every]:
+            sysm = req.system()
+            f = rsm.Factors(ctx, sysm.b, sysm.n, sysm.R, sysm.R_l, -1, delta_rel=sysm.delta_rel)
+            pos = torch.tensor(sysm.pos, dtype=torch.float64, device="cuda")
+            q = torch.tensor(sysm.q, dtype=torch.float64, device="cuda")
+            g64 = torch.empty(sysm.n ** 3, dtype=torch.float64, device="cuda")
+            g32 = torch.empty(sysm.n ** 3, dtype=torch.float32, device="cuda")
+            Es = {}
+            for prec, g in (("fp64", g64), ("mixed_fp16", g32)):
+                T = rsm.assemble(ctx, f, pos, q, g, rsm.make_aopts(sysm.eps_tucker, r_max=min(384, sysm.n),
+                                                                     prec=prec))
+                E = torch.empty(1, dtype=torch.float64, device="cuda")
+                rsm.energy(T, E)
+                Es[prec] = (E.item(), list(T.info().ranks))
+                T.free()
+            samples.append({"idx": req.idx, "N": sysm.N, "n": sysm.n, "R": sysm.R,
+                            "ranks": Es["fp64"][1], "same_ranks": Es["fp64"][1] == Es["mixed_fp16"][1],
+                            "grid_rel_linf": rel_linf_chunked(g32, g64),
+                            "energy_rel_err": abs(Es["mixed_fp16"][0] - Es["fp64"][0]) / abs(Es["fp64"][0])})
+            del g64, g32
+            f.close()
+            torch.cuda.empty_cache()
+    finally:
+        ctx.close()
+    out["mixed_vs_fp64_samples"] = samples
+    out["mixed_vs_fp64_worst"] = {"grid_rel_linf": max(x["grid_rel_linf"] for x in samples),
+                                  "energy_rel_err": max(x["energy_rel_err"] for x in samples)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +437,8 @@ def main():
                     help="also run a plain device copy of known size (for PMC scaling)")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="print only the oracle CPU baseline (no GPU use)")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="print only the full serving measurement (both precisions, two rates)")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         s, _, _ = workload(args.workload)
@@ -375,6 +448,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(every workload here runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving_full:
+        print(json.dumps({"serving_full": serving_full()}), flush=True)
+        return
 
     cpu = None if args.no_cpu_baseline else cpu_baseline_child(args.workload)
 

@@ -17,6 +17,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import sys
 import threading
 import time
 from typing import Any, Callable, Dict, List, Optional
@@ -86,14 +87,17 @@ class Server:
 
     # -- replay of an arrival trace ------------------------------------------
     def run_trace(self, requests: List[Any], arrival_of: Callable[[Any], float] = lambda r: r.arrival_s,
-                  time_scale: float = 1.0) -> List[Record]:
+                  time_scale: float = 1.0, progress_every: int = 0) -> List[Record]:
         """Replay `requests` with their arrival offsets (seconds, scaled by
-        time_scale) in real time and return one Record per request."""
+        time_scale) in real time and return one Record per request.  With
+        progress_every > 0 a line goes to stderr each time that many more
+        requests have finished."""
         order = sorted(range(len(requests)), key=lambda i: arrival_of(requests[i]))
         t0 = self.clock()
         recs = [Record(i, t0 + arrival_of(requests[i]) * time_scale) for i in range(len(requests))]
         pending: collections.deque = collections.deque()
         nxt = 0
+        reported = 0
         threads = []
         for i, r in enumerate(requests):
             recs[i].footprint = int(self.ex.footprint(r))
@@ -128,6 +132,12 @@ class Server:
                     wait = max(0.0, recs[order[nxt]].arrival - self.clock())
                 if nxt < len(order) or pending or self._concurrency > 0:
                     self._cv.wait(timeout=wait if wait is not None else 1.0)
+                if progress_every > 0:
+                    done = sum(1 for r in recs if r.done == r.done)   # done is NaN until set
+                    if done >= reported + progress_every:
+                        reported = done - done % progress_every
+                        print(f"serving: {done} of {len(recs)} requests done", file=sys.stderr,
+                              flush=True)
         for th in threads:
             th.join()
         return recs
@@ -155,7 +165,7 @@ class GpuExecutor(Executor):
     slot's own HIP stream through librs.so."""
 
     def __init__(self, device: int = 0, prec: str = "mixed_fp16", with_grid: bool = True,
-                 eps_tucker: float = 1e-6, r_max: int = 384):
+                 eps_tucker: float = 1e-6, r_max: int = 384, digest: bool = False):
         import torch
 
         from . import _lib
@@ -167,6 +177,7 @@ class GpuExecutor(Executor):
         self.with_grid = with_grid
         self.eps = eps_tucker
         self.r_max = r_max
+        self.digest = digest
         self._factors: Dict[tuple, Any] = {}
         self._lock = threading.Lock()
 
@@ -223,6 +234,18 @@ class GpuExecutor(Executor):
             inf = T.info()
             out = {"energy": E.item(), "ranks": list(inf.ranks), "N": sysm.N, "n": sysm.n,
                    "status": T.status}
+            if self.digest and grid is not None:
+                out["grid_digest"] = grid_digest(grid)
             T.free()
             del grid
         return out
+
+
+def grid_digest(grid) -> tuple:
+    """A few exact reductions of a device grid (sum in FP64, max |value|,
+    and every 9973rd value), computed on the device: two results with the
+    same digest agree bitwise on all sampled values and almost surely
+    everywhere."""
+    g = grid.double()
+    return (float(g.sum().item()), float(g.abs().max().item()),
+            tuple(float(v) for v in g[::9973][:256].cpu().tolist()))

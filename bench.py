@@ -431,7 +431,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 leg")
     ap.add_argument("--secondary", default="cfg2",
                     help="another workload timed in FP64 and split FP16 ('' to skip)")
-    ap.add_argument("--serve-requests", type=int, default=200,
+    ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving trace to replay (0: skip the serving leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")

@@ -17,6 +17,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import queue
 import sys
 import threading
 import time
@@ -57,6 +58,11 @@ class Executor:
 
 
 class Server:
+    """Continuous batching over `n_slots` slots.  Each slot has one worker
+    thread for the whole replay (started by run_trace and joined before it
+    returns), so the number of host threads that call into the GPU runtime
+    is the number of slots, not the number of requests."""
+
     def __init__(self, executor: Executor, n_slots: int = 4, hbm_budget: int = 1 << 40,
                  clock: Callable[[], float] = time.perf_counter):
         if n_slots < 1:
@@ -66,24 +72,31 @@ class Server:
         self.budget = int(hbm_budget)
         self.clock = clock
         self._cv = threading.Condition()
-        self._free_slots = collections.deque(executor.make_slot(i) for i in range(n_slots))
+        self._slots = [executor.make_slot(i) for i in range(n_slots)]
+        self._free_slots = collections.deque(range(n_slots))
         self._in_use = 0
         self.peak_bytes = 0
         self.peak_concurrency = 0
         self._concurrency = 0
 
-    # -- worker -------------------------------------------------------------
-    def _worker(self, req, rec: Record, slot):
-        try:
-            rec.result = self.ex.run(req, slot)
-        except Exception as e:  # a failing request fails alone
-            rec.error = f"{type(e).__name__}: {e}"
-        with self._cv:
-            rec.done = self.clock()
-            self._in_use -= rec.footprint
-            self._free_slots.append(slot)
-            self._concurrency -= 1
-            self._cv.notify_all()
+    # -- worker: one per slot -------------------------------------------------
+    def _worker(self, i: int, inbox: "queue.Queue"):
+        slot = self._slots[i]
+        while True:
+            item = inbox.get()
+            if item is None:
+                return
+            req, rec = item
+            try:
+                rec.result = self.ex.run(req, slot)
+            except Exception as e:  # a failing request fails alone
+                rec.error = f"{type(e).__name__}: {e}"
+            with self._cv:
+                rec.done = self.clock()
+                self._in_use -= rec.footprint
+                self._free_slots.append(i)
+                self._concurrency -= 1
+                self._cv.notify_all()
 
     # -- replay of an arrival trace ------------------------------------------
     def run_trace(self, requests: List[Any], arrival_of: Callable[[Any], float] = lambda r: r.arrival_s,
@@ -98,48 +111,54 @@ class Server:
         pending: collections.deque = collections.deque()
         nxt = 0
         reported = 0
-        threads = []
         for i, r in enumerate(requests):
             recs[i].footprint = int(self.ex.footprint(r))
             if recs[i].footprint > self.budget:
                 recs[i].error = "rejected: footprint exceeds the HBM budget"
-        with self._cv:
-            while nxt < len(order) or pending or self._concurrency > 0:
-                now = self.clock()
-                while nxt < len(order) and recs[order[nxt]].arrival <= now:
-                    i = order[nxt]
-                    nxt += 1
-                    if recs[i].error is None:
-                        pending.append(i)
-                    else:
-                        recs[i].admitted = recs[i].done = now
-                # admit in arrival order while a slot and the memory are free
-                while pending and self._free_slots and \
-                        self._in_use + recs[pending[0]].footprint <= self.budget:
-                    i = pending.popleft()
-                    rec = recs[i]
-                    slot = self._free_slots.popleft()
-                    self._in_use += rec.footprint
-                    self._concurrency += 1
-                    self.peak_bytes = max(self.peak_bytes, self._in_use)
-                    self.peak_concurrency = max(self.peak_concurrency, self._concurrency)
-                    rec.admitted = self.clock()
-                    th = threading.Thread(target=self._worker, args=(requests[i], rec, slot), daemon=True)
-                    threads.append(th)
-                    th.start()
-                wait = None
-                if nxt < len(order):
-                    wait = max(0.0, recs[order[nxt]].arrival - self.clock())
-                if nxt < len(order) or pending or self._concurrency > 0:
-                    self._cv.wait(timeout=wait if wait is not None else 1.0)
-                if progress_every > 0:
-                    done = sum(1 for r in recs if r.done == r.done)   # done is NaN until set
-                    if done >= reported + progress_every:
-                        reported = done - done % progress_every
-                        print(f"serving: {done} of {len(recs)} requests done", file=sys.stderr,
-                              flush=True)
-        for th in threads:
-            th.join()
+        inboxes = [queue.Queue() for _ in range(self.n_slots)]
+        workers = [threading.Thread(target=self._worker, args=(i, inboxes[i]), daemon=True)
+                   for i in range(self.n_slots)]
+        for th in workers:
+            th.start()
+        try:
+            with self._cv:
+                while nxt < len(order) or pending or self._concurrency > 0:
+                    now = self.clock()
+                    while nxt < len(order) and recs[order[nxt]].arrival <= now:
+                        i = order[nxt]
+                        nxt += 1
+                        if recs[i].error is None:
+                            pending.append(i)
+                        else:
+                            recs[i].admitted = recs[i].done = now
+                    # admit in arrival order while a slot and the memory are free
+                    while pending and self._free_slots and \
+                            self._in_use + recs[pending[0]].footprint <= self.budget:
+                        i = pending.popleft()
+                        rec = recs[i]
+                        slot = self._free_slots.popleft()
+                        self._in_use += rec.footprint
+                        self._concurrency += 1
+                        self.peak_bytes = max(self.peak_bytes, self._in_use)
+                        self.peak_concurrency = max(self.peak_concurrency, self._concurrency)
+                        rec.admitted = self.clock()
+                        inboxes[slot].put((requests[i], rec))
+                    wait = None
+                    if nxt < len(order):
+                        wait = max(0.0, recs[order[nxt]].arrival - self.clock())
+                    if nxt < len(order) or pending or self._concurrency > 0:
+                        self._cv.wait(timeout=wait if wait is not None else 1.0)
+                    if progress_every > 0:
+                        done = sum(1 for r in recs if r.done == r.done)   # done is NaN until set
+                        if done >= reported + progress_every:
+                            reported = done - done % progress_every
+                            print(f"serving: {done} of {len(recs)} requests done", file=sys.stderr,
+                                  flush=True)
+        finally:
+            for q in inboxes:
+                q.put(None)
+            for th in workers:
+                th.join()
         return recs
 
 

@@ -326,6 +326,20 @@ rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double s
 rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
                                    double* F, void* stream);
 
+/* The discrete gradient of the RS tensor along one axis on the whole grid
+ * (eq Gradients_Tens in the Tucker form): grid_out receives the finite
+ * difference along `axis` (0, 1, 2 = i1, i2, i3; central inside, one-sided
+ * at the two ends of the axis, spacing h) of beta x_1 V1 x_2 V2 x_3 V3 +
+ * sum_nu z_nu U_nu at every cell centre.  The long-range part is the Tucker
+ * tensor with V_axis replaced by its column-wise difference D V_axis (the
+ * other factors and the core unchanged); each windowed short-range term is
+ * differenced in the same way along the axis (it then reaches one cell
+ * beyond its window).  -grid_out approximates the axis component of the
+ * field -grad P.  grid_out: device, n^3 in C order, FP64 for RS_FP64
+ * tensors, FP32 otherwise.  Synchronizes `stream` once (the size of the
+ * widened short-range lists).  Errors: RS_E_INVALID for another axis. */
+rs_status rs_gradient_grid(const rs_tensor* T, int32_t axis, void* grid_out, void* stream);
+
 /* ---- introspection, persistence --------------------------------------- */
 
 /* Peak device memory rs_assemble needs for this request (with_grid != 0 adds

@@ -91,6 +91,7 @@ def _load():
         "rs_forces": ([P, C.c_double, P, P], C.c_int),
         "rs_energy_forces": ([P, P, P, C.c_double, P, P], C.c_int),
         "rs_energy_forces_noalloc": ([P, P, P, C.c_double, P, P], C.c_int),
+        "rs_gradient_grid": ([P, C.c_int32, P, P], C.c_int),
         "rs_footprint_bytes": ([C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.c_int64, C.c_int32,
                                 C.c_int32, C.c_int32], C.c_size_t),
         "rs_tensor_info": ([P, C.POINTER(rs_info)], C.c_int),
@@ -131,7 +132,8 @@ def _may_release() -> bool:
 EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim",
             "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
-            "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
+            "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_gradient_grid",
+            "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
             "rs_last_error")
 
@@ -337,6 +339,15 @@ def energy_forces_noalloc(T: Tensor, E, F, scale: float = 1.0, dEdq=None, stream
                                         None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
                                         float(scale), _dev_ptr(F, "f64", 3 * N, "F"),
                                         _stream_ptr(stream)))
+
+
+def gradient_grid(T: Tensor, axis: int, grid, stream=None):
+    """rs_gradient_grid: the finite difference of the RS tensor along `axis`
+    on the whole grid (FP64 grid for FP64 tensors, FP32 otherwise)."""
+    inf = T.info()
+    want = "f64" if inf.prec == 0 else "f32"
+    _check(lib.rs_gradient_grid(T.handle, int(axis), _dev_ptr(grid, want, inf.n ** 3, "grid"),
+                                _stream_ptr(stream)))
 
 
 def tensor_export(T: Tensor, V1=None, V2=None, V3=None, beta=None, stream=None):

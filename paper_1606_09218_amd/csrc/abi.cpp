@@ -322,35 +322,39 @@ struct Carve {
 // (output column (b, c) of V1 beta_(1) sent to b n r3 + c); the second
 // contracts b: T2 row i2, column (i1, c) = sum_b V2[i2,b] X[b][i1 r3 + c],
 // sent to i1 n r3 + i2 r3 + c.
-static Gemm64 expand1_gemm(const rs_tensor* T, double* X) {
+// (V1 may be another n x r1 factor, e.g. its finite difference)
+static Gemm64 expand1_gemm(const rs_tensor* T, double* X, const double* V1 = nullptr) {
   const int64_t n = T->n;
   const int r1 = T->r[0], r2 = T->r[1], r3 = T->r[2];
   Gemm64 g;  // X[b][i1][c] = (V1 beta_(1))[i1, (b, c)]
   g.M = n; g.N = (int64_t)r2 * r3; g.K = r1;
-  g.A = T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
+  g.A = V1 ? V1 : T->Q[0].as<double>(); g.sam = r1; g.sak = 1;
   g.B = T->beta.as<double>(); g.sbk = (int64_t)r2 * r3; g.sbn = 1;
   g.C = X; g.scm = r3; g.scn = 1; g.ccb = r3; g.sccb = n * r3;
   return g;
 }
 
-static Gemm64 expand2_gemm(const rs_tensor* T, const double* X) {
+// (V2 and the output may be another factor and buffer)
+static Gemm64 expand2_gemm(const rs_tensor* T, const double* X, const double* V2 = nullptr,
+                           double* T2out = nullptr) {
   const int64_t n = T->n;
   const int r2 = T->r[1], r3 = T->r[2];
   Gemm64 g;  // T2[i1][i2][c] = sum_b V2[i2, b] X[b][i1 r3 + c]
   g.M = n; g.N = n * r3; g.K = r2;
-  g.A = T->Q[1].as<double>(); g.sam = r2; g.sak = 1;
+  g.A = V2 ? V2 : T->Q[1].as<double>(); g.sam = r2; g.sak = 1;
   g.B = X; g.sbk = n * r3; g.sbn = 1;
-  g.C = T->T2.as<double>(); g.scm = r3; g.scn = 1; g.ccb = r3; g.sccb = n * r3;
+  g.C = T2out ? T2out : T->T2.as<double>(); g.scm = r3; g.scn = 1; g.ccb = r3; g.sccb = n * r3;
   return g;
 }
 
-static Gemm64 grid_gemm(const rs_tensor* T, void* grid) {
+static Gemm64 grid_gemm(const rs_tensor* T, void* grid, const double* T2 = nullptr,
+                        const double* V3 = nullptr) {
   const int64_t n = T->n;
   const int r3 = T->r[2];
   Gemm64 g;  // grid[(i1,i2), i3] = sum_c T2[(i1,i2), c] V3[i3, c]
   g.M = n * n; g.N = n; g.K = r3;
-  g.A = T->T2.as<double>(); g.sam = r3; g.sak = 1;
-  g.B = T->Q[2].as<double>(); g.sbk = 1; g.sbn = r3;
+  g.A = T2 ? T2 : T->T2.as<double>(); g.sam = r3; g.sak = 1;
+  g.B = V3 ? V3 : T->Q[2].as<double>(); g.sbk = 1; g.sbn = r3;
   g.C = (double*)grid; g.scm = n; g.scn = 1;
   g.nontemporal = 1;
   return g;
@@ -1041,6 +1045,70 @@ rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, 
     launch_eval_long(T, N, T->pos.as<double>(), 1, o, s);
     launch_energy_reduce(T->q.as<double>(), o.val, o.selfv, N, E, dEdq, s);
     launch_forces(T->q.as<double>(), o.grad, o.selfg, N, scale, F, s);
+    return RS_OK;
+  });
+}
+
+rs_status rs_gradient_grid(const rs_tensor* T, int32_t axis, void* grid_out, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && grid_out, "null argument");
+    RS_REQUIRE(axis >= 0 && axis <= 2, "axis must be 0, 1 or 2");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = T->n;
+    const int r3 = T->r[2], ra = T->r[axis];
+    const int ncu = T->ctx->num_cu;
+    // long range: the Tucker tensor with the axis factor replaced by its
+    // finite difference (eq Gradients_Tens, the Tucker form of the sum)
+    DevBuf dv((size_t)n * ra * sizeof(double), s);
+    launch_fd_rows(T->Q[axis].as<double>(), n, ra, T->h, dv.as<double>(), s);
+    DevBuf t2d;
+    const double* T2src = T->T2.as<double>();
+    const double* V3 = T->Q[2].as<double>();
+    if (axis == 2) {
+      V3 = dv.as<double>();
+    } else {
+      const double* V1 = axis == 0 ? dv.as<double>() : nullptr;
+      const double* V2 = axis == 1 ? dv.as<double>() : nullptr;
+      t2d = DevBuf((size_t)n * n * r3 * sizeof(double), s);
+      DevBuf X((size_t)n * T->r[1] * r3 * sizeof(double), s);
+      const Gemm64 g1 = expand1_gemm(T, X.as<double>(), V1);
+      const Gemm64 g2 = expand2_gemm(T, X.as<double>(), V2, t2d.as<double>());
+      DevBuf w1(gemm64_workspace_bytes(g1, ncu), s), w2(gemm64_workspace_bytes(g2, ncu), s);
+      gemm64(g1, ncu, w1.as<double>(), s);
+      gemm64(g2, ncu, w2.as<double>(), s);
+      T2src = t2d.as<double>();
+    }
+    if (T->prec == RS_FP64) {
+      if (!grid64_stream(T2src, V3, n, r3, (double*)grid_out, ncu, T->ctx->lds_limit, s)) {
+        const Gemm64 gg = grid_gemm(T, grid_out, T2src, V3);
+        DevBuf wg(gemm64_workspace_bytes(gg, ncu), s);
+        gemm64(gg, ncu, wg.as<double>(), s);
+      }
+    } else {
+      DevBuf wg(grid_mixed_workspace_bytes(n, r3), s);
+      grid_mixed(contraction_prec(T->prec), T2src, V3, n, r3, (float*)grid_out, wg.p, ncu, s);
+    }
+    // short range: brick lists for windows one cell wider on each side, then
+    // the finite difference of every local term
+    const int ns2 = T->n_s + 2, nbricks = T->nb * T->nb * T->nb;
+    DevBuf counts((size_t)(nbricks + 1) * sizeof(int), s), start((size_t)(nbricks + 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_count(T->pos.as<double>(), T->N, n, T->b, ns2, T->nb, counts.as<int>(), s);
+    exclusive_scan_int(counts.as<int>(), start.as<int>(), nbricks + 1, s);
+    int total = 0;
+    RS_HIP(hipMemcpyAsync(&total, start.as<int>() + nbricks, sizeof(int), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    DevBuf list((size_t)std::max(total, 1) * sizeof(int), s);
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_fill(T->pos.as<double>(), T->N, n, T->b, ns2, T->nb, start.as<int>(), counts.as<int>(),
+                   list.as<int>(), s);
+    const int64_t cap = short_active_capacity(T->N, ns2, T->nb);
+    DevBuf active((size_t)(cap + 1) * sizeof(int), s);
+    short_bin_sort(start.as<int>(), list.as<int>(), nbricks, active.as<int>(), cap, s);
+    short_gather(grid_out, T->prec != RS_FP64, T->pos.as<double>(), T->q.as<double>(),
+                 T->t_dev.as<double>(), T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
+                 start.as<int>(), list.as<int>(), active.as<int>(), cap, ncu, s, axis);
     return RS_OK;
   });
 }

@@ -87,4 +87,26 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
                      R_l, xi, w, sw);
 }
 
+// DV[i, c] = d/dx of column c of V (n x r row-major) on the cell-centred grid:
+// central differences inside, one-sided at the two ends (eq Gradients_Tens).
+__global__ void fd_rows_kernel(const double* __restrict__ V, int64_t n, int r, double h,
+                               double* __restrict__ DV) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * r;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / r, c = e - (e / r) * r;
+    double d;
+    if (i == 0) d = (V[r + c] - V[c]) / h;
+    else if (i == n - 1) d = (V[i * r + c] - V[(i - 1) * r + c]) / h;
+    else d = (V[(i + 1) * r + c] - V[(i - 1) * r + c]) / (2.0 * h);
+    DV[e] = d;
+  }
+}
+
+void launch_fd_rows(const double* V, int64_t n, int r, double h, double* DV, hipStream_t s) {
+  const int64_t total = n * r;
+  if (total <= 0) return;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(fd_rows_kernel, dim3(blocks), dim3(256), 0, s, V, n, r, h, DV);
+}
+
 }  // namespace rs

@@ -174,7 +174,14 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // The workgroup is one wave, so its barriers are cheap and many bricks stay
 // in flight per compute unit; every wave leaves once active[0] bricks are
 // done.
-template <typename GT>
+// DAX = -1: grid += the windowed short-range sum.  DAX = 0, 1 or 2: grid +=
+// its finite difference along axis DAX (central, one-sided at the grid ends;
+// the discrete gradient of eq Gradients_Tens applied to each local term):
+// every local term is separable, a_k z prod_l g_kl(i_l) chi_l(i_l) with chi_l
+// the window's indicator, so only the axis-DAX factor changes, to the
+// difference of g chi, which reaches one cell beyond the window (the brick
+// lists must be built for windows of n_s + 2).
+template <class GT, int DAX>
 __global__ __launch_bounds__(64) void short_gather_kernel(
     GT* __restrict__ grid, const double* __restrict__ pos, const double* __restrict__ q,
     const double* __restrict__ t, const double* __restrict__ a, int R, int R_l, int64_t n,
@@ -224,23 +231,45 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
           const double p[3] = {readlane_f64(px, e), readlane_f64(py, e), readlane_f64(pz, e)};
           const double z = readlane_f64(pq, e);
           int lo[3], hi[3];
+          int64_t glo[3], ghi[3];
           const int bs[3] = {base0, base1, base2};
 #pragma unroll
           for (int l = 0; l < 3; ++l) {
             int64_t jc = (int64_t)floor((p[l] + b) / h);
             jc = jc < 0 ? 0 : (jc > n - 1 ? n - 1 : jc);
-            const int64_t lo_l = jc - w < 0 ? 0 : jc - w;
-            const int64_t hi_l = jc + w > n - 1 ? n - 1 : jc + w;
-            lo[l] = (int)(lo_l - bs[l]);
-            hi[l] = (int)(hi_l - bs[l]);
+            glo[l] = jc - w < 0 ? 0 : jc - w;
+            ghi[l] = jc + w > n - 1 ? n - 1 : jc + w;
+            lo[l] = (int)(glo[l] - bs[l]);
+            hi[l] = (int)(ghi[l] - bs[l]);
+          }
+          if (DAX >= 0) {   // the masked difference vanishes outside itself
+            lo[DAX] = -BRICK;
+            hi[DAX] = 2 * BRICK;
           }
           __syncthreads();  // the previous particle's factors are no longer read
           for (int idx = lane; idx < 24 * Rs; idx += 64) {
             const int l = idx / (8 * Rs);
             const int rem = idx - l * 8 * Rs;
             const int k = rem >> 3, m = rem & 7;
-            const double d = (-b + ((double)(bs[l] + m) + 0.5) * h) - p[l];
-            f[idx] = exp(-tk2[k] * (d * d));
+            const int64_t gi = bs[l] + m;
+            if (l != DAX) {
+              const double d = (-b + ((double)gi + 0.5) * h) - p[l];
+              f[idx] = exp(-tk2[k] * (d * d));
+            } else {
+              // g chi at global index j (0 outside the window and the grid)
+              auto gchi = [&](int64_t j) {
+                if (j < glo[l] || j > ghi[l]) return 0.0;
+                const double d = (-b + ((double)j + 0.5) * h) - p[l];
+                return exp(-tk2[k] * (d * d));
+              };
+              double v = 0.0;
+              if (gi < n) {
+                if (gi == 0) v = (gchi(1) - gchi(0)) / h;
+                else if (gi == n - 1) v = (gchi(n - 1) - gchi(n - 2)) / h;
+                else v = (gchi(gi + 1) - gchi(gi - 1)) / (2.0 * h);
+              }
+              f[idx] = v;
+            }
           }
           __syncthreads();
           if (c1 >= lo[1] && c1 <= hi[1] && c2 >= lo[2] && c2 <= hi[2]) {
@@ -268,10 +297,33 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
   }
 }
 
+template <class GT, int DAX>
+static void short_gather_t(GT* grid, const double* pos, const double* q, const double* t,
+                           const double* a, int R, int R_l, int64_t n, double b, int w, int nb,
+                           const int* start, const int* list, const int* active, int64_t active_cap,
+                           int64_t wgs, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((short_gather_kernel<GT, DAX>), dim3((unsigned)wgs), dim3(64), lds, s, grid,
+                     pos, q, t, a, R, R_l, n, b, w, nb, start, list, active, active_cap);
+}
+
+template <class GT>
+static void short_gather_axis(int dax, GT* grid, const double* pos, const double* q,
+                              const double* t, const double* a, int R, int R_l, int64_t n, double b,
+                              int w, int nb, const int* start, const int* list, const int* active,
+                              int64_t active_cap, int64_t wgs, size_t lds, hipStream_t s) {
+  switch (dax) {
+    case -1: short_gather_t<GT, -1>(grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active, active_cap, wgs, lds, s); break;
+    case 0: short_gather_t<GT, 0>(grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active, active_cap, wgs, lds, s); break;
+    case 1: short_gather_t<GT, 1>(grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active, active_cap, wgs, lds, s); break;
+    case 2: short_gather_t<GT, 2>(grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active, active_cap, wgs, lds, s); break;
+    default: throw Error{RS_E_INVALID, "axis must be 0, 1 or 2"};
+  }
+}
+
 void short_gather(void* grid, int grid_fp32, const double* pos, const double* q, const double* t,
                   const double* a, int R, int R_l, int64_t n, double b, int n_s, int nb,
                   const int* start, const int* list, const int* active, int64_t active_cap,
-                  int num_cu, hipStream_t s) {
+                  int num_cu, hipStream_t s, int dax) {
   if (R - R_l > MAX_RS) throw Error{RS_E_UNSUPPORTED, "more than 64 short-range terms"};
   if (R - R_l <= 0) return;  // no short-range terms: nothing to add
   const int w = (n_s - 1) / 2;
@@ -279,13 +331,11 @@ void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
   const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(active_cap, (int64_t)num_cu * 16));
   const size_t lds = (size_t)26 * (R - R_l) * sizeof(double);
   if (grid_fp32)
-    hipLaunchKernelGGL(short_gather_kernel<float>, dim3((unsigned)wgs), dim3(64), lds, s,
-                       (float*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active,
-                       active_cap);
+    short_gather_axis<float>(dax, (float*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list,
+                             active, active_cap, wgs, lds, s);
   else
-    hipLaunchKernelGGL(short_gather_kernel<double>, dim3((unsigned)wgs), dim3(64), lds, s,
-                       (double*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list, active,
-                       active_cap);
+    short_gather_axis<double>(dax, (double*)grid, pos, q, t, a, R, R_l, n, b, w, nb, start, list,
+                              active, active_cap, wgs, lds, s);
 }
 
 }  // namespace rs

@@ -172,6 +172,10 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
                           double* w, double* sw, hipStream_t s);
 
+// DV = column-wise finite differences of V (n x r row-major) with spacing h:
+// central inside, one-sided at the ends
+void launch_fd_rows(const double* V, int64_t n, int r, double h, double* DV, hipStream_t s);
+
 // k_gemm64.hip : FP64 MFMA GEMM, C[bt](m,n) = sum_k A[bt](m,k) B[bt](k,n) kscale[k]
 struct Gemm64 {
   int64_t M = 0, N = 0, K = 0;
@@ -316,11 +320,13 @@ void exclusive_scan_int(const int* in, int* out, int count, hipStream_t s);
 size_t exclusive_scan_bytes(int count);
 void exclusive_scan_int(const int* in, int* out, int count, void* tmp, size_t tmp_bytes,
                         hipStream_t s);
-// grid (FP64 or FP32) += sum over particles of the short-range windows
+// grid (FP64 or FP32) += sum over particles of the short-range windows, or,
+// with dax = 0, 1, 2, += its finite difference along that axis (central,
+// one-sided at the grid ends; brick lists then built for windows of n_s + 2)
 void short_gather(void* grid, int grid_fp32, const double* pos, const double* q,
                   const double* t, const double* a, int R, int R_l, int64_t n, double b,
                   int n_s, int nb, const int* start, const int* list, const int* active,
-                  int64_t active_cap, int num_cu, hipStream_t s);
+                  int64_t active_cap, int num_cu, hipStream_t s, int dax = -1);
 
 // k_noalloc.hip: one file-scope device array per GPU for the entry points that
 // allocate nothing (8 MiB: the per-particle evaluations of up to 131072

@@ -296,6 +296,23 @@ rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const do
 rs_status rs_eval_points(const rs_tensor* T, int64_t M, const double* pts, double* vals,
                          int32_t part, void* stream);
 
+/* Gradient of the RS tensor at M arbitrary points (section 4.3), or its
+ * normal derivative: the long-range part is the derivative of the same
+ * order-p interpolant rs_eval_points uses (the interpolated Tucker factor
+ * rows differentiated, eq Gradients_Tens applied to the continuous
+ * factors); the short-range part differentiates each windowed term
+ * z_nu sum_{k>=R_l} a_k exp(-t_k^2 |y - x_nu|^2) analytically, for the
+ * particles whose window holds the point's cell (as in rs_eval_points).
+ * part: 0 long + short, 1 long only (what interface conditions on a surface
+ * at least half a short-range support away from every particle need,
+ * Proposition PBE_RSTensor), 2 short only.
+ * pts: device, M x 3 row-major.  normals: device M x 3 (unit surface normals;
+ * need not be unit, each output is the plain dot product) or NULL.
+ * out: device FP64, M x 3 gradients when normals is NULL, else the M values
+ * <grad P(y_i), normals_i>.  M = 0 is a no-op. */
+rs_status rs_eval_gradient_points(const rs_tensor* T, int64_t M, const double* pts,
+                                  const double* normals, double* out, int32_t part, void* stream);
+
 /* Interaction energy E_N = 1/2 sum_j z_j (P_l(x_j) - z_j g_j) (eq EnergyFree_Tensor),
  * g_j the particle's own long-range term through the same interpolation
  * (= P_{R_l}(0) for a particle on a grid point).

@@ -135,6 +135,28 @@ def short_range_points(points, b: float, n: int, pos, q, t, a, R_l: int, n_s: in
     return out
 
 
+def short_range_points_grad(points, b: float, n: int, pos, q, t, a, R_l: int, n_s: int):
+    """Gradient in y of short_range_points (section 4.3): each windowed term
+    z_nu a_k exp(-t_k^2 |y - x_nu|^2) differentiated analytically,
+    -2 t_k^2 (y - x_nu) times the term, for the particles whose window holds
+    the point's cell.  Result: M x 3."""
+    points = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    cells = _grid.cell_of(points, b, n)
+    lo, hi = window_bounds(pos, b, n, n_s)
+    out = np.zeros((points.shape[0], 3))
+    for nu in range(pos.shape[0]):
+        inside = np.all((cells >= lo[nu]) & (cells <= hi[nu]), axis=1)
+        if not np.any(inside):
+            continue
+        d = points[inside] - pos[nu]
+        d2 = np.sum(d ** 2, axis=1)
+        c = np.zeros(d2.shape[0])
+        for k in range(R_l, len(t)):
+            c += -2.0 * t[k] ** 2 * a[k] * np.exp(-t[k] ** 2 * d2)
+        out[inside] += q[nu] * c[:, None] * d
+    return out
+
+
 def short_range_subgrid(I1, I2, I3, b: float, n: int, pos, q, t, a, R_l: int, n_s: int):
     """The short-range CCT sum_nu z_nu U_nu (as short_range_grid) on the
     index set I1 x I2 x I3 only: each particle adds its windowed local

@@ -85,6 +85,23 @@ def eval_points(T: RSTucker, points, part: int = 0, p: int = 6):
     return out
 
 
+def gradient_points(T: RSTucker, points, part: int = 0, p: int = 6, normals=None):
+    """grad P at the points (section 4.3): the long part as the derivative of
+    the order-p interpolant (long_and_grad), the short part analytically per
+    windowed term.  part 0: both, 1: long, 2: short.  With normals (M x 3),
+    the normal derivatives <grad P(y_i), normals_i> instead."""
+    points = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    g = np.zeros((points.shape[0], 3))
+    if part in (0, 1):
+        g = g + long_and_grad(T, points, p)[1]
+    if part in (0, 2):
+        g = g + canonical.short_range_points_grad(points, T.b, T.n, T.pos, T.q, T.t, T.a,
+                                                  T.R_l, T.n_s)
+    if normals is None:
+        return g
+    return np.sum(g * np.asarray(normals, dtype=np.float64).reshape(-1, 3), axis=1)
+
+
 def self_long_and_grad(T: RSTucker, p: int = 6):
     """Particle j's own long-range reference term seen through the same
     interpolation operator, at its own position:

@@ -92,6 +92,7 @@ def _load():
         "rs_energy_forces": ([P, P, P, C.c_double, P, P], C.c_int),
         "rs_energy_forces_noalloc": ([P, P, P, C.c_double, P, P], C.c_int),
         "rs_gradient_grid": ([P, C.c_int32, P, P], C.c_int),
+        "rs_eval_gradient_points": ([P, C.c_int64, P, P, P, C.c_int32, P], C.c_int),
         "rs_footprint_bytes": ([C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.c_int64, C.c_int32,
                                 C.c_int32, C.c_int32], C.c_size_t),
         "rs_tensor_info": ([P, C.POINTER(rs_info)], C.c_int),
@@ -133,7 +134,7 @@ EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim
             "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_gradient_grid",
-            "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
+            "rs_eval_gradient_points", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
             "rs_last_error")
 
@@ -339,6 +340,16 @@ def energy_forces_noalloc(T: Tensor, E, F, scale: float = 1.0, dEdq=None, stream
                                         None if dEdq is None else _dev_ptr(dEdq, "f64", N, "dEdq"),
                                         float(scale), _dev_ptr(F, "f64", 3 * N, "F"),
                                         _stream_ptr(stream)))
+
+
+def eval_gradient_points(T: Tensor, pts, out, normals=None, part: int = 0, stream=None):
+    """rs_eval_gradient_points: M x 3 gradients at the points, or the M
+    normal derivatives when `normals` (M x 3) is given."""
+    M = int(pts.numel()) // 3
+    p_n = None if normals is None else _dev_ptr(normals, "f64", 3 * M, "normals")
+    _check(lib.rs_eval_gradient_points(T.handle, M, _dev_ptr(pts, "f64", 3 * M, "pts"), p_n,
+                                       _dev_ptr(out, "f64", M if normals is not None else 3 * M, "out"),
+                                       int(part), _stream_ptr(stream)))
 
 
 def gradient_grid(T: Tensor, axis: int, grid, stream=None):

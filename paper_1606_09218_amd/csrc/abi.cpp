@@ -967,6 +967,35 @@ rs_status rs_eval_points(const rs_tensor* T, int64_t M, const double* pts, doubl
   });
 }
 
+rs_status rs_eval_gradient_points(const rs_tensor* T, int64_t M, const double* pts,
+                                  const double* normals, double* out, int32_t part, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T, "null tensor");
+    RS_REQUIRE(M >= 0, "M must be >= 0");
+    RS_REQUIRE(part >= 0 && part <= 2, "part must be 0, 1 or 2");
+    if (M == 0) return RS_OK;
+    RS_REQUIRE(pts && out, "null argument");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf gbuf;
+    double* g = out;
+    if (normals) {
+      gbuf = DevBuf((size_t)M * 3 * sizeof(double), s);
+      g = gbuf.as<double>();
+    }
+    if (part == 0 || part == 1) {
+      DevBuf v((size_t)M * sizeof(double), s);
+      EvalOut o;
+      o.val = v.as<double>();
+      o.grad = g;
+      launch_eval_long(T, M, pts, 0, o, s);
+    }
+    if (part == 0 || part == 2) launch_eval_short_grad(T, M, pts, g, part == 0 ? 1 : 0, s);
+    if (normals) launch_normal_dot(g, normals, M, out, s);
+    return RS_OK;
+  });
+}
+
 rs_status rs_energy(const rs_tensor* T, double* E, double* dEdq, void* stream) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(T && E, "null argument");

@@ -248,6 +248,9 @@ void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with
 
 // Short-range part at arbitrary points: particles whose window contains the
 // point's cell, in index order (from the brick lists), Gaussians at the point.
+// GRAD: the gradient in y of the same terms instead (M x 3 output), each term
+// a_k exp(-t_k^2 |y - x|^2) differentiated analytically.
+template <bool GRAD>
 __global__ void eval_short_kernel(int64_t M, const double* __restrict__ pts,
                                   const double* __restrict__ pos, const double* __restrict__ q,
                                   const double* __restrict__ t, const double* __restrict__ a,
@@ -265,33 +268,71 @@ __global__ void eval_short_kernel(int64_t M, const double* __restrict__ pts,
     cell[l] = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
   }
   const int64_t br = ((cell[0] / 8) * nb + cell[1] / 8) * nb + cell[2] / 8;
-  double acc = 0.0;
+  double acc = 0.0, gacc[3] = {0.0, 0.0, 0.0};
   for (int e = start[br]; e < start[br + 1]; ++e) {
     const int nu = list[e];
     bool inside = true;
-    double r2 = 0.0;
+    double r2 = 0.0, d[3];
     for (int l = 0; l < 3; ++l) {
       const double x = pos[3 * nu + l];
       int64_t j = (int64_t)floor((x + b) / h);
       j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
       if (cell[l] < j - w || cell[l] > j + w) inside = false;
-      const double d = y[l] - x;
-      r2 += d * d;
+      d[l] = y[l] - x;
+      r2 += d[l] * d[l];
     }
     if (!inside) continue;
-    double sum = 0.0;
-    for (int k = R_l; k < R; ++k) sum += a[k] * exp(-t[k] * t[k] * r2);
-    acc += q[nu] * sum;
+    if (GRAD) {
+      double ds = 0.0;   // d/d(r^2) of the term sum
+      for (int k = R_l; k < R; ++k) ds -= t[k] * t[k] * a[k] * exp(-t[k] * t[k] * r2);
+      for (int l = 0; l < 3; ++l) gacc[l] += q[nu] * 2.0 * ds * d[l];
+    } else {
+      double sum = 0.0;
+      for (int k = R_l; k < R; ++k) sum += a[k] * exp(-t[k] * t[k] * r2);
+      acc += q[nu] * sum;
+    }
   }
-  vals[pt] = accumulate ? vals[pt] + acc : acc;
+  if (GRAD) {
+    for (int l = 0; l < 3; ++l)
+      vals[3 * pt + l] = accumulate ? vals[3 * pt + l] + gacc[l] : gacc[l];
+  } else {
+    vals[pt] = accumulate ? vals[pt] + acc : acc;
+  }
+}
+
+static void launch_short(bool grad, const rs_tensor* T, int64_t M, const double* pts, double* out,
+                         int accumulate, hipStream_t s) {
+  const dim3 grid((unsigned)((M + 127) / 128)), block(128);
+#define RS_SHORT(G)                                                                               \
+  hipLaunchKernelGGL(eval_short_kernel<G>, grid, block, 0, s, M, pts, T->pos.as<double>(),        \
+                     T->q.as<double>(), T->t_dev.as<double>(), T->a_dev.as<double>(), T->R,        \
+                     T->R_l, T->n, T->b, (T->n_s - 1) / 2, T->nb, T->brick_start.as<int>(),      \
+                     T->brick_list.as<int>(), out, accumulate)
+  if (grad) RS_SHORT(true);
+  else RS_SHORT(false);
+#undef RS_SHORT
 }
 
 void launch_eval_short(const rs_tensor* T, int64_t M, const double* pts, double* vals,
                        int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(eval_short_kernel, dim3((unsigned)((M + 127) / 128)), dim3(128), 0, s, M, pts,
-                     T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
-                     T->a_dev.as<double>(), T->R, T->R_l, T->n, T->b, (T->n_s - 1) / 2, T->nb,
-                     T->brick_start.as<int>(), T->brick_list.as<int>(), vals, accumulate);
+  launch_short(false, T, M, pts, vals, accumulate, s);
+}
+
+void launch_eval_short_grad(const rs_tensor* T, int64_t M, const double* pts, double* grad,
+                            int accumulate, hipStream_t s) {
+  launch_short(true, T, M, pts, grad, accumulate, s);
+}
+
+__global__ void normal_dot_kernel(const double* __restrict__ g, const double* __restrict__ nrm,
+                                  int64_t M, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) out[i] = g[3 * i] * nrm[3 * i] + g[3 * i + 1] * nrm[3 * i + 1] + g[3 * i + 2] * nrm[3 * i + 2];
+}
+
+void launch_normal_dot(const double* grad, const double* normals, int64_t M, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(normal_dot_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, grad,
+                     normals, M, out);
 }
 
 // Single workgroup, fixed-order FP64 reduction.

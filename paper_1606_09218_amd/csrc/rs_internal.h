@@ -351,6 +351,12 @@ void launch_eval_long(const rs_tensor* T, int64_t M, const double* pts, int with
 void launch_to_float(const double* in, int64_t count, float* out, hipStream_t s);
 void launch_eval_short(const rs_tensor* T, int64_t M, const double* pts, double* vals,
                        int accumulate, hipStream_t s);
+// M x 3 gradient of the short-range part at the points (analytic per term)
+void launch_eval_short_grad(const rs_tensor* T, int64_t M, const double* pts, double* grad,
+                            int accumulate, hipStream_t s);
+// out[i] = <grad[i, :], normals[i, :]>
+void launch_normal_dot(const double* grad, const double* normals, int64_t M, double* out,
+                       hipStream_t s);
 // E = 1/2 sum_j q_j (v_j - q_j g_j); dEdq_j = v_j - q_j g_j (optional)
 void launch_energy_reduce(const double* q, const double* v, const double* g, int64_t N,
                           double* E, double* dEdq, hipStream_t s);

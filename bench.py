@@ -34,7 +34,7 @@ PRODUCTS = {"fp64": 1, "mixed_fp16": 3, "mixed_bf16": 6}   # MFMA products per s
 DTYPE = {"fp64": "f64", "mixed_fp16": "fp16", "mixed_bf16": "bf16"}
 PRECISION = {
     "fp64": "FP64 throughout",
-    "mixed_fp16": ("core and grid expansion in split FP16 (hi + lo 2^-11, 3 MFMA products) with "
+    "mixed_fp16": ("core and grid expansion in split FP16 (hi + lo, 3 MFMA products) with "
                    "FP32 accumulation and FP64 sums per 256 k; quadrature, eigensolve, projection "
                    "and energy reduction FP64; FP32 grid"),
     "mixed_bf16": ("core and grid expansion in split BF16 (3 terms, 6 MFMA products) with FP32 "
@@ -273,7 +273,7 @@ def core_roofline(leg, s, prec):
     dt = DTYPE[prec]
     kname = {"fp64": "rs::core_kernel<CfgRank> (FP64, r1 > 128)" if r1 > 128 else
              "rs::core_stream_kernel (FP64)",
-             "mixed_fp16": "rs::core_tile_kernel<rs::SplitF16, WGM, 4>",
+             "mixed_fp16": "rs::core_tile_kernel<rs::CoreF16, WGM, 4>",
              "mixed_bf16": "rs::core_tile_kernel<rs::SplitBF16, WGM, 2>"}[prec]
     achieved = flops / t / 1e12
     return {"kernel": kname + " (core beta_(1) = U~1 diag(xi) (U~2 kr U~3)^T)",

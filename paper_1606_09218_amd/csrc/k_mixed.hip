@@ -34,6 +34,7 @@ struct SplitF16 {
   static constexpr int TERMS = 2;
   static constexpr int LEVELS = 2;
   static constexpr bool SCALED = true;
+  static constexpr bool PAIRED = false;
   typedef _Float16 T;
   typedef h8 V8;
   __device__ static void split(double x, T* o) {
@@ -62,6 +63,7 @@ struct SplitBF16 {
   static constexpr int TERMS = 3;
   static constexpr int LEVELS = 3;
   static constexpr bool SCALED = false;
+  static constexpr bool PAIRED = false;
   typedef __bf16 T;
   typedef b8 V8;
   __device__ static void split(double x, T* o) {
@@ -91,6 +93,51 @@ struct SplitBF16 {
   __device__ static double combine(const f4 (&acc)[LEVELS], int v) {
     return (double)acc[0][v] + (double)acc[1][v] + (double)acc[2][v];
   }
+};
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+// The core's FP16 split: x 2^s = hi + lo with lo unscaled, and the three
+// products hi*hi, hi*lo, lo*hi summed in one FP32 accumulator (the lo
+// products are 2^-11 of the hi product, so they add no rounding beyond the
+// accumulator's own).  For the Khatri-Rao operand hi is x rounded toward
+// zero, two values per conversion; x - hi is exact in FP32 and lo is it
+// rounded to nearest, so the representation error is unbiased.
+struct CoreF16 {
+  static constexpr int TERMS = 2;
+  static constexpr int LEVELS = 1;
+  static constexpr bool SCALED = true;
+  static constexpr bool PAIRED = true;
+  typedef _Float16 T;
+  typedef h8 V8;
+  __device__ static void split(double x, T* o) {
+    const T hi = (T)x;
+    o[0] = hi;
+    o[1] = (T)(x - (double)hi);
+  }
+  __device__ static h2 pk(float a, float b) {
+    return __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
+  }
+  __device__ static void split8(const float (&x)[8], V8& hi, V8& lo) {
+    h2 H[4], L[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      H[p] = pk(x[2 * p], x[2 * p + 1]);
+      L[p] = h2{(_Float16)(x[2 * p] - (float)H[p][0]), (_Float16)(x[2 * p + 1] - (float)H[p][1])};
+    }
+    hi = __builtin_shufflevector(__builtin_shufflevector(H[0], H[1], 0, 1, 2, 3),
+                                 __builtin_shufflevector(H[2], H[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5,
+                                 6, 7);
+    lo = __builtin_shufflevector(__builtin_shufflevector(L[0], L[1], 0, 1, 2, 3),
+                                 __builtin_shufflevector(L[2], L[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5,
+                                 6, 7);
+  }
+  __device__ static f4 mfma(V8 a, V8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static constexpr int NPROD = 3;
+  static constexpr int PA[NPROD] = {0, 0, 1}, PB[NPROD] = {0, 1, 0}, PL[NPROD] = {0, 0, 0};
+  __device__ static double combine(const f4 (&acc)[LEVELS], int v) { return (double)acc[0][v]; }
 };
 
 static inline int64_t pad32(int64_t k) { return (k + 31) / 32 * 32; }
@@ -123,16 +170,19 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const double* __restr
 }
 
 // FP32 transposed copies for the Khatri-Rao operand:
-// s2[b][j] = xi_j U~2[j, b], u3[c][j] = U~3[j, c]  (zero for j >= K)
+// s2[b][j] = 2^s xi_j U~2[j, b], u3[c][j] = U~3[j, c]  (zero for j >= K), with
+// the operand's power-of-two scale 2^s (exps[1]) when exps is given
 __global__ void kr_factors_kernel(const double* __restrict__ U2t, const double* __restrict__ U3t,
                                   const double* __restrict__ xi, int r2, int r3, int64_t K,
-                                  int64_t kp, float* __restrict__ s2, float* __restrict__ u3) {
+                                  int64_t kp, const int* exps, float* __restrict__ s2,
+                                  float* __restrict__ u3) {
+  const double scale = exps ? pow2(exps[1]) : 1.0;
   const int64_t total = (int64_t)(r2 + r3) * kp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = e / kp, j = e - row * kp;
     if (row < r2) {
-      s2[row * kp + j] = j < K ? (float)(xi[j] * U2t[j * r2 + row]) : 0.0f;
+      s2[row * kp + j] = j < K ? (float)(xi[j] * U2t[j * r2 + row] * scale) : 0.0f;
     } else {
       const int64_t c = row - r2;
       u3[c * kp + j] = j < K ? (float)U3t[j * r3 + c] : 0.0f;
@@ -290,11 +340,25 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
 // per workgroup into LDS.  Workgroup tile 32 WGM rows x 32 FN columns, 2 WGM
 // waves of 32 x 16 FN (2 x FN MFMA blocks).  Per step of 32 k the next A
 // fragments (from the split planes) and the raw s2/u3 values are loaded into
-// registers while the MFMAs of the current step run, then written to LDS
-// (rows padded to 40 elements: the 16-byte fragment reads of 16 rows fall
-// in distinct banks).  FP32 accumulators are folded into FP64 every KCHUNK.
+// registers while the MFMAs of the current step run, then written to LDS.
+// LDS layout: rows of 32 elements (64 bytes, four 16-byte chunks), chunk c
+// of row r stored at chunk c ^ sw(r), sw(r) = 2 ((r / 4) % 2).  A 16-byte
+// LDS access is served in passes of lanes {0-7, 16-23} (and the like); the
+// fragment reads of such a pass (8 consecutive rows, 2 chunks) then hit 16
+// distinct four-bank groups of the 64 banks.  The loads keep 4 consecutive
+// lanes on one row (64 contiguous bytes: one request per quad), and quad Q
+// of a 16-row group takes row rho(Q), Q with bits 1 and 2 swapped, so that
+// the 4 quads of a store pass write 4 rows of distinct r % 4 with one sw:
+// also conflict-free.  FP32 accumulators are folded into FP64 every KCHUNK.
 // FN column blocks per wave: 4 for the two-term FP16 split, 2 for the
 // three-term BF16 split (whose accumulators take more registers).
+// LDS row of loader quad Q (bits 1 and 2 of Q swapped within its 16-row
+// group) and the chunk swizzle of row r
+__device__ __forceinline__ int lds_row(int Q) {
+  return (Q & ~6) | ((Q & 2) << 1) | ((Q & 4) >> 1);
+}
+__device__ __forceinline__ int lds_sw(int r) { return ((r >> 2) & 1) << 1; }
+
 template <class SP, int WGM, int FN>
 __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
     const typename SP::T* __restrict__ Ap, const float* __restrict__ s2,
@@ -302,7 +366,7 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
     int row_tiles, double* __restrict__ out, int64_t split_stride, const int* exps) {
   typedef typename SP::T T;
   typedef typename SP::V8 V8;
-  constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 40;
+  constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 32;
   constexpr int A_ITEMS = BM * 4 * SP::TERMS, A_PER = (A_ITEMS + NT - 1) / NT;
   constexpr int B_ITEMS = BN * 4, B_PER = (B_ITEMS + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) T As[SP::TERMS][BM][LDK];
@@ -315,9 +379,9 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = kbeg + kchunk < kp ? kbeg + kchunk : kp;
   const int64_t planeA = (int64_t)r1 * kp;
-  const float bscale = SP::SCALED && exps ? (float)pow2(exps[1]) : 1.0f;
 
-  // loader coordinates (fixed over k)
+  // loader coordinates (fixed over k); item i of a term: quad Q = i / 4 on
+  // row (Q & ~15) | rho(Q & 15), 16-byte chunk i % 4
   int64_t a_src[A_PER];
   int a_dst[A_PER];
   bool a_ok[A_PER];
@@ -325,10 +389,10 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   for (int u = 0; u < A_PER; ++u) {
     const int idx = tid + NT * u;
     const int term = idx / (BM * 4), rem = idx - term * (BM * 4);
-    const int row = rem >> 2, q = rem & 3;
+    const int row = lds_row(rem >> 2), q = rem & 3;
     a_ok[u] = idx < A_ITEMS && a0 + row < r1;
     a_src[u] = a_ok[u] ? term * planeA + (int64_t)(a0 + row) * kp + 8 * q : 0;
-    a_dst[u] = idx < A_ITEMS ? (term * BM + row) * LDK + 8 * q : 0;
+    a_dst[u] = idx < A_ITEMS ? (term * BM + row) * LDK + 8 * (q ^ lds_sw(row)) : 0;
   }
   int64_t s_src[B_PER], u_src[B_PER];
   int b_dst[B_PER];
@@ -336,14 +400,14 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
 #pragma unroll
   for (int u = 0; u < B_PER; ++u) {
     const int idx = tid + NT * u;
-    const int n = idx >> 2, q = idx & 3;
+    const int n = lds_row(idx >> 2), q = idx & 3;
     const int col = n0 + n;
     b_in[u] = idx < B_ITEMS;
     b_ok[u] = b_in[u] && col < W;
     const int b = b_ok[u] ? col / r3 : 0, c = b_ok[u] ? col - (col / r3) * r3 : 0;
     s_src[u] = (int64_t)b * kp + 8 * q;
     u_src[u] = (int64_t)c * kp + 8 * q;
-    b_dst[u] = n * LDK + 8 * q;
+    b_dst[u] = n * LDK + 8 * (q ^ lds_sw(n));
   }
   V8 ra[A_PER];
   float4 rs[B_PER][2], ru[B_PER][2];
@@ -376,12 +440,16 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
                           rs[u][0].w * ru[u][0].w, rs[u][1].x * ru[u][1].x, rs[u][1].y * ru[u][1].y,
                           rs[u][1].z * ru[u][1].z, rs[u][1].w * ru[u][1].w};
       V8 bv[SP::TERMS];
+      if constexpr (SP::PAIRED) {
+        SP::split8(x, bv[0], bv[1]);
+      } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        T parts[SP::TERMS];
-        SP::split32(x[t] * bscale, parts);
+        for (int t = 0; t < 8; ++t) {
+          T parts[SP::TERMS];
+          SP::split32(x[t], parts);
 #pragma unroll
-        for (int term = 0; term < SP::TERMS; ++term) bv[term][t] = parts[term];
+          for (int term = 0; term < SP::TERMS; ++term) bv[term][t] = parts[term];
+        }
       }
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
@@ -405,22 +473,26 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
     store();
   }
   __syncthreads();
-  const int frow = lane & 15, fk = 8 * (lane >> 4);
+  const int frow = lane & 15, fc = lane >> 4;
   int since = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
     const bool more = k0 + 32 < kend;
     if (more) load(k0 + 32);
     V8 af[2][SP::TERMS], bf[FN][SP::TERMS];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 32 + i * 16 + frow;
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
-        af[i][term] = *(const V8*)(&As[term][wm * 32 + i * 16 + frow][fk]);
+        af[i][term] = *(const V8*)(&As[term][r][8 * (fc ^ lds_sw(r))]);
+    }
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int j = 0; j < FN; ++j) {
+      const int r = wn * (16 * FN) + j * 16 + frow;
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
-        bf[j][term] = *(const V8*)(&Bs[term][wn * (16 * FN) + j * 16 + frow][fk]);
+        bf[j][term] = *(const V8*)(&Bs[term][r][8 * (fc ^ lds_sw(r))]);
+    }
     // products in the outer loop: the MFMAs that accumulate into one level
     // of one block are 2 FN instructions apart
 #pragma unroll
@@ -610,7 +682,7 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   // A = U~1^T: row a, column j at U1t[j r1 + a]
   split_planes<SP>(U1t, r1, K, 1, r1, P.kp, exps, 0, planes, s);
   hipLaunchKernelGGL(kr_factors_kernel, dim3(grid_blocks((int64_t)(r2 + r3) * P.kp)), dim3(256), 0,
-                     s, U2t, U3t, xi, r2, r3, K, P.kp, s2, u3);
+                     s, U2t, U3t, xi, r2, r3, K, P.kp, SP::SCALED ? exps : nullptr, s2, u3);
   const dim3 grid((unsigned)(P.row_tiles * P.col_tiles), 1, (unsigned)P.splits);
   double* out = part ? part : beta;
   const int64_t stride = (int64_t)r1 * r2 * r3;
@@ -633,7 +705,7 @@ void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
                 hipStream_t s, const KernelTimer* kt) {
   if (prec == RS_MIXED_FP16)
-    core_mixed_t<SplitF16>(1, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s, kt);
+    core_mixed_t<CoreF16>(1, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s, kt);
   else
     core_mixed_t<SplitBF16>(0, U1t, U2t, U3t, xi, r1, r2, r3, K, beta, num_cu, (char*)work, s, kt);
 }

@@ -337,8 +337,10 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
 
 // ---- core, LDS-tiled: beta_(1)[a, col] = sum_j A[a, j] B[j, col] ------------------
 // col = b r3 + c, B[j, col] = s2[b][j] u3[c][j] formed in FP32 and split once
-// per workgroup into LDS.  Workgroup tile 32 WGM rows x 32 FN columns, 2 WGM
-// waves of 32 x 16 FN (2 x FN MFMA blocks).  Per step of 32 k the next A
+// per workgroup into LDS.  Workgroup tile 32 WGM rows x 32 FN columns, the
+// columns being FN values of b times 32 values of c (so that a tile reads 32
+// rows of u3 and FN of s2, and the workgroups resident together share
+// them), 2 WGM waves of 32 x 16 FN (2 x FN MFMA blocks).  Per step of 32 k the next A
 // fragments (from the split planes) and the raw s2/u3 values are loaded into
 // registers while the MFMAs of the current step run, then written to LDS.
 // LDS layout: rows of 32 elements (64 bytes, four 16-byte chunks), chunk c
@@ -363,10 +365,11 @@ template <class SP, int WGM, int FN>
 __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
     const typename SP::T* __restrict__ Ap, const float* __restrict__ s2,
     const float* __restrict__ u3, int r1, int r2, int r3, int64_t kp, int64_t kchunk,
-    int row_tiles, double* __restrict__ out, int64_t split_stride, const int* exps) {
+    int row_tiles, int b_tiles, double* __restrict__ out, int64_t split_stride, const int* exps) {
   typedef typename SP::T T;
   typedef typename SP::V8 V8;
   constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 32;
+  constexpr int BB = FN;   // column tile: BB values of b x 32 values of c
   constexpr int A_ITEMS = BM * 4 * SP::TERMS, A_PER = (A_ITEMS + NT - 1) / NT;
   constexpr int B_ITEMS = BN * 4, B_PER = (B_ITEMS + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) T As[SP::TERMS][BM][LDK];
@@ -374,8 +377,12 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int W = r2 * r3;
-  const int rt = blockIdx.x % row_tiles, ct = blockIdx.x / row_tiles;
-  const int a0 = rt * BM, n0 = ct * BN;
+  // workgroup order: row tile fastest, then b tile, then c group, so that the
+  // workgroups resident at one time (spread over the XCDs in order) share
+  // the 32 u3 rows of one c group and the A rows of every row tile in L2
+  const int rt = blockIdx.x % row_tiles;
+  const int bt = (blockIdx.x / row_tiles) % b_tiles, cg = blockIdx.x / row_tiles / b_tiles;
+  const int a0 = rt * BM, b0 = bt * BB, c0 = cg * 32;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = kbeg + kchunk < kp ? kbeg + kchunk : kp;
   const int64_t planeA = (int64_t)r1 * kp;
@@ -401,10 +408,9 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   for (int u = 0; u < B_PER; ++u) {
     const int idx = tid + NT * u;
     const int n = lds_row(idx >> 2), q = idx & 3;
-    const int col = n0 + n;
     b_in[u] = idx < B_ITEMS;
-    b_ok[u] = b_in[u] && col < W;
-    const int b = b_ok[u] ? col / r3 : 0, c = b_ok[u] ? col - (col / r3) * r3 : 0;
+    b_ok[u] = b_in[u] && b0 + n / 32 < r2 && c0 + n % 32 < r3;
+    const int b = b_ok[u] ? b0 + n / 32 : 0, c = b_ok[u] ? c0 + n % 32 : 0;
     s_src[u] = (int64_t)b * kp + 8 * q;
     u_src[u] = (int64_t)c * kp + 8 * q;
     b_dst[u] = n * LDK + 8 * (q ^ lds_sw(n));
@@ -528,11 +534,13 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * (16 * FN) + j * 16 + frow;
+      const int n = wn * (16 * FN) + j * 16 + frow;
+      const int b = b0 + n / 32, c = c0 + n % 32;
+      const int col = b * r3 + c;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int a = a0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-        if (a < r1 && col < W) o[(int64_t)a * W + col] = acc64[i][j][v] * out_scale;
+        if (a < r1 && b < r2 && c < r3) o[(int64_t)a * W + col] = acc64[i][j][v] * out_scale;
       }
     }
 }
@@ -607,7 +615,7 @@ static void split_planes(const double* src, int64_t rows, int64_t cols, int64_t 
 // ---- core ------------------------------------------------------------------------
 struct CoreMixedPlan {
   int64_t kp, kchunk;
-  int splits, wgm, row_tiles, col_tiles;
+  int splits, wgm, row_tiles, col_tiles, b_tiles;
   size_t o_mx, o_exps, o_planes, o_s2, o_u3, o_part, total;
 };
 
@@ -632,7 +640,8 @@ static CoreMixedPlan plan_core_mixed(int prec, int r1, int r2, int r3, int64_t K
   P.kp = pad32(K);
   P.wgm = core_wgm(r1);
   P.row_tiles = (r1 + 32 * P.wgm - 1) / (32 * P.wgm);
-  P.col_tiles = (int)(((int64_t)r2 * r3 + 32 * fn - 1) / (32 * fn));
+  P.b_tiles = (r2 + fn - 1) / fn;   // column tiles: fn values of b x 32 of c
+  P.col_tiles = P.b_tiles * ((r3 + 31) / 32);
   const int64_t wgs = (int64_t)P.row_tiles * P.col_tiles;
   P.splits = 1;
   if (wgs < 2LL * num_cu) {
@@ -690,13 +699,13 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   if (kt) RS_HIP(hipEventRecord(kt->begin, s));
   if (P.wgm == 4)
     hipLaunchKernelGGL((core_tile_kernel<SP, 4, FN>), grid, dim3(512), 0, s, planes, s2, u3, r1, r2,
-                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+                       r3, P.kp, P.kchunk, P.row_tiles, P.b_tiles, out, stride, exps);
   else if (P.wgm == 3)
     hipLaunchKernelGGL((core_tile_kernel<SP, 3, FN>), grid, dim3(384), 0, s, planes, s2, u3, r1, r2,
-                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+                       r3, P.kp, P.kchunk, P.row_tiles, P.b_tiles, out, stride, exps);
   else
     hipLaunchKernelGGL((core_tile_kernel<SP, 2, FN>), grid, dim3(256), 0, s, planes, s2, u3, r1, r2,
-                       r3, P.kp, P.kchunk, P.row_tiles, out, stride, exps);
+                       r3, P.kp, P.kchunk, P.row_tiles, P.b_tiles, out, stride, exps);
   if (kt) RS_HIP(hipEventRecord(kt->end, s));
   if (part) core64_reduce(part, P.splits, (int64_t)r1 * r2 * r3, beta, s);
 }

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle import rs
+from oracle import pointeval, rs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -67,3 +67,30 @@ def test_mixed_matches_fp64(rsm, ctx, name, prec):
         err_o = float(np.max(np.abs(gmx - full)) / np.max(np.abs(full)))
         say(f"   vs oracle {err_o:.2e}")
         assert err_o <= TOL
+
+
+@pytest.mark.parametrize("ranks", [[12, 10, 8], [40, 33, 20], [70, 50, 19], [100, 64, 40]])
+@pytest.mark.parametrize("prec", ["mixed_fp16", "mixed_bf16"])
+def test_mixed_core_tile_shapes(rsm, ctx, ranks, prec):
+    """The split core at ranks that pick each row-tile height (r1 = 12, 40:
+    64-row tiles; 70: 96; 100: 128) and both ways of staging the Khatri-Rao
+    factor rows (r3 = 8: a 128-column tile spans 17 b rows, more than the
+    8 staged by the common kernel; r3 = 19, 20, 40: within 8), against the
+    FP64 path at the same ranks and the oracle."""
+    s = workloads.tiny_system(93, 30, 6.0, 104, 24, 10, 9, min_sep=0.6)
+    ref = rs.assemble_system(s, fixed_ranks=ranks)
+    g64, E64 = run(rsm, ctx, s, "fp64", ranks)
+    gmx, Emx = run(rsm, ctx, s, prec, ranks)
+    err = float(np.max(np.abs(gmx - g64)) / np.max(np.abs(g64)))
+    full = ref.full_grid().ravel()
+    err_o = float(np.max(np.abs(gmx - full)) / np.max(np.abs(full)))
+    # the energy of 30 random charges nearly cancels, so its error is bounded
+    # on its own scale: 1/2 sum_j |z_j| max_j |dE/dz_j| (dE/dz_j = P_l(x_j) -
+    # z_j g_j), the bound a field error of 1e-5 of its maximum gives
+    _, dEdq = pointeval.energy(ref)
+    e_scale = 0.5 * float(np.sum(np.abs(s.q))) * float(np.max(np.abs(dEdq)))
+    e_err = abs(Emx - E64) / e_scale
+    say(f"ranks {ranks} {prec}: vs FP64 {err:.2e}, energy {abs(Emx - E64) / abs(E64):.2e} "
+        f"relative, {e_err:.2e} of its scale, vs oracle {err_o:.2e}")
+    assert err <= TOL and err_o <= TOL
+    assert e_err <= 1e-5

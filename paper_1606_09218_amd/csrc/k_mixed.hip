@@ -372,8 +372,8 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   constexpr int BB = FN;   // column tile: BB values of b x 32 values of c
   constexpr int A_ITEMS = BM * 4 * SP::TERMS, A_PER = (A_ITEMS + NT - 1) / NT;
   constexpr int B_ITEMS = BN * 4, B_PER = (B_ITEMS + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) T As[SP::TERMS][BM][LDK];
-  __shared__ __attribute__((aligned(16))) T Bs[SP::TERMS][BN][LDK];
+  __shared__ __attribute__((aligned(16))) T As[2][SP::TERMS][BM][LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][SP::TERMS][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int W = r2 * r3;
@@ -388,63 +388,73 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
   const int64_t planeA = (int64_t)r1 * kp;
 
   // loader coordinates (fixed over k); item i of a term: quad Q = i / 4 on
-  // row (Q & ~15) | rho(Q & 15), 16-byte chunk i % 4
+  // row (Q & ~15) | rho(Q & 15), 16-byte chunk i % 4.  Rows of A beyond r1
+  // and columns beyond the b, c ranges load a valid row instead (the last
+  // one): they only feed output rows and columns that are never written, so
+  // the loads need no branches.  Items past the tile (when the threads
+  // outnumber them) reload item 0 and are not stored.
   int64_t a_src[A_PER];
   int a_dst[A_PER];
-  bool a_ok[A_PER];
 #pragma unroll
   for (int u = 0; u < A_PER; ++u) {
-    const int idx = tid + NT * u;
+    const int idx = tid + NT * u < A_ITEMS ? tid + NT * u : 0;
     const int term = idx / (BM * 4), rem = idx - term * (BM * 4);
     const int row = lds_row(rem >> 2), q = rem & 3;
-    a_ok[u] = idx < A_ITEMS && a0 + row < r1;
-    a_src[u] = a_ok[u] ? term * planeA + (int64_t)(a0 + row) * kp + 8 * q : 0;
-    a_dst[u] = idx < A_ITEMS ? (term * BM + row) * LDK + 8 * (q ^ lds_sw(row)) : 0;
+    const int grow = a0 + row < r1 ? a0 + row : r1 - 1;
+    a_src[u] = term * planeA + (int64_t)grow * kp + 8 * q;
+    a_dst[u] = (term * BM + row) * LDK + 8 * (q ^ lds_sw(row));
   }
   int64_t s_src[B_PER], u_src[B_PER];
   int b_dst[B_PER];
-  bool b_ok[B_PER], b_in[B_PER];
 #pragma unroll
   for (int u = 0; u < B_PER; ++u) {
-    const int idx = tid + NT * u;
+    const int idx = tid + NT * u < B_ITEMS ? tid + NT * u : 0;
     const int n = lds_row(idx >> 2), q = idx & 3;
-    b_in[u] = idx < B_ITEMS;
-    b_ok[u] = b_in[u] && b0 + n / 32 < r2 && c0 + n % 32 < r3;
-    const int b = b_ok[u] ? b0 + n / 32 : 0, c = b_ok[u] ? c0 + n % 32 : 0;
+    const int b = b0 + n / 32 < r2 ? b0 + n / 32 : r2 - 1;
+    const int c = c0 + n % 32 < r3 ? c0 + n % 32 : r3 - 1;
     s_src[u] = (int64_t)b * kp + 8 * q;
     u_src[u] = (int64_t)c * kp + 8 * q;
     b_dst[u] = n * LDK + 8 * (q ^ lds_sw(n));
   }
-  V8 ra[A_PER];
-  float4 rs[B_PER][2], ru[B_PER][2];
-  auto load = [&](int64_t k0) {
+  // Pipeline: LDS buffer s % 2 holds step s.  While the MFMAs of step s
+  // run, the workgroup forms step s + 1 (from registers) into the other
+  // buffer and issues the loads of step s + 3; one barrier per step.  Two
+  // register sets hold steps s + 1 and s + 2, so a load has two steps to
+  // land.  The loop body has no branch (loads past the end re-read the last
+  // step, and the last step's formation goes to a buffer nobody reads), so
+  // the MFMAs and the formation share one scheduling region and interleave.
+  struct Regs {
+    V8 ra[A_PER];
+    float4 rs[B_PER][2], ru[B_PER][2];
+  };
+  Regs R0, R1;
+  const int64_t klast = kend - 32;
+  auto load = [&](int64_t k0, Regs& R) {
+    k0 = k0 < klast ? k0 : klast;
 #pragma unroll
-    for (int u = 0; u < A_PER; ++u) {
-      if (a_ok[u]) ra[u] = *(const V8*)(Ap + a_src[u] + k0);
-      else ra[u] = V8{};
-    }
+    for (int u = 0; u < A_PER; ++u) R.ra[u] = *(const V8*)(Ap + a_src[u] + k0);
 #pragma unroll
     for (int u = 0; u < B_PER; ++u) {
-      if (b_ok[u]) {
-        rs[u][0] = *(const float4*)(s2 + s_src[u] + k0);
-        rs[u][1] = *(const float4*)(s2 + s_src[u] + k0 + 4);
-        ru[u][0] = *(const float4*)(u3 + u_src[u] + k0);
-        ru[u][1] = *(const float4*)(u3 + u_src[u] + k0 + 4);
-      } else {
-        rs[u][0] = rs[u][1] = ru[u][0] = ru[u][1] = float4{0.f, 0.f, 0.f, 0.f};
-      }
+      R.rs[u][0] = *(const float4*)(s2 + s_src[u] + k0);
+      R.rs[u][1] = *(const float4*)(s2 + s_src[u] + k0 + 4);
+      R.ru[u][0] = *(const float4*)(u3 + u_src[u] + k0);
+      R.ru[u][1] = *(const float4*)(u3 + u_src[u] + k0 + 4);
     }
   };
-  auto store = [&]() {
+  auto store = [&](const Regs& R, int buf) {
 #pragma unroll
     for (int u = 0; u < A_PER; ++u)
-      if (tid + NT * u < A_ITEMS) *(V8*)(&As[0][0][0] + a_dst[u]) = ra[u];
+      if (A_ITEMS % NT == 0 || tid + NT * u < A_ITEMS)
+        *(V8*)(&As[buf][0][0][0] + a_dst[u]) = R.ra[u];
 #pragma unroll
     for (int u = 0; u < B_PER; ++u) {
-      if (!b_in[u]) continue;
-      const float x[8] = {rs[u][0].x * ru[u][0].x, rs[u][0].y * ru[u][0].y, rs[u][0].z * ru[u][0].z,
-                          rs[u][0].w * ru[u][0].w, rs[u][1].x * ru[u][1].x, rs[u][1].y * ru[u][1].y,
-                          rs[u][1].z * ru[u][1].z, rs[u][1].w * ru[u][1].w};
+      // threads past the tile store nothing (no test where the items fill
+      // every thread: the formation then stays in the MFMAs' basic block)
+      if (B_ITEMS % NT != 0 && tid + NT * u >= B_ITEMS) break;
+      const float x[8] = {R.rs[u][0].x * R.ru[u][0].x, R.rs[u][0].y * R.ru[u][0].y,
+                          R.rs[u][0].z * R.ru[u][0].z, R.rs[u][0].w * R.ru[u][0].w,
+                          R.rs[u][1].x * R.ru[u][1].x, R.rs[u][1].y * R.ru[u][1].y,
+                          R.rs[u][1].z * R.ru[u][1].z, R.rs[u][1].w * R.ru[u][1].w};
       V8 bv[SP::TERMS];
       if constexpr (SP::PAIRED) {
         SP::split8(x, bv[0], bv[1]);
@@ -459,7 +469,7 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
       }
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
-        *(V8*)(&Bs[term][0][0] + b_dst[u]) = bv[term];
+        *(V8*)(&Bs[buf][term][0][0] + b_dst[u]) = bv[term];
     }
   };
 
@@ -474,30 +484,33 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
     }
-  if (kbeg < kend) {
-    load(kbeg);
-    store();
+  const int nsteps = kbeg < kend ? (int)((kend - kbeg) / 32) : 0;
+  if (nsteps > 0) {
+    load(kbeg, R0);
+    load(kbeg + 32, R1);
+    store(R0, 0);
+    load(kbeg + 64, R0);
   }
   __syncthreads();
   const int frow = lane & 15, fc = lane >> 4;
-  int since = 0;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
-    const bool more = k0 + 32 < kend;
-    if (more) load(k0 + 32);
+  // step s: MFMAs on buffer s % 2; `R` holds step s + 1 (formed into the
+  // other buffer) and then receives step s + 3
+  auto step = [&](int st, Regs& R) {
+    const int cur = st & 1;
     V8 af[2][SP::TERMS], bf[FN][SP::TERMS];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = wm * 32 + i * 16 + frow;
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
-        af[i][term] = *(const V8*)(&As[term][r][8 * (fc ^ lds_sw(r))]);
+        af[i][term] = *(const V8*)(&As[cur][term][r][8 * (fc ^ lds_sw(r))]);
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int r = wn * (16 * FN) + j * 16 + frow;
 #pragma unroll
       for (int term = 0; term < SP::TERMS; ++term)
-        bf[j][term] = *(const V8*)(&Bs[term][r][8 * (fc ^ lds_sw(r))]);
+        bf[j][term] = *(const V8*)(&Bs[cur][term][r][8 * (fc ^ lds_sw(r))]);
     }
     // products in the outer loop: the MFMAs that accumulate into one level
     // of one block are 2 FN instructions apart
@@ -509,8 +522,20 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
         for (int j = 0; j < FN; ++j)
           acc[i][j][SP::PL[pi]] =
               SP::mfma(af[i][SP::PA[pi]], bf[j][SP::PB[pi]], acc[i][j][SP::PL[pi]]);
-    since += 32;
-    if (since >= KCHUNK || !more) {
+    store(R, cur ^ 1);
+    load(kbeg + 32 * (int64_t)(st + 3), R);
+    // schedule: fragment reads first, then each MFMA followed by a share of
+    // the formation's VALU work, LDS writes and global loads
+    constexpr int NMF = SP::NPROD * 2 * FN;
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * SP::TERMS + FN * SP::TERMS, 0);
+#pragma unroll
+    for (int m = 0; m < NMF; ++m) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+      if (m % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      if (m % 4 == 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    if ((st + 1) % (KCHUNK / 32) == 0 || st + 1 == nsteps) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -520,13 +545,12 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
 #pragma unroll
           for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
         }
-      since = 0;
     }
     __syncthreads();
-    if (more) {
-      store();
-      __syncthreads();
-    }
+  };
+  for (int st = 0; st < nsteps; st += 2) {
+    step(st, R1);
+    if (st + 1 < nsteps) step(st + 1, R0);
   }
   const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
   double* o = out + (int64_t)blockIdx.z * split_stride;

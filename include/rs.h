@@ -12,7 +12,7 @@
  * alg1) and U_nu are short-range windows of the reference tensor
  * (Definitions ComCanF, CCT_Uniform).  It also evaluates P at points, the
  * interaction energy (Lemma InterEnergy, eq EnergyFree_Tensor) and the forces
- * F_j = -dE/dx_j (section 4.4).
+ * F_j = -dE/dx_j (section 4.3).
  *
  * Conventions for every call
  *  - "device" pointers are HIP device memory on the context's device (for
@@ -74,7 +74,7 @@ typedef enum { RS_NEWTON = 0, RS_YUKAWA = 1, RS_NEWTON_PLUS_YUKAWA = 2 } rs_kern
  *    products).
  *  RS_FP32: assembled as RS_MIXED_FP16; point values, the energy's per-
  *    particle terms and the forces are evaluated from FP32 copies of the
- *    Tucker field in FP32 arithmetic (section 4.3's energy and forces at
+ *    Tucker field in FP32 arithmetic (the energy and forces of sections 4.2-4.3 at
  *    single precision), with the energy's final reduction and every output
  *    in FP64. */
 typedef enum { RS_FP64 = 0, RS_MIXED_FP16 = 1, RS_MIXED_BF16 = 2, RS_FP32 = 3 } rs_prec;
@@ -284,7 +284,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 rs_status rs_weighted_gram(rs_ctx* ctx, const rs_factors* f, int64_t N, const double* pos,
                            const double* q, int32_t method, double* G, void* stream);
 
-/* ---- evaluation (Lemma Property_RST_Tuck, section 4.3-4.4) ------------- */
+/* ---- evaluation (Lemma Property_RST_Tuck, sections 4.2-4.3) ------------ */
 
 /* Values of the RS tensor at M arbitrary points.
  *  pts: device, M x 3 row-major FP64 inside Omega;  vals: device, M FP64.
@@ -342,6 +342,13 @@ rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double s
  * null E or F, or a non-finite scale. */
 rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
                                    double* F, void* stream);
+
+/* The n^3 grid of the RS tensor (Definition RS-Tucker_format) from its
+ * handle: T2 x_3 V3 plus the short-range windows, the same kernels and
+ * arithmetic as the grid rs_assemble writes, so the result is bitwise that
+ * grid (also for a tensor from rs_tensor_load).  grid_out: device, n^3 in C
+ * order, FP64 for RS_FP64 tensors, FP32 otherwise.  Asynchronous. */
+rs_status rs_tensor_grid(const rs_tensor* T, void* grid_out, void* stream);
 
 /* The discrete gradient of the RS tensor along one axis on the whole grid
  * (eq Gradients_Tens in the Tucker form): grid_out receives the finite

@@ -14,8 +14,9 @@ Modules
   canonical   direct and canonical potential sums, short-range CCT windows (sec. 3.2-3.3)
   rhosvd      side matrices, weighted Gram, RHOSVD basis, core, Tucker (sec. 3.2, Appendix)
   rs          the RS-Tucker assembly (Definition RS-Tucker_format)
-  pointeval   point evaluation, interaction energy and forces (sec. 4.3-4.4)
+  pointeval   point evaluation, interaction energy and forces (sec. 4.2-4.3)
   pairwise    O(N^2) pairwise energies and forces (eq EnergyLatSum)
+  gradient    finite-difference gradient of the RS tensor on the grid (sec. 4.3, eq Gradients_Tens)
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against a closed form, an identity, an invariant, brute force, or a value the

@@ -1,10 +1,10 @@
 """Pairwise interaction energies and forces, O(N^2) (eq EnergyLatSum,
-section 4.4).
+section 4.2; forces, section 4.3).
 
 E = 1/2 sum_j z_j sum_{k != j} z_k f(|x_j - x_k|) for f = p (exact kernel) or
 f = S_K (a subset K of the Gaussian sum, e.g. the long-range part).
 F_j = -dE/dx_j = -z_j sum_{k != j} z_k f'(r_jk) (x_j - x_k)/r_jk.
-The force formula printed in section 4.4 carries a spurious factor 1/2; the
+The force formula printed in section 4.3 carries a spurious factor 1/2; the
 expression above is the derivative of eq EnergyLatSum.
 """
 from __future__ import annotations

@@ -2,7 +2,7 @@
 
 Energy: Lemma InterEnergy (eq EnergyFree_Tensor)
     E_N = 1/2 sum_j z_j (P_l(x_j) - z_j P_{R_l}(0)),
-uses the long-range part only.  Forces: F_j = -grad_{x_j} E_N (section 4.4).
+uses the long-range part only.  Forces: F_j = -grad_{x_j} E_N (section 4.3).
 Differentiating the Lemma's expression with the Tucker basis held fixed gives
 dE/dx_j = z_j grad P_l(x_j) (the self term has zero gradient) and
 dE/dz_j = P_l(x_j) - z_j P_{R_l}(0).

@@ -1078,6 +1078,33 @@ rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, 
   });
 }
 
+rs_status rs_tensor_grid(const rs_tensor* T, void* grid_out, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(T && grid_out, "null argument");
+    RS_HIP(hipSetDevice(T->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = T->n;
+    const int r3 = T->r[2], ncu = T->ctx->num_cu;
+    if (T->prec == RS_FP64) {
+      if (!grid64_stream(T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (double*)grid_out, ncu,
+                         T->ctx->lds_limit, s)) {
+        const Gemm64 gg = grid_gemm(T, grid_out);
+        DevBuf wg(gemm64_workspace_bytes(gg, ncu), s);
+        gemm64(gg, ncu, wg.as<double>(), s);
+      }
+    } else {
+      DevBuf wg(grid_mixed_workspace_bytes(n, r3), s);
+      grid_mixed(contraction_prec(T->prec), T->T2.as<double>(), T->Q[2].as<double>(), n, r3,
+                 (float*)grid_out, wg.p, ncu, s);
+    }
+    short_gather(grid_out, T->prec != RS_FP64, T->pos.as<double>(), T->q.as<double>(),
+                 T->t_dev.as<double>(), T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
+                 T->brick_start.as<int>(), T->brick_list.as<int>(), T->brick_active.as<int>(),
+                 T->active_cap, ncu, s);
+    return RS_OK;
+  });
+}
+
 rs_status rs_gradient_grid(const rs_tensor* T, int32_t axis, void* grid_out, void* stream) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(T && grid_out, "null argument");

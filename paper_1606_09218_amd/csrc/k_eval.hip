@@ -12,7 +12,7 @@
 //   E = 1/2 sum_j z_j (P_l(x_j) - z_j g_j),
 // g_j = particle j's own long-range reference term through the same
 // interpolation operator (P_{R_l}(0) exactly when x_j is a grid point).
-// Forces: F_j = -z_j grad[P_l - z_j g_j](x_j) (section 4.4, basis held fixed).
+// Forces: F_j = -z_j grad[P_l - z_j g_j](x_j) (section 4.3, basis held fixed).
 #include "rs_internal.h"
 
 namespace rs {

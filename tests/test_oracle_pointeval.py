@@ -1,4 +1,4 @@
-"""Pins for oracle.pointeval and oracle.pairwise (sections 4.3-4.4)."""
+"""Pins for oracle.pointeval and oracle.pairwise (sections 4.2-4.3)."""
 import math
 
 import numpy as np

@@ -7,7 +7,7 @@ that both the CPU oracle and the GPU path can read identical bytes without
 sharing any of the computation.
 
 The paper's own particle data (protein-type clusters of 100..782 atoms and
-finite lattices with random charges, sections 3.2 and 4.3) is not available;
+finite lattices with random charges, sections 3.2 and 4.2) is not available;
 the systems below are synthetic stand-ins of the same kinds: uniform clouds
 with a minimum separation (the sigma*-separable sets of Definition
 QU_Distrib), a jittered lattice with vacancies and alternating charges, and

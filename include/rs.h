@@ -146,7 +146,15 @@ typedef enum { RS_GRAM_IDENTITY = 0, RS_GRAM_GEMM = 1 } rs_gram_method;
  *     0 (default) the Gram G_l itself (n x n, 2 n^2 p FLOP; its spectrum is
  *     the square of the side matrix's, so the directions at the threshold are
  *     resolved as by one subspace iteration), 1 the weighted side matrix
- *     U_l diag(|xi|^{1/3}) (n x N R_l, 2 n N R_l p FLOP). */
+ *     U_l diag(|xi|^{1/3}) (n x N R_l, 2 n N R_l p FLOP).
+ *  subspace_min: the rank rule's subspace is searched: the eigensolver runs
+ *     first with p = subspace_min (default 128 when <= 0) and again with the
+ *     full size (r_max + oversample) only when some mode's rank plus twice
+ *     the oversampling exceeds p, so small-rank systems never pay for an
+ *     r_max-sized eigenproblem (one more rank readback when they grow).  A
+ *     value at or above the full size turns the search off; fixed ranks
+ *     size the subspace directly.  The result depends only on the inputs and
+ *     options, not on earlier calls. */
 typedef struct {
   double eps_tucker;
   int32_t r_max;
@@ -157,6 +165,7 @@ typedef struct {
   int32_t interp_order;
   int32_t gram;          /* rs_gram_method */
   int32_t sketch;        /* 0: G_l, 1: U_l diag(|xi|^{1/3}) */
+  int32_t subspace_min;  /* first subspace size of the rank rule's search */
 } rs_aopts;
 
 typedef struct {

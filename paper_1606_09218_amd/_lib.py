@@ -48,7 +48,8 @@ class rs_aopts(C.Structure):
     _fields_ = [("eps_tucker", C.c_double), ("r_max", C.c_int32),
                 ("fixed_ranks", C.c_int32 * 3), ("prec", C.c_int32),
                 ("oversample", C.c_int32), ("power_iters", C.c_int32),
-                ("interp_order", C.c_int32), ("gram", C.c_int32), ("sketch", C.c_int32)]
+                ("interp_order", C.c_int32), ("gram", C.c_int32), ("sketch", C.c_int32),
+                ("subspace_min", C.c_int32)]
 
 
 class rs_info(C.Structure):
@@ -239,10 +240,11 @@ class Factors:
 
 def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = None,
                prec="fp64", oversample=0, power_iters=-1, interp_order=0,
-               gram="identity", sketch="gram") -> rs_aopts:
+               gram="identity", sketch="gram", subspace_min=0) -> rs_aopts:
     fr = (C.c_int32 * 3)(*(list(fixed_ranks) if fixed_ranks else [0, 0, 0]))
     return rs_aopts(float(eps_tucker), int(r_max), fr, PRECS[prec], int(oversample),
-                    int(power_iters), int(interp_order), GRAMS[gram], SKETCHES[sketch])
+                    int(power_iters), int(interp_order), GRAMS[gram], SKETCHES[sketch],
+                    int(subspace_min))
 
 
 class Tensor:

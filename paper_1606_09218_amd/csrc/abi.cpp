@@ -171,6 +171,7 @@ struct Plan {
   int64_t N, n, K;
   int R, R_l, n_s;
   int r_max, p, power_iters, interp, prec, gram, sketch;
+  int os, p_first;   // oversampling; first subspace size of the rank rule's search
   int fixed[3];
   double eps;
 };
@@ -210,7 +211,14 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   if (p % 2) ++p;
   if (p > P.n) p = P.n;
   P.p = (int)p;
+  P.os = os;
   RS_REQUIRE(P.p <= 512 || P.p == P.n, "r_max + oversample must not exceed 512 (eigensolver subspace)");
+  // the rank rule's subspace search starts at subspace_min (even, default
+  // 128); fixed ranks size the subspace directly
+  RS_REQUIRE(d.subspace_min >= 0, "subspace_min must be >= 0");
+  int pf = d.subspace_min > 0 ? d.subspace_min : 128;
+  if (pf % 2) ++pf;
+  P.p_first = all_fixed ? P.p : std::min(P.p, pf);
   RS_REQUIRE(rcap <= 512, "r_max and fixed ranks must not exceed 512");
   P.power_iters = d.power_iters >= 0 ? d.power_iters : 0;
   RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
@@ -574,7 +582,11 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     hipStream_t s = (hipStream_t)stream;
     const Plan P = make_plan(f, N, opts);
     const int64_t n = P.n, K = P.K;
-    const int p = P.p;
+    // eigensolver subspace: every buffer is sized for the plan's p; the rank
+    // rule runs first at P.p_first and again at the plan's p only when a
+    // mode's rank comes within twice the oversampling of the subspace
+    const int p_max = P.p;
+    int p = P.p_first;
     const int ncu = ctx->num_cu;
 
     auto T = std::make_unique<rs_tensor>();
@@ -622,17 +634,38 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     // Every buffer of the stages before the rank readback is a piece of one
     // allocation (a stream-ordered allocation between two launches costs a
     // queue dependency each); the pieces live until the assembly returns.
-    const int rc = std::min<int>(p, std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]}));
+    const int rcap_all = std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]});
+    const int rc_max = std::min<int>(p_max, rcap_all);
+    int rc = std::min<int>(p, rcap_all);
     T->nb = bricks_per_axis(n);
     const int nbricks = T->nb * T->nb * T->nb;
-    Gemm64 gq_shape;  // G Q0 (n x p)
-    gq_shape.M = n; gq_shape.N = p; gq_shape.K = n; gq_shape.batch = 3;
-    Gemm64 qgq_shape;  // B = Q0^T (G Q0) (upper)
-    qgq_shape.M = p; qgq_shape.N = p; qgq_shape.K = n; qgq_shape.batch = 3; qgq_shape.upper_only = 1;
-    Gemm64 yty_shape;  // C = Y^T Y (upper)
-    yty_shape.M = p; yty_shape.N = p; yty_shape.K = n; yty_shape.batch = 3; yty_shape.upper_only = 1;
-    Gemm64 zz_shape;  // C = Z^T Z (upper)
-    zz_shape.M = rc; zz_shape.N = rc; zz_shape.K = p; zz_shape.batch = 3; zz_shape.upper_only = 1;
+    Gemm64 gq_shape, qgq_shape, yty_shape, zz_shape;
+    auto set_shapes = [&](int pp, int rr) {
+      gq_shape.M = n; gq_shape.N = pp; gq_shape.K = n; gq_shape.batch = 3;   // G Q0 (n x p)
+      qgq_shape.M = pp; qgq_shape.N = pp; qgq_shape.K = n; qgq_shape.batch = 3;   // Q0^T (G Q0)
+      qgq_shape.upper_only = 1;
+      yty_shape.M = pp; yty_shape.N = pp; yty_shape.K = n; yty_shape.batch = 3;   // Y^T Y
+      yty_shape.upper_only = 1;
+      zz_shape.M = rr; zz_shape.N = rr; zz_shape.K = pp; zz_shape.batch = 3;   // Z^T Z
+      zz_shape.upper_only = 1;
+    };
+    // workspace of the split-K products at either subspace size
+    auto eig_ws = [&](int pp, int rr, bool sub_path, size_t* wke, size_t* wkz, size_t* ews) {
+      set_shapes(pp, rr);
+      *wke = sub_path ? std::max({sketch64_workspace_bytes(n, P.sketch ? K : n, 3, pp, ncu),
+                                  gemm64_workspace_bytes(gq_shape, ncu),
+                                  gemm64_workspace_bytes(qgq_shape, ncu),
+                                  gemm64_workspace_bytes(yty_shape, ncu)})
+                      : 0;
+      *wkz = gemm64_workspace_bytes(zz_shape, ncu);
+      *ews = eig_sym_workspace_bytes(pp, rr, 3);
+    };
+    size_t wke_a, wkz_a, ews_a, wke_b, wkz_b, ews_b;
+    eig_ws(p_max, rc_max, p_max < n, &wke_a, &wkz_a, &ews_a);
+    eig_ws(p, rc, p < n, &wke_b, &wkz_b, &ews_b);
+    const size_t wke_bytes = std::max(wke_a, wke_b), wkz_bytes = std::max(wkz_a, wkz_b);
+    const size_t ews_bytes = std::max(ews_a, ews_b);
+    set_shapes(p, rc);
     const size_t d8 = sizeof(double);
     const size_t scan_bytes = exclusive_scan_bytes(nbricks + 1);
     Carve pre;
@@ -641,28 +674,24 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const size_t o_w = pre.add((size_t)K * d8), o_sw = pre.add((size_t)K * d8);
     // the three n x n Gram matrices: by the Gaussian-product identity
     // (O(n K + n^2 R_l)) or by the MFMA GEMM U diag(w) U^T (2 n^2 K FLOP)
-    const bool subspace = p < n;
+    const bool subspace = p < n;   // the first pass (the smaller subspace) runs the range finder
     const size_t o_G = pre.add((size_t)3 * n * n * d8);
     const size_t wgram_bytes = P.gram == RS_GRAM_GEMM
                                    ? gemm64_workspace_bytes(gram_gemm(P, nullptr, nullptr, nullptr), ncu)
                                    : gauss_gram_workspace_bytes(P.N, P.R_l, n, ncu);
     const size_t o_wgram = pre.add(wgram_bytes);
-    const size_t o_Q0 = pre.add((size_t)3 * n * p * d8), o_Bm = pre.add((size_t)3 * p * p * d8);
-    const size_t o_Y = pre.add(subspace ? (size_t)3 * n * p * d8 : 0);
-    const size_t o_Cq = pre.add(subspace ? (size_t)3 * p * p * d8 : 0);
+    const size_t o_Q0 = pre.add((size_t)3 * n * p_max * d8);
+    const size_t o_Bm = pre.add((size_t)3 * p_max * p_max * d8);
+    const size_t o_Y = pre.add(subspace ? (size_t)3 * n * p_max * d8 : 0);
+    const size_t o_Cq = pre.add(subspace ? (size_t)3 * p_max * p_max * d8 : 0);
     const size_t o_eta = pre.add(sketch_eta_bytes(3));
-    const size_t wke_bytes =
-        subspace ? std::max({sketch64_workspace_bytes(n, P.sketch ? K : n, 3, p, ncu),
-                             gemm64_workspace_bytes(gq_shape, ncu),
-                             gemm64_workspace_bytes(qgq_shape, ncu),
-                             gemm64_workspace_bytes(yty_shape, ncu)})
-                 : 0;
     const size_t o_wke = pre.add(wke_bytes);
-    const size_t o_ews = pre.add(eig_sym_workspace_bytes(p, rc, 3));
-    const size_t o_Z = pre.add((size_t)3 * p * rc * d8), o_Zsave = pre.add((size_t)3 * p * rc * d8);
-    const size_t o_Cz = pre.add((size_t)3 * rc * rc * d8);
-    const size_t o_wkz = pre.add(gemm64_workspace_bytes(zz_shape, ncu));
-    const size_t o_perm = pre.add((size_t)3 * p * sizeof(int)), o_fixed = pre.add(3 * sizeof(int));
+    const size_t o_ews = pre.add(ews_bytes);
+    const size_t o_Z = pre.add((size_t)3 * p_max * rc_max * d8);
+    const size_t o_Zsave = pre.add((size_t)3 * p_max * rc_max * d8);
+    const size_t o_Cz = pre.add((size_t)3 * rc_max * rc_max * d8);
+    const size_t o_wkz = pre.add(wkz_bytes);
+    const size_t o_perm = pre.add((size_t)3 * p_max * sizeof(int)), o_fixed = pre.add(3 * sizeof(int));
     const size_t o_counts = pre.add((size_t)(nbricks + 1) * sizeof(int));
     const size_t o_scan = pre.add(scan_bytes);
     DevBuf pre_buf(pre.total, s);
@@ -682,10 +711,24 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
                          sw.as<double>(), G.as<double>(), P.gram, s, T.get(),
                          (double*)(pre_buf.as<char>() + o_wgram));
 
+    // short-range binning (counts and offsets; the total is read back with the ranks)
+    Span counts = piece(o_counts, (size_t)(nbricks + 1) * sizeof(int));
+    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
+    short_bin_count(dpos, N, n, f->grid.b, P.n_s, T->nb, counts.as<int>(), s);
+    T->brick_start = DevBuf((size_t)(nbricks + 1) * sizeof(int), s);
+    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1,
+                       pre_buf.as<char>() + o_scan, scan_bytes, s);
+    RS_HIP(hipMemcpyAsync(&rbd->total_pairs, T->brick_start.as<int>() + nbricks, sizeof(int),
+                          hipMemcpyDeviceToDevice, s));
+
     // (a4) dominant eigenvectors: Q0 (n x p per mode, row-major) spans the subspace
     mark(T.get(), RS_STAGE_EIGEN, s);
+    Span Q0, Bm, ews, Z, Zsave, Cz, perm, fixed_dev;
+    Readback host;
+    for (;;) {   // the subspace search: at most two passes
     mark_eig(T.get(), 0, s);
-    Span Q0 = piece(o_Q0, (size_t)3 * n * p * d8), Bm = piece(o_Bm, (size_t)3 * p * p * d8);
+    Q0 = piece(o_Q0, (size_t)3 * n * p * d8);
+    Bm = piece(o_Bm, (size_t)3 * p * p * d8);
     if (p == n) {
       launch_identity(Q0.as<double>(), n, 3, s);
       RS_HIP(hipMemcpyAsync(Bm.p, G.p, G.bytes, hipMemcpyDeviceToDevice, s));
@@ -760,8 +803,8 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       gemm64(qgq_gemm(Q0.as<double>(), Y.as<double>()), ncu, wk_eig.as<double>(), s);
     }
     // eigenvectors are formed only for the rc columns the rank rule can keep
-    Span ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));
-    Span Z = piece(o_Z, (size_t)3 * p * rc * d8);
+    ews = piece(o_ews, eig_sym_workspace_bytes(p, rc, 3));
+    Z = piece(o_Z, (size_t)3 * p * rc * d8);
     mark_eig(T.get(), 1, s);
     launch_eig_tridiag(Bm.as<double>(), ews.as<double>(), p, rc, 3, ctx->lds_limit, s);
     mark_eig(T.get(), 2, s);
@@ -772,14 +815,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     // iteration leaves them nearly orthonormal, so two plain passes suffice;
     // a breakdown (near-parallel vectors, flag bit 4) is redone from the
     // saved vectors with a shifted pass first, after the readback.
-    Span Zsave = piece(o_Zsave, (size_t)3 * p * rc * d8);
+    Zsave = piece(o_Zsave, (size_t)3 * p * rc * d8);
     RS_HIP(hipMemcpyAsync(Zsave.p, Z.p, Zsave.bytes, hipMemcpyDeviceToDevice, s));
-    Span Cz = piece(o_Cz, (size_t)3 * rc * rc * d8);
+    Cz = piece(o_Cz, (size_t)3 * rc * rc * d8);
     Gemm64 gz = zz_shape;  // C = Z^T Z (symmetric)
     gz.A = Z.as<double>(); gz.sam = 1; gz.sak = rc; gz.sab = (int64_t)p * rc;
     gz.B = Z.as<double>(); gz.sbk = rc; gz.sbn = 1; gz.sbb = (int64_t)p * rc;
     gz.C = Cz.as<double>(); gz.scm = rc; gz.scn = 1; gz.scb = (int64_t)rc * rc;
-    Span wkz = piece(o_wkz, gemm64_workspace_bytes(zz_shape, ncu));
+    Span wkz = piece(o_wkz, wkz_bytes);
     auto orth_z = [&](int passes, bool shifted_first, int fail_bit) {
       for (int pass = 0; pass < passes; ++pass) {
         gemm64(gz, ncu, wkz.as<double>(), s);
@@ -795,25 +838,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     orth_z(1, false, 4);
     launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, rc, 3, s);
     mark_eig(T.get(), 4, s);
-    Span perm = piece(o_perm, (size_t)3 * p * sizeof(int));
-    Span fixed_dev = piece(o_fixed, 3 * sizeof(int));
+    perm = piece(o_perm, (size_t)3 * p * sizeof(int));
+    fixed_dev = piece(o_fixed, 3 * sizeof(int));
     RS_HIP(hipMemcpyAsync(fixed_dev.p, P.fixed, 3 * sizeof(int), hipMemcpyHostToDevice, s));
     launch_rank_select(Bm.as<double>(), p, 3, P.eps * P.eps, fixed_dev.as<int>(), P.r_max,
                        perm.as<int>(), &rbd->info, s);
 
-    // short-range binning (counts and offsets; the total is read back with the ranks)
-    Span counts = piece(o_counts, (size_t)(nbricks + 1) * sizeof(int));
-    RS_HIP(hipMemsetAsync(counts.p, 0, counts.bytes, s));
-    short_bin_count(dpos, N, n, f->grid.b, P.n_s, T->nb, counts.as<int>(), s);
-    T->brick_start = DevBuf((size_t)(nbricks + 1) * sizeof(int), s);
-    exclusive_scan_int(counts.as<int>(), T->brick_start.as<int>(), nbricks + 1,
-                       pre_buf.as<char>() + o_scan, scan_bytes, s);
-    RS_HIP(hipMemcpyAsync(&rbd->total_pairs, T->brick_start.as<int>() + nbricks, sizeof(int),
-                          hipMemcpyDeviceToDevice, s));
-
     // the readback lands in a pinned host slot of the context (a copy to
     // pageable memory would be staged through a driver buffer)
-    Readback host;
     {
       void* slot = nullptr;
       {
@@ -850,6 +882,18 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       RS_HIP(hipStreamSynchronize(s));
       if (again & 1) throw Error{RS_E_DEVICE, "eigensolver: Cholesky breakdown in the eigenvectors"};
     }
+    // a rank within twice the oversampling of the subspace is not resolved
+    // well enough: run the eigensolver again at the plan's full size
+    bool grow = false;
+    for (int l = 0; l < 3; ++l)
+      if (host.info.r[l] + 2 * P.os > p) grow = true;
+    if (!grow || p >= p_max) break;
+    p = p_max;
+    rc = rc_max;
+    set_shapes(p, rc);
+    RS_HIP(hipMemsetAsync(&rbd->chol_fail, 0, sizeof(int), s));
+    }   // subspace search
+    for (int l = 0; l < 3; ++l) T->p[l] = p;
 
     for (int l = 0; l < 3; ++l) {
       T->r[l] = host.info.r[l];

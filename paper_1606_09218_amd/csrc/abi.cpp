@@ -473,9 +473,6 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
     if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, device) == hipSuccess && wk > 0)
       c->wall_khz = (double)wk;
     noalloc_scratch_init(device);
-    RS_HIP(hipDeviceGetDefaultMemPool(&c->pool, device));
-    uint64_t thr = UINT64_MAX;  // keep freed blocks cached for reuse
-    RS_HIP(hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &thr));
     *out = c.release();
     return RS_OK;
   });

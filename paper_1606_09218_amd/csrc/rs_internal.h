@@ -71,7 +71,6 @@ struct KernelTimer {
 struct rs_ctx {
   int device = 0;
   int num_cu = 256;
-  hipMemPool_t pool = nullptr;
   int timing = 0;
   int lds_limit = 65536;   // dynamic LDS bytes one workgroup may use
   double wall_khz = 100000.0;  // rate of the device wall clock

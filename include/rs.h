@@ -147,14 +147,15 @@ typedef enum { RS_GRAM_IDENTITY = 0, RS_GRAM_GEMM = 1 } rs_gram_method;
  *     the square of the side matrix's, so the directions at the threshold are
  *     resolved as by one subspace iteration), 1 the weighted side matrix
  *     U_l diag(|xi|^{1/3}) (n x N R_l, 2 n N R_l p FLOP).
- *  subspace_min: the rank rule's subspace is searched: the eigensolver runs
- *     first with p = subspace_min (default 128 when <= 0) and again with the
- *     full size (r_max + oversample) only when some mode's rank plus twice
- *     the oversampling exceeds p, so small-rank systems never pay for an
- *     r_max-sized eigenproblem (one more rank readback when they grow).  A
- *     value at or above the full size turns the search off; fixed ranks
- *     size the subspace directly.  The result depends only on the inputs and
- *     options, not on earlier calls. */
+ *  subspace_min: when > 0, the rank rule's subspace is searched: the
+ *     eigensolver runs first with p = subspace_min and again with the full
+ *     size (r_max + oversample) only when some mode's rank plus twice the
+ *     oversampling exceeds p, so a system whose ranks are far below r_max
+ *     does not pay for an r_max-sized eigenproblem (a system that grows pays
+ *     for both passes and one more rank readback).  0 (default) or a value at
+ *     or above the full size: no search.  Fixed ranks size the subspace
+ *     directly.  The result depends only on the inputs and options, not on
+ *     earlier calls. */
 typedef struct {
   double eps_tucker;
   int32_t r_max;

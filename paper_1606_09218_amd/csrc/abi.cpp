@@ -213,10 +213,11 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   P.p = (int)p;
   P.os = os;
   RS_REQUIRE(P.p <= 512 || P.p == P.n, "r_max + oversample must not exceed 512 (eigensolver subspace)");
-  // the rank rule's subspace search starts at subspace_min (even, default
-  // 128); fixed ranks size the subspace directly
+  // the rank rule's subspace search starts at subspace_min (even; 0, the
+  // default, is the full size: no search); fixed ranks size the subspace
+  // directly
   RS_REQUIRE(d.subspace_min >= 0, "subspace_min must be >= 0");
-  int pf = d.subspace_min > 0 ? d.subspace_min : 128;
+  int pf = d.subspace_min > 0 ? d.subspace_min : P.p;
   if (pf % 2) ++pf;
   P.p_first = all_fixed ? P.p : std::min(P.p, pf);
   RS_REQUIRE(rcap <= 512, "r_max and fixed ranks must not exceed 512");

@@ -198,10 +198,10 @@ def test_mid_subspace_full_grid_parity(rsm, ctx, case):
     s = workloads.tiny_system(case["seed"], case["N"], case["b"], case["n"], case["R"],
                               case["R_l"], case["n_s"], min_sep=0.5)
     say(f"mid-subspace grid parity {s.name} r_max={case['r_max']}")
-    # the GPU's own rank rule with the subspace search off, so that the
-    # subspace is r_max + 16 (fixed ranks would size it from the ranks); the
-    # oracle then keeps the same ranks
-    f, T, g = run_gpu(rsm, ctx, s, r_max=case["r_max"], subspace_min=512)
+    # the GPU's own rank rule (no subspace search), so that the subspace is
+    # r_max + 16 (fixed ranks would size it from the ranks); the oracle then
+    # keeps the same ranks
+    f, T, g = run_gpu(rsm, ctx, s, r_max=case["r_max"])
     inf = T.info()
     own = list(inf.ranks)
     assert min(inf.subspace) > 128
@@ -477,11 +477,11 @@ def test_subspace_search(rsm, ctx):
     128 is solved in one pass at p = 128 although r_max allows 180 (n = 192),
     with the
     oracle's ranks (+-1) and its grid at 1e-6; a system whose ranks need more
-    grows to r_max + 16; both match the search turned off (subspace_min at the
-    full size) in ranks."""
+    grows to r_max + 16; both match the search turned off (the default) in
+    ranks."""
     small = workloads.tiny_system(85, 40, 8.0, 192, 24, 10, 9, min_sep=0.5)
     say(f"subspace search {small.name}")
-    f, T, g = run_gpu(rsm, ctx, small, r_max=180)
+    f, T, g = run_gpu(rsm, ctx, small, r_max=180, subspace_min=128)
     inf = T.info()
     assert max(inf.ranks) + 32 <= 128 and list(inf.subspace) == [128] * 3, (list(inf.ranks), list(inf.subspace))
     ref = rs.assemble_system(small, fixed_ranks=list(inf.ranks))
@@ -489,15 +489,15 @@ def test_subspace_search(rsm, ctx):
     err = rel_linf(g.cpu().numpy().reshape(full.shape), full)
     say(f"  ranks {list(inf.ranks)} subspace {list(inf.subspace)} rel-Linf {err:.2e}")
     assert err <= TOL
-    f2, T2, g2 = run_gpu(rsm, ctx, small, r_max=180, subspace_min=512)
+    f2, T2, g2 = run_gpu(rsm, ctx, small, r_max=180)
     assert list(T2.info().subspace) == [192] * 3     # min(n, r_max + 16): the whole space
     assert list(T2.info().ranks) == list(inf.ranks)
     big = workloads.tiny_system(83, 150, 25.0, 256, 32, 12, 9, min_sep=0.8, box_frac=0.8)
     say(f"subspace search {big.name}")
-    f3, T3, g3 = run_gpu(rsm, ctx, big, r_max=240, eps=1e-9)
+    f3, T3, g3 = run_gpu(rsm, ctx, big, r_max=240, eps=1e-9, subspace_min=128)
     inf3 = T3.info()
     say(f"  ranks {list(inf3.ranks)} subspace {list(inf3.subspace)}")
     assert list(inf3.subspace) == [256] * 3     # grown to min(n, r_max + 16)
-    f4, T4, g4 = run_gpu(rsm, ctx, big, r_max=240, eps=1e-9, subspace_min=512)
+    f4, T4, g4 = run_gpu(rsm, ctx, big, r_max=240, eps=1e-9)
     assert list(T4.info().ranks) == list(inf3.ranks)
     assert torch.equal(g3, g4)

@@ -17,6 +17,7 @@ Modules
   pointeval   point evaluation, interaction energy and forces (sec. 4.2-4.3)
   pairwise    O(N^2) pairwise energies and forces (eq EnergyLatSum)
   gradient    finite-difference gradient of the RS tensor on the grid (sec. 4.3, eq Gradients_Tens)
+  dot         scalar product of two RS tensors on one grid (sec. 3.4)
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against a closed form, an identity, an invariant, brute force, or a value the

@@ -353,6 +353,18 @@ rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double s
 rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
                                    double* F, void* stream);
 
+/* Scalar product <A, B> = sum_i A(i) B(i) of two RS tensors over all n^3
+ * cells of their common grid (section 3.4, item (d)), computed in the
+ * format: the long-range parts through their Tucker factors
+ * (M_l = V_l^A^T V_l^B and three small contractions of the cores), plus the
+ * cells the short-range windows of either tensor touch (outside them each
+ * tensor equals its long part), where A B - A_l B_l is summed brick by brick.
+ * FP64 arithmetic (split-precision tensors keep FP64 factors and cores); the
+ * sums run in a fixed order (deterministic).  The tensors may hold other
+ * particles, charges, kernels and ranks.  out: device, 1 FP64.
+ * Errors: RS_E_INVALID when n or b differ. */
+rs_status rs_dot(const rs_tensor* A, const rs_tensor* B, double* out, void* stream);
+
 /* The n^3 grid of the RS tensor (Definition RS-Tucker_format) from its
  * handle: T2 x_3 V3 plus the short-range windows, the same kernels and
  * arithmetic as the grid rs_assemble writes, so the result is bitwise that

@@ -1120,6 +1120,81 @@ rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, 
   });
 }
 
+rs_status rs_dot(const rs_tensor* A, const rs_tensor* B, double* out, void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(A && B && out, "null argument");
+    RS_REQUIRE(A->ctx->device == B->ctx->device, "tensors on different devices");
+    RS_REQUIRE(A->n == B->n && A->b == B->b, "the tensors must live on the same grid (n and b)");
+    RS_HIP(hipSetDevice(A->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = A->n;
+    const int ncu = A->ctx->num_cu;
+    const int ra[3] = {A->r[0], A->r[1], A->r[2]}, rb[3] = {B->r[0], B->r[1], B->r[2]};
+    // <A_l, B_l> = sum beta_A[abc] beta_B[a'b'c'] M1[a,a'] M2[b,b'] M3[c,c'],
+    // M_l = V_l^A^T V_l^B: X = beta_A x_1 M1^T x_2 M2^T x_3 M3^T, then X . beta_B
+    Gemm64 gm[3], g1, g2, g3;
+    DevBuf M[3];
+    for (int l = 0; l < 3; ++l) {
+      M[l] = DevBuf((size_t)ra[l] * rb[l] * sizeof(double), s);
+      Gemm64& g = gm[l];   // M_l (ra x rb) = V_A^T V_B, contraction over the n grid points
+      g.M = ra[l]; g.N = rb[l]; g.K = n;
+      g.A = A->Q[l].as<double>(); g.sam = 1; g.sak = ra[l];
+      g.B = B->Q[l].as<double>(); g.sbk = rb[l]; g.sbn = 1;
+      g.C = M[l].as<double>(); g.scm = rb[l]; g.scn = 1;
+    }
+    DevBuf X1((size_t)rb[0] * ra[1] * ra[2] * sizeof(double), s);
+    DevBuf X2((size_t)rb[0] * rb[1] * ra[2] * sizeof(double), s);
+    DevBuf X3((size_t)rb[0] * rb[1] * rb[2] * sizeof(double), s);
+    // X1[a', (b, c)] = sum_a M1[a, a'] beta_A[a, (b, c)]
+    g1.M = rb[0]; g1.N = (int64_t)ra[1] * ra[2]; g1.K = ra[0];
+    g1.A = M[0].as<double>(); g1.sam = 1; g1.sak = rb[0];
+    g1.B = A->beta.as<double>(); g1.sbk = (int64_t)ra[1] * ra[2]; g1.sbn = 1;
+    g1.C = X1.as<double>(); g1.scm = (int64_t)ra[1] * ra[2]; g1.scn = 1;
+    // X2[a'][b', c] = sum_b M2[b, b'] X1[a'][b, c]   (batched over a')
+    g2.M = rb[1]; g2.N = ra[2]; g2.K = ra[1]; g2.batch = rb[0];
+    g2.A = M[1].as<double>(); g2.sam = 1; g2.sak = rb[1]; g2.sab = 0;
+    g2.B = X1.as<double>(); g2.sbk = ra[2]; g2.sbn = 1; g2.sbb = (int64_t)ra[1] * ra[2];
+    g2.C = X2.as<double>(); g2.scm = ra[2]; g2.scn = 1; g2.scb = (int64_t)rb[1] * ra[2];
+    // X3[(a', b'), c'] = sum_c X2[(a', b'), c] M3[c, c']
+    g3.M = (int64_t)rb[0] * rb[1]; g3.N = rb[2]; g3.K = ra[2];
+    g3.A = X2.as<double>(); g3.sam = ra[2]; g3.sak = 1;
+    g3.B = M[2].as<double>(); g3.sbk = rb[2]; g3.sbn = 1;
+    g3.C = X3.as<double>(); g3.scm = rb[2]; g3.scn = 1;
+    size_t wk = 0;
+    for (int l = 0; l < 3; ++l) wk = std::max(wk, gemm64_workspace_bytes(gm[l], ncu));
+    wk = std::max({wk, gemm64_workspace_bytes(g1, ncu), gemm64_workspace_bytes(g2, ncu),
+                   gemm64_workspace_bytes(g3, ncu)});
+    DevBuf work(wk, s);
+    for (int l = 0; l < 3; ++l) gemm64(gm[l], ncu, work.as<double>(), s);
+    gemm64(g1, ncu, work.as<double>(), s);
+    gemm64(g2, ncu, work.as<double>(), s);
+    gemm64(g3, ncu, work.as<double>(), s);
+    DevBuf ll(dot_partials_bytes(), s);
+    launch_dot_partial(X3.as<double>(), B->beta.as<double>(), (int64_t)rb[0] * rb[1] * rb[2],
+                       ll.as<double>(), s);
+    // the touched-brick correction: A's bricks, then B's bricks A does not touch
+    auto side = [](const rs_tensor* T) {
+      DotSide d;
+      d.T2 = T->T2.as<double>(); d.V3 = T->Q[2].as<double>();
+      d.pos = T->pos.as<double>(); d.q = T->q.as<double>();
+      d.t = T->t_dev.as<double>(); d.a = T->a_dev.as<double>();
+      d.start = T->brick_start.as<int>(); d.list = T->brick_list.as<int>();
+      d.r3 = T->r[2]; d.R = T->R; d.R_l = T->R_l; d.w = (T->n_s - 1) / 2;
+      return d;
+    };
+    const DotSide da = side(A), db = side(B);
+    DevBuf pa((size_t)std::max<int64_t>(A->active_cap, 1) * sizeof(double), s);
+    DevBuf pb((size_t)std::max<int64_t>(B->active_cap, 1) * sizeof(double), s);
+    launch_dot_bricks(da, db, A->brick_active.as<int>(), A->active_cap, nullptr, A->nb, n, A->b, ncu,
+                      pa.as<double>(), s);
+    launch_dot_bricks(da, db, B->brick_active.as<int>(), B->active_cap, A->brick_start.as<int>(),
+                      B->nb, n, A->b, ncu, pb.as<double>(), s);
+    launch_dot_final(ll.as<double>(), pa.as<double>(), A->brick_active.as<int>(), A->active_cap,
+                     pb.as<double>(), B->brick_active.as<int>(), B->active_cap, out, s);
+    return RS_OK;
+  });
+}
+
 rs_status rs_tensor_grid(const rs_tensor* T, void* grid_out, void* stream) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(T && grid_out, "null argument");

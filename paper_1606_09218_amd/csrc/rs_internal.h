@@ -171,6 +171,24 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
                           double* w, double* sw, hipStream_t s);
 
+// k_dot.hip : scalar product of two RS tensors (the touched-brick correction
+// and fixed-order reductions; the long-long term is formed by the caller)
+struct DotSide {
+  const double *T2 = nullptr, *V3 = nullptr, *pos = nullptr, *q = nullptr, *t = nullptr,
+               *a = nullptr;
+  const int *start = nullptr, *list = nullptr;
+  int r3 = 0, R = 0, R_l = 0, w = 0;
+};
+size_t dot_partials_bytes();
+void launch_dot_partial(const double* x, const double* y, int64_t count, double* partial,
+                        hipStream_t s);
+void launch_dot_bricks(const DotSide& A, const DotSide& B, const int* active, int64_t cap,
+                       const int* skip, int nb, int64_t n, double b, int num_cu, double* partials,
+                       hipStream_t s);
+void launch_dot_final(const double* ll, const double* pa, const int* active_a, int64_t cap_a,
+                      const double* pb, const int* active_b, int64_t cap_b, double* out,
+                      hipStream_t s);
+
 // DV = column-wise finite differences of V (n x r row-major) with spacing h:
 // central inside, one-sided at the ends
 void launch_fd_rows(const double* V, int64_t n, int r, double h, double* DV, hipStream_t s);

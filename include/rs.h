@@ -155,7 +155,16 @@ typedef enum { RS_GRAM_IDENTITY = 0, RS_GRAM_GEMM = 1 } rs_gram_method;
  *     for both passes and one more rank readback).  0 (default) or a value at
  *     or above the full size: no search.  Fixed ranks size the subspace
  *     directly.  The result depends only on the inputs and options, not on
- *     earlier calls. */
+ *     earlier calls.
+ *  als_sweeps: sweeps of the ALS refinement that follows the RHOSVD bases
+ *     (Appendix, steps (III)-(V), eq alg2; default 0): for l = 1, 2, 3 in
+ *     turn, the partially projected image M_l = U_l diag(xi) (U~_m (.) U~_p)^T
+ *     (n x r_m r_p, formed by the core's contraction in the core's
+ *     precision) replaces the mode-l basis by its r_l dominant left singular
+ *     vectors (eigenvectors of M_l M_l^T, FP64); the ranks stay those of the
+ *     rank rule (or fixed).  Each sweep costs about 3 n / r_l times the
+ *     core's contraction and does not decrease ||beta|| (the Tucker error
+ *     does not grow). */
 typedef struct {
   double eps_tucker;
   int32_t r_max;
@@ -167,6 +176,7 @@ typedef struct {
   int32_t gram;          /* rs_gram_method */
   int32_t sketch;        /* 0: G_l, 1: U_l diag(|xi|^{1/3}) */
   int32_t subspace_min;  /* first subspace size of the rank rule's search */
+  int32_t als_sweeps;    /* ALS refinement sweeps of the Tucker bases (0: none) */
 } rs_aopts;
 
 typedef struct {

@@ -49,7 +49,7 @@ class rs_aopts(C.Structure):
                 ("fixed_ranks", C.c_int32 * 3), ("prec", C.c_int32),
                 ("oversample", C.c_int32), ("power_iters", C.c_int32),
                 ("interp_order", C.c_int32), ("gram", C.c_int32), ("sketch", C.c_int32),
-                ("subspace_min", C.c_int32)]
+                ("subspace_min", C.c_int32), ("als_sweeps", C.c_int32)]
 
 
 class rs_info(C.Structure):
@@ -241,11 +241,11 @@ class Factors:
 
 def make_aopts(eps_tucker=1e-6, r_max=0, fixed_ranks: Optional[Sequence[int]] = None,
                prec="fp64", oversample=0, power_iters=-1, interp_order=0,
-               gram="identity", sketch="gram", subspace_min=0) -> rs_aopts:
+               gram="identity", sketch="gram", subspace_min=0, als_sweeps=0) -> rs_aopts:
     fr = (C.c_int32 * 3)(*(list(fixed_ranks) if fixed_ranks else [0, 0, 0]))
     return rs_aopts(float(eps_tucker), int(r_max), fr, PRECS[prec], int(oversample),
                     int(power_iters), int(interp_order), GRAMS[gram], SKETCHES[sketch],
-                    int(subspace_min))
+                    int(subspace_min), int(als_sweeps))
 
 
 class Tensor:

@@ -172,6 +172,7 @@ struct Plan {
   int R, R_l, n_s;
   int r_max, p, power_iters, interp, prec, gram, sketch;
   int os, p_first;   // oversampling; first subspace size of the rank rule's search
+  int als;           // ALS refinement sweeps
   int fixed[3];
   double eps;
 };
@@ -220,6 +221,8 @@ static Plan make_plan(const rs_factors* f, int64_t N, const rs_aopts* o) {
   int pf = d.subspace_min > 0 ? d.subspace_min : P.p;
   if (pf % 2) ++pf;
   P.p_first = all_fixed ? P.p : std::min(P.p, pf);
+  RS_REQUIRE(d.als_sweeps >= 0 && d.als_sweeps <= 16, "als_sweeps must be in [0, 16]");
+  P.als = d.als_sweeps;
   RS_REQUIRE(rcap <= 512, "r_max and fixed ranks must not exceed 512");
   P.power_iters = d.power_iters >= 0 ? d.power_iters : 0;
   RS_REQUIRE(P.power_iters <= 8, "power_iters must be <= 8");
@@ -422,6 +425,89 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
                  T->active_cap, ncu, s);
   }
   mark(T, RS_STAGE_COUNT, s);
+}
+
+// The r dominant eigenvectors of the symmetric n x n matrix G (row-major)
+// into V (n x r row-major, canonical signs), by the same steps as the
+// assembly's eigensolver for one matrix: the range finder Y = G Omega,
+// shifted and plain Cholesky QR, Rayleigh-Ritz, the dense eigensolver,
+// Cholesky QR of the eigenvectors, V = Q W.  Breakdowns set bits of *fail.
+static void dominant_eigvecs(const rs_ctx* ctx, const double* G, int64_t n, int r, double* V,
+                             int* fail, hipStream_t s) {
+  const int ncu = ctx->num_cu, lds = ctx->lds_limit;
+  int64_t pp = std::min<int64_t>(n, (int64_t)r + 48);
+  if (pp % 2) ++pp;
+  if (pp > n) pp = n;
+  const int p = (int)pp;
+  DevBuf Q0((size_t)n * p * sizeof(double), s), Bm((size_t)p * p * sizeof(double), s);
+  if (p == n) {
+    launch_identity(Q0.as<double>(), n, 1, s);
+    RS_HIP(hipMemcpyAsync(Bm.p, G, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    DevBuf Y((size_t)n * p * sizeof(double), s), Cq((size_t)p * p * sizeof(double), s);
+    DevBuf eta(sketch_eta_bytes(1), s);
+    Gemm64 yty;   // Cq = Q0^T Q0 (upper)
+    yty.M = p; yty.N = p; yty.K = n; yty.upper_only = 1;
+    yty.A = Q0.as<double>(); yty.sam = 1; yty.sak = p;
+    yty.B = Q0.as<double>(); yty.sbk = p; yty.sbn = 1;
+    yty.C = Cq.as<double>(); yty.scm = p; yty.scn = 1;
+    Gemm64 gq;    // Y = G Q0
+    gq.M = n; gq.N = p; gq.K = n;
+    gq.A = G; gq.sam = n; gq.sak = 1;
+    gq.B = Q0.as<double>(); gq.sbk = p; gq.sbn = 1;
+    gq.C = Y.as<double>(); gq.scm = p; gq.scn = 1;
+    Gemm64 qgq;   // B = Q0^T Y (upper)
+    qgq.M = p; qgq.N = p; qgq.K = n; qgq.upper_only = 1;
+    qgq.A = Q0.as<double>(); qgq.sam = 1; qgq.sak = p;
+    qgq.B = Y.as<double>(); qgq.sbk = p; qgq.sbn = 1;
+    qgq.C = Bm.as<double>(); qgq.scm = p; qgq.scn = 1;
+    DevBuf work(std::max({sketch64_workspace_bytes(n, n, 1, p, ncu), gemm64_workspace_bytes(yty, ncu),
+                          gemm64_workspace_bytes(gq, ncu), gemm64_workspace_bytes(qgq, ncu)}),
+                s);
+    sketch64(G, n, n, n * n, nullptr, 0, 1, p, 0x5eed1234ULL, Q0.as<double>(), p, 1, ncu,
+             work.as<double>(), s);
+    launch_sketch_eta(Q0.as<double>(), n, p, 1, eta.as<double>(), s);
+    launch_perturb_eta(Q0.as<double>(), eta.as<double>(), n, p, 1, 1e-13, 0x9e3779b9ULL, s);
+    for (int pass = 0; pass < 4; ++pass) {
+      gemm64(yty, ncu, work.as<double>(), s);
+      launch_chol(Cq.as<double>(), p, n, 1, pass < 2, lds, fail, 1, s);
+      launch_trsm_rows(Q0.as<double>(), Cq.as<double>(), n, p, 1, lds, s);
+    }
+    gemm64(gq, ncu, work.as<double>(), s);
+    gemm64(qgq, ncu, work.as<double>(), s);
+  }
+  DevBuf ews(eig_sym_workspace_bytes(p, r, 1), s), Z((size_t)p * r * sizeof(double), s);
+  DevBuf Cz((size_t)r * r * sizeof(double), s), Wr((size_t)p * r * sizeof(double), s);
+  DevBuf perm((size_t)p * sizeof(int), s), fixed(3 * sizeof(int), s), info(sizeof(RankInfo), s);
+  launch_eig_tridiag(Bm.as<double>(), ews.as<double>(), p, r, 1, lds, s);
+  launch_eig_values_vectors(Bm.as<double>(), ews.as<double>(), Z.as<double>(), p, r, 1, lds, s);
+  Gemm64 gz;      // Cz = Z^T Z (upper)
+  gz.M = r; gz.N = r; gz.K = p; gz.upper_only = 1;
+  gz.A = Z.as<double>(); gz.sam = 1; gz.sak = r;
+  gz.B = Z.as<double>(); gz.sbk = r; gz.sbn = 1;
+  gz.C = Cz.as<double>(); gz.scm = r; gz.scn = 1;
+  DevBuf wz(gemm64_workspace_bytes(gz, ncu), s);
+  gemm64(gz, ncu, wz.as<double>(), s);
+  launch_chol(Cz.as<double>(), r, p, 1, 0, lds, fail, 4, s);
+  launch_trsm_rows(Z.as<double>(), Cz.as<double>(), p, r, 1, lds, s);
+  launch_eig_backtransform(Z.as<double>(), ews.as<double>(), p, r, 1, s);
+  const int fx[3] = {r, 0, 0};
+  RS_HIP(hipMemcpyAsync(fixed.p, fx, sizeof(fx), hipMemcpyHostToDevice, s));
+  launch_rank_select(Bm.as<double>(), p, 1, 0.0, fixed.as<int>(), r, perm.as<int>(),
+                     info.as<RankInfo>(), s);
+  Mode3 w{{Wr.as<double>(), nullptr, nullptr}, {r, 0, 0}};
+  launch_gather_cols3(Z.as<double>(), r, (int64_t)p * r, perm.as<int>(), p, w, s);
+  Gemm64 gb;      // V = Q0 W_r (n x r)
+  gb.M = n; gb.N = r; gb.K = p;
+  gb.A = Q0.as<double>(); gb.sam = p; gb.sak = 1;
+  gb.B = Wr.as<double>(); gb.sbk = 1; gb.sbn = p;
+  gb.C = V; gb.scm = r; gb.scn = 1;
+  DevBuf wb(gemm64_workspace_bytes(gb, ncu), s);
+  gemm64(gb, ncu, wb.as<double>(), s);
+  Mode3 q{{V, nullptr, nullptr}, {r, 0, 0}};
+  Mode3 none{{nullptr, nullptr, nullptr}, {r, 0, 0}};
+  launch_canonical_signs3(q, n, none, p, s);
+  RS_HIP(hipStreamSynchronize(s));   // the host-side constant above and the buffers' lifetimes
 }
 
 struct Readback {
@@ -970,6 +1056,47 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     for (int l = 0; l < 3; ++l) {
       gp[l].C = at(o_ut[l]);
       gemm64(gp[l], ncu, at(o_wkp[l]), s);
+    }
+    // ALS refinement (Appendix, steps (III)-(IV)): for each mode in turn the
+    // partially projected image M_l = U_l diag(xi) (U~_m (.) U~_p)^T (the
+    // core's contraction with the side matrix itself as first factor: U_l,
+    // column-major n x K, is the K x n row-major operand), its Gram M M^T,
+    // the r_l dominant eigenvectors as the new basis, the new projection
+    if (P.als > 0) {
+      DevBuf dfail(sizeof(int), s);
+      RS_HIP(hipMemsetAsync(dfail.p, 0, sizeof(int), s));
+      for (int sweep = 0; sweep < P.als; ++sweep) {
+        for (int l = 0; l < 3; ++l) {
+          const int m = l == 0 ? 1 : 0, q = l == 2 ? 1 : 2;
+          const int rm = T->r[m], rq = T->r[q];
+          const int64_t W = (int64_t)rm * rq;
+          DevBuf Mb((size_t)n * W * sizeof(double), s);
+          const double* Ul = U.as<double>() + (int64_t)l * n * K;
+          if (P.prec == RS_FP64) {
+            DevBuf wc(core64_workspace_bytes((int)n, rm, rq, K, ncu), s);
+            core64(Ul, at(o_ut[m]), at(o_ut[q]), xi.as<double>(), (int)n, rm, rq, K, Mb.as<double>(),
+                   ncu, wc.as<double>(), s);
+          } else {
+            DevBuf wc(core_mixed_workspace_bytes((int)n, rm, rq, K, ncu), s);
+            core_mixed(contraction_prec(P.prec), Ul, at(o_ut[m]), at(o_ut[q]), xi.as<double>(), (int)n,
+                       rm, rq, K, Mb.as<double>(), ncu, wc.as<double>(), s);
+          }
+          DevBuf Gm((size_t)n * n * sizeof(double), s);
+          Gemm64 gg;   // G = M M^T (upper, mirrored)
+          gg.M = n; gg.N = n; gg.K = W; gg.upper_only = 1;
+          gg.A = Mb.as<double>(); gg.sam = W; gg.sak = 1;
+          gg.B = Mb.as<double>(); gg.sbk = 1; gg.sbn = W;
+          gg.C = Gm.as<double>(); gg.scm = n; gg.scn = 1;
+          DevBuf wg(gemm64_workspace_bytes(gg, ncu), s);
+          gemm64(gg, ncu, wg.as<double>(), s);
+          dominant_eigvecs(ctx, Gm.as<double>(), n, T->r[l], T->Q[l].as<double>(), dfail.as<int>(), s);
+          gemm64(gp[l], ncu, at(o_wkp[l]), s);
+        }
+      }
+      int hf = 0;
+      RS_HIP(hipMemcpyAsync(&hf, dfail.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      RS_HIP(hipStreamSynchronize(s));
+      if (hf & 5) throw Error{RS_E_DEVICE, "ALS refinement: Cholesky breakdown in a basis"};
     }
     mark(T.get(), RS_STAGE_CORE, s);
     const KernelTimer* kt = T->kevents.begin ? &T->kevents : nullptr;

@@ -19,6 +19,7 @@ Modules
   gradient    finite-difference gradient of the RS tensor on the grid (sec. 4.3, eq Gradients_Tens)
   dot         scalar product of two RS tensors on one grid (sec. 3.4)
   als         ALS refinement of the RHOSVD bases and core (Appendix, steps (III)-(V))
+  rbf         RS form of the RBF interpolation matrix and its matrix-vector product (sec. 4.1)
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against a closed form, an identity, an invariant, brute force, or a value the

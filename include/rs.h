@@ -363,6 +363,21 @@ rs_status rs_energy_forces(const rs_tensor* T, double* E, double* dEdq, double s
 rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, double scale,
                                    double* F, void* stream);
 
+/* Matrix-vector product with the RBF interpolation matrix of the kernel p
+ * on the n^3 grid points in RS form (section 4.1, case (A)):
+ *   y = A c,  A = sum_k a_k T_k (x) T_k (x) T_k,
+ * T_k[i][j] = exp(-t_k^2 ((i - j) h)^2) the symmetric Toeplitz Gaussian of
+ * quadrature node k, truncated for the short-range terms k >= R_l to the
+ * window |i - j| <= (n_s - 1)/2 (the localised part of the split).  The
+ * Kronecker factors are applied mode by mode as FP64 MFMA GEMMs, the sum
+ * over k folded into the last one (6 R n^4 FLOP: dense Toeplitz products
+ * suit the matrix cores for n up to a few hundred; the paper's 1D FFTs
+ * would scale as R n^3 log n).
+ * c, y: device, n^3 FP64 in C order (distinct buffers).  Takes R n^3 + n^3
+ * doubles of device workspace. */
+rs_status rs_rbf_matvec(rs_ctx* ctx, const rs_factors* f, const double* c, double* y,
+                        void* stream);
+
 /* Scalar product <A, B> = sum_i A(i) B(i) of two RS tensors over all n^3
  * cells of their common grid (section 3.4, item (d)), computed in the
  * format: the long-range parts through their Tucker factors

@@ -95,6 +95,7 @@ def _load():
         "rs_gradient_grid": ([P, C.c_int32, P, P], C.c_int),
         "rs_tensor_grid": ([P, P, P], C.c_int),
         "rs_dot": ([P, P, P, P], C.c_int),
+        "rs_rbf_matvec": ([P, P, P, P, P], C.c_int),
         "rs_eval_gradient_points": ([P, C.c_int64, P, P, P, C.c_int32, P], C.c_int),
         "rs_footprint_bytes": ([C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.c_int64, C.c_int32,
                                 C.c_int32, C.c_int32], C.c_size_t),
@@ -137,7 +138,8 @@ EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim
             "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_gradient_grid",
-            "rs_eval_gradient_points", "rs_tensor_grid", "rs_dot", "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
+            "rs_eval_gradient_points", "rs_tensor_grid", "rs_dot", "rs_rbf_matvec",
+            "rs_footprint_bytes", "rs_tensor_info", "rs_tensor_export",
             "rs_tensor_save", "rs_tensor_load", "rs_tensor_free", "rs_status_str",
             "rs_last_error")
 
@@ -354,6 +356,14 @@ def eval_gradient_points(T: Tensor, pts, out, normals=None, part: int = 0, strea
     _check(lib.rs_eval_gradient_points(T.handle, M, _dev_ptr(pts, "f64", 3 * M, "pts"), p_n,
                                        _dev_ptr(out, "f64", M if normals is not None else 3 * M, "out"),
                                        int(part), _stream_ptr(stream)))
+
+
+def rbf_matvec(ctx: Context, f: Factors, c, y, stream=None):
+    """rs_rbf_matvec: y = A c with the RS form of the RBF matrix on the n^3
+    grid (c, y device FP64 n^3)."""
+    n3 = f.n ** 3
+    _check(lib.rs_rbf_matvec(ctx.handle, f.handle, _dev_ptr(c, "f64", n3, "c"),
+                             _dev_ptr(y, "f64", n3, "y"), _stream_ptr(stream)))
 
 
 def dot(A: Tensor, B: Tensor, out, stream=None):

@@ -1247,6 +1247,52 @@ rs_status rs_energy_forces_noalloc(const rs_tensor* T, double* E, double* dEdq, 
   });
 }
 
+rs_status rs_rbf_matvec(rs_ctx* ctx, const rs_factors* f, const double* c, double* y,
+                        void* stream) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx && f && c && y, "null argument");
+    RS_REQUIRE(f->device == ctx->device, "factors built for another device");
+    RS_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = f->grid.n;
+    const int R = f->table.R, R_l = f->table.R_l, ncu = ctx->num_cu;
+    const double h = 2.0 * f->grid.b / (double)n;
+    const int64_t n2 = n * n, n3 = n2 * n;
+    DevBuf T((size_t)R * n2 * sizeof(double), s), Acat((size_t)R * n2 * sizeof(double), s);
+    DevBuf Z1((size_t)n3 * sizeof(double), s), Z2((size_t)R * n3 * sizeof(double), s);
+    launch_rbf_toeplitz(f->t_dev, f->a_dev, R, R_l, n, h, (f->table.n_s - 1) / 2, T.as<double>(),
+                        Acat.as<double>(), s);
+    // y = sum_k a_k (T_k (x) T_k (x) T_k) c: modes 3 and 2 per term (Z2_k kept
+    // for every k), then mode 1 and the sum over k in one GEMM of depth R n
+    Gemm64 g3, g2, g1;
+    g3.M = n2; g3.N = n; g3.K = n;               // Z1 = c_(12) T_k
+    g3.A = c; g3.sam = n; g3.sak = 1;
+    g3.sbk = n; g3.sbn = 1;
+    g3.C = Z1.as<double>(); g3.scm = n; g3.scn = 1;
+    g2.M = n; g2.N = n; g2.K = n; g2.batch = n;   // Z2_k[i1] = T_k Z1[i1]
+    g2.sam = n; g2.sak = 1; g2.sab = 0;
+    g2.B = Z1.as<double>(); g2.sbk = n; g2.sbn = 1; g2.sbb = n2;
+    g2.scm = n; g2.scn = 1; g2.scb = n2;
+    g1.M = n; g1.N = n2; g1.K = (int64_t)R * n;   // y = [a_1 T_1 .. a_R T_R] [Z2_1; ..; Z2_R]
+    g1.A = Acat.as<double>(); g1.sam = (int64_t)R * n; g1.sak = 1;
+    g1.B = Z2.as<double>(); g1.sbk = n2; g1.sbn = 1;
+    g1.C = y; g1.scm = n2; g1.scn = 1;
+    DevBuf work(std::max({gemm64_workspace_bytes(g3, ncu), gemm64_workspace_bytes(g2, ncu),
+                          gemm64_workspace_bytes(g1, ncu)}),
+                s);
+    for (int k = 0; k < R; ++k) {
+      const double* Tk = T.as<double>() + (int64_t)k * n2;
+      g3.B = Tk;
+      gemm64(g3, ncu, work.as<double>(), s);
+      g2.A = Tk;
+      g2.C = Z2.as<double>() + (int64_t)k * n3;
+      gemm64(g2, ncu, work.as<double>(), s);
+    }
+    gemm64(g1, ncu, work.as<double>(), s);
+    return RS_OK;
+  });
+}
+
 rs_status rs_dot(const rs_tensor* A, const rs_tensor* B, double* out, void* stream) {
   return guarded([&]() -> rs_status {
     RS_REQUIRE(A && B && out, "null argument");

@@ -87,6 +87,36 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
                      R_l, xi, w, sw);
 }
 
+// The Toeplitz factors of the RS form of the RBF matrix (section 4.1):
+// T[k][i][j] = exp(-t_k^2 ((i - j) h)^2), for the short-range terms k >= R_l
+// only within the window |i - j| <= w; Acat[i][k n + j] = a_k T[k][i][j].
+__global__ void rbf_toeplitz_kernel(const double* __restrict__ t, const double* __restrict__ a,
+                                    int R, int R_l, int64_t n, double h, int w,
+                                    double* __restrict__ T, double* __restrict__ Acat) {
+  const int64_t total = (int64_t)R * n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / (n * n));
+    const int64_t ij = e - (int64_t)k * n * n, i = ij / n, j = ij - (ij / n) * n;
+    const int64_t d = i - j;
+    double v = 0.0;
+    if (k < R_l || (d <= w && d >= -w)) {
+      const double x = (double)d * h;
+      v = exp(-t[k] * t[k] * (x * x));
+    }
+    T[e] = v;
+    Acat[i * (int64_t)R * n + (int64_t)k * n + j] = a[k] * v;
+  }
+}
+
+void launch_rbf_toeplitz(const double* t, const double* a, int R, int R_l, int64_t n, double h,
+                         int w, double* T, double* Acat, hipStream_t s) {
+  const int64_t total = (int64_t)R * n * n;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(rbf_toeplitz_kernel, dim3(blocks), dim3(256), 0, s, t, a, R, R_l, n, h, w, T,
+                     Acat);
+}
+
 // DV[i, c] = d/dx of column c of V (n x r row-major) on the cell-centred grid:
 // central differences inside, one-sided at the two ends (eq Gradients_Tens).
 __global__ void fd_rows_kernel(const double* __restrict__ V, int64_t n, int r, double h,

@@ -189,6 +189,9 @@ void launch_dot_final(const double* ll, const double* pa, const int* active_a, i
                       const double* pb, const int* active_b, int64_t cap_b, double* out,
                       hipStream_t s);
 
+// Toeplitz factors of the RS RBF matrix: T (R x n x n) and Acat (n x R n)
+void launch_rbf_toeplitz(const double* t, const double* a, int R, int R_l, int64_t n, double h,
+                         int w, double* T, double* Acat, hipStream_t s);
 // DV = column-wise finite differences of V (n x r row-major) with spacing h:
 // central inside, one-sided at the ends
 void launch_fd_rows(const double* V, int64_t n, int r, double h, double* DV, hipStream_t s);

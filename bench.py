@@ -309,6 +309,84 @@ def secondary_leg(rsm, ctx, name, steps, warmup, stream):
     return out
 
 
+def _event_ms(fn, reps: int = 3):
+    """Mean milliseconds of fn() over `reps` calls on torch's current stream
+    (one warm-up call first), from HIP events around the calls."""
+    import torch
+    fn()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return b.elapsed_time(e) / reps
+
+
+def extras_leg(rsm, ctx):
+    """The operations beside the assembly, each timed on a workload of its
+    own with its algorithmic work (FP64 arithmetic, peak 78.6 TFLOP/s):
+    the scalar product and the gradient field of the protein-like tensor
+    (split FP16), the RBF matrix-vector product at 256^3, and one ALS sweep
+    on the lattice workload."""
+    import torch
+    out = {}
+    s, cfg, r_max = workload("cfg3")
+    f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, -1, kernel=s.kernel, lam=s.lam, delta_rel=s.delta_rel)
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    q = torch.tensor(s.q, dtype=torch.float64, device="cuda")
+    T = rsm.assemble(ctx, f, pos, q, None, rsm.make_aopts(s.eps_tucker, r_max=r_max, prec="mixed_fp16"))
+    r = list(T.info().ranks)
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    ms = _event_ms(lambda: rsm.dot(T, T, E))
+    ll_flop = 2.0 * s.n * sum(x * x for x in r) + 2.0 * r[0] * r[1] * r[2] * (r[0] + r[1] + r[2])
+    out["scalar_product"] = {"workload": cfg["workload"], "ranks": r, "ms": round(ms, 3),
+                             "long_long_gflop": round(ll_flop / 1e9, 2),
+                             "what": "<A, A> in the format: Tucker long-long term + touched-brick correction"}
+    g = torch.empty(s.n ** 3, dtype=torch.float32, device="cuda")
+    ms = _event_ms(lambda: rsm.gradient_grid(T, 0, g))
+    out["gradient_grid"] = {"workload": cfg["workload"], "axis": 0, "ms": round(ms, 3),
+                            "grid_gbytes_written": round(4.0 * s.n ** 3 / 1e9, 2),
+                            "what": "eq Gradients_Tens on the n^3 grid (split FP16 contraction, FP32 grid)"}
+    del g
+    T.free()
+    f.close()
+    torch.cuda.empty_cache()
+    n = 256
+    fr = rsm.Factors(ctx, 25.0, n, 24, 10, 9)
+    c = torch.randn(n ** 3, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(c)
+    ms = _event_ms(lambda: rsm.rbf_matvec(ctx, fr, c, y))
+    flop = 6.0 * 24 * n ** 4
+    out["rbf_matvec"] = {"n": n, "R": 24, "R_l": 10, "n_s": 9, "ms": round(ms, 3),
+                         "tflops": round(flop / (ms * 1e-3) / 1e12, 2),
+                         "frac_fp64_peak": round(flop / (ms * 1e-3) / 78.6e12, 4)}
+    del c, y
+    fr.close()
+    s2, cfg2, r_max2 = workload("cfg2")
+    f2 = rsm.Factors(ctx, s2.b, s2.n, s2.R, s2.R_l, s2.n_s, kernel=s2.kernel, lam=s2.lam,
+                     delta_rel=s2.delta_rel)
+    pos2 = torch.tensor(s2.pos, dtype=torch.float64, device="cuda")
+    q2 = torch.tensor(s2.q, dtype=torch.float64, device="cuda")
+    times, ranks = {}, []
+    for sweeps in (0, 1):
+        opts = rsm.make_aopts(s2.eps_tucker, r_max=r_max2, als_sweeps=sweeps)
+        def one():
+            Tx = rsm.assemble(ctx, f2, pos2, q2, None, opts)
+            ranks[:] = list(Tx.info().ranks)
+            Tx.free()
+        times[sweeps] = _event_ms(one)
+    K = s2.N * s2.R_l
+    flop = sum(2.0 * s2.n * K * ranks[m] * ranks[p] for m, p in ((1, 2), (0, 2), (0, 1)))
+    out["als_sweep"] = {"workload": cfg2["workload"], "ranks": ranks, "ms_per_sweep": round(times[1] - times[0], 3),
+                        "assembly_ms_without": round(times[0], 3),
+                        "partial_image_gflop": round(flop / 1e9, 1),
+                        "what": "Appendix steps (III)-(IV): three partially projected images, their Grams and bases"}
+    f2.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(n_requests: int, n_slots: int = 4, prec: str = "mixed_fp16"):
     """The first `n_requests` requests of the seeded Poisson serving trace
     (rate 200/s; N log-uniform in [32, 20000]; n in {256, 512, 1024}; R in
@@ -433,6 +511,8 @@ def main():
                     help="another workload timed in FP64 and split FP16 ('' to skip)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving trace to replay (0: skip the serving leg)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the scalar product, gradient field, RBF product, ALS")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
     ap.add_argument("--cpu-baseline-only", action="store_true",
@@ -529,6 +609,9 @@ def main():
         print(f"bench: secondary workload {args.secondary}", file=sys.stderr, flush=True)
         out["secondary"] = {args.secondary: secondary_leg(rsm, ctx, args.secondary, args.steps,
                                                           args.warmup, stream)}
+    if not args.no_extras:
+        print("bench: extras", file=sys.stderr, flush=True)
+        out["extras"] = extras_leg(rsm, ctx)
     if args.serve_requests > 0:
         try:
             out["serving"] = serving_leg(args.serve_requests)

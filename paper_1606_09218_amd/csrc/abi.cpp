@@ -1356,14 +1356,10 @@ rs_status rs_dot(const rs_tensor* A, const rs_tensor* B, double* out, void* stre
       return d;
     };
     const DotSide da = side(A), db = side(B);
-    DevBuf pa((size_t)std::max<int64_t>(A->active_cap, 1) * sizeof(double), s);
-    DevBuf pb((size_t)std::max<int64_t>(B->active_cap, 1) * sizeof(double), s);
-    launch_dot_bricks(da, db, A->brick_active.as<int>(), A->active_cap, nullptr, A->nb, n, A->b, ncu,
-                      pa.as<double>(), s);
-    launch_dot_bricks(da, db, B->brick_active.as<int>(), B->active_cap, A->brick_start.as<int>(),
-                      B->nb, n, A->b, ncu, pb.as<double>(), s);
-    launch_dot_final(ll.as<double>(), pa.as<double>(), A->brick_active.as<int>(), A->active_cap,
-                     pb.as<double>(), B->brick_active.as<int>(), B->active_cap, out, s);
+    const int64_t ncols = (int64_t)A->nb * A->nb;
+    DevBuf pc((size_t)ncols * sizeof(double), s);
+    launch_dot_cols(da, db, A->nb, n, A->b, pc.as<double>(), s);
+    launch_dot_final(ll.as<double>(), pc.as<double>(), ncols, out, s);
     return RS_OK;
   });
 }

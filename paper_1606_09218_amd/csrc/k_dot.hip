@@ -8,6 +8,8 @@
 
 namespace rs {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double dot_readlane(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
@@ -19,24 +21,28 @@ __device__ __forceinline__ double dot_wave_sum(double v) {
   return v;
 }
 
-// Short-range values of one tensor at the cells (base0 + m, i1, i2), m = 0..7,
-// of this lane: the windowed terms z_nu sum_{k >= R_l} a_k g g g of the
-// particles listed for brick `br` (the same sum the grid's short gather adds).
-// f: LDS [3][Rs][8] factors, ak / tk2: LDS [Rs] (one wave per workgroup, so
-// __syncthreads is a wave barrier).
+// Wave-scope barrier for LDS data exchanged between the lanes of one wave
+// (the waves of a workgroup run different trip counts here).
+__device__ __forceinline__ void dot_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Short-range values of one tensor at the cells (bs0 + m, bs1 + c1, bs2 + c2),
+// m = 0..7, of this lane (c1 = lane / 8, c2 = lane % 8): the windowed terms
+// z_nu sum_{k >= R_l} a_k g g g of the particles listed for brick `br` (the
+// same sum the grid's short gather adds).  Run by one wave; f: its LDS table
+// [3][Rs][8] of 1D factors, ak / tk2: LDS [Rs] weights and squared exponents.
 __device__ void dot_side_short(const DotSide& S, int br, int64_t n, double b, const int bs[3],
-                               int c1, int c2, double* f, double* ak, double* tk2,
+                               double* f, const double* ak, const double* tk2,
                                double (&out)[8]) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int c1 = lane >> 3, c2 = lane & 7;
   const int Rs = S.R - S.R_l;
 #pragma unroll
   for (int m = 0; m < 8; ++m) out[m] = 0.0;
   if (Rs <= 0) return;
-  __syncthreads();   // the previous side's factors are no longer read
-  for (int k = lane; k < Rs; k += 64) {
-    ak[k] = S.a[S.R_l + k];
-    tk2[k] = S.t[S.R_l + k] * S.t[S.R_l + k];
-  }
   const double h = 2.0 * b / (double)n;
   const int s0 = S.start[br], s1 = S.start[br + 1];
   for (int e0 = s0; e0 < s1; e0 += 64) {
@@ -57,7 +63,7 @@ __device__ void dot_side_short(const DotSide& S, int br, int64_t n, double b, co
         lo[l] = (int)(glo - bs[l]);
         hi[l] = (int)(ghi - bs[l]);
       }
-      __syncthreads();
+      dot_wave_sync();   // the previous particle's table has been read
       for (int idx = lane; idx < 24 * Rs; idx += 64) {
         const int l = idx / (8 * Rs);
         const int rem = idx - l * 8 * Rs;
@@ -65,7 +71,7 @@ __device__ void dot_side_short(const DotSide& S, int br, int64_t n, double b, co
         const double d = (-b + ((double)(bs[l] + m) + 0.5) * h) - p[l];
         f[idx] = exp(-tk2[k] * (d * d));
       }
-      __syncthreads();
+      dot_wave_sync();
       if (c1 >= lo[1] && c1 <= hi[1] && c2 >= lo[2] && c2 <= hi[2]) {
         double sm[8];
 #pragma unroll
@@ -81,61 +87,182 @@ __device__ void dot_side_short(const DotSide& S, int br, int64_t n, double b, co
       }
     }
   }
+  dot_wave_sync();   // the table is free for the next brick
 }
 
-// long-range Tucker values of one tensor at the lane's 8 cells:
-// sum_c T2[(i0 n + i1) r3 + c] V3[i2 r3 + c]
-__device__ void dot_side_long(const DotSide& S, int64_t n, int64_t i0b, int64_t i1, int64_t i2,
-                              double (&out)[8]) {
-  const double* v = S.V3 + i2 * S.r3;
-  const double* t[8];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int64_t i0 = i0b + m < n ? i0b + m : n - 1;
-    t[m] = S.T2 + (i0 * n + i1) * S.r3;
-    out[m] = 0.0;
-  }
-  for (int c = 0; c < S.r3; ++c) {
-    const double vc = v[c];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) out[m] += t[m][c] * vc;
-  }
-}
+// ---- the touched-cell correction, one workgroup per brick column ---------------
+// Workgroup (b0, b1) lists the bricks b2 of its column that a window of A or
+// of B touches (in increasing b2) and takes them in groups of DG.  For a
+// group, wave j forms the short-range values of A and B on brick j (LDS sv),
+// then the four waves contract the long parts on the matrix cores:
+//   L[rho][kappa] = sum_c T2[(i0 n + i1) r3 + c] V3[i2 r3 + c],
+// rho = 8 (i0 - 8 b0) + (i1 - 8 b1) (64 rows), kappa = 8 j + (i2 - 8 b2_j)
+// (32 columns), T2 and V3 chunks of DKC values staged through LDS (double
+// buffered); wave w holds rows 16w..16w+15 as two 16 x 16 blocks of
+// v_mfma_f64_16x16x4f64.  Each lane then adds L_A S_B + S_A L_B + S_A S_B
+// over its 8 cells.  partials[column] is the column's sum, formed in a fixed
+// order (the same tree on every call).
+constexpr int DG = 4;           // bricks per group
+constexpr int DKC = 16;         // k values per LDS chunk
+constexpr int DLA = DKC + 1;    // padded LDS row of a chunk (doubles)
 
-// One wave per brick of `active` (count in active[0]); bricks that `skip`
-// (a start array) lists as touched are left out (they were counted in the
-// other tensor's pass).  partials[ia] = the brick's sum of A B - A_l B_l.
-__global__ __launch_bounds__(64) void dot_bricks_kernel(DotSide A, DotSide B, const int* active,
-                                                        int64_t cap, const int* skip, int nb,
-                                                        int64_t n, double b, int rs_max,
-                                                        double* __restrict__ partials) {
-  extern __shared__ double dlds[];
-  double* f = dlds;                  // [3][rs_max][8]
-  double* ak = dlds + 24 * rs_max;   // [rs_max]
-  double* tk2 = ak + rs_max;         // [rs_max]
-  const int lane = threadIdx.x;
-  const int c1 = lane >> 3, c2 = lane & 7;
-  const int64_t count = active[0] < cap ? active[0] : cap;
-  for (int64_t ia = blockIdx.x; ia < count; ia += gridDim.x) {
-    const int br = active[1 + ia];
-    double sum = 0.0;
-    if (!skip || skip[br + 1] == skip[br]) {
-      const int b0 = br / (nb * nb), b1 = (br / nb) % nb, b2 = br % nb;
-      const int bs[3] = {b0 * 8, b1 * 8, b2 * 8};
-      const int64_t i1 = bs[1] + c1, i2 = bs[2] + c2;
-      const bool col_ok = i1 < n && i2 < n;
-      double la[8], lb[8], sa[8], sb[8];
-      dot_side_long(A, n, bs[0], col_ok ? i1 : 0, col_ok ? i2 : 0, la);
-      dot_side_long(B, n, bs[0], col_ok ? i1 : 0, col_ok ? i2 : 0, lb);
-      dot_side_short(A, br, n, b, bs, c1, c2, f, ak, tk2, sa);
-      dot_side_short(B, br, n, b, bs, c1, c2, f, ak, tk2, sb);
+__device__ __forceinline__ void dot_long(const DotSide& S, int64_t n, int bs0, int bs1,
+                                         const int* b2g, int gc, double* as, double* bsm,
+                                         d4 (&acc)[2]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K = S.r3;
+  acc[0] = d4{0.0, 0.0, 0.0, 0.0};
+  acc[1] = d4{0.0, 0.0, 0.0, 0.0};
+  // loader of thread tid: T2 row tid / 4 (4 values), V3 row tid / 8 (2 values)
+  const int ra = tid >> 2, ka = (tid & 3) * 4;
+  int64_t i0 = bs0 + (ra >> 3), i1 = bs1 + (ra & 7);
+  i0 = i0 < n ? i0 : n - 1;
+  i1 = i1 < n ? i1 : n - 1;
+  const double* pa = S.T2 + (i0 * n + i1) * K;
+  const int rb = tid >> 3, kb = (tid & 7) * 2;
+  const int jb = (rb >> 3) < gc ? (rb >> 3) : gc - 1;
+  int64_t i2 = 8 * (int64_t)b2g[jb] + (rb & 7);
+  i2 = i2 < n ? i2 : n - 1;
+  const double* pb = S.V3 + i2 * K;
+  double va[4], vb[2];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m)
-        if (col_ok && bs[0] + m < n) sum += la[m] * sb[m] + sa[m] * lb[m] + sa[m] * sb[m];
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + ka + e;
+      const double v = pa[k < K ? k : K - 1];
+      va[e] = k < K ? v : 0.0;
     }
-    sum = dot_wave_sum(sum);
-    if (lane == 0) partials[ia] = sum;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + kb + e;
+      const double v = pb[k < K ? k : K - 1];
+      vb[e] = k < K ? v : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+    double* a = as + buf * 64 * DLA + ra * DLA + ka;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = va[e];
+    double* bq = bsm + buf * 32 * DLA + rb * DLA + kb;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) bq[e] = vb[e];
+  };
+  const int nch = (K + DKC - 1) / DKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const bool more = ch + 1 < nch;
+    if (more) load((ch + 1) * DKC);
+    const double* a = as + buf * 64 * DLA + (16 * wave + (lane & 15)) * DLA;
+    const double* b0 = bsm + buf * 32 * DLA + (lane & 15) * DLA;
+    const double* b1 = b0 + 16 * DLA;
+#pragma unroll
+    for (int kk = 0; kk < DKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double fa = a[kr];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b0[kr], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b1[kr], acc[1], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
+}
+
+__global__ __launch_bounds__(256) void dot_cols_kernel(DotSide A, DotSide B, int nb, int64_t n,
+                                                       double b, int rs_max,
+                                                       double* __restrict__ partials) {
+  extern __shared__ double dlds[];
+  double* sv = dlds;                        // [2][DG][512] short values of A and B
+  double* as = sv + 2 * DG * 512;           // [2][64][DLA]
+  double* bsm = as + 2 * 64 * DLA;          // [2][32][DLA]
+  double* ftab = bsm + 2 * 32 * DLA;        // [4][24 rs_max]
+  double* akA = ftab + 4 * 24 * rs_max;     // [rs_max] x 4: akA, tkA, akB, tkB
+  double* tkA = akA + rs_max;
+  double* akB = tkA + rs_max;
+  double* tkB = akB + rs_max;
+  double* wsum = tkB + rs_max;              // [4]
+  int* wcnt = (int*)(wsum + 4);             // [4]
+  int* blist = wcnt + 4;                    // [nb]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = blockIdx.x;
+  const int b0 = col / nb, b1 = col - (col / nb) * nb;
+  const int64_t cbase = ((int64_t)b0 * nb + b1) * nb;
+  // the touched bricks of the column, in increasing b2
+  int total = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int b2 = base + tid;
+    bool touched = false;
+    if (b2 < nb) {
+      const int64_t br = cbase + b2;
+      touched = A.start[br + 1] > A.start[br] || B.start[br + 1] > B.start[br];
+    }
+    const unsigned long long m = __ballot(touched);
+    if (lane == 0) wcnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = total;
+    for (int w = 0; w < wave; ++w) off += wcnt[w];
+    if (touched) blist[off + __popcll(m & ((1ull << lane) - 1ull))] = b2;
+    total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (total == 0) {
+    if (tid == 0) partials[col] = 0.0;
+    return;
+  }
+  const int RsA = A.R - A.R_l, RsB = B.R - B.R_l;
+  for (int k = tid; k < RsA; k += 256) {
+    akA[k] = A.a[A.R_l + k];
+    tkA[k] = A.t[A.R_l + k] * A.t[A.R_l + k];
+  }
+  for (int k = tid; k < RsB; k += 256) {
+    akB[k] = B.a[B.R_l + k];
+    tkB[k] = B.t[B.R_l + k] * B.t[B.R_l + k];
+  }
+  __syncthreads();
+  const int bs0 = 8 * b0, bs1 = 8 * b1;
+  double* fw = ftab + wave * 24 * rs_max;
+  double wacc = 0.0;
+  for (int g0 = 0; g0 < total; g0 += DG) {
+    const int gc = total - g0 < DG ? total - g0 : DG;
+    const int* b2g = blist + g0;
+    if (wave < gc) {
+      const int br = (int)(cbase + b2g[wave]);
+      const int bs[3] = {bs0, bs1, 8 * b2g[wave]};
+      double o[8];
+      dot_side_short(A, br, n, b, bs, fw, akA, tkA, o);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) sv[wave * 512 + m * 64 + lane] = o[m];
+      dot_side_short(B, br, n, b, bs, fw, akB, tkB, o);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) sv[(DG + wave) * 512 + m * 64 + lane] = o[m];
+    }
+    d4 la[2], lb[2];
+    dot_long(A, n, bs0, bs1, b2g, gc, as, bsm, la);   // its first barrier publishes sv
+    dot_long(B, n, bs0, bs1, b2g, gc, as, bsm, lb);
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int kap = 16 * blk + (lane & 15);
+      const int j = kap >> 3, c2 = kap & 7;
+      const bool colok = j < gc && 8 * (int64_t)b2g[j < gc ? j : 0] + c2 < n;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rho = 16 * wave + (lane >> 4) + 4 * v;
+        const bool ok = colok && bs0 + (rho >> 3) < n && bs1 + (rho & 7) < n;
+        if (ok) {
+          const double sa = sv[j * 512 + rho * 8 + c2], sb = sv[(DG + j) * 512 + rho * 8 + c2];
+          wacc += la[blk][v] * sb + sa * lb[blk][v] + sa * sb;
+        }
+      }
+    }
+    __syncthreads();   // sv is rewritten by the next group
+  }
+  wacc = dot_wave_sum(wacc);
+  if (lane == 0) wsum[wave] = wacc;
+  __syncthreads();
+  if (tid == 0) partials[col] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
 // partial[blk] = sum over the fixed stride class of x[i] y[i]; one value per block
@@ -158,21 +285,15 @@ __global__ __launch_bounds__(DOT_THREADS) void dot_partial_kernel(const double* 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// out = sum of the DOT_BLOCKS long-long partials + the first active_a[0]
-// brick partials of pass A + the first active_b[0] of pass B (fixed order)
+// out = sum of the DOT_BLOCKS long-long partials + the ncols column partials
+// of the correction (fixed order)
 __global__ __launch_bounds__(1024) void dot_final_kernel(const double* __restrict__ ll,
-                                                         const double* __restrict__ pa,
-                                                         const int* active_a, int64_t cap_a,
-                                                         const double* __restrict__ pb,
-                                                         const int* active_b, int64_t cap_b,
-                                                         double* __restrict__ out) {
+                                                         const double* __restrict__ pc,
+                                                         int64_t ncols, double* __restrict__ out) {
   __shared__ double red[1024];
-  const int64_t na = active_a[0] < cap_a ? active_a[0] : cap_a;
-  const int64_t nbk = active_b[0] < cap_b ? active_b[0] : cap_b;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < DOT_BLOCKS; i += 1024) s += ll[i];
-  for (int64_t i = threadIdx.x; i < na; i += 1024) s += pa[i];
-  for (int64_t i = threadIdx.x; i < nbk; i += 1024) s += pb[i];
+  for (int64_t i = threadIdx.x; i < ncols; i += 1024) s += pc[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 512; off > 0; off >>= 1) {
@@ -190,22 +311,26 @@ void launch_dot_partial(const double* x, const double* y, int64_t count, double*
                      partial);
 }
 
-void launch_dot_bricks(const DotSide& A, const DotSide& B, const int* active, int64_t cap,
-                       const int* skip, int nb, int64_t n, double b, int num_cu, double* partials,
-                       hipStream_t s) {
+void launch_dot_cols(const DotSide& A, const DotSide& B, int nb, int64_t n, double b,
+                     double* partials, hipStream_t s) {
   const int rs_max = std::max(std::max(A.R - A.R_l, B.R - B.R_l), 1);
   if (rs_max > 64) throw Error{RS_E_UNSUPPORTED, "more than 64 short-range terms"};
-  const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(cap, (int64_t)num_cu * 16));
-  const size_t lds = (size_t)26 * rs_max * sizeof(double);
-  hipLaunchKernelGGL(dot_bricks_kernel, dim3((unsigned)wgs), dim3(64), lds, s, A, B, active, cap,
-                     skip, nb, n, b, rs_max, partials);
+  if (A.r3 < 1 || B.r3 < 1) throw Error{RS_E_INVALID, "scalar product: empty Tucker rank"};
+  const size_t lds = sizeof(double) * ((size_t)2 * DG * 512 + 2 * 64 * DLA + 2 * 32 * DLA +
+                                       (size_t)4 * 24 * rs_max + 4 * (size_t)rs_max + 4) +
+                     sizeof(int) * (4 + (size_t)nb);
+  if (lds > 160 * 1024) throw Error{RS_E_UNSUPPORTED, "scalar product: grid too large for one column"};
+  if (lds > 64 * 1024)
+    RS_HIP(hipFuncSetAttribute((const void*)dot_cols_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int64_t ncols = (int64_t)nb * nb;
+  hipLaunchKernelGGL(dot_cols_kernel, dim3((unsigned)ncols), dim3(256), lds, s, A, B, nb, n, b,
+                     rs_max, partials);
 }
 
-void launch_dot_final(const double* ll, const double* pa, const int* active_a, int64_t cap_a,
-                      const double* pb, const int* active_b, int64_t cap_b, double* out,
+void launch_dot_final(const double* ll, const double* pc, int64_t ncols, double* out,
                       hipStream_t s) {
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(1024), 0, s, ll, pa, active_a, cap_a, pb,
-                     active_b, cap_b, out);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(1024), 0, s, ll, pc, ncols, out);
 }
 
 }  // namespace rs

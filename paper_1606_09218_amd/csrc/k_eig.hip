@@ -696,9 +696,11 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(double* __restrict__ Ya
 
 // Blocked Cholesky for 128 < p <= 512: one workgroup of 1024 threads per
 // mode, the matrix in global memory (it stays in L2), worked on in panels of
-// CB = 16 rows of R.  A panel (rows K0..K0+15, columns K0..p-1) is factored
-// in LDS by the right-looking steps restricted to its rows, written back as
-// rows of R, and the trailing upper triangle then takes one rank-16 update
+// CB = 16 rows of R.  A panel (rows K0..K0+15, columns K0..p-1) is loaded to
+// LDS; one wave factors its 16 x 16 diagonal block, M11 = R11^T R11; every
+// thread then solves R11^T R12[:, i] = M12[:, i] for its columns i (forward
+// substitution, R11 read as broadcasts); the panel is written back as rows
+// of R, and the trailing upper triangle then takes one rank-16 update
 //   M[j][i] -= sum_k R[k][j] R[k][i],  K0 + 16 <= j <= i < p,
 // so that every trailing entry is read and written once per panel instead
 // of once per column.  The shift of a shifted pass is added to each diagonal
@@ -742,24 +744,47 @@ __global__ __launch_bounds__(CHB_THREADS) void chol_blk_kernel(double* __restric
       pan[r * ldp + c] = v;
     }
     __syncthreads();
-    for (int k = 0; k < nb; ++k) {
-      double d = pan[k * ldp + k];
-      if (!(d > 0.0)) {
-        if (tid == 0) atomicOr(fail, fail_bit);
-        d = 1e-300;
+    // the diagonal block by wave 0: lane entries (r, c) = (e / 16, e % 16), e = lane + 64 t
+    if (wave == 0) {
+      for (int k = 0; k < nb; ++k) {
+        double d = pan[k * ldp + k];
+        if (!(d > 0.0)) {
+          if (lane == 0) atomicOr(fail, fail_bit);
+          d = 1e-300;
+        }
+        const double invd = 1.0 / d;
+#pragma unroll
+        for (int t = 0; t < CB * CB / 64; ++t) {
+          const int e = lane + 64 * t, j = e / CB, i = e - (e / CB) * CB;
+          if (j > k && i >= j && i < nb) pan[j * ldp + i] -= pan[k * ldp + i] * (pan[k * ldp + j] * invd);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double sq = sqrt(d), isq = 1.0 / sq;
+        if (lane > k && lane < nb) pan[k * ldp + lane] *= isq;
+        if (lane == 0) pan[k * ldp + k] = sq;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      const double invd = 1.0 / d;
-      const int rows = nb - k - 1;
-      for (int e = tid; e < rows * w; e += CHB_THREADS) {
-        const int j = k + 1 + e / w, i = e - (e / w) * w;
-        if (i >= j) pan[j * ldp + i] -= pan[k * ldp + i] * (pan[k * ldp + j] * invd);
-      }
-      __syncthreads();
-      const double sq = sqrt(d), isq = 1.0 / sq;
-      for (int i = k + 1 + tid; i < w; i += CHB_THREADS) pan[k * ldp + i] *= isq;
-      if (tid == 0) pan[k * ldp + k] = sq;
-      __syncthreads();
     }
+    __syncthreads();
+    // the rest of the panel's rows: R12 = R11^{-T} M12, one column per thread
+    for (int i = nb + tid; i < w; i += CHB_THREADS) {
+      double x[CB];
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        if (k < nb) {
+          double v = pan[k * ldp + i];
+#pragma unroll
+          for (int l = 0; l < k; ++l) v -= pan[l * ldp + k] * x[l];
+          x[k] = v / pan[k * ldp + k];
+          pan[k * ldp + i] = x[k];
+        }
+      }
+    }
+    __syncthreads();
     for (int e = tid; e < nb * w; e += CHB_THREADS) {
       const int r = e / w, c = e - r * w;
       if (c >= r) C[(int64_t)(K0 + r) * p + K0 + c] = pan[r * ldp + c];

@@ -169,23 +169,59 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const double* __restr
   }
 }
 
-// FP32 transposed copies for the Khatri-Rao operand:
-// s2[b][j] = 2^s xi_j U~2[j, b], u3[c][j] = U~3[j, c]  (zero for j >= K), with
-// the operand's power-of-two scale 2^s (exps[1]) when exps is given
-__global__ void kr_factors_kernel(const double* __restrict__ U2t, const double* __restrict__ U3t,
-                                  const double* __restrict__ xi, int r2, int r3, int64_t K,
-                                  int64_t kp, const int* exps, float* __restrict__ s2,
-                                  float* __restrict__ u3) {
-  const double scale = exps ? pow2(exps[1]) : 1.0;
-  const int64_t total = (int64_t)(r2 + r3) * kp;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = e / kp, j = e - row * kp;
-    if (row < r2) {
-      s2[row * kp + j] = j < K ? (float)(xi[j] * U2t[j * r2 + row] * scale) : 0.0f;
+// The core's operands from the projected factors in one pass: U~_l^T is
+// K x r_l (row j holds the r_l values of term j), the core wants rows of K
+// values per rank index.  A workgroup transposes a 64 j x 64 rank tile
+// through LDS (reads and writes both along contiguous rows) and writes
+//   op 0: the split planes of U~1^T, planes[term][a][j], scaled by 2^exps[0],
+//   op 1: s2[b][j] = 2^exps[1] xi_j U~2[j, b] (FP32),
+//   op 2: u3[c][j] = U~3[j, c] (FP32),
+// zero for K <= j < kp.  The Khatri-Rao operand s2[b][j] u3[c][j] itself is
+// formed on chip by the core kernel.
+template <class SP>
+__global__ __launch_bounds__(256) void core_operands_kernel(
+    const double* __restrict__ U1t, const double* __restrict__ U2t, const double* __restrict__ U3t,
+    const double* __restrict__ xi, int r1, int r2, int r3, int64_t K, int64_t kp, const int* exps,
+    typename SP::T* __restrict__ planes, float* __restrict__ s2, float* __restrict__ u3) {
+  __shared__ double tile[64][65];
+  const int op = blockIdx.z;
+  const int r = op == 0 ? r1 : (op == 1 ? r2 : r3);
+  const double* src = op == 0 ? U1t : (op == 1 ? U2t : U3t);
+  const int c0 = blockIdx.y * 64;
+  if (c0 >= r) return;   // uniform over the workgroup
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int jl = ty + 4 * i;
+    const int64_t j = j0 + jl;
+    const int c = c0 + tx;
+    double v = 0.0;
+    if (j < K && c < r) {
+      v = src[j * r + c];
+      if (op == 1) v = xi[j] * v;
+    }
+    tile[jl][tx] = v;
+  }
+  __syncthreads();
+  const double scale = SP::SCALED && exps && op < 2 ? pow2(exps[op]) : 1.0;
+  const int64_t plane = (int64_t)r1 * kp;
+  const int64_t j = j0 + tx;
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int cl = ty + 4 * i;
+    const int c = c0 + cl;
+    if (c >= r || j >= kp) continue;
+    const double x = tile[tx][cl];
+    if (op == 0) {
+      typename SP::T t[SP::TERMS];
+      SP::split(x * scale, t);
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term) planes[term * plane + c * kp + j] = t[term];
+    } else if (op == 1) {
+      s2[c * kp + j] = (float)(x * scale);
     } else {
-      const int64_t c = row - r2;
-      u3[c * kp + j] = j < K ? (float)U3t[j * r3 + c] : 0.0f;
+      u3[c * kp + j] = (float)x;
     }
   }
 }
@@ -712,10 +748,11 @@ static void core_mixed_t(int fp16, const double* U1t, const double* U2t, const d
   const double* Bops[3] = {xi, U2t, U3t};
   const int64_t nb[3] = {K, K * r2, K * r3};
   scale_setup(U1t, K * r1, Bops, nb, 3, fp16, mx, exps, s);
-  // A = U~1^T: row a, column j at U1t[j r1 + a]
-  split_planes<SP>(U1t, r1, K, 1, r1, P.kp, exps, 0, planes, s);
-  hipLaunchKernelGGL(kr_factors_kernel, dim3(grid_blocks((int64_t)(r2 + r3) * P.kp)), dim3(256), 0,
-                     s, U2t, U3t, xi, r2, r3, K, P.kp, SP::SCALED ? exps : nullptr, s2, u3);
+  // A = U~1^T: row a, column j at U1t[j r1 + a]; the Khatri-Rao factors s2, u3
+  const int rmax = std::max(r1, std::max(r2, r3));
+  hipLaunchKernelGGL(core_operands_kernel<SP>,
+                     dim3((unsigned)((P.kp + 63) / 64), (unsigned)((rmax + 63) / 64), 3), dim3(256),
+                     0, s, U1t, U2t, U3t, xi, r1, r2, r3, K, P.kp, exps, planes, s2, u3);
   const dim3 grid((unsigned)(P.row_tiles * P.col_tiles), 1, (unsigned)P.splits);
   double* out = part ? part : beta;
   const int64_t stride = (int64_t)r1 * r2 * r3;

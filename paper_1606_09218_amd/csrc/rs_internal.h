@@ -182,11 +182,10 @@ struct DotSide {
 size_t dot_partials_bytes();
 void launch_dot_partial(const double* x, const double* y, int64_t count, double* partial,
                         hipStream_t s);
-void launch_dot_bricks(const DotSide& A, const DotSide& B, const int* active, int64_t cap,
-                       const int* skip, int nb, int64_t n, double b, int num_cu, double* partials,
-                       hipStream_t s);
-void launch_dot_final(const double* ll, const double* pa, const int* active_a, int64_t cap_a,
-                      const double* pb, const int* active_b, int64_t cap_b, double* out,
+// correction over the touched cells, one partial per brick column (nb^2 of them)
+void launch_dot_cols(const DotSide& A, const DotSide& B, int nb, int64_t n, double b,
+                     double* partials, hipStream_t s);
+void launch_dot_final(const double* ll, const double* pc, int64_t ncols, double* out,
                       hipStream_t s);
 
 // Toeplitz factors of the RS RBF matrix: T (R x n x n) and Acat (n x R n)

@@ -298,8 +298,10 @@ static size_t gram_workspace_bytes(const Plan& P, int method, int ncu) {
 static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P,
                                  const double* pos, const double* q, double* U, double* xi,
                                  double* w, double* sw, double* G, int method, hipStream_t s,
-                                 rs_tensor* T = nullptr, double* work = nullptr) {
-  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s);
+                                 rs_tensor* T = nullptr, double* work = nullptr,
+                                 void* planes16 = nullptr, int64_t kp = 0) {
+  launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s,
+                       planes16, kp);
   if (T) mark(T, RS_STAGE_GRAM, s);
   DevBuf own;
   if (!work) {
@@ -383,7 +385,8 @@ static ExpansionScratch expansion_scratch(const rs_tensor* T, bool with_grid) {
   Carve c;
   e.w1 = c.add((size_t)T->n * T->r[1] * T->r[2] * sizeof(double));
   e.wk1 = c.add(gemm64_workspace_bytes(expand1_gemm(T, nullptr), ncu));
-  e.wk2 = c.add(gemm64_workspace_bytes(expand2_gemm(T, nullptr), ncu));
+  e.wk2 = c.add(T->prec == RS_FP64 ? gemm64_workspace_bytes(expand2_gemm(T, nullptr), ncu)
+                                    : expand2_mixed_workspace_bytes(T->n, T->r[1], T->r[2]));
   e.wkg = c.add(!with_grid ? 0
                 : T->prec == RS_FP64 ? gemm64_workspace_bytes(grid_gemm(T, nullptr), ncu)
                                      : grid_mixed_workspace_bytes(T->n, T->r[2]));
@@ -403,7 +406,11 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
   mark(T, RS_STAGE_EXPAND1, s);
   gemm64(expand1_gemm(T, X), ncu, (double*)(scratch + e.wk1), s);
   mark(T, RS_STAGE_EXPAND2, s);
-  gemm64(expand2_gemm(T, X), ncu, (double*)(scratch + e.wk2), s);
+  if (T->prec == RS_FP64)
+    gemm64(expand2_gemm(T, X), ncu, (double*)(scratch + e.wk2), s);
+  else
+    expand2_mixed(contraction_prec(T->prec), X, T->Q[1].as<double>(), n, T->r[1], r3,
+                  T->T2.as<double>(), scratch + e.wk2, s);
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
     grid_mixed(contraction_prec(T->prec), T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
@@ -754,7 +761,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     const size_t scan_bytes = exclusive_scan_bytes(nbricks + 1);
     Carve pre;
     const size_t o_rb = pre.add(sizeof(Readback));
-    const size_t o_U = pre.add((size_t)3 * n * K * d8), o_xi = pre.add((size_t)K * d8);
+    // The split-FP16 projection reads FP16 planes of U written with the side
+    // matrices; U itself (FP64) is kept only where something else reads it
+    // (FP64 or BF16 contractions, the GEMM Gram, the side-matrix sketch, ALS).
+    const bool fused16 = contraction_prec(P.prec) == RS_MIXED_FP16;
+    const bool need_u64 = !fused16 || P.gram == RS_GRAM_GEMM || P.sketch != 0 || P.als > 0;
+    const int64_t kpn = (n + 31) / 32 * 32;
+    const size_t o_U = pre.add(need_u64 ? (size_t)3 * n * K * d8 : 0), o_xi = pre.add((size_t)K * d8);
+    const size_t o_P16 = pre.add(fused16 ? (size_t)3 * 2 * K * kpn * 2 : 0);
     const size_t o_w = pre.add((size_t)K * d8), o_sw = pre.add((size_t)K * d8);
     // the three n x n Gram matrices: by the Gaussian-product identity
     // (O(n K + n^2 R_l)) or by the MFMA GEMM U diag(w) U^T (2 n^2 K FLOP)
@@ -788,12 +802,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
 
     // (a2, a3) side matrices and charge-weighted Gram matrices
     mark(T.get(), RS_STAGE_FACTORS, s);
-    Span U = piece(o_U, (size_t)3 * n * K * d8), xi = piece(o_xi, (size_t)K * d8);
+    Span U = need_u64 ? piece(o_U, (size_t)3 * n * K * d8) : Span{};
+    Span xi = piece(o_xi, (size_t)K * d8);
+    Span P16 = fused16 ? piece(o_P16, (size_t)3 * 2 * K * kpn * 2) : Span{};
     Span w = piece(o_w, (size_t)K * d8), sw = piece(o_sw, (size_t)K * d8);
     Span G = piece(o_G, (size_t)3 * n * n * d8);
     run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
                          sw.as<double>(), G.as<double>(), P.gram, s, T.get(),
-                         (double*)(pre_buf.as<char>() + o_wgram));
+                         (double*)(pre_buf.as<char>() + o_wgram), P16.p, kpn);
 
     // short-range binning (counts and offsets; the total is read back with the ranks)
     Span counts = piece(o_counts, (size_t)(nbricks + 1) * sizeof(int));
@@ -1018,7 +1034,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       g.C = T->Q[l].as<double>(); g.scm = r; g.scn = 1;
       Gemm64& h = gp[l];  // U~_l^T = U_l^T V_l (K x r row-major, i.e. U~[j*r + a]): the
       h.M = K; h.N = r; h.K = n;   // long dimension K is the GEMM's row dimension
-      h.A = U.as<double>() + (int64_t)l * n * K; h.sam = n; h.sak = 1;
+      h.A = need_u64 ? U.as<double>() + (int64_t)l * n * K : nullptr; h.sam = n; h.sak = 1;
       h.B = T->Q[l].as<double>(); h.sbk = r; h.sbn = 1;
       h.scm = r; h.scn = 1;
     }
@@ -1028,14 +1044,25 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
       o_wr[l] = cv.add((size_t)p * T->r[l] * sizeof(double));
       o_wkb[l] = cv.add(gemm64_workspace_bytes(gb[l], ncu));
       o_ut[l] = cv.add((size_t)K * T->r[l] * sizeof(double));
-      o_wkp[l] = cv.add(gemm64_workspace_bytes(gp[l], ncu));
+      o_wkp[l] = P.prec == RS_FP64 ? cv.add(gemm64_workspace_bytes(gp[l], ncu)) : 0;
     }
     const size_t o_core = cv.add(P.prec == RS_FP64 ? core64_workspace_bytes(r1, r2, r3, K, ncu)
                                                    : core_mixed_workspace_bytes(r1, r2, r3, K, ncu));
+    const size_t o_pmix =
+        P.prec == RS_FP64 ? 0 : cv.add(proj_mixed_workspace_bytes(n, K, std::max(r1, std::max(r2, r3)), fused16));
     const size_t o_exp = cv.add(expansion_scratch(T.get(), grid_out != nullptr).total);
     DevBuf arena(cv.total, s);
     char* ab = arena.as<char>();
     auto at = [&](size_t off) { return (double*)(ab + off); };
+    // U~_l^T = U_l^T V_l: FP64 GEMM, or split precision like the core
+    auto project = [&](int l) {
+      if (P.prec == RS_FP64)
+        gemm64(gp[l], ncu, at(o_wkp[l]), s);
+      else
+        proj_mixed(contraction_prec(P.prec), need_u64 ? U.as<double>() + (int64_t)l * n * K : nullptr,
+                   fused16 ? P16.as<char>() + (size_t)l * 2 * K * kpn * 2 : nullptr, n, K,
+                   T->Q[l].as<double>(), T->r[l], gp[l].C, at(o_pmix), s);
+    };
 
     // final bases V_l = Q0 W[:, perm[:r]] (n x r row-major), canonical signs
     mark(T.get(), RS_STAGE_BASIS, s);
@@ -1055,7 +1082,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     mark(T.get(), RS_STAGE_PROJECT, s);
     for (int l = 0; l < 3; ++l) {
       gp[l].C = at(o_ut[l]);
-      gemm64(gp[l], ncu, at(o_wkp[l]), s);
+      project(l);
     }
     // ALS refinement (Appendix, steps (III)-(IV)): for each mode in turn the
     // partially projected image M_l = U_l diag(xi) (U~_m (.) U~_p)^T (the
@@ -1090,7 +1117,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
           DevBuf wg(gemm64_workspace_bytes(gg, ncu), s);
           gemm64(gg, ncu, wg.as<double>(), s);
           dominant_eigvecs(ctx, Gm.as<double>(), n, T->r[l], T->Q[l].as<double>(), dfail.as<int>(), s);
-          gemm64(gp[l], ncu, at(o_wkp[l]), s);
+          project(l);
         }
       }
       int hf = 0;
@@ -1483,7 +1510,8 @@ size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
   Gemm64 zz;
   zz.M = r; zz.N = r; zz.K = p; zz.batch = 3; zz.upper_only = 1;
   size_t inputs = (size_t)N * 4 * d + 2 * (size_t)t.R * d;
-  size_t factors = (size_t)(3 * n * K + 3 * K) * d;
+  size_t factors = (size_t)(3 * n * K + 3 * K) * d +
+                   (prec == RS_FP64 || prec == RS_MIXED_BF16 ? 0 : (size_t)12 * ((n + 31) / 32 * 32) * K);
   size_t gram_b = (size_t)3 * n * n * d + gemm64_workspace_bytes(gram, ncu);
   // the pieces of the pre-readback arena: subspace, eigenproblem, eigenvectors
   size_t eig = (size_t)(3 * n * p * 2 + 3 * p * p * 2) * d +
@@ -1494,7 +1522,8 @@ size_t rs_footprint_bytes(const rs_grid* grid, const rs_fdesc* fdesc, int64_t N,
   size_t result = (size_t)(3 * n * r + r * r * r + n * n * r) * d;
   size_t arena = (size_t)(3 * p * r + 3 * K * r + n * r * r) * d +
                  (prec == RS_FP64 ? core64_workspace_bytes((int)r, (int)r, (int)r, K, ncu)
-                                  : core_mixed_workspace_bytes((int)r, (int)r, (int)r, K, ncu)) +
+                                  : core_mixed_workspace_bytes((int)r, (int)r, (int)r, K, ncu) +
+                                        proj_mixed_workspace_bytes(n, K, (int)r, false)) +
                  (size_t)8 * n * n * d;  // split-K partials of the projections and expansions (bound)
   size_t bins = ((n / 8 + 1) * (n / 8 + 1) * (n / 8 + 1) * 3 + 64 * N + 1) * sizeof(int);
   return inputs + factors + gram_b + eig + result + arena + bins;

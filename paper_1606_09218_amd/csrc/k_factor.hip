@@ -37,26 +37,64 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
                      flags);
 }
 
-// One thread per (i, j): consecutive threads walk down a column (i fastest),
-// so the stores are fully coalesced.  grid.y = mode.
+// U (FP64, column j = k N + nu contiguous) and/or the FP16 split planes of
+// the projection, planes[l][term][j][i] with i padded to kp (a multiple of
+// 32) by zeros.  Every entry is at most 1, so the planes hold
+// x 2^14 = hi + lo (hi = x 2^14 rounded to FP16, lo = the rest rounded to
+// FP16) under the fixed scale 2^14.  grid.y = mode.
+typedef _Float16 sm_h8 __attribute__((ext_vector_type(8)));
+
 __global__ void side_matrix_kernel(const double* __restrict__ pos, const double* __restrict__ t,
-                                   int64_t N, int R_l, int64_t n, double b, double* __restrict__ U) {
-  // one column j = k N + nu per workgroup step (its index arithmetic done
-  // once), the threads over the n grid points of the column (coalesced)
+                                   int64_t N, int R_l, int64_t n, double b, double* __restrict__ U,
+                                   _Float16* __restrict__ planes, int64_t kp) {
   const int l = blockIdx.y;
   const int64_t K = N * R_l;
   const double h = 2.0 * b / (double)n;
-  double* Ul = U + (int64_t)l * n * K;
-  for (int64_t j = blockIdx.x; j < K; j += gridDim.x) {
-    const int64_t k = j / N;
-    const int64_t nu = j - k * N;
-    const double x = pos[3 * nu + l];
+  double* Ul = U ? U + (int64_t)l * n * K : nullptr;
+  if (!planes) {
+    // one column per workgroup step, the threads over its n grid points
+    // (consecutive threads, consecutive addresses)
+    for (int64_t j = blockIdx.x; j < K; j += gridDim.x) {
+      const int64_t k = j / N;
+      const int64_t nu = j - k * N;
+      const double x = pos[3 * nu + l];
+      const double tk = t[k];
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = (-b + ((double)i + 0.5) * h) - x;
+        Ul[j * n + i] = exp(-(tk * tk) * (d * d));
+      }
+    }
+    return;
+  }
+  // eight consecutive grid points per thread (one 16-byte store per plane),
+  // cpb columns per workgroup step when a column needs at most 256 threads
+  _Float16* P0 = planes + (int64_t)l * 2 * K * kp;
+  const int kq = (int)(kp / 8);
+  const int cpb = kq <= (int)blockDim.x ? (int)blockDim.x / kq : 1;
+  const int cs = kq <= (int)blockDim.x ? (int)threadIdx.x / kq : 0;
+  const int i8s = kq <= (int)blockDim.x ? (int)threadIdx.x - cs * kq : (int)threadIdx.x;
+  const int istep = kq <= (int)blockDim.x ? kq : (int)blockDim.x;
+  if (cs >= cpb) return;
+  for (int64_t j = (int64_t)blockIdx.x * cpb + cs; j < K; j += (int64_t)gridDim.x * cpb) {
+    const int k = (int)j / (int)N;   // K < 2^31 (checked by the launcher)
+    const int nu = (int)j - k * (int)N;
+    const double x = pos[3 * (int64_t)nu + l];
     const double tk = t[k];
-    double* col = Ul + j * n;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const double xi = -b + ((double)i + 0.5) * h;
-      const double d = xi - x;
-      col[i] = exp(-(tk * tk) * (d * d));
+    for (int i8 = i8s; i8 < kq; i8 += istep) {
+      const int64_t i0 = 8 * (int64_t)i8;
+      sm_h8 hi, lo;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u;
+        const double d = (-b + ((double)i + 0.5) * h) - x;
+        const double v = i < n ? exp(-(tk * tk) * (d * d)) : 0.0;
+        if (Ul && i < n) Ul[j * n + i] = v;
+        const double y = v * 16384.0;
+        hi[u] = (_Float16)y;
+        lo[u] = (_Float16)(y - (double)hi[u]);
+      }
+      *(sm_h8*)(P0 + j * kp + i0) = hi;
+      *(sm_h8*)(P0 + (K + j) * kp + i0) = lo;
     }
   }
 }
@@ -76,13 +114,17 @@ __global__ void weights_kernel(const double* __restrict__ q, const double* __res
 
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
-                          double* w, double* sw, hipStream_t s) {
+                          double* w, double* sw, hipStream_t s, void* planes16, int64_t kp) {
   const int64_t K = N * R_l;
-  const int threads = n >= 256 ? 256 : 64;
-  const int64_t blocks = std::min<int64_t>(K, 65535LL * 16);
+  const int threads = planes16 ? 256 : (n >= 256 ? 256 : 64);
+  const int64_t cpb = planes16 && kp / 8 <= 256 ? 256 / (kp / 8) : 1;
+  const int64_t blocks = planes16 ? std::min<int64_t>((K + cpb - 1) / cpb, 65535LL * 16)
+                                  : std::min<int64_t>(K, 65535LL * 16);
   if (blocks <= 0 || n <= 0) return;
+  if (planes16 && (kp % 32 != 0 || kp < n)) throw Error{RS_E_INVALID, "side-matrix planes: bad padding"};
+  if (planes16 && K >= (1LL << 31)) throw Error{RS_E_UNSUPPORTED, "side matrices: more than 2^31 terms"};
   hipLaunchKernelGGL(side_matrix_kernel, dim3((unsigned)blocks, 3), dim3(threads), 0, s, pos, t,
-                     N, R_l, n, b, U);
+                     N, R_l, n, b, U, (_Float16*)planes16, kp);
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, q, a, N,
                      R_l, xi, w, sw);
 }

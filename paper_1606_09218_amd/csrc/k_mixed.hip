@@ -226,6 +226,40 @@ __global__ __launch_bounds__(256) void core_operands_kernel(
   }
 }
 
+// out[term][c][j] = term of src[j * cols + c] 2^exps[which] (zero for
+// rows <= j < kp): the split planes of a row-major matrix's transpose, a
+// 64 x 64 tile per workgroup through LDS (coalesced reads and writes).
+template <class SP>
+__global__ __launch_bounds__(256) void transpose_split_kernel(const double* __restrict__ src,
+                                                              int64_t rows, int64_t cols,
+                                                              int64_t kp, const int* exps,
+                                                              int which,
+                                                              typename SP::T* __restrict__ out) {
+  __shared__ double tile[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int jl = ty + 4 * i;
+    const int64_t j = j0 + jl, c = c0 + tx;
+    tile[jl][tx] = j < rows && c < cols ? src[j * cols + c] : 0.0;
+  }
+  __syncthreads();
+  const double scale = SP::SCALED && exps ? pow2(exps[which]) : 1.0;
+  const int64_t plane = cols * kp;
+  const int64_t j = j0 + tx;
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int cl = ty + 4 * i;
+    const int64_t c = c0 + cl;
+    if (c >= cols || j >= kp) continue;
+    typename SP::T t[SP::TERMS];
+    SP::split(tile[tx][cl] * scale, t);
+#pragma unroll
+    for (int term = 0; term < SP::TERMS; ++term) out[term * plane + c * kp + j] = t[term];
+  }
+}
+
 // ---- grid, streaming form -------------------------------------------------------
 // Persistent workgroups of 8 waves.  Workgroup (panel, group) keeps the B
 // planes of a panel of BN columns in LDS and walks the row tiles (128 rows:
@@ -605,6 +639,156 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
     }
 }
 
+// ---- split GEMM, LDS-tiled: C[m, c] = sum_i A[m, i] B[c, i] ----------------------
+// Both operands come as split planes [term][row][kp] (the projection: A the
+// side matrix, one row per canonical term, i over the grid, B the basis
+// transposed; the second expansion: A the basis V2, B the first expansion
+// with the rank index b contiguous).  The same tiling, LDS layout,
+// two-register-set pipeline and FP64 folds as the core kernel below, with B
+// loaded like A instead of formed.  Output FP64 at
+// (c / ccb) sccb + (c % ccb) + m ldc.  Workgroup order: column tile fastest
+// (the workgroups that share a row tile of A run together) or, with
+// row_fast, row tile fastest (they share a column tile of B).
+template <class SP, int WGM, int FN>
+__global__ __launch_bounds__(128 * WGM) void proj_tile_kernel(
+    const typename SP::T* __restrict__ Ap, const typename SP::T* __restrict__ Bp, int64_t M,
+    int64_t N, int64_t kp, int64_t col_tiles, int64_t row_tiles, int row_fast,
+    double* __restrict__ out, int64_t ldc, int64_t ccb, int64_t sccb, const int* exps) {
+  typedef typename SP::T T;
+  typedef typename SP::V8 V8;
+  constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 32;
+  constexpr int A_ITEMS = BM * 4 * SP::TERMS, A_PER = (A_ITEMS + NT - 1) / NT;
+  constexpr int B_ITEMS = BN * 4 * SP::TERMS, B_PER = (B_ITEMS + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) T As[2][SP::TERMS][BM][LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][SP::TERMS][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t x = blockIdx.x;
+  const int64_t ct = row_fast ? x / row_tiles : x % col_tiles;
+  const int64_t m0 = (row_fast ? x % row_tiles : x / col_tiles) * BM;
+  const int64_t c0 = ct * BN;
+  const int64_t planeA = M * kp, planeB = N * kp;
+  int64_t a_src[A_PER];
+  int a_dst[A_PER];
+#pragma unroll
+  for (int u = 0; u < A_PER; ++u) {
+    const int idx = tid + NT * u < A_ITEMS ? tid + NT * u : 0;
+    const int term = idx / (BM * 4), rem = idx - term * (BM * 4);
+    const int row = lds_row(rem >> 2), q = rem & 3;
+    const int64_t grow = m0 + row < M ? m0 + row : M - 1;
+    a_src[u] = term * planeA + grow * kp + 8 * q;
+    a_dst[u] = (term * BM + row) * LDK + 8 * (q ^ lds_sw(row));
+  }
+  int64_t b_src[B_PER];
+  int b_dst[B_PER];
+#pragma unroll
+  for (int u = 0; u < B_PER; ++u) {
+    const int idx = tid + NT * u < B_ITEMS ? tid + NT * u : 0;
+    const int term = idx / (BN * 4), rem = idx - term * (BN * 4);
+    const int row = lds_row(rem >> 2), q = rem & 3;
+    const int64_t gcol = c0 + row < N ? c0 + row : N - 1;
+    b_src[u] = term * planeB + gcol * kp + 8 * q;
+    b_dst[u] = (term * BN + row) * LDK + 8 * (q ^ lds_sw(row));
+  }
+  struct Regs {
+    V8 ra[A_PER], rb[B_PER];
+  };
+  Regs R0, R1;
+  const int64_t klast = kp - 32;
+  auto load = [&](int64_t k0, Regs& R) {
+    k0 = k0 < klast ? k0 : klast;
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) R.ra[u] = *(const V8*)(Ap + a_src[u] + k0);
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) R.rb[u] = *(const V8*)(Bp + b_src[u] + k0);
+  };
+  auto store = [&](const Regs& R, int buf) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u)
+      if (A_ITEMS % NT == 0 || tid + NT * u < A_ITEMS)
+        *(V8*)(&As[buf][0][0][0] + a_dst[u]) = R.ra[u];
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u)
+      if (B_ITEMS % NT == 0 || tid + NT * u < B_ITEMS)
+        *(V8*)(&Bs[buf][0][0][0] + b_dst[u]) = R.rb[u];
+  };
+  f4 acc[2][FN][SP::LEVELS];
+  double acc64[2][FN][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+#pragma unroll
+      for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    }
+  const int nsteps = (int)(kp / 32);
+  load(0, R0);
+  load(32, R1);
+  store(R0, 0);
+  load(64, R0);
+  __syncthreads();
+  const int frow = lane & 15, fc = lane >> 4;
+  auto step = [&](int st, Regs& R) {
+    const int cur = st & 1;
+    V8 af[2][SP::TERMS], bf[FN][SP::TERMS];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 32 + i * 16 + frow;
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term)
+        af[i][term] = *(const V8*)(&As[cur][term][r][8 * (fc ^ lds_sw(r))]);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int r = wn * (16 * FN) + j * 16 + frow;
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term)
+        bf[j][term] = *(const V8*)(&Bs[cur][term][r][8 * (fc ^ lds_sw(r))]);
+    }
+#pragma unroll
+    for (int pi = 0; pi < SP::NPROD; ++pi)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j][SP::PL[pi]] =
+              SP::mfma(af[i][SP::PA[pi]], bf[j][SP::PB[pi]], acc[i][j][SP::PL[pi]]);
+    store(R, cur ^ 1);
+    load(32 * (int64_t)(st + 3), R);
+    if ((st + 1) % (KCHUNK / 32) == 0 || st + 1 == nsteps) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[i][j][v] += SP::combine(acc[i][j], v);
+#pragma unroll
+          for (int l = 0; l < SP::LEVELS; ++l) acc[i][j][l] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    __syncthreads();
+  };
+  for (int st = 0; st < nsteps; st += 2) {
+    step(st, R1);
+    if (st + 1 < nsteps) step(st + 1, R0);
+  }
+  const double out_scale = SP::SCALED && exps ? pow2(-exps[0] - exps[1]) : 1.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t c = c0 + wn * (16 * FN) + j * 16 + frow;
+      const int64_t coff = (c / ccb) * sccb + (c % ccb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        if (m < M && c < N) out[coff + m * ldc] = acc64[i][j][v] * out_scale;
+      }
+    }
+}
+
 // ---- max |x| of FP64 arrays as ordered bit patterns (deterministic) ----------
 // Wave maxima are combined in LDS; one integer atomic per workgroup (the
 // maximum does not depend on the order).
@@ -861,6 +1045,141 @@ static void grid_mixed_t(int fp16, const double* T2, const double* V3, int64_t n
   split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
   split_planes<SP>(V3, n, r3, r3, 1, P.kp, exps, 1, bp, s);
   grid_stream<SP>(ap, bp, n * n, n, P.kp, grid, exps, num_cu, s);
+}
+
+// ---- projection ------------------------------------------------------------------
+struct ProjMixedPlan {
+  int64_t kp;
+  size_t o_mx, o_exps, o_a, o_b, total;
+};
+
+static ProjMixedPlan plan_proj_mixed(int64_t n, int64_t K, int r, bool a_given) {
+  ProjMixedPlan P{};
+  P.kp = pad32(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  P.o_mx = take(4 * sizeof(unsigned long long));
+  P.o_exps = take(2 * sizeof(int));
+  P.o_a = take(a_given ? 0 : (size_t)3 * K * P.kp * 2);   // up to 3 terms of 2 bytes
+  P.o_b = take((size_t)3 * r * P.kp * 2);
+  P.total = off;
+  return P;
+}
+
+size_t proj_mixed_workspace_bytes(int64_t n, int64_t K, int r, bool a_given) {
+  return plan_proj_mixed(n, K, r, a_given).total;
+}
+
+// mx[0] = 1.0 (the bound of a side-matrix entry) as an ordered bit pattern
+__global__ void unit_max_kernel(unsigned long long* mx) {
+  if (threadIdx.x == 0) mx[0] = (unsigned long long)__double_as_longlong(1.0);
+}
+
+template <class SP>
+static void proj_mixed_t(int fp16, const double* U, const void* a_planes, int64_t n, int64_t K,
+                         const double* V, int r, double* Ut, char* work, hipStream_t s) {
+  const ProjMixedPlan P = plan_proj_mixed(n, K, r, a_planes != nullptr);
+  unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
+  int* exps = (int*)(work + P.o_exps);
+  typename SP::T* ap = (typename SP::T*)(work + P.o_a);
+  typename SP::T* bp = (typename SP::T*)(work + P.o_b);
+  const double* Bops[1] = {V};
+  const int64_t nb[1] = {n * r};
+  // A: row j = column j of U (n x K column-major); B: row a = column a of V (n x r row-major)
+  if (a_planes) {
+    // planes formed with the fixed scale 2^14 = 2^(14 - ceil(log2 1))
+    RS_HIP(hipMemsetAsync(mx, 0, 4 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(unit_max_kernel, dim3(1), dim3(64), 0, s, mx);
+    absmax(V, n * r, mx + 1, s);
+    hipLaunchKernelGGL(scale_exponents_kernel, dim3(1), dim3(64), 0, s, mx, 1, fp16, exps);
+    ap = (typename SP::T*)a_planes;
+  } else {
+    scale_setup(U, n * K, Bops, nb, 1, fp16, mx, exps, s);
+    split_planes<SP>(U, K, n, n, 1, P.kp, exps, 0, ap, s);
+  }
+  split_planes<SP>(V, r, n, 1, r, P.kp, exps, 1, bp, s);
+  constexpr int FN = SP::TERMS == 2 ? 4 : 2;
+  constexpr int WGM = 4;
+  const int64_t col_tiles = (r + 32 * FN - 1) / (32 * FN);
+  const int64_t row_tiles = (K + 32 * WGM - 1) / (32 * WGM);
+  hipLaunchKernelGGL((proj_tile_kernel<SP, WGM, FN>), dim3((unsigned)(row_tiles * col_tiles)),
+                     dim3(128 * WGM), 0, s, ap, bp, K, (int64_t)r, P.kp, col_tiles, row_tiles, 0, Ut,
+                     (int64_t)r, (int64_t)r, (int64_t)0, exps);
+}
+
+void proj_mixed(int prec, const double* U, const void* a_planes, int64_t n, int64_t K,
+                const double* V, int r, double* Ut, void* work, hipStream_t s) {
+  if (prec == RS_MIXED_BF16) {
+    if (a_planes) throw Error{RS_E_INVALID, "split-BF16 projection from FP16 planes"};
+    proj_mixed_t<SplitBF16>(0, U, nullptr, n, K, V, r, Ut, (char*)work, s);
+  } else {
+    proj_mixed_t<CoreF16>(1, U, a_planes, n, K, V, r, Ut, (char*)work, s);
+  }
+}
+
+// ---- second expansion --------------------------------------------------------------
+// T2[i1][i2][c] = sum_b V2[i2, b] X[b][i1][c] in split precision: A = V2
+// (rows i2, b contiguous), B = X transposed to rows (i1, c) with b
+// contiguous; the output's column (i1, c) goes to i1 n r3 + i2 r3 + c.
+struct Expand2MixedPlan {
+  int64_t kp;
+  size_t o_mx, o_exps, o_a, o_b, total;
+};
+
+static Expand2MixedPlan plan_expand2_mixed(int64_t n, int r2, int r3) {
+  Expand2MixedPlan P{};
+  P.kp = pad32(r2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  P.o_mx = take(4 * sizeof(unsigned long long));
+  P.o_exps = take(2 * sizeof(int));
+  P.o_a = take((size_t)3 * n * P.kp * 2);
+  P.o_b = take((size_t)3 * n * r3 * P.kp * 2);
+  P.total = off;
+  return P;
+}
+
+size_t expand2_mixed_workspace_bytes(int64_t n, int r2, int r3) {
+  return plan_expand2_mixed(n, r2, r3).total;
+}
+
+template <class SP>
+static void expand2_mixed_t(int fp16, const double* X, const double* V2, int64_t n, int r2, int r3,
+                            double* T2, char* work, hipStream_t s) {
+  const Expand2MixedPlan P = plan_expand2_mixed(n, r2, r3);
+  unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
+  int* exps = (int*)(work + P.o_exps);
+  typename SP::T* ap = (typename SP::T*)(work + P.o_a);
+  typename SP::T* bp = (typename SP::T*)(work + P.o_b);
+  const int64_t cols = n * r3;
+  const double* Bops[1] = {X};
+  const int64_t nb[1] = {(int64_t)r2 * cols};
+  scale_setup(V2, n * r2, Bops, nb, 1, fp16, mx, exps, s);
+  split_planes<SP>(V2, n, r2, r2, 1, P.kp, exps, 0, ap, s);
+  hipLaunchKernelGGL(transpose_split_kernel<SP>,
+                     dim3((unsigned)((P.kp + 63) / 64), (unsigned)((cols + 63) / 64)), dim3(256), 0,
+                     s, X, (int64_t)r2, cols, P.kp, exps, 1, bp);
+  constexpr int FN = SP::TERMS == 2 ? 4 : 2;
+  constexpr int WGM = 4;
+  const int64_t row_tiles = (n + 32 * WGM - 1) / (32 * WGM);
+  const int64_t col_tiles = (cols + 32 * FN - 1) / (32 * FN);
+  hipLaunchKernelGGL((proj_tile_kernel<SP, WGM, FN>), dim3((unsigned)(row_tiles * col_tiles)),
+                     dim3(128 * WGM), 0, s, ap, bp, n, cols, P.kp, col_tiles, row_tiles, 1, T2,
+                     (int64_t)r3, (int64_t)r3, n * r3, exps);
+}
+
+void expand2_mixed(int prec, const double* X, const double* V2, int64_t n, int r2, int r3,
+                   double* T2, void* work, hipStream_t s) {
+  if (prec == RS_MIXED_BF16) expand2_mixed_t<SplitBF16>(0, X, V2, n, r2, r3, T2, (char*)work, s);
+  else expand2_mixed_t<CoreF16>(1, X, V2, n, r2, r3, T2, (char*)work, s);
 }
 
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,

@@ -167,9 +167,12 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
                      hipStream_t s);
 // Side matrices U[l][i + j*n] = exp(-t_k^2 (x_i - x_{nu,l})^2), j = k*N + nu, k < R_l;
 // xi[j] = q[nu] a_k, w[j] = |xi_j|^{2/3}.
+// U (FP64, may be null) and/or planes16 (FP16 split planes of the
+// projection, [mode][hi, lo][K][kp], scale 2^14; may be null)
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
-                          double* w, double* sw, hipStream_t s);
+                          double* w, double* sw, hipStream_t s, void* planes16 = nullptr,
+                          int64_t kp = 0);
 
 // k_dot.hip : scalar product of two RS tensors (the touched-brick correction
 // and fixed-order reductions; the long-long term is formed by the caller)
@@ -308,6 +311,16 @@ void core64(const double* U1t, const double* U2t, const double* U3t, const doubl
 void core64_reduce(const double* part, int splits, int64_t total, double* out, hipStream_t s);
 
 // k_mixed.hip: split-FP16 (prec RS_MIXED_FP16) or split-BF16 contractions
+// U~^T (K x r, FP64) = U^T V in split precision: U n x K column-major, V n x r row-major
+size_t proj_mixed_workspace_bytes(int64_t n, int64_t K, int r, bool a_given);
+// a_planes: the FP16 planes of U written by the side-matrix kernel (scale
+// 2^14), or null to split U here
+void proj_mixed(int prec, const double* U, const void* a_planes, int64_t n, int64_t K,
+                const double* V, int r, double* Ut, void* work, hipStream_t s);
+// T2 (n x n x r3, FP64) = X x_2 V2 in split precision, X[b][i1][c] (r2 x n x r3)
+size_t expand2_mixed_workspace_bytes(int64_t n, int r2, int r3);
+void expand2_mixed(int prec, const double* X, const double* V2, int64_t n, int r2, int r3,
+                   double* T2, void* work, hipStream_t s);
 size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,

@@ -40,9 +40,29 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
 // U (FP64, column j = k N + nu contiguous) and/or the FP16 split planes of
 // the projection, planes[l][term][j][i] with i padded to kp (a multiple of
 // 32) by zeros.  Every entry is at most 1, so the planes hold
-// x 2^14 = hi + lo (hi = x 2^14 rounded to FP16, lo = the rest rounded to
-// FP16) under the fixed scale 2^14.  grid.y = mode.
+// x 2^14 = hi + lo (x from plane_exp in FP32, hi = x 2^14 rounded to FP16,
+// lo = the exact FP32 rest rounded to FP16) under the fixed scale 2^14.
+// grid.y = mode.
 typedef _Float16 sm_h8 __attribute__((ext_vector_type(8)));
+
+// e^arg (arg <= 0) to about 2^-23 relative for the FP16 planes, with
+// zero-mean rounding errors: arg log2 e = m + f (m integer, |f| <= 1/2, both
+// in FP64), e^(f ln 2) by its Taylor series to degree 7 in FP32 (truncation
+// below 6e-9 for |f ln 2| <= 0.35), scaled by 2^m.
+__device__ __forceinline__ float plane_exp(double arg) {
+  const double A = arg * 1.4426950408889634;
+  const double m = rint(A);
+  const float x = (float)(A - m) * 0.69314718f;
+  float p = 1.0f / 5040.0f;
+  p = fmaf(p, x, 1.0f / 720.0f);
+  p = fmaf(p, x, 1.0f / 120.0f);
+  p = fmaf(p, x, 1.0f / 24.0f);
+  p = fmaf(p, x, 1.0f / 6.0f);
+  p = fmaf(p, x, 0.5f);
+  p = fmaf(p, x, 1.0f);
+  p = fmaf(p, x, 1.0f);
+  return m < -200.0 ? 0.0f : ldexpf(p, (int)m);
+}
 
 __global__ void side_matrix_kernel(const double* __restrict__ pos, const double* __restrict__ t,
                                    int64_t N, int R_l, int64_t n, double b, double* __restrict__ U,
@@ -87,11 +107,12 @@ __global__ void side_matrix_kernel(const double* __restrict__ pos, const double*
       for (int u = 0; u < 8; ++u) {
         const int64_t i = i0 + u;
         const double d = (-b + ((double)i + 0.5) * h) - x;
-        const double v = i < n ? exp(-(tk * tk) * (d * d)) : 0.0;
-        if (Ul && i < n) Ul[j * n + i] = v;
-        const double y = v * 16384.0;
+        const double arg = -(tk * tk) * (d * d);
+        if (Ul && i < n) Ul[j * n + i] = exp(arg);
+        const float v = i < n ? plane_exp(arg) : 0.0f;
+        const float y = v * 16384.0f;
         hi[u] = (_Float16)y;
-        lo[u] = (_Float16)(y - (double)hi[u]);
+        lo[u] = (_Float16)(y - (float)hi[u]);
       }
       *(sm_h8*)(P0 + j * kp + i0) = hi;
       *(sm_h8*)(P0 + (K + j) * kp + i0) = lo;

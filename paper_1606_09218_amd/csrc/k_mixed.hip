@@ -37,10 +37,12 @@ struct SplitF16 {
   static constexpr bool PAIRED = false;
   typedef _Float16 T;
   typedef h8 V8;
+  // FP64 -> FP16 through FP32 (hi need not be the nearest FP16 value: lo
+  // takes the exact residual x - hi)
   __device__ static void split(double x, T* o) {
-    const T hi = (T)x;
+    const T hi = (T)(float)x;
     o[0] = hi;
-    o[1] = (T)((x - (double)hi) * 2048.0);
+    o[1] = (T)(float)((x - (double)hi) * 2048.0);
   }
   __device__ static void split32(float x, T* o) {
     const T hi = (T)x;
@@ -111,9 +113,9 @@ struct CoreF16 {
   typedef _Float16 T;
   typedef h8 V8;
   __device__ static void split(double x, T* o) {
-    const T hi = (T)x;
+    const T hi = (T)(float)x;
     o[0] = hi;
-    o[1] = (T)(x - (double)hi);
+    o[1] = (T)(float)(x - (double)hi);
   }
   __device__ static h2 pk(float a, float b) {
     return __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b));
@@ -828,7 +830,7 @@ __global__ void scale_exponents_kernel(const unsigned long long* mx, int nbops, 
 }
 
 static void absmax(const double* x, int64_t count, unsigned long long* out, hipStream_t s) {
-  unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 512);
+  unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, s, x, count, out);
 }
@@ -1167,8 +1169,10 @@ static void expand2_mixed_t(int fp16, const double* X, const double* V2, int64_t
   hipLaunchKernelGGL(transpose_split_kernel<SP>,
                      dim3((unsigned)((P.kp + 63) / 64), (unsigned)((cols + 63) / 64)), dim3(256), 0,
                      s, X, (int64_t)r2, cols, P.kp, exps, 1, bp);
+  // short contraction (r2): 64-row tiles, so that two workgroups share a
+  // compute unit and one's loads and stores overlap the other's MFMAs
   constexpr int FN = SP::TERMS == 2 ? 4 : 2;
-  constexpr int WGM = 4;
+  constexpr int WGM = 2;
   const int64_t row_tiles = (n + 32 * WGM - 1) / (32 * WGM);
   const int64_t col_tiles = (cols + 32 * FN - 1) / (32 * FN);
   hipLaunchKernelGGL((proj_tile_kernel<SP, WGM, FN>), dim3((unsigned)(row_tiles * col_tiles)),

@@ -410,11 +410,12 @@ static void build_expansion(rs_tensor* T, void* grid, char* scratch, hipStream_t
     gemm64(expand2_gemm(T, X), ncu, (double*)(scratch + e.wk2), s);
   else
     expand2_mixed(contraction_prec(T->prec), X, T->Q[1].as<double>(), n, T->r[1], r3,
-                  T->T2.as<double>(), scratch + e.wk2, s);
+                  T->T2.as<double>(), scratch + e.wk2, grid ? scratch + e.wkg : nullptr,
+                  T->t2exp.as<int>(), s);
   if (grid && T->prec != RS_FP64) {
     mark(T, RS_STAGE_GRID, s);
     grid_mixed(contraction_prec(T->prec), T->T2.as<double>(), T->Q[2].as<double>(), n, r3, (float*)grid,
-               scratch + e.wkg, ncu, s);
+               scratch + e.wkg, ncu, s, true);
     mark(T, RS_STAGE_SHORT, s);
     short_gather(grid, 1, T->pos.as<double>(), T->q.as<double>(), T->t_dev.as<double>(),
                  T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
@@ -1024,6 +1025,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
                    T->brick_active.as<int>(), T->active_cap, s);
 
     T->T2 = DevBuf((size_t)n * n * r3 * sizeof(double), s);
+    if (P.prec != RS_FP64) T->t2exp = DevBuf(sizeof(int), s);
     Gemm64 gb[3], gp[3];
     for (int l = 0; l < 3; ++l) {
       const int r = T->r[l];
@@ -1406,9 +1408,10 @@ rs_status rs_tensor_grid(const rs_tensor* T, void* grid_out, void* stream) {
         gemm64(gg, ncu, wg.as<double>(), s);
       }
     } else {
+      // T2 split under the exponent the assembly's grid used: the same bits
       DevBuf wg(grid_mixed_workspace_bytes(n, r3), s);
       grid_mixed(contraction_prec(T->prec), T->T2.as<double>(), T->Q[2].as<double>(), n, r3,
-                 (float*)grid_out, wg.p, ncu, s);
+                 (float*)grid_out, wg.p, ncu, s, false, T->t2exp.as<int>());
     }
     short_gather(grid_out, T->prec != RS_FP64, T->pos.as<double>(), T->q.as<double>(),
                  T->t_dev.as<double>(), T->a_dev.as<double>(), T->R, T->R_l, n, T->b, T->n_s, T->nb,
@@ -1741,6 +1744,7 @@ rs_status rs_tensor_load(rs_ctx* ctx, const char* path, rs_tensor** out) {
     short_bin_sort(T->brick_start.as<int>(), T->brick_list.as<int>(), nbricks,
                    T->brick_active.as<int>(), T->active_cap, s);
     T->T2 = DevBuf((size_t)T->n * T->n * T->r[2] * sizeof(double), s);
+    if (T->prec != RS_FP64) T->t2exp = DevBuf(sizeof(int), s);
     DevBuf scratch(expansion_scratch(T.get(), false).total, s);
     build_expansion(T.get(), nullptr, scratch.as<char>(), s);
     make_fp32_field(T.get(), s);

@@ -651,11 +651,15 @@ __global__ __launch_bounds__(128 * WGM) void core_tile_kernel(
 // (c / ccb) sccb + (c % ccb) + m ldc.  Workgroup order: column tile fastest
 // (the workgroups that share a row tile of A run together) or, with
 // row_fast, row tile fastest (they share a column tile of B).
+template <class SP> struct GridSplitOf { typedef SplitF16 type; };
+template <> struct GridSplitOf<SplitBF16> { typedef SplitBF16 type; };
+
 template <class SP, int WGM, int FN>
 __global__ __launch_bounds__(128 * WGM) void proj_tile_kernel(
     const typename SP::T* __restrict__ Ap, const typename SP::T* __restrict__ Bp, int64_t M,
     int64_t N, int64_t kp, int64_t col_tiles, int64_t row_tiles, int row_fast,
-    double* __restrict__ out, int64_t ldc, int64_t ccb, int64_t sccb, const int* exps) {
+    double* __restrict__ out, int64_t ldc, int64_t ccb, int64_t sccb, const int* exps,
+    typename GridSplitOf<SP>::type::T* __restrict__ pout, int64_t pkp, const int* pexp) {
   typedef typename SP::T T;
   typedef typename SP::V8 V8;
   constexpr int NT = 128 * WGM, BM = 32 * WGM, BN = 32 * FN, LDK = 32;
@@ -782,13 +786,79 @@ __global__ __launch_bounds__(128 * WGM) void proj_tile_kernel(
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int64_t c = c0 + wn * (16 * FN) + j * 16 + frow;
-      const int64_t coff = (c / ccb) * sccb + (c % ccb);
+      const int64_t cb = c / ccb, cr = c - cb * ccb;
+      const int64_t coff = cb * sccb + cr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
         if (m < M && c < N) out[coff + m * ldc] = acc64[i][j][v] * out_scale;
       }
     }
+  if (!pout) return;
+  // The grid's split planes of the output: element (m, c) goes to plane row
+  // (c / ccb) M + m, column c % ccb.  The tile is staged in LDS (the B
+  // buffers, free after the last step) and written along plane rows, 64
+  // consecutive columns per store instruction.
+  typedef typename GridSplitOf<SP>::type GP;
+  typedef typename GP::T PT;
+  const double pscale = GP::SCALED ? pow2(pexp[0]) : 1.0;
+  const int64_t pplane = (N / ccb) * M * pkp;
+  if constexpr (GP::TERMS * BM * BN > 2 * SP::TERMS * BN * LDK) {
+    // (tiles whose staging would exceed the B buffers: element by element)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int64_t c = c0 + wn * (16 * FN) + j * 16 + frow;
+        const int64_t cb = c / ccb, cr = c - cb * ccb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+          if (m >= M || c >= N) continue;
+          PT t[GP::TERMS];
+          GP::split(acc64[i][j][v] * out_scale * pscale, t);
+#pragma unroll
+          for (int term = 0; term < GP::TERMS; ++term) pout[term * pplane + (cb * M + m) * pkp + cr] = t[term];
+        }
+      }
+    return;
+  }
+  PT* stg = (PT*)&Bs[0][0][0][0];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int col = wn * (16 * FN) + j * 16 + frow;
+        PT t[GP::TERMS];
+        GP::split(acc64[i][j][v] * out_scale * pscale, t);
+#pragma unroll
+        for (int term = 0; term < GP::TERMS; ++term) stg[(term * BM + row) * BN + col] = t[term];
+      }
+  __syncthreads();
+  int64_t pcb[BN / 64], pcr[BN / 64];
+#pragma unroll
+  for (int hh = 0; hh < BN / 64; ++hh) {
+    const int64_t c = c0 + hh * 64 + lane;
+    pcb[hh] = c / ccb;
+    pcr[hh] = c - pcb[hh] * ccb;
+  }
+  for (int row = wave; row < BM; row += NT / 64) {
+    const int64_t m = m0 + row;
+    if (m >= M) break;
+#pragma unroll
+    for (int hh = 0; hh < BN / 64; ++hh) {
+      const int64_t c = c0 + hh * 64 + lane;
+      if (c >= N) continue;
+      const int64_t pe = (pcb[hh] * M + m) * pkp + pcr[hh];
+#pragma unroll
+      for (int term = 0; term < GP::TERMS; ++term)
+        pout[term * pplane + pe] = stg[(term * BM + row) * BN + hh * 64 + lane];
+    }
+  }
 }
 
 // ---- max |x| of FP64 arrays as ordered bit patterns (deterministic) ----------
@@ -1032,19 +1102,39 @@ static void grid_stream(const typename SP::T* ap, const typename SP::T* bp, int6
   }
 }
 
+// exps[1] = 14 - ceil(log2(mx[1])) (0 for BF16 or a zero operand); exps[0]
+// = *e0 when given, else kept
+__global__ void b_exp_kernel(const unsigned long long* mx, int fp16, const int* e0, int* exps) {
+  if (threadIdx.x != 0) return;
+  const double b = __longlong_as_double((long long)mx[1]);
+  exps[1] = fp16 && b > 0.0 ? 14 - (int)ceil(log2(b)) : 0;
+  if (e0) exps[0] = e0[0];
+}
+
 template <class SP>
 static void grid_mixed_t(int fp16, const double* T2, const double* V3, int64_t n, int r3,
-                         float* grid, char* work, int num_cu, hipStream_t s) {
+                         float* grid, char* work, int num_cu, bool planes_ready, const int* t2exp,
+                         hipStream_t s) {
   const GridMixedPlan P = plan_grid_mixed(n, r3);
   if (P.kp > 512) throw Error{RS_E_UNSUPPORTED, "mixed grid: Tucker rank above 512"};
   unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
   int* exps = (int*)(work + P.o_exps);
   typename SP::T* ap = (typename SP::T*)(work + P.o_a);
   typename SP::T* bp = (typename SP::T*)(work + P.o_b);
-  const double* Bops[1] = {V3};
-  const int64_t nb[1] = {n * r3};
-  scale_setup(T2, n * n * r3, Bops, nb, 1, fp16, mx, exps, s);
-  split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
+  if (planes_ready || t2exp) {
+    // T2's planes and exps[0] came with the second expansion, or T2 is
+    // split here under the exponent that expansion chose
+    RS_HIP(hipMemsetAsync(mx, 0, 4 * sizeof(unsigned long long), s));
+    absmax(V3, n * r3, mx + 1, s);
+    hipLaunchKernelGGL(b_exp_kernel, dim3(1), dim3(64), 0, s, mx, fp16, planes_ready ? nullptr : t2exp,
+                       exps);
+    if (!planes_ready) split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
+  } else {
+    const double* Bops[1] = {V3};
+    const int64_t nb[1] = {n * r3};
+    scale_setup(T2, n * n * r3, Bops, nb, 1, fp16, mx, exps, s);
+    split_planes<SP>(T2, n * n, r3, r3, 1, P.kp, exps, 0, ap, s);
+  }
   split_planes<SP>(V3, n, r3, r3, 1, P.kp, exps, 1, bp, s);
   grid_stream<SP>(ap, bp, n * n, n, P.kp, grid, exps, num_cu, s);
 }
@@ -1110,7 +1200,8 @@ static void proj_mixed_t(int fp16, const double* U, const void* a_planes, int64_
   const int64_t row_tiles = (K + 32 * WGM - 1) / (32 * WGM);
   hipLaunchKernelGGL((proj_tile_kernel<SP, WGM, FN>), dim3((unsigned)(row_tiles * col_tiles)),
                      dim3(128 * WGM), 0, s, ap, bp, K, (int64_t)r, P.kp, col_tiles, row_tiles, 0, Ut,
-                     (int64_t)r, (int64_t)r, (int64_t)0, exps);
+                     (int64_t)r, (int64_t)r, (int64_t)0, exps,
+                     (typename GridSplitOf<SP>::type::T*)nullptr, (int64_t)0, (const int*)nullptr);
 }
 
 void proj_mixed(int prec, const double* U, const void* a_planes, int64_t n, int64_t K,
@@ -1153,9 +1244,36 @@ size_t expand2_mixed_workspace_bytes(int64_t n, int r2, int r3) {
   return plan_expand2_mixed(n, r2, r3).total;
 }
 
+// zero the padding columns r3 <= k < kp of the grid's A planes (rows n^2)
+template <class GP>
+__global__ void pad_planes_kernel(typename GP::T* __restrict__ planes, int64_t rows, int r3, int kp) {
+  const int w = kp - r3;
+  const int64_t total = rows * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / w;
+    const int k = r3 + (int)(e - row * w);
+#pragma unroll
+    for (int term = 0; term < GP::TERMS; ++term) planes[(term * rows + row) * kp + k] = (typename GP::T)0.0f;
+  }
+}
+
+// The grid's scale for T2 from a bound: |T2[i1, i2, c]| <= |V2[i2, :]|_2
+// |X[:, i1, c]|_2 <= sqrt(r2) max|X| (the rows of the orthonormal V2 have
+// norm at most 1), so gexps[0] = 14 - ceil(log2(sqrt(r2) max|X|)) keeps the
+// scaled T2 below 2^14 (0 for the unscaled BF16 split).
+__global__ void t2_bound_exp_kernel(const unsigned long long* mx_x, int r2, int fp16, int* t2exp,
+                                    int* gexps) {
+  if (threadIdx.x != 0) return;
+  const double b = __longlong_as_double((long long)mx_x[0]) * sqrt((double)r2);
+  const int e = fp16 && b > 0.0 ? 14 - (int)ceil(log2(b)) : 0;
+  t2exp[0] = e;
+  if (gexps) gexps[0] = e;
+}
+
 template <class SP>
 static void expand2_mixed_t(int fp16, const double* X, const double* V2, int64_t n, int r2, int r3,
-                            double* T2, char* work, hipStream_t s) {
+                            double* T2, char* work, char* gwork, int* t2exp, hipStream_t s) {
   const Expand2MixedPlan P = plan_expand2_mixed(n, r2, r3);
   unsigned long long* mx = (unsigned long long*)(work + P.o_mx);
   int* exps = (int*)(work + P.o_exps);
@@ -1175,21 +1293,44 @@ static void expand2_mixed_t(int fp16, const double* X, const double* V2, int64_t
   constexpr int WGM = 2;
   const int64_t row_tiles = (n + 32 * WGM - 1) / (32 * WGM);
   const int64_t col_tiles = (cols + 32 * FN - 1) / (32 * FN);
+  typedef typename GridSplitOf<SP>::type GP;
+  typename GP::T* gp = nullptr;
+  int* gexps = nullptr;
+  int64_t gkp = 0;
+  if (gwork) grid_mixed_planes(gwork, n, r3, (void**)&gp, &gexps, &gkp);
+  hipLaunchKernelGGL(t2_bound_exp_kernel, dim3(1), dim3(64), 0, s, mx + 1, r2, fp16, t2exp, gexps);
+  if (gwork) {
+    // the grid's A planes of T2, written by the epilogue below
+    if (gkp > r3)
+      hipLaunchKernelGGL(pad_planes_kernel<GP>, dim3(grid_blocks(n * n * (gkp - r3))), dim3(256), 0, s,
+                         gp, n * n, r3, (int)gkp);
+  }
   hipLaunchKernelGGL((proj_tile_kernel<SP, WGM, FN>), dim3((unsigned)(row_tiles * col_tiles)),
                      dim3(128 * WGM), 0, s, ap, bp, n, cols, P.kp, col_tiles, row_tiles, 1, T2,
-                     (int64_t)r3, (int64_t)r3, n * r3, exps);
+                     (int64_t)r3, (int64_t)r3, n * r3, exps, gp, gkp, (const int*)gexps);
 }
 
 void expand2_mixed(int prec, const double* X, const double* V2, int64_t n, int r2, int r3,
-                   double* T2, void* work, hipStream_t s) {
-  if (prec == RS_MIXED_BF16) expand2_mixed_t<SplitBF16>(0, X, V2, n, r2, r3, T2, (char*)work, s);
-  else expand2_mixed_t<CoreF16>(1, X, V2, n, r2, r3, T2, (char*)work, s);
+                   double* T2, void* work, void* grid_work, int* t2exp, hipStream_t s) {
+  if (prec == RS_MIXED_BF16)
+    expand2_mixed_t<SplitBF16>(0, X, V2, n, r2, r3, T2, (char*)work, (char*)grid_work, t2exp, s);
+  else
+    expand2_mixed_t<CoreF16>(1, X, V2, n, r2, r3, T2, (char*)work, (char*)grid_work, t2exp, s);
 }
 
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                void* work, int num_cu, hipStream_t s) {
-  if (prec == RS_MIXED_FP16) grid_mixed_t<SplitF16>(1, T2, V3, n, r3, grid, (char*)work, num_cu, s);
-  else grid_mixed_t<SplitBF16>(0, T2, V3, n, r3, grid, (char*)work, num_cu, s);
+                void* work, int num_cu, hipStream_t s, bool planes_ready, const int* t2exp) {
+  if (prec == RS_MIXED_FP16)
+    grid_mixed_t<SplitF16>(1, T2, V3, n, r3, grid, (char*)work, num_cu, planes_ready, t2exp, s);
+  else
+    grid_mixed_t<SplitBF16>(0, T2, V3, n, r3, grid, (char*)work, num_cu, planes_ready, t2exp, s);
+}
+
+void grid_mixed_planes(void* work, int64_t n, int r3, void** planes, int** exps, int64_t* kp) {
+  const GridMixedPlan P = plan_grid_mixed(n, r3);
+  *planes = (char*)work + P.o_a;
+  *exps = (int*)((char*)work + P.o_exps);
+  *kp = P.kp;
 }
 
 }  // namespace rs

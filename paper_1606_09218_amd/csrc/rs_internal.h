@@ -132,6 +132,7 @@ struct rs_tensor {
   rs::DevBuf beta;               // r1 x r2 x r3
   rs::DevBuf T2;                 // n x n x r3: beta x_1 V1 x_2 V2 (long-range, modes 1,2 expanded)
   rs::DevBuf T2f, V3f;           // FP32 copies of T2 and V3 (RS_FP32 tensors only)
+  rs::DevBuf t2exp;              // 1 int: the split grid's scale exponent of T2 (split tensors)
   // short-range binning: bricks of 8^3 cells; pairs (brick, particle) sorted by particle
   int nb = 0;                    // bricks per axis
   int64_t n_pairs = 0;
@@ -319,8 +320,13 @@ void proj_mixed(int prec, const double* U, const void* a_planes, int64_t n, int6
                 const double* V, int r, double* Ut, void* work, hipStream_t s);
 // T2 (n x n x r3, FP64) = X x_2 V2 in split precision, X[b][i1][c] (r2 x n x r3)
 size_t expand2_mixed_workspace_bytes(int64_t n, int r2, int r3);
+// grid_work (the grid_mixed workspace, or null): also write the grid's A
+// planes of T2 and their exponent there, for grid_mixed(..., planes_ready);
+// grid_mixed with t2exp splits T2 under that exponent (the same planes)
+// t2exp (device int): receives the exponent of the grid's T2 planes
 void expand2_mixed(int prec, const double* X, const double* V2, int64_t n, int r2, int r3,
-                   double* T2, void* work, hipStream_t s);
+                   double* T2, void* work, void* grid_work, int* t2exp, hipStream_t s);
+void grid_mixed_planes(void* work, int64_t n, int r3, void** planes, int** exps, int64_t* kp);
 size_t core_mixed_workspace_bytes(int r1, int r2, int r3, int64_t K, int num_cu);
 void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3t, const double* xi,
                 int r1, int r2, int r3, int64_t K, double* beta, int num_cu, double* work,
@@ -329,7 +335,8 @@ void core_mixed(int prec, const double* U1t, const double* U2t, const double* U3
 // grid_mixed_workspace_bytes(n, r3) bytes
 size_t grid_mixed_workspace_bytes(int64_t n, int r3);
 void grid_mixed(int prec, const double* T2, const double* V3, int64_t n, int r3, float* grid,
-                void* work, int num_cu, hipStream_t s);
+                void* work, int num_cu, hipStream_t s,
+                bool planes_ready = false, const int* t2exp = nullptr);
 
 // k_short.hip
 struct ShortBins {

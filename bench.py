@@ -439,13 +439,15 @@ def _serve_trace(ex, trace, n_requests, n_slots, prec):
     return out
 
 
-def serving_full(n_slots: int = 4, sample_every: int = 125):
+def serving_full(n_slots: int = 4, sample_every: int = 125, part: str = "all"):
     """The serving workload in full: the 2000-request Poisson trace (200/s)
     replayed in real time with split-FP16 and with FP64 assemblies (same
     slots, same HBM budget), the first 400 requests at 20/s (below one GPU's
     capacity, so that latency is service time rather than queueing) in both
     precisions, and the split-FP16 against the FP64 result (grid rel-Linf,
-    energy) of every `sample_every`-th request, each run alone."""
+    energy) of every `sample_every`-th request, each run alone.  `part`
+    selects one of "mixed_fp16", "fp64", "samples" (one library context per
+    process), or "all"."""
     import torch
 
     import paper_1606_09218_amd as rsm
@@ -458,6 +460,8 @@ def serving_full(n_slots: int = 4, sample_every: int = 125):
     out = {"slots": n_slots, "hbm_budget_GB": round(budget / 2**30, 1), "r_max": 384,
            "trace": "seed 5: N log-uniform in [32, 20000], n in {256, 512, 1024}, R in 24..32"}
     for prec in ("mixed_fp16", "fp64"):
+        if part not in ("all", prec):
+            continue
         ex = GpuExecutor(0, prec=prec, r_max=384)
         try:
             for r in full:
@@ -476,6 +480,8 @@ def serving_full(n_slots: int = 4, sample_every: int = 125):
             out[prec] = res
         finally:
             ex.close()
+    if part not in ("all", "samples"):
+        return out
     # split-FP16 against FP64 for a sample of requests, each alone
     ctx = rsm.Context(0)
     samples = []
@@ -530,6 +536,8 @@ def main():
                     help="print only the oracle CPU baseline (no GPU use)")
     ap.add_argument("--serving-full", action="store_true",
                     help="print only the full serving measurement (both precisions, two rates)")
+    ap.add_argument("--serving-part", default="all", choices=["all", "mixed_fp16", "fp64", "samples"],
+                    help="with --serving-full: one precision's replays or the sampled comparison")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         s, _, _ = workload(args.workload)
@@ -541,7 +549,7 @@ def main():
         sys.exit(2)
 
     if args.serving_full:
-        print(json.dumps({"serving_full": serving_full()}), flush=True)
+        print(json.dumps({"serving_full": serving_full(part=args.serving_part)}), flush=True)
         return
 
     cpu = None if args.no_cpu_baseline else cpu_baseline_child(args.workload)

@@ -311,12 +311,27 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
     const int64_t r = tile * 128 + wave * 16 + (lane & 15);
     return (r < M ? r : 0) * kp + kofs;
   };
-  // A fragments of a whole row block (all k blocks) for the current and next tile
-  constexpr int KBMAX = 16;   // kp <= 512
+  // A fragments two steps ahead in two register sets: a0 / a1 hold steps
+  // kb, kb + 1 of the tile; a step past the tile's end is that step of the
+  // next tile of this group (or a valid reload of this one after the last
+  // tile), so the loads run ahead across tiles too
   const int nkb = kp / 32;
   int64_t tile = g;
   if (tile >= tiles) return;
   int64_t arow = arow_of(tile);
+  auto loadA = [&](int64_t ar, int64_t ar_next, int step, V8 (&dst)[SP::TERMS]) {
+    const int sn = step - nkb < nkb - 1 ? step - nkb : nkb - 1;
+    const int64_t off = step < nkb ? ar + 32 * (int64_t)step : ar_next + 32 * (int64_t)sn;
+#pragma unroll
+    for (int term = 0; term < SP::TERMS; ++term) dst[term] = *(const V8*)(Ap + term * planeA + off);
+  };
+  V8 a0[SP::TERMS], a1[SP::TERMS];
+  {
+    const int64_t t1 = tile + groups;
+    const int64_t ar_next = t1 < tiles ? arow_of(t1) : arow;
+    loadA(arow, ar_next, 0, a0);
+    loadA(arow, ar_next, 1, a1);
+  }
   for (; tile < tiles; tile += groups) {
     const int64_t next = tile + groups;
     const int64_t arow_next = next < tiles ? arow_of(next) : arow;
@@ -331,17 +346,8 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
       for (int j = 0; j < (FOLD ? FN : 1); ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc64[j][v] = 0.0;
-    V8 a[SP::TERMS];
-#pragma unroll
-    for (int term = 0; term < SP::TERMS; ++term) a[term] = *(const V8*)(Ap + term * planeA + arow);
     int since = 0;
-    for (int kb = 0; kb < nkb; ++kb) {
-      V8 an[SP::TERMS];
-      const bool more = kb + 1 < nkb;
-#pragma unroll
-      for (int term = 0; term < SP::TERMS; ++term)
-        an[term] = more ? *(const V8*)(Ap + term * planeA + arow + 32 * (kb + 1))
-                        : *(const V8*)(Ap + term * planeA + arow_next);
+    auto step = [&](const V8 (&a)[SP::TERMS], int kb) {
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         V8 b[SP::TERMS];
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
       }
       if (FOLD) {
         since += 32;
-        if (since >= KCHUNK && more) {
+        if (since >= KCHUNK && kb + 1 < nkb) {
 #pragma unroll
           for (int j = 0; j < (FOLD ? FN : 1); ++j) {
 #pragma unroll
@@ -365,10 +371,30 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
           since = 0;
         }
       }
+    };
+    for (int kb = 0; kb < nkb; kb += 2) {
+      V8 f0[SP::TERMS];
+      loadA(arow, arow_next, kb + 2, f0);
+      step(a0, kb);
 #pragma unroll
-      for (int term = 0; term < SP::TERMS; ++term) a[term] = an[term];
+      for (int term = 0; term < SP::TERMS; ++term) a0[term] = f0[term];
+      if (kb + 1 < nkb) {
+        V8 f1[SP::TERMS];
+        loadA(arow, arow_next, kb + 3, f1);
+        step(a1, kb + 1);
+#pragma unroll
+        for (int term = 0; term < SP::TERMS; ++term) a1[term] = f1[term];
+      }
     }
-    (void)KBMAX;
+    if (nkb & 1) {
+      // odd step count: the next tile's step 0 landed in a1, its step 1 in a0
+#pragma unroll
+      for (int term = 0; term < SP::TERMS; ++term) {
+        const V8 t = a0[term];
+        a0[term] = a1[term];
+        a1[term] = t;
+      }
+    }
     // stage the 16 x BN tile: lane holds D[4 (lane / 16) + v][16 j + lane % 16]
 #pragma unroll
     for (int j = 0; j < FN; ++j)

@@ -181,6 +181,9 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // the window's indicator, so only the axis-DAX factor changes, to the
 // difference of g chi, which reaches one cell beyond the window (the brick
 // lists must be built for windows of n_s + 2).
+// The factors, their products and the sums are formed in the grid's own
+// type (FP32 for an FP32 grid, exponentials from FP64 arguments), the
+// positions and the exponents' arguments in FP64.
 template <class GT, int DAX>
 __global__ __launch_bounds__(64) void short_gather_kernel(
     GT* __restrict__ grid, const double* __restrict__ pos, const double* __restrict__ q,
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
     const int* __restrict__ active, int64_t active_cap) {
   extern __shared__ double sg_lds[];
   const int Rs = R - R_l;
-  double* f = sg_lds;               // [3][Rs][8]
+  GT* f = (GT*)sg_lds;              // [3][Rs][8] (in the space of 24 Rs doubles)
   double* ak = sg_lds + 24 * Rs;    // [Rs]
   double* tk2 = ak + Rs;            // [Rs]
   const int lane = threadIdx.x;
@@ -212,15 +215,15 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
       const int base0 = b0 * 8, base1 = b1 * 8, base2 = b2 * 8;
       const int64_t i1 = base1 + c1, i2 = base2 + c2;
       const bool col_ok = i1 < n && i2 < n;
-      double old[8];
+      GT old[8];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int64_t i0 = base0 + m;
-        old[m] = (col_ok && i0 < n) ? (double)grid[(i0 * n + i1) * n + i2] : 0.0;
+        old[m] = (col_ok && i0 < n) ? grid[(i0 * n + i1) * n + i2] : (GT)0;
       }
-      double acc[8];
+      GT acc[8];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) acc[m] = 0.0;
+      for (int m = 0; m < 8; ++m) acc[m] = (GT)0;
       const int s0 = start[br], s1 = start[br + 1];
       for (int e0 = s0; e0 < s1; e0 += 64) {
         const int cnt = std::min(64, s1 - e0);
@@ -254,7 +257,8 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
             const int64_t gi = bs[l] + m;
             if (l != DAX) {
               const double d = (-b + ((double)gi + 0.5) * h) - p[l];
-              f[idx] = exp(-tk2[k] * (d * d));
+              if constexpr (sizeof(GT) == 4) f[idx] = expf((float)(-tk2[k] * (d * d)));
+              else f[idx] = exp(-tk2[k] * (d * d));
             } else {
               // g chi at global index j (0 outside the window and the grid)
               auto gchi = [&](int64_t j) {
@@ -268,30 +272,30 @@ __global__ __launch_bounds__(64) void short_gather_kernel(
                 else if (gi == n - 1) v = (gchi(n - 1) - gchi(n - 2)) / h;
                 else v = (gchi(gi + 1) - gchi(gi - 1)) / (2.0 * h);
               }
-              f[idx] = v;
+              f[idx] = (GT)v;
             }
           }
           __syncthreads();
           if (c1 >= lo[1] && c1 <= hi[1] && c2 >= lo[2] && c2 <= hi[2]) {
-            double s[8];
+            GT s[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) s[m] = 0.0;
+            for (int m = 0; m < 8; ++m) s[m] = (GT)0;
             for (int k = 0; k < Rs; ++k) {
-              const double g = ak[k] * f[(Rs + k) * 8 + c1] * f[(2 * Rs + k) * 8 + c2];
+              const GT g = (GT)ak[k] * f[(Rs + k) * 8 + c1] * f[(2 * Rs + k) * 8 + c2];
 #pragma unroll
               for (int m = 0; m < 8; ++m) s[m] += g * f[k * 8 + m];
             }
 #pragma unroll
             for (int m = 0; m < 8; ++m)
-              if (m >= lo[0] && m <= hi[0]) acc[m] += z * s[m];
+              if (m >= lo[0] && m <= hi[0]) acc[m] += (GT)z * s[m];
           }
         }
       }
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int64_t i0 = base0 + m;
-        if (col_ok && i0 < n && acc[m] != 0.0)
-          grid[(i0 * n + i1) * n + i2] = (GT)(old[m] + acc[m]);
+        if (col_ok && i0 < n && acc[m] != (GT)0)
+          grid[(i0 * n + i1) * n + i2] = old[m] + acc[m];
       }
     }
   }

@@ -115,3 +115,31 @@ def test_dot_rejects_other_grids(rsm, ctx):
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     with pytest.raises(rsm.RSError):
         rsm.dot(A, B, out)
+
+
+def test_dot_dense_columns_against_own_grids(rsm, ctx):
+    """Dense windows on a 192^3 grid (1500 and 900 particles in [-6, 6]^3):
+    brick columns with many touched bricks (several groups of four per
+    column) and bricks listed by several particles, A and B with different
+    windows and quadratures; FP64 tensors at the rank rule's ranks against
+    the product of their own FP64 grids at 1e-10."""
+    sa = workloads.tiny_system(81, 1500, 6.0, 192, 24, 10, 13, min_sep=0.35)
+    sb = workloads.tiny_system(82, 900, 6.0, 192, 20, 8, 9, min_sep=0.35)
+    out = []
+    for s in (sa, sb):
+        f = rsm.Factors(ctx, s.b, s.n, s.R, s.R_l, s.n_s, kernel=s.kernel, lam=s.lam)
+        g = torch.empty(s.n ** 3, dtype=torch.float64, device="cuda")
+        T = rsm.assemble(ctx, f, dev(s.pos), dev(s.q), g, rsm.make_aopts(s.eps_tucker, r_max=192))
+        out.append((f, T, g))
+    (fa, A, ga), (fb, B, gb) = out
+    got = gpu_dot(rsm, A, B)
+    ref = float(torch.dot(ga, gb).item())
+    aa = gpu_dot(rsm, A, A)
+    ref_aa = float(torch.dot(ga, ga).item())
+    say(f"dense dot: ranks {list(A.info().ranks)} {list(B.info().ranks)}: <A,B> {got:.15e} "
+        f"grids {ref:.15e} rel {abs(got - ref) / abs(ref):.2e}; <A,A> rel {abs(aa - ref_aa) / ref_aa:.2e}")
+    assert abs(got - ref) <= 1e-10 * abs(ref)
+    assert abs(aa - ref_aa) <= 1e-10 * ref_aa
+    for f, T, _ in out:
+        T.free()
+        f.close()

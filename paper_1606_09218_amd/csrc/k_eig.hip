@@ -820,10 +820,177 @@ __global__ __launch_bounds__(CHB_THREADS) void chol_blk_kernel(double* __restric
   }
 }
 
+// Blocked Cholesky for 128 < p <= 512 on CG workgroups per mode (cooperative
+// launch: all co-resident).  Workgroup g keeps rows i = g + CG t of M in LDS
+// (the upper part, from column i) for the whole factorisation.  Per panel of
+// CB rows: the owners publish their panel rows through the lower triangle of
+// C (M[i][c], c >= i, at C[c][i]: nothing reads that part, and the panels
+// use distinct columns of it), one grid barrier, then every workgroup loads
+// the panel and factors it with the same arithmetic as chol_blk_kernel (the
+// 16 x 16 diagonal block by one wave, forward substitution per column), and
+// applies the rank-CB update to its own rows in LDS.  Workgroup 0 writes R:
+// the strictly upper entries of each panel at once, the diagonal (whose slot
+// carried the published M[i][i]) after a last barrier.
+constexpr int CC_THREADS = 512;
+
+__global__ __launch_bounds__(CC_THREADS) void chol_coop_kernel(double* __restrict__ Call, int p,
+                                                               int64_t nrows, int shifted, int cg,
+                                                               int* __restrict__ fail, int fail_bit) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  extern __shared__ double ccl[];
+  __shared__ double red[CC_THREADS / 64];
+  __shared__ double sh_s;
+  const int mode = blockIdx.x / cg, g = blockIdx.x - (blockIdx.x / cg) * cg;
+  double* C = Call + (int64_t)mode * p * p;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ldp = p + 1;
+  const int nlm = (p + cg - 1) / cg;
+  const int nloc = (p - g + cg - 1) / cg;   // own rows i = g + cg t, t < nloc
+  double* rows = ccl;                        // [nlm][p], row t at rows + t p (columns >= i used)
+  double* pan = rows + (size_t)nlm * p;      // [CB][ldp]
+  double* rdiag = pan + (size_t)CB * ldp;    // [p] the diagonal of R (workgroup 0)
+  double sh = 0.0;
+  if (shifted) {
+    double tr = 0.0;
+    for (int i = tid; i < p; i += CC_THREADS) tr += C[(int64_t)i * p + i];
+    tr = wave_sum(tr);
+    if (lane == 0) red[wave] = tr;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < CC_THREADS / 64; ++w) t += red[w];
+      sh_s = 11.0 * ((double)nrows * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * t;
+    }
+    __syncthreads();
+    sh = sh_s;
+  }
+  for (int t = 0; t < nloc; ++t) {
+    const int i = g + cg * t;
+    for (int j = i + tid; j < p; j += CC_THREADS) {
+      double v = C[(int64_t)i * p + j];
+      if (j == i) v += sh;
+      rows[(size_t)t * p + j] = v;
+    }
+  }
+  grid.sync();   // every workgroup has read the diagonal (the shift) and its rows
+  for (int K0 = 0; K0 < p; K0 += CB) {
+    const int nb = p - K0 < CB ? p - K0 : CB;
+    const int w = p - K0;
+    // publish the owned panel rows: M[i][c] (c >= i) to C[c][i]
+    for (int rr = 0; rr < nb; ++rr) {
+      const int i = K0 + rr;
+      if (i % cg != g) continue;   // uniform over the workgroup
+      const double* ri = rows + (size_t)(i / cg) * p;
+      for (int c = i + tid; c < p; c += CC_THREADS) C[(int64_t)c * p + i] = ri[c];
+    }
+    grid.sync();
+    // the panel, pan[rr][cc] = M[K0 + rr][K0 + cc] for cc >= rr
+    for (int e = tid; e < nb * w; e += CC_THREADS) {
+      const int cc = e / nb, rr = e - (e / nb) * nb;
+      pan[rr * ldp + cc] = cc >= rr ? C[(int64_t)(K0 + cc) * p + K0 + rr] : 0.0;
+    }
+    __syncthreads();
+    // the diagonal block by wave 0 (as chol_blk_kernel)
+    if (wave == 0) {
+      for (int k = 0; k < nb; ++k) {
+        double d = pan[k * ldp + k];
+        if (!(d > 0.0)) {
+          if (lane == 0 && g == 0) atomicOr(fail, fail_bit);
+          d = 1e-300;
+        }
+        const double invd = 1.0 / d;
+#pragma unroll
+        for (int t = 0; t < CB * CB / 64; ++t) {
+          const int e = lane + 64 * t, j = e / CB, i = e - (e / CB) * CB;
+          if (j > k && i >= j && i < nb) pan[j * ldp + i] -= pan[k * ldp + i] * (pan[k * ldp + j] * invd);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double sq = sqrt(d), isq = 1.0 / sq;
+        if (lane > k && lane < nb) pan[k * ldp + lane] *= isq;
+        if (lane == 0) pan[k * ldp + k] = sq;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    // the rest of the panel's rows: R12 = R11^{-T} M12, one column per thread
+    for (int i = nb + tid; i < w; i += CC_THREADS) {
+      double x[CB];
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        if (k < nb) {
+          double v = pan[k * ldp + i];
+#pragma unroll
+          for (int l = 0; l < k; ++l) v -= pan[l * ldp + k] * x[l];
+          x[k] = v / pan[k * ldp + k];
+          pan[k * ldp + i] = x[k];
+        }
+      }
+    }
+    __syncthreads();
+    if (g == 0) {   // R's panel rows: strictly upper entries now, the diagonal at the end
+      for (int e = tid; e < nb * w; e += CC_THREADS) {
+        const int r = e / w, c = e - (e / w) * w;
+        if (c > r) C[(int64_t)(K0 + r) * p + K0 + c] = pan[r * ldp + c];
+        else if (c == r) rdiag[K0 + r] = pan[r * ldp + c];
+      }
+    }
+    // rank-nb update of the own rows j >= K0 + nb: M[j][i] -= sum_k R[k][j] R[k][i], i >= j
+    for (int t = wave; t < nloc; t += CC_THREADS / 64) {
+      const int j = g + cg * t;
+      if (j < K0 + nb) continue;   // uniform over the wave
+      double* rj = rows + (size_t)t * p;
+      for (int i = j + lane; i < p; i += 64) {
+        double acc = rj[i];
+        for (int k = 0; k < nb; ++k) acc -= pan[k * ldp + (j - K0)] * pan[k * ldp + (i - K0)];
+        rj[i] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  grid.sync();   // every panel has been read: the diagonal slots are free
+  if (g == 0)
+    for (int i = tid; i < p; i += CC_THREADS) C[(int64_t)i * p + i] = rdiag[i];
+}
+
+static size_t chol_coop_lds(int p, int cg) {
+  const int nlm = (p + cg - 1) / cg;
+  return ((size_t)nlm * p + (size_t)CB * (p + 1) + (size_t)p) * sizeof(double);
+}
+
 // kernels that use more than the default dynamic LDS opt in to the device limit
 static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 48 * 1024)
     RS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+// the cooperative form, when the device can launch it and its LDS fits
+static bool launch_chol_coop(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit,
+                             int* fail, int fail_bit, hipStream_t s) {
+  static int coop = -1;
+  if (coop < 0) {
+    int dev = 0, v = 0;
+    coop = (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && v)
+               ? 1 : 0;
+  }
+  if (!coop) return false;
+  int cg = 16;
+  if (chol_coop_lds(p, cg) + 1024 > (size_t)lds_limit) cg = 32;
+  const size_t lds = chol_coop_lds(p, cg);
+  if (lds + 1024 > (size_t)lds_limit) return false;
+  allow_lds((const void*)chol_coop_kernel, lds);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chol_coop_kernel, CC_THREADS, lds) !=
+          hipSuccess || per_cu < 1)
+    return false;
+  void* args[] = {&C, &p, &nrows, &shifted, &cg, &fail, &fail_bit};
+  RS_HIP(hipLaunchCooperativeKernel((const void*)chol_coop_kernel, dim3(modes * cg),
+                                    dim3(CC_THREADS), args, lds, s));
+  return true;
 }
 
 void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int lds_limit, int* fail,
@@ -840,6 +1007,7 @@ void launch_chol(double* C, int p, int64_t nrows, int modes, int shifted, int ld
   }
   const size_t bytes = (size_t)p * p * sizeof(double);
   const size_t pbytes = (size_t)CB * (p + 1) * sizeof(double);
+  if (p <= 512 && launch_chol_coop(C, p, nrows, modes, shifted, lds_limit, fail, fail_bit, s)) return;
   if (p <= 512 && pbytes + 1024 <= (size_t)lds_limit) {
     allow_lds((const void*)chol_blk_kernel, pbytes);
     hipLaunchKernelGGL(chol_blk_kernel, dim3(modes), dim3(CHB_THREADS), pbytes, s, C, p, nrows,

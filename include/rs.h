@@ -64,12 +64,15 @@ typedef enum { RS_NEWTON = 0, RS_YUKAWA = 1, RS_NEWTON_PLUS_YUKAWA = 2 } rs_kern
 
 /* Arithmetic of the assembly.
  *  RS_FP64: everything in FP64; the grid is FP64.
- *  RS_MIXED_FP16: the core contraction and the last grid-expansion
- *    contraction (T2 x_3 V3) use split FP16 operands (value = hi + lo * 2^-11,
- *    three MFMA products) with FP32 MFMA accumulation and FP64 sums across K
- *    chunks; the side matrices, Gram, eigensolve, projection, the first two
- *    expansion contractions, quadrature table, point evaluation and energy
- *    reduction stay FP64.  The grid is FP32.
+ *  RS_MIXED_FP16: the projection (U~ = V^T U), the core contraction, the
+ *    second expansion contraction (T2 = X x_2 V2) and the last grid-expansion
+ *    contraction (T2 x_3 V3) use split FP16 operands (value = hi + lo,
+ *    power-of-two scaled, three MFMA products) with FP32 MFMA accumulation
+ *    and FP64 sums across K chunks; the side matrices are formed directly as
+ *    the projection's FP16 planes (FP64 only where an option needs them); the
+ *    Gram, eigensolve, first expansion contraction, quadrature table, point
+ *    evaluation and energy reduction stay FP64, and T2 is kept in FP64.  The
+ *    grid is FP32.
  *  RS_MIXED_BF16: as RS_MIXED_FP16 with three-way split BF16 operands (six
  *    products).
  *  RS_FP32: assembled as RS_MIXED_FP16; point values, the energy's per-

@@ -1437,29 +1437,42 @@ rs_status rs_gradient_grid(const rs_tensor* T, int32_t axis, void* grid_out, voi
     DevBuf t2d;
     const double* T2src = T->T2.as<double>();
     const double* V3 = T->Q[2].as<double>();
+    const bool f64 = T->prec == RS_FP64;
+    DevBuf wg(f64 ? 0 : grid_mixed_workspace_bytes(n, r3), s);
+    bool planes_ready = false;
     if (axis == 2) {
       V3 = dv.as<double>();
     } else {
+      // the two expansions as in the assembly (the second in split precision
+      // for split tensors, writing the grid's T2 planes as it goes)
       const double* V1 = axis == 0 ? dv.as<double>() : nullptr;
       const double* V2 = axis == 1 ? dv.as<double>() : nullptr;
       t2d = DevBuf((size_t)n * n * r3 * sizeof(double), s);
       DevBuf X((size_t)n * T->r[1] * r3 * sizeof(double), s);
       const Gemm64 g1 = expand1_gemm(T, X.as<double>(), V1);
-      const Gemm64 g2 = expand2_gemm(T, X.as<double>(), V2, t2d.as<double>());
-      DevBuf w1(gemm64_workspace_bytes(g1, ncu), s), w2(gemm64_workspace_bytes(g2, ncu), s);
+      DevBuf w1(gemm64_workspace_bytes(g1, ncu), s);
       gemm64(g1, ncu, w1.as<double>(), s);
-      gemm64(g2, ncu, w2.as<double>(), s);
+      if (f64) {
+        const Gemm64 g2 = expand2_gemm(T, X.as<double>(), V2, t2d.as<double>());
+        DevBuf w2(gemm64_workspace_bytes(g2, ncu), s);
+        gemm64(g2, ncu, w2.as<double>(), s);
+      } else {
+        DevBuf w2(expand2_mixed_workspace_bytes(n, T->r[1], r3), s), e2(sizeof(int), s);
+        expand2_mixed(contraction_prec(T->prec), X.as<double>(), V2 ? V2 : T->Q[1].as<double>(), n,
+                      T->r[1], r3, t2d.as<double>(), w2.p, wg.p, e2.as<int>(), s);
+        planes_ready = true;
+      }
       T2src = t2d.as<double>();
     }
-    if (T->prec == RS_FP64) {
+    if (f64) {
       if (!grid64_stream(T2src, V3, n, r3, (double*)grid_out, ncu, T->ctx->lds_limit, s)) {
         const Gemm64 gg = grid_gemm(T, grid_out, T2src, V3);
-        DevBuf wg(gemm64_workspace_bytes(gg, ncu), s);
-        gemm64(gg, ncu, wg.as<double>(), s);
+        DevBuf wgg(gemm64_workspace_bytes(gg, ncu), s);
+        gemm64(gg, ncu, wgg.as<double>(), s);
       }
     } else {
-      DevBuf wg(grid_mixed_workspace_bytes(n, r3), s);
-      grid_mixed(contraction_prec(T->prec), T2src, V3, n, r3, (float*)grid_out, wg.p, ncu, s);
+      grid_mixed(contraction_prec(T->prec), T2src, V3, n, r3, (float*)grid_out, wg.p, ncu, s,
+                 planes_ready, planes_ready ? nullptr : T->t2exp.as<int>());
     }
     // short range: brick lists for windows one cell wider on each side, then
     // the finite difference of every local term

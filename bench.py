@@ -544,7 +544,7 @@ def main():
         print(json.dumps(cpu_baseline(s)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(every workload here runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ typedef enum {
   RS_E_NOMEM = 2,        /* device allocation failed */
   RS_E_DEVICE = 3,       /* a HIP call failed */
   RS_E_RANK_CAP = 4,     /* rank rule exceeded r_max: result produced at r_max (non-fatal) */
-  RS_E_UNSUPPORTED = 5   /* valid request this build does not support */
+  RS_E_UNSUPPORTED = 5   /* valid request the library does not support */
 } rs_status;
 
 /* Generating kernel p(r) (section 2.2): Newton 1/r, Yukawa e^{-lambda r}/r,

@@ -159,8 +159,8 @@ def cfg3_protein_like(seed: int = 3, N: int = 10000, n: int = 1024) -> System:
 def cfg4_forces(seed: int = 4, N: int = 4096, kernel: str = "newton+yukawa") -> System:
     """N=4096 uniform in [-15,15]^3 with min separation 0.7, charges +-1
     summing to zero; n=512, R=28; kernel 1/r + e^{-0.5 r}/r.  The box half
-    width b=18 and R_l=11 are this build's choices (the workload statement
-    leaves them open)."""
+    width b=18 and R_l=11 are chosen here (the workload's statement leaves
+    them open)."""
     rng = np.random.default_rng(seed)
     pos = _min_sep_uniform(rng, N, -15.0, 15.0, 0.7)
     q = np.concatenate([np.ones(N // 2), -np.ones(N - N // 2)])

@@ -299,9 +299,10 @@ static void run_factors_and_gram(rs_ctx* ctx, const rs_factors* f, const Plan& P
                                  const double* pos, const double* q, double* U, double* xi,
                                  double* w, double* sw, double* G, int method, hipStream_t s,
                                  rs_tensor* T = nullptr, double* work = nullptr,
-                                 void* planes16 = nullptr, int64_t kp = 0) {
+                                 void* planes16 = nullptr, int64_t kp = 0,
+                                 hipStream_t side_s = nullptr, bool on_side = false) {
   launch_side_matrices(pos, q, f->t_dev, f->a_dev, P.N, P.R_l, P.n, f->grid.b, U, xi, w, sw, s,
-                       planes16, kp);
+                       planes16, kp, side_s, on_side);
   if (T) mark(T, RS_STAGE_GRAM, s);
   DevBuf own;
   if (!work) {
@@ -319,6 +320,29 @@ struct Span {
   void* p = nullptr;
   size_t bytes = 0;
   template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// The caller's stream waits for work put on the context's second stream:
+// at join(), or when the assembly leaves early (declared after the arena
+// that work writes, so that the wait is enqueued before the arena goes back
+// to the allocator on the caller's stream).
+struct SideJoin {
+  hipEvent_t start = nullptr, done = nullptr;
+  hipStream_t s = nullptr, aux = nullptr;
+  void join() {
+    if (start && !done && aux && hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess)
+      (void)hipEventRecord(done, aux);
+    if (done) {
+      (void)hipStreamWaitEvent(s, done, 0);
+      (void)hipEventDestroy(done);
+      done = nullptr;
+    }
+    if (start) {
+      (void)hipEventDestroy(start);
+      start = nullptr;
+    }
+  }
+  ~SideJoin() { join(); }
 };
 
 // Scratch carved from one allocation: offsets are 256-byte aligned.
@@ -568,12 +592,17 @@ rs_status rs_ctx_create(int device, rs_ctx** out) {
     if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, device) == hipSuccess && wk > 0)
       c->wall_khz = (double)wk;
     noalloc_scratch_init(device);
+    RS_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     *out = c.release();
     return RS_OK;
   });
 }
 
 rs_ctx::~rs_ctx() {
+  if (aux) {
+    (void)hipStreamSynchronize(aux);
+    (void)hipStreamDestroy(aux);
+  }
   for (void* p : pin_all) (void)hipHostFree(p);
 }
 
@@ -808,9 +837,27 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     Span P16 = fused16 ? piece(o_P16, (size_t)3 * 2 * K * kpn * 2) : Span{};
     Span w = piece(o_w, (size_t)K * d8), sw = piece(o_sw, (size_t)K * d8);
     Span G = piece(o_G, (size_t)3 * n * n * d8);
+    // Nothing before the projection reads the side matrices on the identity
+    // Gram route with the Gram sketch: they are formed on the context's
+    // second stream, concurrently with the Gram and the eigensolver, and the
+    // caller's stream waits for them before the projection (or, on an early
+    // exit, before the arena that holds them is released).
+    const bool side_overlap = ctx->aux && P.gram == RS_GRAM_IDENTITY && P.sketch == 0;
+    SideJoin side_join;
+    if (side_overlap) {
+      side_join.s = s;
+      side_join.aux = ctx->aux;
+      RS_HIP(hipEventCreateWithFlags(&side_join.start, hipEventDisableTiming));
+      RS_HIP(hipEventRecord(side_join.start, s));
+      RS_HIP(hipStreamWaitEvent(ctx->aux, side_join.start, 0));
+    }
     run_factors_and_gram(ctx, f, P, dpos, dq, U.as<double>(), xi.as<double>(), w.as<double>(),
                          sw.as<double>(), G.as<double>(), P.gram, s, T.get(),
-                         (double*)(pre_buf.as<char>() + o_wgram), P16.p, kpn);
+                         (double*)(pre_buf.as<char>() + o_wgram), P16.p, kpn, ctx->aux, side_overlap);
+    if (side_overlap) {
+      RS_HIP(hipEventCreateWithFlags(&side_join.done, hipEventDisableTiming));
+      RS_HIP(hipEventRecord(side_join.done, ctx->aux));
+    }
 
     // short-range binning (counts and offsets; the total is read back with the ranks)
     Span counts = piece(o_counts, (size_t)(nbricks + 1) * sizeof(int));
@@ -1081,6 +1128,7 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     launch_canonical_signs3(q3, n, none, p, s);
 
     // (a5) projection U~_l = V_l^T U_l and core
+    side_join.join();
     mark(T.get(), RS_STAGE_PROJECT, s);
     for (int l = 0; l < 3; ++l) {
       gp[l].C = at(o_ut[l]);

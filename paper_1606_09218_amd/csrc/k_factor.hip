@@ -135,7 +135,8 @@ __global__ void weights_kernel(const double* __restrict__ q, const double* __res
 
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
-                          double* w, double* sw, hipStream_t s, void* planes16, int64_t kp) {
+                          double* w, double* sw, hipStream_t s, void* planes16, int64_t kp,
+                          hipStream_t side_s, bool on_side) {
   const int64_t K = N * R_l;
   const int threads = planes16 ? 256 : (n >= 256 ? 256 : 64);
   const int64_t cpb = planes16 && kp / 8 <= 256 ? 256 / (kp / 8) : 1;
@@ -144,8 +145,8 @@ void launch_side_matrices(const double* pos, const double* q, const double* t, c
   if (blocks <= 0 || n <= 0) return;
   if (planes16 && (kp % 32 != 0 || kp < n)) throw Error{RS_E_INVALID, "side-matrix planes: bad padding"};
   if (planes16 && K >= (1LL << 31)) throw Error{RS_E_UNSUPPORTED, "side matrices: more than 2^31 terms"};
-  hipLaunchKernelGGL(side_matrix_kernel, dim3((unsigned)blocks, 3), dim3(threads), 0, s, pos, t,
-                     N, R_l, n, b, U, (_Float16*)planes16, kp);
+  hipLaunchKernelGGL(side_matrix_kernel, dim3((unsigned)blocks, 3), dim3(threads), 0,
+                     on_side ? side_s : s, pos, t, N, R_l, n, b, U, (_Float16*)planes16, kp);
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, q, a, N,
                      R_l, xi, w, sw);
 }

@@ -82,6 +82,10 @@ struct rs_ctx {
   // tensor; the context is deleted when the last one is released, so a
   // tensor freed after rs_ctx_destroy still finds it
   std::atomic<int> refs{1};
+  // a second stream of the context (default priority): the side matrices of
+  // an assembly run there while the eigensolver, which they do not feed,
+  // runs on the caller's stream
+  hipStream_t aux = nullptr;
   ~rs_ctx();
 };
 
@@ -169,11 +173,12 @@ void launch_validate(const double* pos, const double* q, int64_t N, double b, in
 // Side matrices U[l][i + j*n] = exp(-t_k^2 (x_i - x_{nu,l})^2), j = k*N + nu, k < R_l;
 // xi[j] = q[nu] a_k, w[j] = |xi_j|^{2/3}.
 // U (FP64, may be null) and/or planes16 (FP16 split planes of the
-// projection, [mode][hi, lo][K][kp], scale 2^14; may be null)
+// projection, [mode][hi, lo][K][kp], scale 2^14; may be null); with on_side
+// the side matrices go to side_s and the weights to s
 void launch_side_matrices(const double* pos, const double* q, const double* t, const double* a,
                           int64_t N, int R_l, int64_t n, double b, double* U, double* xi,
                           double* w, double* sw, hipStream_t s, void* planes16 = nullptr,
-                          int64_t kp = 0);
+                          int64_t kp = 0, hipStream_t side_s = nullptr, bool on_side = false);
 
 // k_dot.hip : scalar product of two RS tensors (the touched-brick correction
 // and fixed-order reductions; the long-long term is formed by the caller)

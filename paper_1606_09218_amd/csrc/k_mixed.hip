@@ -889,13 +889,27 @@ __global__ __launch_bounds__(128 * WGM) void proj_tile_kernel(
 
 // ---- max |x| of FP64 arrays as ordered bit patterns (deterministic) ----------
 // Wave maxima are combined in LDS; one integer atomic per workgroup (the
-// maximum does not depend on the order).
+// maximum does not depend on the order).  Device-scope atomics on one address
+// are serialised (about 12 ns each), so the launch holds few workgroups and
+// each thread keeps ABS_UNROLL coalesced loads in flight per pass.
+constexpr int ABS_UNROLL = 8;
+constexpr int ABS_MAX_BLOCKS = 512;
+
 __global__ __launch_bounds__(256) void absmax_kernel(const double* __restrict__ x, int64_t count,
                                                      unsigned long long* __restrict__ out) {
   __shared__ double wmax[4];
   double m = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + (ABS_UNROLL - 1) * stride < count; e += ABS_UNROLL * stride) {
+    double v[ABS_UNROLL];
+#pragma unroll
+    for (int k = 0; k < ABS_UNROLL; ++k) v[k] = fabs(x[e + k * stride]);
+#pragma unroll
+    for (int k = 0; k < ABS_UNROLL; ++k)
+      if (v[k] > m) m = v[k];
+  }
+  for (; e < count; e += stride) {
     const double v = fabs(x[e]);
     if (v > m) m = v;
   }
@@ -926,7 +940,8 @@ __global__ void scale_exponents_kernel(const unsigned long long* mx, int nbops, 
 }
 
 static void absmax(const double* x, int64_t count, unsigned long long* out, hipStream_t s) {
-  unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  unsigned blocks = (unsigned)std::min<int64_t>((count + 256 * ABS_UNROLL - 1) / (256 * ABS_UNROLL),
+                                                 ABS_MAX_BLOCKS);
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, s, x, count, out);
 }

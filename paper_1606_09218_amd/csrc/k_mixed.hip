@@ -263,6 +263,16 @@ __global__ __launch_bounds__(256) void transpose_split_kernel(const double* __re
 }
 
 // ---- grid, streaming form -------------------------------------------------------
+// B rows in LDS are padded by GRID_BPAD elements.  A 16-byte LDS read is served
+// in passes of lanes {0-7, 16-23} (and the like) over 64 four-byte banks; the
+// B fragment reads of such a pass take two adjacent 16-byte chunks of 8
+// consecutive rows.  With kp a multiple of 32, a row stride of kp + 16 half
+// words is an odd multiple of 8 banks modulo 64, so the 8 rows start on 8
+// distinct multiples of 8 banks and the 16 reads hit 64 distinct banks (a pad
+// of 8 gave a stride of 52 banks at kp = 352: rows 5, 6, 7 met the second
+// chunks of rows 0, 1, 2, a two-way conflict in every pass).
+constexpr int GRID_BPAD = 16;
+
 // Persistent workgroups of 8 waves.  Workgroup (panel, group) keeps the B
 // planes of a panel of BN columns in LDS and walks the row tiles (128 rows:
 // 16 per wave) of its group; the A fragments of the next tile are loaded
@@ -282,9 +292,7 @@ __global__ __launch_bounds__(512) void grid_stream_kernel(const typename SP::T* 
   constexpr int FN = BN / 16;
   constexpr int SLD = BN + 4;   // staging row stride (floats)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // B rows are padded by 8 elements (16 bytes): consecutive rows start 4 banks
-  // apart, so the 16-byte reads of 16 lanes from 16 rows hit distinct banks
-  const int ks = kp + 8;
+  const int ks = kp + GRID_BPAD;
   T* Bs = (T*)smem;                                          // [term][BN][ks]
   float* stage = (float*)(smem + (size_t)SP::TERMS * BN * ks * sizeof(T));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1113,8 +1121,8 @@ static void launch_grid_stream(const typename SP::T* ap, const typename SP::T* b
   int gq = std::max(1, num_cu / (8 * npanels));
   while (gq > 1 && (int64_t)gq * 8 > tiles) --gq;
   const int groups = gq * 8;
-  // padded B rows (kp + 8 elements) and the per-wave staging tiles
-  const size_t lds = (size_t)SP::TERMS * BN * (kp + 8) * sizeof(typename SP::T) +
+  // padded B rows (kp + GRID_BPAD elements) and the per-wave staging tiles
+  const size_t lds = (size_t)SP::TERMS * BN * (kp + GRID_BPAD) * sizeof(typename SP::T) +
                      (size_t)8 * 16 * (BN + 4) * sizeof(float);
   auto fn = grid_stream_kernel<SP, BN, FOLD>;
   if (lds > 48 * 1024)
@@ -1129,7 +1137,7 @@ static void grid_stream(const typename SP::T* ap, const typename SP::T* bp, int6
                         int64_t kp, float* grid, const int* exps, int num_cu, hipStream_t s) {
   const size_t budget = 150 * 1024;
   auto need = [&](int bn) {
-    return (size_t)SP::TERMS * bn * (kp + 8) * 2 + (size_t)8 * 16 * (bn + 4) * 4;
+    return (size_t)SP::TERMS * bn * (kp + GRID_BPAD) * 2 + (size_t)8 * 16 * (bn + 4) * 4;
   };
   const bool fold = kp > KCHUNK;
   if (need(128) <= budget && !fold) launch_grid_stream<SP, 128, false>(ap, bp, M, N, kp, grid, exps, num_cu, s);

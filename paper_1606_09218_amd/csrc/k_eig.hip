@@ -884,10 +884,27 @@ __global__ __launch_bounds__(CC_THREADS) void chol_coop_kernel(double* __restric
       for (int c = i + tid; c < p; c += CC_THREADS) C[(int64_t)c * p + i] = ri[c];
     }
     grid.sync();
-    // the panel, pan[rr][cc] = M[K0 + rr][K0 + cc] for cc >= rr
-    for (int e = tid; e < nb * w; e += CC_THREADS) {
-      const int cc = e / nb, rr = e - (e / nb) * nb;
-      pan[rr * ldp + cc] = cc >= rr ? C[(int64_t)(K0 + cc) * p + K0 + rr] : 0.0;
+    // the panel, pan[rr][cc] = M[K0 + rr][K0 + cc] for cc >= rr: loads in
+    // batches of PB per thread, issued together before their LDS stores (one
+    // memory latency per batch instead of one per element)
+    {
+      constexpr int PB = 8;
+      const int tot = nb * w;
+      for (int e0 = 0; e0 < tot; e0 += PB * CC_THREADS) {
+        double v[PB];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+          const int e = e0 + u * CC_THREADS + tid;
+          const int cc = e / nb, rr = e - (e / nb) * nb;
+          v[u] = e < tot && cc >= rr ? C[(int64_t)(K0 + cc) * p + K0 + rr] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+          const int e = e0 + u * CC_THREADS + tid;
+          const int cc = e / nb, rr = e - (e / nb) * nb;
+          if (e < tot) pan[rr * ldp + cc] = v[u];
+        }
+      }
     }
     __syncthreads();
     // the diagonal block by wave 0 (as chol_blk_kernel)
@@ -1606,17 +1623,21 @@ __global__ __launch_bounds__(TD_THREADS) void tridiag_dist_kernel(const double* 
   double beta_prev = 0.0;
   for (int k = 0; k + 2 < p; ++k) {
     const int par = k & 1, ppar = par ^ 1;
+    // one column per thread (p <= TD_THREADS); row k as published is loaded
+    // with the previous step's products and partial sums, in one memory latency
+    const int jc = k + tid;
+    const double* pub = k == 0 ? B : rowb[ppar];   // row k before the pending update
+    const double pub_j = jc < p ? pub[jc] : 0.0;
     if (k > 0) {   // the pending w_{k-1} = pw_{k-1} - kc v_{k-1}
       double ps = 0.0;
       for (int b = 0; b < TD_G; ++b) ps += partb[ppar][b];
       const double kc = 0.5 * beta_prev * ps;
-      for (int j = k + tid; j < p; j += TD_THREADS) wold[j] = pwb[ppar][j] - kc * vold[j];
+      if (jc < p) wold[jc] = pwb[ppar][jc] - kc * vold[jc];
     }
     __syncthreads();
-    const double* pub = k == 0 ? B : rowb[ppar];   // row k before the pending update
     {
       const double vk = vold[k], wk = wold[k];
-      for (int j = k + tid; j < p; j += TD_THREADS) rk[j] = pub[j] - (vk * wold[j] + wk * vold[j]);
+      if (jc < p) rk[jc] = pub_j - (vk * wold[jc] + wk * vold[jc]);
     }
     __syncthreads();
     double prt = 0.0;
@@ -1718,7 +1739,7 @@ static bool launch_tridiag_dist(double* B, double* ws, int p, int rc, int modes,
             hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && v)
                ? 1 : 0;
   }
-  if (!coop || p < 3) return false;
+  if (!coop || p < 3 || p > TD_THREADS) return false;
   const int nlm = (p + TD_G - 1) / TD_G;
   const size_t lds = ((size_t)nlm * p + 4 * (size_t)p) * sizeof(double);
   if (lds > 150 * 1024) return false;

@@ -864,12 +864,27 @@ __global__ __launch_bounds__(CC_THREADS) void chol_coop_kernel(double* __restric
     __syncthreads();
     sh = sh_s;
   }
-  for (int t = 0; t < nloc; ++t) {
-    const int i = g + cg * t;
-    for (int j = i + tid; j < p; j += CC_THREADS) {
-      double v = C[(int64_t)i * p + j];
-      if (j == i) v += sh;
-      rows[(size_t)t * p + j] = v;
+  // own rows, column j = i + tid (p <= CC_THREADS), RB rows per batch of
+  // loads issued together before their LDS stores
+  {
+    constexpr int RB = 8;
+    for (int t0 = 0; t0 < nloc; t0 += RB) {
+      double v[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int t = t0 + u, i = g + cg * t, j = i + tid;
+        double x = 0.0;
+        if (t < nloc && j < p) {
+          x = C[(int64_t)i * p + j];
+          if (j == i) x += sh;
+        }
+        v[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int t = t0 + u, i = g + cg * t, j = i + tid;
+        if (t < nloc && j < p) rows[(size_t)t * p + j] = v[u];
+      }
     }
   }
   grid.sync();   // every workgroup has read the diagonal (the shift) and its rows
@@ -994,7 +1009,7 @@ static bool launch_chol_coop(double* C, int p, int64_t nrows, int modes, int shi
             hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && v)
                ? 1 : 0;
   }
-  if (!coop) return false;
+  if (!coop || p > CC_THREADS) return false;
   int cg = 16;
   if (chol_coop_lds(p, cg) + 1024 > (size_t)lds_limit) cg = 32;
   const size_t lds = chol_coop_lds(p, cg);
@@ -1609,8 +1624,22 @@ __global__ __launch_bounds__(TD_THREADS) void tridiag_dist_kernel(const double* 
   double* pwb[2] = {W.sx, W.sx + p};
   double* rowb[2] = {W.sx + 2 * p, W.sx + 3 * p};
   double* partb[2] = {W.sx + 4 * p, W.sx + 4 * p + TD_G};
-  for (int t = 0; t < nloc; ++t)
-    for (int j = tid; j < p; j += TD_THREADS) rows[t * p + j] = B[(int64_t)(g + TD_G * t) * p + j];
+  {   // own rows, column tid (p <= TD_THREADS), RB rows per batch of loads
+    constexpr int RB = 8;
+    for (int t0 = 0; t0 < nloc; t0 += RB) {
+      double v[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int t = t0 + u;
+        v[u] = t < nloc && tid < p ? B[(int64_t)(g + TD_G * t) * p + tid] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int t = t0 + u;
+        if (t < nloc && tid < p) rows[t * p + tid] = v[u];
+      }
+    }
+  }
   for (int j = tid; j < p; j += TD_THREADS) {
     vold[j] = 0.0;
     wold[j] = 0.0;
@@ -1945,13 +1974,28 @@ __global__ __launch_bounds__(256) void invit_kernel(double* __restrict__ ws,
     }
     scale = mx > 0.0 ? 1.0 / mx : 1.0;
   }
+  // unit norm; chunks of IC loads issued together, the sum in row order
   double nrm = 0.0;
-  for (int i = 0; i < p; ++i) {
-    const double v = scale * z[i * ld];
-    nrm += v * v;
+  for (int i0 = 0; i0 < p; i0 += IC) {
+    double zz[IC];
+#pragma unroll
+    for (int c = 0; c < IC; ++c) zz[c] = i0 + c < p ? z[(i0 + c) * ld] : 0.0;
+#pragma unroll
+    for (int c = 0; c < IC; ++c)
+      if (i0 + c < p) {
+        const double v = scale * zz[c];
+        nrm += v * v;
+      }
   }
   const double s = nrm > 0.0 ? scale / sqrt(nrm) : 0.0;
-  for (int i = 0; i < p; ++i) z[i * ld] *= s;
+  for (int i0 = 0; i0 < p; i0 += IC) {
+    double zz[IC];
+#pragma unroll
+    for (int c = 0; c < IC; ++c) zz[c] = i0 + c < p ? z[(i0 + c) * ld] : 0.0;
+#pragma unroll
+    for (int c = 0; c < IC; ++c)
+      if (i0 + c < p) z[(i0 + c) * ld] = zz[c] * s;
+  }
 }
 
 // The same inverse iteration with the per-vector arrays in LDS ([array][i][t],

@@ -873,17 +873,18 @@ __global__ __launch_bounds__(CC_THREADS) void chol_coop_kernel(double* __restric
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
         const int t = t0 + u, i = g + cg * t, j = i + tid;
-        double x = 0.0;
-        if (t < nloc && j < p) {
-          x = C[(int64_t)i * p + j];
-          if (j == i) x += sh;
-        }
-        v[u] = x;
+        v[u] = t < nloc && j < p ? C[(int64_t)i * p + j] : 0.0;
       }
+      // the shift goes onto the diagonal after the batch (an add inside the
+      // load's branch would make each load wait for its data)
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
         const int t = t0 + u, i = g + cg * t, j = i + tid;
-        if (t < nloc && j < p) rows[(size_t)t * p + j] = v[u];
+        if (t < nloc && j < p) {
+          double x = v[u];
+          if (j == i) x += sh;
+          rows[(size_t)t * p + j] = x;
+        }
       }
     }
   }

@@ -258,6 +258,14 @@ rs_status rs_stream_release(rs_ctx* ctx, void* stream);
  * synchronises the context's device and returns every cached block now.
  * Buffers still held by live tensors are not affected. */
 rs_status rs_ctx_trim(rs_ctx* ctx);
+/* Admission budget of the context, for callers that size several requests
+ * against one device (a serving loop): rs_assemble refuses, with RS_E_NOMEM
+ * and before it allocates anything, a request whose rs_footprint_bytes bound
+ * (the factors' grid and quadrature, N, the larger of r_max and the fixed
+ * ranks, the precision) exceeds `bytes`.  The bound is per request:
+ * concurrent assemblies on one context are each checked alone.  0, the
+ * default, sets no budget.  Errors: RS_E_INVALID for a null context. */
+rs_status rs_ctx_set_hbm_budget(rs_ctx* ctx, size_t bytes);
 
 /* ---- quadrature table and split (sections 2.2-2.3) --------------------- */
 

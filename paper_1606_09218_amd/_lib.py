@@ -79,6 +79,7 @@ def _load():
         "rs_ctx_create": ([C.c_int, C.POINTER(P)], C.c_int),
         "rs_ctx_destroy": ([P], None),
         "rs_ctx_set_timing": ([P, C.c_int], C.c_int),
+        "rs_ctx_set_hbm_budget": ([P, C.c_size_t], C.c_int),
         "rs_ctx_trim": ([P], C.c_int),
         "rs_stream_release": ([P, P], C.c_int),
         "rs_build_factors": ([P, C.POINTER(rs_grid), C.POINTER(rs_fdesc), C.POINTER(P)], C.c_int),
@@ -134,7 +135,8 @@ atexit.register(_at_exit)
 def _may_release() -> bool:
     return not _exiting and not sys.is_finalizing()
 
-EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_trim",
+EXPORTED = ("rs_ctx_create", "rs_ctx_destroy", "rs_ctx_set_timing", "rs_ctx_set_hbm_budget",
+            "rs_ctx_trim",
             "rs_stream_release", "rs_build_factors", "rs_factors_get",
             "rs_factors_free", "rs_assemble", "rs_weighted_gram", "rs_eval_points", "rs_energy",
             "rs_forces", "rs_energy_forces", "rs_energy_forces_noalloc", "rs_gradient_grid",
@@ -176,11 +178,19 @@ def _stream_ptr(stream):
 
 
 class Context:
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
         h = C.c_void_p()
         _check(lib.rs_ctx_create(int(device), C.byref(h)))
         self.handle = h
         self.device = device
+        if hbm_budget:
+            self.set_hbm_budget(hbm_budget)
+
+    def set_hbm_budget(self, nbytes: int):
+        """Admission budget: later assemblies whose footprint bound exceeds
+        `nbytes` are refused with RS_E_NOMEM before allocating; 0 sets no
+        budget (rs_ctx_set_hbm_budget)."""
+        _check(lib.rs_ctx_set_hbm_budget(self.handle, int(nbytes)))
 
     def set_timing(self, enable=True):
         """HIP-event timing of later assemblies: False/0 off, True/1 every

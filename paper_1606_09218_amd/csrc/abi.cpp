@@ -637,6 +637,14 @@ rs_status rs_ctx_set_timing(rs_ctx* ctx, int enable) {
   });
 }
 
+rs_status rs_ctx_set_hbm_budget(rs_ctx* ctx, size_t bytes) {
+  return guarded([&]() -> rs_status {
+    RS_REQUIRE(ctx != nullptr, "null context");
+    ctx->hbm_budget = bytes;
+    return RS_OK;
+  });
+}
+
 rs_status rs_build_factors(rs_ctx* ctx, const rs_grid* grid, const rs_fdesc* fdesc,
                            rs_factors** out) {
   return guarded([&]() -> rs_status {
@@ -702,6 +710,14 @@ rs_status rs_assemble(rs_ctx* ctx, const rs_factors* f, int64_t N, const double*
     RS_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const Plan P = make_plan(f, N, opts);
+    if (ctx->hbm_budget) {   // admission, before anything is allocated
+      const int rb = std::max({P.r_max, P.fixed[0], P.fixed[1], P.fixed[2]});
+      const size_t need = rs_footprint_bytes(&f->grid, &f->fdesc, N, rb, P.prec, grid_out != nullptr);
+      if (need > ctx->hbm_budget)
+        throw Error{RS_E_NOMEM, "the request's footprint bound (" + std::to_string(need) +
+                                    " bytes) exceeds the context's budget (" +
+                                    std::to_string(ctx->hbm_budget) + " bytes)"};
+    }
     const int64_t n = P.n, K = P.K;
     // eigensolver subspace: every buffer is sized for the plan's p; the rank
     // rule runs first at P.p_first and again at the plan's p only when a

@@ -73,6 +73,7 @@ struct rs_ctx {
   int num_cu = 256;
   int timing = 0;
   int lds_limit = 65536;   // dynamic LDS bytes one workgroup may use
+  size_t hbm_budget = 0;   // admission bound per assembly (0: none)
   double wall_khz = 100000.0;  // rate of the device wall clock
   // pinned host slots for the rank readback of concurrent assemblies
   // (hipHostMalloc'd on first use, freed with the context)

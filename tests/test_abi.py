@@ -34,3 +34,7 @@ def test_status_strings_and_host_only_calls():
     assert nb > 3 * 128 * 64 * 8 * 8
     bad = _lib.rs_grid(10.0, 127)   # odd n: the footprint call reports 0
     assert _lib.lib.rs_footprint_bytes(ctypes.byref(bad), ctypes.byref(f), 64, 128, 0, 1) == 0
+    # the context setters check their handle before anything else
+    assert _lib.lib.rs_ctx_set_hbm_budget(None, 1 << 30) == 1
+    assert b"null context" in _lib.lib.rs_last_error()
+    assert _lib.lib.rs_ctx_set_timing(None, 0) == 1
